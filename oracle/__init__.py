@@ -1,0 +1,264 @@
+"""CPU oracle for the FlashSplat splat-and-accumulate pass and its assignment.
+
+TEST INFRASTRUCTURE ONLY: tests, the smoke check and the bench's CPU-baseline
+leg may use it; the GPU library never does. It shares no code with the GPU
+path; both sides read the same inputs from `scenegen`.
+
+Pieces (paper sections in brackets):
+  project32 / bin_view   strict binary32 projection and tile binning
+                         [Sec. 3.1]; the reference of the bit-exact contract
+  project64              binary64 mean2D / conic [Sec. 3.1]
+  composite64 / solve64  binary64 alpha compositing, A = sum of alpha*T per
+                         (Gaussian, pixel label) [Eq. (1), Eq. (6), Eq. (7),
+                         Supp. Sec. 6]
+  render64               Eq. (1) with an arbitrary per-Gaussian property
+  weights64              dense per-pixel weights (tiny scenes only)
+  assign64               L1-normalised, background-biased argmax per object
+                         [Sec. 3.2 "Regularized ILP", Eq. (7), Supp. Sec. 6]
+  objective_eq2 / brute_force_binary   exhaustive checks of Eq. (2)/(5)
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import subprocess
+from typing import Dict, Optional, Sequence
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SRC = os.path.join(_HERE, "fs_oracle.c")
+_LIB = os.path.join(_HERE, "liboracle.so")
+
+# default rasterizer constants (inherited by the paper from 3DGS; see DESIGN)
+DEFAULT = dict(tile_w=16, tile_h=16, sigma_k=3.0, lowpass=0.3, znear=0.2, guard=1.3,
+               alpha_min=1.0 / 255.0, alpha_max=0.99, t_min=1e-4, fp64_cond=64.0,
+               band_eps=2.0 ** -10)
+# no compositing thresholds besides the elliptical support
+EXACT = dict(DEFAULT, alpha_min=0.0, alpha_max=1.0, t_min=0.0)
+
+_KEYS = ["tile_w", "tile_h", "sigma_k", "lowpass", "znear", "guard",
+         "alpha_min", "alpha_max", "t_min", "fp64_cond", "band_eps"]
+
+
+def build(force: bool = False) -> str:
+    """Compile the C oracle (strict IEEE, no FP contraction)."""
+    if force or not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
+        tmp = _LIB + ".tmp%d" % os.getpid()
+        cmd = ["gcc", "-O2", "-std=c11", "-fPIC", "-shared", "-fopenmp",
+               "-ffp-contract=off", "-fno-fast-math", "-fexcess-precision=standard",
+               "-o", tmp, _SRC, "-lm"]
+        subprocess.check_call(cmd)
+        os.replace(tmp, _LIB)
+    return _LIB
+
+
+_lib = None
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        build()
+        L = ctypes.CDLL(_LIB)
+        P = ctypes.c_void_p
+        I64 = ctypes.c_int64
+        I32 = ctypes.c_int32
+        L.or_project32.argtypes = [I64, P, P, P, P, P, P, P, P, P]
+        L.or_project32.restype = None
+        L.or_bin.argtypes = [I64, P, P, P, P, I32, I32, P, P, P]
+        L.or_bin.restype = I64
+        L.or_project64.argtypes = [I64, P, P, P, P]
+        L.or_project64.restype = None
+        L.or_composite64.argtypes = [I64, P, P, P, P, P, P, P, I32, P, P, P, P, P]
+        L.or_composite64.restype = None
+        L.or_render64.argtypes = [I64, P, P, P, P, P, P, P, P]
+        L.or_render64.restype = None
+        L.or_weights64.argtypes = [I64, P, P, P, P, P, P, P]
+        L.or_weights64.restype = None
+        _lib = L
+    return _lib
+
+
+def _p(a: np.ndarray):
+    assert a.flags["C_CONTIGUOUS"], "arrays passed to the oracle must be C-contiguous"
+    return ctypes.c_void_p(a.ctypes.data)
+
+
+def params(**over) -> np.ndarray:
+    d = dict(DEFAULT)
+    d.update(over)
+    out = np.zeros(12, np.float32)
+    for i, k in enumerate(_KEYS):
+        out[i] = d[k]
+    return out
+
+
+def _gauss(scene) -> np.ndarray:
+    return np.ascontiguousarray(np.stack(scene.gaussian_arrays()).astype(np.float32))
+
+
+def tiles_of(scene, v, prm) -> tuple:
+    tw, th = int(prm[0]), int(prm[1])
+    W, H = int(scene.W[v]), int(scene.H[v])
+    return (W + tw - 1) // tw, (H + th - 1) // th
+
+
+def project32(scene, v: int, prm: np.ndarray, gauss: Optional[np.ndarray] = None) -> Dict[str, np.ndarray]:
+    """Strict binary32 projection of every Gaussian into view v."""
+    g = _gauss(scene) if gauss is None else gauss
+    n = g.shape[1]
+    cam = np.ascontiguousarray(scene.camera_rows()[v])
+    out = dict(flags=np.zeros(n, np.uint8), rect=np.zeros((n, 4), np.int32),
+               ntiles=np.zeros(n, np.int32), depth=np.zeros(n, np.float32),
+               cov=np.zeros((n, 3), np.float32), mean2d=np.zeros((n, 2), np.float32))
+    lib().or_project32(n, _p(g), _p(cam), _p(prm), _p(out["flags"]), _p(out["rect"]),
+                       _p(out["ntiles"]), _p(out["depth"]), _p(out["cov"]), _p(out["mean2d"]))
+    return out
+
+
+def bin_view(scene, v: int, prm: np.ndarray, proj: Optional[dict] = None) -> Dict[str, np.ndarray]:
+    """Tile lists of view v in (tile, depth, id) order and per-tile [start, end)."""
+    pr = project32(scene, v, prm) if proj is None else proj
+    tx, ty = tiles_of(scene, v, prm)
+    vis = (pr["flags"] & 1) != 0
+    total = int(np.sum(pr["ntiles"][vis].astype(np.int64)))
+    tile = np.zeros(max(total, 1), np.int32)
+    gid = np.zeros(max(total, 1), np.uint32)
+    ranges = np.zeros((tx * ty, 2), np.uint32)
+    n = pr["flags"].shape[0]
+    got = lib().or_bin(n, _p(pr["flags"]), _p(pr["rect"]), _p(pr["ntiles"]), _p(pr["depth"]),
+                       tx, ty, _p(tile), _p(gid), _p(ranges))
+    assert got == total
+    return dict(tile=tile[:total], g=gid[:total], ranges=ranges, proj=pr, tiles_x=tx, tiles_y=ty)
+
+
+def project64(scene, v: int, prm: np.ndarray, gauss: Optional[np.ndarray] = None) -> np.ndarray:
+    g = _gauss(scene) if gauss is None else gauss
+    n = g.shape[1]
+    cam = np.ascontiguousarray(scene.camera_rows()[v])
+    out = np.zeros((n, 5), np.float64)
+    lib().or_project64(n, _p(g), _p(cam), _p(prm), _p(out))
+    return out
+
+
+def composite64(scene, v: int, prm: np.ndarray, bins: dict, A: np.ndarray, slack: np.ndarray,
+                p64: Optional[np.ndarray] = None, want_pixels: bool = False):
+    """Add view v's contributions into A (float64 [n][E]) and slack (float64 [n])."""
+    if p64 is None:
+        p64 = project64(scene, v, prm)
+    n = scene.n
+    cam = np.ascontiguousarray(scene.camera_rows()[v])
+    mask = np.ascontiguousarray(scene.masks[v], dtype=np.uint8)
+    W, H = int(scene.W[v]), int(scene.H[v])
+    tf = np.zeros((H, W), np.float64) if want_pixels else None
+    nb = np.zeros((H, W), np.int32) if want_pixels else None
+    stats = np.zeros(4, np.int64)
+    op = np.ascontiguousarray(scene.op)
+    lst = np.ascontiguousarray(bins["g"]) if bins["g"].size else np.zeros(1, np.uint32)
+    lib().or_composite64(n, _p(p64), _p(op), _p(cam), _p(prm), _p(lst), _p(bins["ranges"]),
+                         _p(mask), int(scene.E), _p(A), _p(slack),
+                         _p(tf) if tf is not None else None, _p(nb) if nb is not None else None, _p(stats))
+    return dict(tfinal=tf, nblend=nb, blends=int(stats[0]), flagged=int(stats[1]),
+                bad_labels=int(stats[2]), evaluated=int(stats[3]))
+
+
+def solve64(scene, prm: Optional[np.ndarray] = None, views: Optional[Sequence[int]] = None,
+            want_pixels: bool = False, E: Optional[int] = None):
+    """A64 and slack over the given views (default: all), plus per-view details."""
+    prm = params() if prm is None else prm
+    E = scene.E if E is None else E
+    views = range(scene.n_views) if views is None else views
+    A = np.zeros((scene.n, E), np.float64)
+    slack = np.zeros(scene.n, np.float64)
+    per_view = {}
+    tot = dict(blends=0, flagged=0, bad_labels=0, evaluated=0)
+    g = _gauss(scene)
+    for v in views:
+        b = bin_view(scene, v, prm, project32(scene, v, prm, g))
+        p64 = project64(scene, v, prm, g)
+        r = composite64(scene, v, prm, b, A, slack, p64=p64, want_pixels=want_pixels)
+        for k in tot:
+            tot[k] += r[k]
+        per_view[v] = dict(bins=b, p64=p64, **r)
+    return dict(A=A, slack=slack, views=per_view, **tot)
+
+
+def render64(scene, v: int, prm: np.ndarray, x: np.ndarray, bins: Optional[dict] = None,
+             p64: Optional[np.ndarray] = None) -> np.ndarray:
+    """Eq. (1): per-pixel sum of x_i * alpha_i * prod_{j<i}(1 - alpha_j)."""
+    b = bin_view(scene, v, prm) if bins is None else bins
+    p = project64(scene, v, prm) if p64 is None else p64
+    cam = np.ascontiguousarray(scene.camera_rows()[v])
+    W, H = int(scene.W[v]), int(scene.H[v])
+    out = np.zeros((H, W), np.float64)
+    xx = np.ascontiguousarray(x, dtype=np.float64)
+    lst = np.ascontiguousarray(b["g"]) if b["g"].size else np.zeros(1, np.uint32)
+    lib().or_render64(scene.n, _p(p), _p(np.ascontiguousarray(scene.op)), _p(cam), _p(prm),
+                      _p(lst), _p(b["ranges"]), _p(xx), _p(out))
+    return out
+
+
+def weights64(scene, v: int, prm: np.ndarray) -> np.ndarray:
+    """Dense weights alpha_i*T_i, float64 [H*W, n] (tiny scenes only)."""
+    b = bin_view(scene, v, prm)
+    p = project64(scene, v, prm)
+    cam = np.ascontiguousarray(scene.camera_rows()[v])
+    W, H = int(scene.W[v]), int(scene.H[v])
+    assert W * H * scene.n <= 50_000_000
+    out = np.zeros((H * W, scene.n), np.float64)
+    lst = np.ascontiguousarray(b["g"]) if b["g"].size else np.zeros(1, np.uint32)
+    lib().or_weights64(scene.n, _p(p), _p(np.ascontiguousarray(scene.op)), _p(cam), _p(prm),
+                       _p(lst), _p(b["ranges"]), _p(out))
+    return out
+
+
+# --------------------------------------------------------------------------
+# assignment
+
+def assign64(A: np.ndarray, gamma: float = 0.0):
+    """Closed-form assignment for every object t (Eq. (7), Sec. 3.2 bias).
+
+    For row g and object t: a = A[g,t], o = sum_{e != t} A[g,e] (others);
+    normalise (o, a) by max(o + a, 1e-12) (L1 normalisation as in the
+    supplementary PyTorch listing, whose normalize uses eps = 1e-12); the
+    Gaussian belongs to t iff a_n > o_n + gamma (ties go to "others", the
+    first index of the argmax). margin = |a_n - o_n - gamma|.
+    Returns S uint8 [E][n] and margin float64 [E][n].
+    """
+    A = np.asarray(A, dtype=np.float64)
+    n, E = A.shape
+    # sum over e != t via exclusive prefix + exclusive suffix sums (no subtraction)
+    pre = np.zeros_like(A)
+    pre[:, 1:] = np.cumsum(A[:, :-1], axis=1)
+    suf = np.zeros_like(A)
+    suf[:, :-1] = np.cumsum(A[:, :0:-1], axis=1)[:, ::-1]
+    others = pre + suf
+    s = np.maximum(A + others, 1e-12)
+    a_n = A / s
+    o_n = others / s
+    S = (a_n > o_n + gamma).T.astype(np.uint8)
+    margin = np.abs(a_n - o_n - gamma).T
+    return np.ascontiguousarray(S), np.ascontiguousarray(margin)
+
+
+def objective_eq2(weights: Sequence[np.ndarray], masks: Sequence[np.ndarray], P: np.ndarray) -> float:
+    """Eq. (2): sum over views and pixels of |sum_i P_i alpha_i T_i - M|."""
+    tot = 0.0
+    for w, m in zip(weights, masks):
+        tot += float(np.sum(np.abs(w @ P.astype(np.float64) - m.reshape(-1).astype(np.float64))))
+    return tot
+
+
+def brute_force_binary(weights: Sequence[np.ndarray], masks: Sequence[np.ndarray]):
+    """Exhaustive minimum of Eq. (2) over all P in {0,1}^n (n <= 16)."""
+    n = weights[0].shape[1]
+    assert n <= 16
+    best, best_P, vals = None, None, np.zeros(1 << n)
+    for code in range(1 << n):
+        P = np.array([(code >> i) & 1 for i in range(n)], np.float64)
+        f = objective_eq2(weights, masks, P)
+        vals[code] = f
+        if best is None or f < best:
+            best, best_P = f, P
+    return best, best_P, vals
