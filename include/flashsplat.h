@@ -1,0 +1,222 @@
+/*
+ * flashsplat.h -- C ABI of the MI355X (gfx950) splat-and-accumulate library.
+ *
+ * The library lifts per-view 2D label masks onto a reconstructed 3D Gaussian
+ * Splatting scene as described in "FlashSplat: 2D to 3D Gaussian Splatting
+ * Segmentation Solved Optimally" (Shen, Yang, Wang, ECCV 2024):
+ *
+ *   fs_project     3D Gaussians -> 2D Gaussians per view (Sec. 3.1)
+ *   fs_bin_sort    16x16 tile lists in depth order (Sec. 3.1)
+ *   fs_accumulate  front-to-back alpha compositing (Eq. (1)); every weight
+ *                  w = alpha*T is added into A[g][label(pixel)]
+ *                  (Eq. (6), Eq. (7), Supp. Sec. 6)
+ *   fs_assign      closed-form, L1-normalised, background-biased argmax per
+ *                  object (Sec. 3.2 "Regularized ILP", Eq. (7), Supp. Sec. 6)
+ *
+ * Conventions shared by all calls
+ *  - Memory: every array argument documented as "device" is device memory
+ *    owned by the caller; the library never frees or retains it past the
+ *    call's completion on the stream. Arguments documented as "host" are read
+ *    during the call only. The library owns only its context workspace.
+ *  - Asynchrony: calls enqueue work on the context's stream and return
+ *    without waiting, except fs_status_get, fs_bin_sort with a non-NULL
+ *    n_pairs argument, and fs_batch_* planning calls, which synchronise the
+ *    stream.
+ *  - Errors: every call returns FS_OK (0) or a negative FS_ERR_* code and
+ *    throws nothing. Argument errors are detected before any work is
+ *    enqueued. Conditions found on the device (a mask label >= n_classes, an
+ *    overflowing pair buffer, invalid Gaussian parameters) are latched in the
+ *    context's status word and reported by fs_status_get.
+ *  - Threads: one context per host thread; a context is not thread-safe.
+ *  - Layout: Gaussians are structure-of-arrays float32 with post-activation
+ *    values (linear scales, opacity in [0,1]); quaternions are (w,x,y,z) and
+ *    need not be normalised. Cameras map world to camera with OpenCV axes
+ *    (x right, y down, z forward); pixel (row j, column k) is sampled at
+ *    (k + 0.5, j + 0.5). Masks are uint8, row-major [H][W] per view, views
+ *    concatenated; label 0 is background.
+ */
+#ifndef FLASHSPLAT_H
+#define FLASHSPLAT_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define FS_OK 0
+#define FS_ERR_ARG (-1)      /* invalid argument (null pointer, bad size or range) */
+#define FS_ERR_ALLOC (-2)    /* device or host allocation failed */
+#define FS_ERR_HIP (-3)      /* a HIP runtime call failed */
+#define FS_ERR_CAPACITY (-4) /* output buffer too small; required size reported */
+#define FS_ERR_DEVICE (-5)   /* a condition latched on the device (see fs_status) */
+#define FS_ERR_STATE (-6)    /* call not valid in the current state */
+
+/* status bits latched on the device */
+#define FS_DEV_BAD_LABEL 1u      /* a mask pixel had label >= n_classes (pixel skipped) */
+#define FS_DEV_PAIR_OVERFLOW 2u  /* more tile pairs than the bins capacity (excess dropped) */
+#define FS_DEV_INVALID_GAUSS 4u  /* a Gaussian had non-finite values, a zero quaternion or a
+                                    non-positive scale (culled) */
+#define FS_DEV_MANY_LABELS 8u    /* a tile held more distinct labels than the pre-reduction
+                                    slots; that tile used per-pixel atomics (informational) */
+
+/* reduction strategies of fs_accumulate */
+#define FS_RED_AUTO 0   /* library choice (currently FS_RED_LDS2SUM when A_lo != NULL, else FS_RED_LDS) */
+#define FS_RED_PLAIN 1  /* one global atomic per contributing (pixel, Gaussian) */
+#define FS_RED_LDS 2    /* per-tile pre-reduction over the tile's pixels, one atomic per (tile, Gaussian, label) */
+#define FS_RED_LDS2SUM 3 /* as FS_RED_LDS, plus the rounding error of each atomic (exact two-sum) into A_lo */
+
+typedef struct fs_ctx fs_ctx;
+
+/* Gaussians G_i = {m_i, q_i, s_i, o_i} (Sec. 3.1; the colour c_i is not used,
+ * Sec. 4.2). device float32 arrays of length n. */
+typedef struct {
+    const float *mx, *my, *mz;       /* mean, world frame */
+    const float *qw, *qx, *qy, *qz;  /* rotation quaternion */
+    const float *sx, *sy, *sz;       /* linear scales (> 0) */
+    const float *opacity;            /* in [0, 1] */
+    int64_t n;
+} fs_gaussians;
+
+/* One pinhole view (Sec. 3.2: "L rendered views with associated masks").
+ * host memory. R is row-major world->camera rotation, t its translation. */
+typedef struct {
+    float R[9];
+    float t[3];
+    float fx, fy, cx, cy;
+    int32_t width, height;
+} fs_camera;
+
+/* Rasterisation constants. The paper inherits them from the 3DGS renderer
+ * without stating values; fs_params_default gives 3DGS-like ones. */
+typedef struct {
+    int32_t tile_w, tile_h;  /* tile size in pixels; fs_accumulate needs tile_w*tile_h == 256
+                                with tile_w in {8, 16, 32} (default 16x16, Sec. 3.1) */
+    float sigma_k;           /* support: pixels with Mahalanobis distance <= sigma_k (3) */
+    float lowpass;           /* added to the 2D covariance diagonal, px^2 (0.3) */
+    float znear;             /* Gaussians with camera depth <= znear are not visible (0.2) */
+    float guard;             /* Jacobian clamp, as a multiple of the half field of view (1.3) */
+    float alpha_min;         /* smaller alphas are skipped (1/255) */
+    float alpha_max;         /* alphas are clamped to this (0.99) */
+    float t_min;             /* compositing stops before T would fall below this (1e-4) */
+    float fp64_cond;         /* a splat whose float32 2D covariance has a*c >= fp64_cond*det
+                                (or det <= 0) gets its conic inverted in float64 (64) */
+    int32_t fp64_conic;      /* 1 (default): use the float64 inversion for such splats */
+    int32_t reserved;
+} fs_params;
+
+/* Projected Gaussians, caller-owned device buffers, one plane per view:
+ * element (v, g) lives at index v*n + g. */
+typedef struct {
+    float *rec;       /* float32 [n_views][n][8]: u, v (pixel), conic_xx, conic_xy, conic_yy
+                         (inverse 2D covariance), opacity, depth (camera z), 0 */
+    int16_t *rect;    /* int16 [n_views][n][4]: tile rectangle x0, y0, x1, y1, inclusive */
+    int32_t *ntiles;  /* int32 [n_views][n]: tiles in the rectangle, 0 if not visible */
+    uint8_t *flags;   /* uint8 [n_views][n]: bit0 visible, bit1 float64 conic, bit2 invalid input */
+    int64_t n;
+    int32_t n_views;
+} fs_proj;
+
+/* Tile lists. Tiles of the views of one call are numbered globally: view v's
+ * tile (tx, ty) has id tile_base(v) + ty*tiles_x(v) + tx, where tile_base is
+ * the running sum of tiles_x*tiles_y over the earlier views. */
+typedef struct {
+    uint32_t *vals;    /* device uint32 [capacity]: Gaussian ids, ordered by (tile, depth, id) */
+    uint32_t *tiles;   /* device uint32 [capacity]: tile id of each entry */
+    uint32_t *ranges;  /* device uint32 [total tiles][2]: [start, end) into vals; [0,0) if empty */
+    int64_t capacity;  /* entries available in vals / tiles */
+} fs_bins;
+
+/* Optional per-pixel outputs of fs_accumulate, device, views concatenated
+ * like the masks; either pointer may be NULL. */
+typedef struct {
+    float *t_final;    /* float32: transmittance after the last blended Gaussian */
+    int32_t *n_blend;  /* int32: number of Gaussians blended into the pixel */
+} fs_pixel_out;
+
+typedef struct {
+    uint32_t flags;          /* FS_DEV_* bits latched since the last clear */
+    int64_t bad_labels;      /* pixels skipped for label >= n_classes */
+    int64_t invalid_gauss;   /* (Gaussian, view) pairs culled for invalid input */
+    int64_t fp64_splats;     /* (Gaussian, view) pairs inverted in float64 */
+    int64_t pairs_dropped;   /* tile pairs beyond capacity */
+    int64_t blends;          /* (pixel, Gaussian) weights added into A */
+    int64_t evaluated;       /* (pixel, Gaussian) pairs evaluated before each pixel's compositing ended */
+    int64_t unseen;          /* fs_assign: rows of A that are all zero */
+    int64_t multi_member;    /* fs_assign: Gaussians assigned to more than one object */
+    int64_t low_margin;      /* fs_assign: (object, Gaussian) entries with margin < 1e-4 */
+} fs_status;
+
+/* Library and context ---------------------------------------------------- */
+const char *fs_version(void);
+const char *fs_error_string(int code);
+void fs_params_default(fs_params *p);   /* 16x16, k=3, 0.3, 0.2, 1.3, 1/255, 0.99, 1e-4, 64, fp64 on */
+void fs_params_exact(fs_params *p);     /* as default but alpha_min=0, alpha_max=1, t_min=0 */
+
+/* Creates a context on the current HIP device that enqueues on `stream`
+ * (a hipStream_t; NULL = the null stream). */
+int fs_ctx_create(fs_ctx **out, void *stream);
+int fs_ctx_set_stream(fs_ctx *ctx, void *stream);
+int fs_ctx_destroy(fs_ctx *ctx);
+/* Message describing the last error returned on this context ("" if none). */
+const char *fs_ctx_last_error(fs_ctx *ctx);
+/* Synchronises the stream, copies the latched status and counters to *out
+ * (host), and clears them if `clear` is non-zero. Returns FS_ERR_DEVICE if
+ * any error bit (not FS_DEV_MANY_LABELS) was set. */
+int fs_status_get(fs_ctx *ctx, fs_status *out, int32_t clear);
+
+/* a1: projection (Sec. 3.1; EWA splatting of 3DGS, which the paper's renderer
+ * inherits). For every view v in cams[0..n_views) and Gaussian g: camera-space
+ * mean, 2D covariance J W Sigma3 W^T J^T + lowpass*I, its inverse (conic),
+ * pixel mean, depth, bounding radius ceil(sigma_k*sqrt(lambda_max)) and the
+ * tile rectangle of the pixel square mean +- radius. Visibility, rectangle and
+ * ntiles are computed in strict binary32 in a fixed operation order (the
+ * bit-exact contract); the conic is float32 except for splats selected by
+ * fp64_cond, which are inverted in float64. cams: host [n_views];
+ * out: caller-owned planes for n_views x g->n elements. */
+int fs_project(fs_ctx *ctx, const fs_gaussians *g, const fs_camera *cams, int32_t n_views,
+               const fs_params *p, const fs_proj *out);
+
+/* a2-a5: count, scan, emit, sort, ranges (Sec. 3.1: the pixels of a 16x16
+ * tile share one subset of Gaussians, blended in depth order). Emits one
+ * entry per (visible Gaussian, overlapped tile), ordered by tile, then depth,
+ * then Gaussian id (ties), and the [start, end) range of every tile.
+ * n_pairs: if non-NULL, the call synchronises, writes the exact number of
+ * entries to *n_pairs (host) and returns FS_ERR_CAPACITY without touching
+ * `out` when it exceeds out->capacity; if NULL the call stays asynchronous
+ * and entries beyond capacity are dropped and latched (FS_DEV_PAIR_OVERFLOW).
+ * cams: host [proj->n_views] (the same views as fs_project). */
+int fs_bin_sort(fs_ctx *ctx, const fs_proj *proj, const fs_camera *cams, const fs_params *p,
+                const fs_bins *out, int64_t *n_pairs);
+
+/* a6: compositing and accumulation (Eq. (1), Eq. (6)-(7), Supp. Sec. 6).
+ * For every pixel of every view, front to back over its tile's list:
+ * alpha = min(alpha_max, o*exp(-d^T conic d / 2)) for pixels within the
+ * support; Gaussians with alpha < alpha_min are skipped; compositing stops
+ * before the Gaussian after which T would drop below t_min; otherwise
+ * A[g][label(pixel)] += alpha*T and T *= 1 - alpha.
+ * masks: device uint8, views concatenated, each [H][W]. A_hi: device float32
+ * [n][n_classes], ADDED INTO (the caller zeroes it once; views may be
+ * processed over any number of calls). A_lo: same shape, receives the exact
+ * rounding error of the additions into A_hi (FS_RED_LDS2SUM) or NULL.
+ * n_classes in [2, 256]. pix: optional per-pixel outputs, or NULL. */
+int fs_accumulate(fs_ctx *ctx, const fs_proj *proj, const fs_bins *bins, const fs_camera *cams,
+                  const uint8_t *masks, int32_t n_classes, const fs_params *p,
+                  float *A_hi, float *A_lo, int32_t reduction, const fs_pixel_out *pix);
+
+/* a7: assignment (Sec. 3.2 Eq. (6) and "Regularized ILP"; Sec. 3.3 Eq. (7);
+ * Supp. Sec. 6 and its listing). For every Gaussian g and object t:
+ * a = A[g][t], o = sum_{e != t} A[g][e] (prefix + suffix sums, no
+ * subtraction), (o_n, a_n) = (o, a) / max(o + a, 1e-12);
+ * S[t][g] = a_n > o_n + gamma (ties go to "others"); margin[t][g] =
+ * |a_n - o_n - gamma|. Sums are formed in float64 from A_hi + A_lo.
+ * A_hi, A_lo (A_lo may be NULL): device float32 [n][n_classes].
+ * S: device uint8 [n_classes][n]; margin: device float32 [n_classes][n] or NULL.
+ * gamma: finite, in [-1, 1]. */
+int fs_assign(fs_ctx *ctx, const float *A_hi, const float *A_lo, int64_t n, int32_t n_classes,
+              float gamma, uint8_t *S, float *margin);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* FLASHSPLAT_H */

@@ -1,0 +1,281 @@
+"""ctypes binding of libflashsplat.so (include/flashsplat.h).
+
+Argument marshalling only: every step of the path runs in the library's HIP
+kernels. PyTorch provides device memory and the stream. The binding refuses
+to run when the library is missing; there is no CPU fallback.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from typing import Optional, Sequence
+
+import numpy as np
+import torch
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libflashsplat.so")
+
+FS_OK = 0
+FS_ERR_ARG = -1
+FS_ERR_ALLOC = -2
+FS_ERR_HIP = -3
+FS_ERR_CAPACITY = -4
+FS_ERR_DEVICE = -5
+FS_ERR_STATE = -6
+
+FS_DEV_BAD_LABEL = 1
+FS_DEV_PAIR_OVERFLOW = 2
+FS_DEV_INVALID_GAUSS = 4
+FS_DEV_MANY_LABELS = 8
+
+FS_RED_AUTO = 0
+FS_RED_PLAIN = 1
+FS_RED_LDS = 2
+FS_RED_LDS2SUM = 3
+
+_P = ctypes.c_void_p
+_F = ctypes.c_float
+_I32 = ctypes.c_int32
+_I64 = ctypes.c_int64
+
+
+class FsGaussians(ctypes.Structure):
+    _fields_ = [(k, _P) for k in ("mx", "my", "mz", "qw", "qx", "qy", "qz", "sx", "sy", "sz", "opacity")] + [("n", _I64)]
+
+
+class FsCamera(ctypes.Structure):
+    _fields_ = [("R", _F * 9), ("t", _F * 3), ("fx", _F), ("fy", _F), ("cx", _F), ("cy", _F),
+                ("width", _I32), ("height", _I32)]
+
+
+class FsParams(ctypes.Structure):
+    _fields_ = [("tile_w", _I32), ("tile_h", _I32), ("sigma_k", _F), ("lowpass", _F), ("znear", _F),
+                ("guard", _F), ("alpha_min", _F), ("alpha_max", _F), ("t_min", _F), ("fp64_cond", _F),
+                ("fp64_conic", _I32), ("reserved", _I32)]
+
+
+class FsProj(ctypes.Structure):
+    _fields_ = [("rec", _P), ("rect", _P), ("ntiles", _P), ("flags", _P), ("n", _I64), ("n_views", _I32)]
+
+
+class FsBins(ctypes.Structure):
+    _fields_ = [("vals", _P), ("tiles", _P), ("ranges", _P), ("capacity", _I64)]
+
+
+class FsPixelOut(ctypes.Structure):
+    _fields_ = [("t_final", _P), ("n_blend", _P)]
+
+
+class FsStatus(ctypes.Structure):
+    _fields_ = [("flags", ctypes.c_uint32), ("bad_labels", _I64), ("invalid_gauss", _I64),
+                ("fp64_splats", _I64), ("pairs_dropped", _I64), ("blends", _I64), ("evaluated", _I64), ("unseen", _I64),
+                ("multi_member", _I64), ("low_margin", _I64)]
+
+    def as_dict(self):
+        return {k: int(getattr(self, k)) for k, _ in self._fields_}
+
+
+# every symbol the header declares (checked by the CPU test)
+EXPORTS = ["fs_version", "fs_error_string", "fs_params_default", "fs_params_exact", "fs_ctx_create",
+           "fs_ctx_set_stream", "fs_ctx_destroy", "fs_ctx_last_error", "fs_status_get", "fs_project",
+           "fs_bin_sort", "fs_accumulate", "fs_assign"]
+
+_lib = None
+
+
+def load(path: str = LIB_PATH):
+    """Load the library (after torch, so it binds to torch's HIP runtime)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(path):
+        raise RuntimeError(f"libflashsplat.so not found at {path}: run paper_2409_08270_amd/build.py "
+                           "(or __graft_entry__.build()) first; there is no fallback")
+    L = ctypes.CDLL(path)
+    sig = {
+        "fs_version": ([], ctypes.c_char_p),
+        "fs_error_string": ([_I32], ctypes.c_char_p),
+        "fs_params_default": ([ctypes.POINTER(FsParams)], None),
+        "fs_params_exact": ([ctypes.POINTER(FsParams)], None),
+        "fs_ctx_create": ([ctypes.POINTER(_P), _P], _I32),
+        "fs_ctx_set_stream": ([_P, _P], _I32),
+        "fs_ctx_destroy": ([_P], _I32),
+        "fs_ctx_last_error": ([_P], ctypes.c_char_p),
+        "fs_status_get": ([_P, ctypes.POINTER(FsStatus), _I32], _I32),
+        "fs_project": ([_P, ctypes.POINTER(FsGaussians), ctypes.POINTER(FsCamera), _I32,
+                        ctypes.POINTER(FsParams), ctypes.POINTER(FsProj)], _I32),
+        "fs_bin_sort": ([_P, ctypes.POINTER(FsProj), ctypes.POINTER(FsCamera), ctypes.POINTER(FsParams),
+                         ctypes.POINTER(FsBins), ctypes.POINTER(_I64)], _I32),
+        "fs_accumulate": ([_P, ctypes.POINTER(FsProj), ctypes.POINTER(FsBins), ctypes.POINTER(FsCamera), _P, _I32,
+                           ctypes.POINTER(FsParams), _P, _P, _I32, ctypes.POINTER(FsPixelOut)], _I32),
+        "fs_assign": ([_P, _P, _P, _I64, _I32, _F, _P, _P], _I32),
+    }
+    for name, (args, res) in sig.items():
+        f = getattr(L, name)
+        f.argtypes = args
+        f.restype = res
+    _lib = L
+    return L
+
+
+class FlashSplatError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__(f"{msg} (code {code})")
+        self.code = code
+
+
+def params(**over) -> FsParams:
+    p = FsParams()
+    load().fs_params_default(ctypes.byref(p))
+    for k, v in over.items():
+        setattr(p, k, v)
+    return p
+
+
+def params_exact(**over) -> FsParams:
+    p = FsParams()
+    load().fs_params_exact(ctypes.byref(p))
+    for k, v in over.items():
+        setattr(p, k, v)
+    return p
+
+
+def cameras(rows: np.ndarray):
+    """FsCamera array from float32 [V, 18] rows (R9, t3, fx, fy, cx, cy, W, H)."""
+    rows = np.asarray(rows, np.float32).reshape(-1, 18)
+    arr = (FsCamera * rows.shape[0])()
+    for i, r in enumerate(rows):
+        arr[i].R[:] = [float(x) for x in r[0:9]]
+        arr[i].t[:] = [float(x) for x in r[9:12]]
+        arr[i].fx, arr[i].fy, arr[i].cx, arr[i].cy = [float(x) for x in r[12:16]]
+        arr[i].width = int(r[16])
+        arr[i].height = int(r[17])
+    return arr
+
+
+def _ptr(t: Optional[torch.Tensor]):
+    if t is None:
+        return None
+    assert t.is_cuda and t.is_contiguous(), "device tensors must be contiguous and on the GPU"
+    return ctypes.c_void_p(t.data_ptr())
+
+
+class Context:
+    """An fs_ctx bound to a torch stream (default: the current stream)."""
+
+    def __init__(self, stream: Optional[torch.cuda.Stream] = None):
+        self.L = load()
+        self.stream = stream or torch.cuda.current_stream()
+        h = _P()
+        self._check(self.L.fs_ctx_create(ctypes.byref(h), _P(self.stream.cuda_stream)), ctx=None)
+        self.h = h
+
+    def _check(self, rc, ctx="self"):
+        if rc != FS_OK:
+            msg = self.L.fs_error_string(rc).decode()
+            if ctx is not None and getattr(self, "h", None) is not None:
+                last = self.L.fs_ctx_last_error(self.h).decode()
+                if last:
+                    msg = f"{msg}: {last}"
+            raise FlashSplatError(rc, msg)
+        return rc
+
+    def close(self):
+        if getattr(self, "h", None) is not None:
+            self.L.fs_ctx_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def status(self, clear: bool = True, raise_on_error: bool = False) -> dict:
+        st = FsStatus()
+        rc = self.L.fs_status_get(self.h, ctypes.byref(st), 1 if clear else 0)
+        if rc != FS_OK and (rc != FS_ERR_DEVICE or raise_on_error):
+            self._check(rc)
+        return st.as_dict()
+
+    # -- the four calls ----------------------------------------------------
+    def fs_project(self, gauss: "DeviceScene", cams, n_views: int, prm: FsParams, proj: "Proj"):
+        return self._check(self.L.fs_project(self.h, ctypes.byref(gauss.struct()), cams, n_views,
+                                             ctypes.byref(prm), ctypes.byref(proj.struct())))
+
+    def fs_bin_sort(self, proj: "Proj", cams, prm: FsParams, bins: "Bins", sync_count: bool = True):
+        n = _I64(0)
+        rc = self.L.fs_bin_sort(self.h, ctypes.byref(proj.struct()), cams, ctypes.byref(prm),
+                                ctypes.byref(bins.struct()), ctypes.byref(n) if sync_count else None)
+        if rc == FS_ERR_CAPACITY:
+            return -int(n.value)
+        self._check(rc)
+        return int(n.value) if sync_count else None
+
+    def fs_accumulate(self, proj: "Proj", bins: "Bins", cams, masks: torch.Tensor, n_classes: int,
+                      prm: FsParams, A_hi: torch.Tensor, A_lo: Optional[torch.Tensor],
+                      reduction: int = FS_RED_AUTO, t_final: Optional[torch.Tensor] = None,
+                      n_blend: Optional[torch.Tensor] = None):
+        pix = None
+        if t_final is not None or n_blend is not None:
+            pix = FsPixelOut(_ptr(t_final), _ptr(n_blend))
+        return self._check(self.L.fs_accumulate(self.h, ctypes.byref(proj.struct()), ctypes.byref(bins.struct()),
+                                                cams, _ptr(masks), n_classes, ctypes.byref(prm), _ptr(A_hi),
+                                                _ptr(A_lo), reduction, ctypes.byref(pix) if pix else None))
+
+    def fs_assign(self, A_hi: torch.Tensor, A_lo: Optional[torch.Tensor], n: int, n_classes: int, gamma: float,
+                  S: torch.Tensor, margin: Optional[torch.Tensor] = None):
+        return self._check(self.L.fs_assign(self.h, _ptr(A_hi), _ptr(A_lo), n, n_classes, float(gamma), _ptr(S),
+                                            _ptr(margin)))
+
+
+class DeviceScene:
+    """A scene's Gaussians, cameras and masks resident on the GPU."""
+
+    def __init__(self, scene, device="cuda"):
+        self.n = scene.n
+        self.E = scene.E
+        self.arrays = [torch.from_numpy(np.ascontiguousarray(a)).to(device) for a in scene.gaussian_arrays()]
+        self.cam_rows = scene.camera_rows()
+        self.n_views = scene.n_views
+        self.W = scene.W.copy()
+        self.H = scene.H.copy()
+        self.mask_off = np.concatenate([[0], np.cumsum(scene.W.astype(np.int64) * scene.H.astype(np.int64))])
+        self.masks = torch.from_numpy(np.concatenate([m.reshape(-1) for m in scene.masks])).to(device)
+
+    def struct(self) -> FsGaussians:
+        g = FsGaussians(*[_ptr(a) for a in self.arrays], self.n)
+        return g
+
+    def cams(self, views: Optional[Sequence[int]] = None):
+        rows = self.cam_rows if views is None else self.cam_rows[list(views)]
+        return cameras(rows), rows.shape[0]
+
+    def masks_of(self, v0: int, v1: int) -> torch.Tensor:
+        return self.masks[int(self.mask_off[v0]):int(self.mask_off[v1])]
+
+
+class Proj:
+    """Caller-owned fs_proj planes for n_views x n elements."""
+
+    def __init__(self, n: int, n_views: int, device="cuda"):
+        self.n, self.n_views = n, n_views
+        self.rec = torch.empty((n_views, n, 8), dtype=torch.float32, device=device)
+        self.rect = torch.empty((n_views, n, 4), dtype=torch.int16, device=device)
+        self.ntiles = torch.empty((n_views, n), dtype=torch.int32, device=device)
+        self.flags = torch.empty((n_views, n), dtype=torch.uint8, device=device)
+
+    def struct(self) -> FsProj:
+        return FsProj(_ptr(self.rec), _ptr(self.rect), _ptr(self.ntiles), _ptr(self.flags), self.n, self.n_views)
+
+
+class Bins:
+    def __init__(self, capacity: int, total_tiles: int, device="cuda"):
+        self.capacity = int(capacity)
+        self.vals = torch.empty(max(1, self.capacity), dtype=torch.int32, device=device)
+        self.tiles = torch.empty(max(1, self.capacity), dtype=torch.int32, device=device)
+        self.ranges = torch.empty((max(1, total_tiles), 2), dtype=torch.int32, device=device)
+
+    def struct(self) -> FsBins:
+        return FsBins(_ptr(self.vals), _ptr(self.tiles), _ptr(self.ranges), self.capacity)

@@ -1,0 +1,240 @@
+// a6: front-to-back alpha compositing with accumulation of every weight
+// w = alpha * T into A[g][label(pixel)] (paper Eq. (1), Eq. (6)-(7),
+// Supp. Sec. 6).
+//
+// One workgroup of 256 threads composites one tile of 256 pixels; each wave
+// owns an 8x8 block of the tile. The tile's depth-ordered list is staged
+// through LDS in batches of 256 Gaussians (one coalesced gather per thread),
+// and every thread walks the batch for its pixel.
+//
+// Scatter-add. The paper adds alpha*T with one atomic per (pixel, Gaussian).
+// Here the distinct labels of the tile are compacted into a few slots; for
+// each Gaussian, each wave sums its lanes' weights per slot with DPP
+// (cross-lane) adds, the four waves combine in an LDS partial, and one
+// global atomic per (tile, Gaussian, label) remains. With A_lo, the exact
+// rounding error of that atomic (two-sum on the returned old value) goes to
+// A_lo, so that A_hi + A_lo carries the sum to about one rounding.
+#include "fs_internal.h"
+
+namespace fs {
+namespace {
+
+constexpr int kSlots = 8;     // distinct labels per tile handled by pre-reduction
+constexpr int kBatch = 256;   // Gaussians staged per batch
+
+template <int CTRL>
+__device__ __forceinline__ float dpp_mov(float x)
+{
+    return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(x), CTRL, 0xF, 0xF, false));
+}
+
+// sum over the 64 lanes; the result is returned in every lane
+__device__ __forceinline__ float wave_sum(float x)
+{
+    x += dpp_mov<0xB1>(x);   // quad_perm [1,0,3,2]
+    x += dpp_mov<0x4E>(x);   // quad_perm [2,3,0,1]
+    x += dpp_mov<0x124>(x);  // row_ror:4
+    x += dpp_mov<0x128>(x);  // row_ror:8  -> every lane holds its row's sum
+    const float r0 = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(x), 0));
+    const float r1 = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(x), 16));
+    const float r2 = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(x), 32));
+    const float r3 = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(x), 48));
+    return (r0 + r1) + (r2 + r3);
+}
+
+__device__ __forceinline__ void add_global(float *hi, float *lo, int64_t idx, float x)
+{
+    if (lo == nullptr) {
+        unsafeAtomicAdd(hi + idx, x);
+        return;
+    }
+    // exact two-sum of the value the atomic found and x
+    const float old = unsafeAtomicAdd(hi + idx, x);
+    const float s = old + x;
+    const float bp = s - old;
+    const float err = (old - (s - bp)) + (x - bp);
+    if (err != 0.0f) unsafeAtomicAdd(lo + idx, err);
+}
+
+__global__ __launch_bounds__(256) void k_accum(const float4 *__restrict__ rec, const uint32_t *__restrict__ vals,
+                                               const uint2 *__restrict__ ranges, const CamDev *__restrict__ cams,
+                                               int32_t n_views, const uint32_t *__restrict__ items, int64_t n,
+                                               const uint8_t *__restrict__ masks, AccParams P,
+                                               float *__restrict__ A_hi, float *__restrict__ A_lo,
+                                               float *__restrict__ t_final, int32_t *__restrict__ n_blend,
+                                               unsigned long long *__restrict__ status)
+{
+    __shared__ float4 s_rec[kBatch];       // u, v, a', b'
+    __shared__ float2 s_rec2[kBatch];      // c', opacity
+    __shared__ uint32_t s_g[kBatch];
+    __shared__ float s_part[kBatch][kSlots];
+    __shared__ uint32_t s_bits[8];
+    __shared__ int32_t s_slot_label[kSlots];
+    __shared__ uint32_t s_wslots[4];
+    __shared__ uint32_t s_misc[2];
+
+    const uint32_t tile = items ? items[blockIdx.x] : blockIdx.x;
+    // view of this tile: last view whose tile_base <= tile
+    int lo = 0, hi = n_views - 1;
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (cams[mid].tile_base <= tile) lo = mid; else hi = mid - 1;
+    }
+    const int view = lo;
+    const CamDev &C = cams[view];
+    const uint32_t local = tile - C.tile_base;
+    const int tx = (int)(local % (uint32_t)C.tiles_x), ty = (int)(local / (uint32_t)C.tiles_x);
+
+    const int tid = threadIdx.x, w = tid >> 6, lane = tid & 63;
+    const int bpr = P.tile_w >> 3;  // 8x8 blocks per tile row
+    const int x = tx * P.tile_w + (w % bpr) * 8 + (lane & 7);
+    const int y = ty * P.tile_h + (w / bpr) * 8 + (lane >> 3);
+    const bool inside = x < C.W && y < C.H;
+    const int64_t pix = (int64_t)C.mask_off + (int64_t)y * C.W + x;
+
+    int lab = 0;
+    bool active = inside;
+    if (inside) {
+        lab = masks[pix];
+        if (lab >= P.E) active = false;
+    }
+    if (tid < 8) s_bits[tid] = 0;
+    if (tid < 4) s_wslots[tid] = 0;
+    if (tid < 2) s_misc[tid] = 0;
+    __syncthreads();
+    if (inside && !active) {
+        atomicAdd(&s_misc[0], 1u);
+    }
+    if (active) atomicOr(&s_bits[lab >> 5], 1u << (lab & 31));
+    __syncthreads();
+    int slot = 0, nslot = 0;
+    {
+        const int word = lab >> 5;
+#pragma unroll
+        for (int i = 0; i < 8; ++i) {
+            const int pc = __popc(s_bits[i]);
+            nslot += pc;
+            if (i < word) slot += pc;
+        }
+        slot += __popc(s_bits[word] & ((1u << (lab & 31)) - 1u));
+    }
+    const bool plain = (P.reduction == FS_RED_PLAIN) || nslot > kSlots;
+    if (active && !plain) {
+        s_slot_label[slot] = lab;
+        atomicOr(&s_wslots[w], 1u << slot);
+    }
+    __syncthreads();
+    const uint32_t wslots = s_wslots[w];
+    if (tid == 0) {
+        if (s_misc[0]) {
+            atomicAdd(&status[ST_BAD_LABELS], (unsigned long long)s_misc[0]);
+            atomicOr(&status[ST_FLAGS], (unsigned long long)FS_DEV_BAD_LABEL);
+        }
+        if (nslot > kSlots && P.reduction != FS_RED_PLAIN) atomicOr(&status[ST_FLAGS], (unsigned long long)FS_DEV_MANY_LABELS);
+    }
+    for (int i = tid; i < kBatch * kSlots; i += 256) (&s_part[0][0])[i] = 0.0f;
+
+    const uint2 rg = ranges[tile];
+    const float pxc = (float)x + 0.5f, pyc = (float)y + 0.5f;
+    const float LOG2E = 1.4426950408889634f;
+    float T = 1.0f;
+    int nb = 0, ne = 0;
+    bool done = !active;
+    const int64_t rec_base = (int64_t)view * n;
+    const int E = P.E;
+
+    for (uint32_t base = rg.x; base < rg.y; base += kBatch) {
+        const uint32_t cnt = min((uint32_t)kBatch, rg.y - base);
+        __syncthreads();  // previous batch fully consumed
+        if ((uint32_t)tid < cnt) {
+            const uint32_t g = vals[base + tid];
+            const float4 r0 = rec[(rec_base + g) * 2];
+            const float4 r1 = rec[(rec_base + g) * 2 + 1];
+            s_rec[tid] = make_float4(r0.x, r0.y, -0.5f * LOG2E * r0.z, -LOG2E * r0.w);
+            s_rec2[tid] = make_float2(-0.5f * LOG2E * r1.x, r1.y);
+            s_g[tid] = g;
+        }
+        __syncthreads();
+        if (__ballot(!done) != 0ull) {
+            for (uint32_t j = 0; j < cnt; ++j) {
+                float wgt = 0.0f;
+                if (!done) {
+                    ne++;
+                    const float4 q = s_rec[j];
+                    const float2 q2 = s_rec2[j];
+                    const float dx = pxc - q.x, dy = pyc - q.y;
+                    const float pw = (q.z * dx * dx + q2.x * dy * dy) + q.w * dx * dy;
+                    if (pw >= P.cut2) {
+                        const float alpha = fminf(P.alpha_max, q2.y * __builtin_amdgcn_exp2f(pw));
+                        if (alpha >= P.alpha_min) {
+                            const float Tn = T * (1.0f - alpha);
+                            if (Tn < P.t_min) {
+                                done = true;
+                            } else {
+                                wgt = alpha * T;
+                                T = Tn;
+                                nb++;
+                            }
+                        }
+                    }
+                }
+                const unsigned long long any = __ballot(wgt != 0.0f);
+                if (any) {
+                    if (plain) {
+                        if (wgt != 0.0f) add_global(A_hi, A_lo, (int64_t)s_g[j] * E + lab, wgt);
+                    } else {
+                        uint32_t sl = wslots;
+                        while (sl) {
+                            const int sidx = __ffs(sl) - 1;
+                            sl &= sl - 1u;
+                            const float part = wave_sum(slot == sidx ? wgt : 0.0f);
+                            if (lane == 0 && part != 0.0f) atomicAdd(&s_part[j][sidx], part);
+                        }
+                    }
+                }
+                if ((j & 15u) == 15u && __ballot(!done) == 0ull) break;
+            }
+        }
+        __syncthreads();
+        if (!plain && (uint32_t)tid < cnt) {
+            const uint32_t g = s_g[tid];
+            for (int sidx = 0; sidx < nslot; ++sidx) {
+                const float vpart = s_part[tid][sidx];
+                if (vpart != 0.0f) {
+                    add_global(A_hi, A_lo, (int64_t)g * E + s_slot_label[sidx], vpart);
+                    s_part[tid][sidx] = 0.0f;
+                }
+            }
+        }
+        if (__syncthreads_or(!done) == 0) break;
+    }
+
+    if (inside) {
+        if (t_final) t_final[pix] = T;
+        if (n_blend) n_blend[pix] = nb;
+    }
+    // blend and evaluation counters: one atomic per wave
+    int tot = nb, tev = ne;
+    for (int off = 32; off > 0; off >>= 1) {
+        tot += __shfl_xor(tot, off);
+        tev += __shfl_xor(tev, off);
+    }
+    if (lane == 0 && tot) atomicAdd(&status[ST_BLENDS], (unsigned long long)tot);
+    if (lane == 0 && tev) atomicAdd(&status[ST_EVALS], (unsigned long long)tev);
+}
+
+}  // namespace
+
+hipError_t launch_accumulate(hipStream_t s, const float *rec, const uint32_t *vals, const uint32_t *ranges,
+                             const CamDev *cams_dev, int32_t n_views, const uint32_t *items, uint32_t n_items,
+                             int64_t n, const uint8_t *masks, const AccParams &p, float *A_hi, float *A_lo,
+                             float *t_final, int32_t *n_blend, unsigned long long *status)
+{
+    if (n_items == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_accum, dim3(n_items), dim3(256), 0, s, reinterpret_cast<const float4 *>(rec), vals,
+                       reinterpret_cast<const uint2 *>(ranges), cams_dev, n_views, items, n, masks, p, A_hi,
+                       p.reduction == FS_RED_LDS2SUM ? A_lo : nullptr, t_final, n_blend, status);
+    return hipGetLastError();
+}
+
+}  // namespace fs

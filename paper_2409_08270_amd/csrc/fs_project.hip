@@ -1,0 +1,196 @@
+// a1: projection of 3D Gaussians to 2D Gaussians per view (paper Sec. 3.1,
+// which inherits EWA splatting from the 3DGS renderer).
+//
+// This translation unit is compiled with -ffp-contract=off: the visibility
+// decision, the bounding radius and the tile rectangle are part of the
+// bit-exact binning contract, so every binary32 operation below is evaluated
+// exactly as written, in the order written (products rounded, sums left to
+// right, correctly rounded division and square root).
+#include "fs_internal.h"
+
+namespace fs {
+namespace {
+
+constexpr int kViewsPerThread = 8;
+
+__device__ __forceinline__ bool finite32(float x) { return __builtin_isfinite(x); }
+
+__global__ __launch_bounds__(256) void k_project(GaussPtrs G, int64_t n, const CamDev *__restrict__ cams,
+                                                 int32_t n_views, ProjParams P, float4 *__restrict__ rec,
+                                                 short4 *__restrict__ rect, int32_t *__restrict__ ntiles,
+                                                 uint8_t *__restrict__ flags,
+                                                 unsigned long long *__restrict__ status)
+{
+    const int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int v0 = blockIdx.y * kViewsPerThread;
+    const int v1 = min(n_views, v0 + kViewsPerThread);
+    const bool live = g < n;
+
+    float mx = 0.f, my = 0.f, mz = 0.f, qw = 1.f, qx = 0.f, qy = 0.f, qz = 0.f, sx = 1.f, sy = 1.f, sz = 1.f, op = 0.f;
+    if (live) {
+        mx = G.mx[g]; my = G.my[g]; mz = G.mz[g];
+        qw = G.qw[g]; qx = G.qx[g]; qy = G.qy[g]; qz = G.qz[g];
+        sx = G.sx[g]; sy = G.sy[g]; sz = G.sz[g];
+        op = G.op[g];
+    }
+    // input validity (independent of the view)
+    bool valid = finite32(mx) && finite32(my) && finite32(mz) && finite32(qw) && finite32(qx) &&
+                 finite32(qy) && finite32(qz) && finite32(sx) && finite32(sy) && finite32(sz) && finite32(op);
+    float n2 = ((qw * qw + qx * qx) + qy * qy) + qz * qz;
+    valid = valid && (n2 > 0.0f) && finite32(n2) && (sx > 0.0f) && (sy > 0.0f) && (sz > 0.0f);
+
+    // rotation of the Gaussian (unit quaternion -> matrix) times its scales
+    float L[9];
+    {
+        float nrm = sqrtf(n2);
+        float w = qw / nrm, x = qx / nrm, y = qy / nrm, z = qz / nrm;
+        float q[9];
+        q[0] = 1.0f - 2.0f * (y * y + z * z);
+        q[1] = 2.0f * (x * y - w * z);
+        q[2] = 2.0f * (x * z + w * y);
+        q[3] = 2.0f * (x * y + w * z);
+        q[4] = 1.0f - 2.0f * (x * x + z * z);
+        q[5] = 2.0f * (y * z - w * x);
+        q[6] = 2.0f * (x * z - w * y);
+        q[7] = 2.0f * (y * z + w * x);
+        q[8] = 1.0f - 2.0f * (x * x + y * y);
+        const float s[3] = {sx, sy, sz};
+#pragma unroll
+        for (int i = 0; i < 3; ++i)
+#pragma unroll
+            for (int j = 0; j < 3; ++j) L[i * 3 + j] = q[i * 3 + j] * s[j];
+    }
+
+    int n_invalid = 0, n_fp64 = 0;
+    for (int v = v0; v < v1; ++v) {
+        const CamDev &C = cams[v];
+        const float *R = C.R;
+        const int64_t idx = (int64_t)v * n + g;
+        uint8_t f = 0;
+        int nt = 0;
+        short4 rc = make_short4(0, 0, 0, 0);
+        float4 r0 = make_float4(0.f, 0.f, 0.f, 0.f), r1 = make_float4(0.f, 0.f, 0.f, 0.f);
+        if (live && !valid) {
+            f = 4;
+            n_invalid++;
+        } else if (live) {
+            float px = ((R[0] * mx + R[1] * my) + R[2] * mz) + C.t[0];
+            float py = ((R[3] * mx + R[4] * my) + R[5] * mz) + C.t[1];
+            float pz = ((R[6] * mx + R[7] * my) + R[8] * mz) + C.t[2];
+            r1.z = pz;
+            if (pz > P.znear) {
+                float Vm[9];
+#pragma unroll
+                for (int i = 0; i < 3; ++i)
+#pragma unroll
+                    for (int j = 0; j < 3; ++j)
+                        Vm[i * 3 + j] = (R[i * 3 + 0] * L[0 * 3 + j] + R[i * 3 + 1] * L[1 * 3 + j]) + R[i * 3 + 2] * L[2 * 3 + j];
+                const float Wf = (float)C.W, Hf = (float)C.H;
+                float xr = px / pz, yr = py / pz;
+                float limx = P.guard * ((0.5f * Wf) / C.fx);
+                float limy = P.guard * ((0.5f * Hf) / C.fy);
+                float txc = fminf(fmaxf(xr, -limx), limx);
+                float tyc = fminf(fmaxf(yr, -limy), limy);
+                float j00 = C.fx / pz, j02 = -((C.fx * txc) / pz);
+                float j11 = C.fy / pz, j12 = -((C.fy * tyc) / pz);
+                float m0[3], m1[3];
+#pragma unroll
+                for (int j = 0; j < 3; ++j) {
+                    m0[j] = j00 * Vm[0 * 3 + j] + j02 * Vm[2 * 3 + j];
+                    m1[j] = j11 * Vm[1 * 3 + j] + j12 * Vm[2 * 3 + j];
+                }
+                const float lp = P.lowpass;
+                float a = ((m0[0] * m0[0] + m0[1] * m0[1]) + m0[2] * m0[2]) + lp;
+                float b = (m0[0] * m1[0] + m0[1] * m1[1]) + m0[2] * m1[2];
+                float c = ((m1[0] * m1[0] + m1[1] * m1[1]) + m1[2] * m1[2]) + lp;
+                float u = C.fx * xr + C.cx;
+                float vv = C.fy * yr + C.cy;
+                float mid = 0.5f * (a + c);
+                float hd = 0.5f * (a - c);
+                float lam = mid + sqrtf(hd * hd + b * b);
+                float r = ceilf(P.sigma_k * sqrtf(lam));
+                if (finite32(u) && finite32(vv) && finite32(r) && finite32(a) && finite32(b) && finite32(c)) {
+                    float det = a * c - b * b;
+                    bool deg = !(det > 0.0f) || (a * c >= P.fp64_cond * det);
+                    f = deg ? 3 : 1;
+                    // conic (inverse 2D covariance)
+                    float ca, cb, cc;
+                    if (deg && P.fp64_conic) {
+                        n_fp64++;
+                        const double d00 = (double)m0[0], d01 = (double)m0[1], d02 = (double)m0[2];
+                        const double d10 = (double)m1[0], d11 = (double)m1[1], d12 = (double)m1[2];
+                        const double s00 = d00 * d00 + d01 * d01 + d02 * d02;
+                        const double s01 = d00 * d10 + d01 * d11 + d02 * d12;
+                        const double s11 = d10 * d10 + d11 * d11 + d12 * d12;
+                        const double mn01 = d00 * d11 - d01 * d10;
+                        const double mn02 = d00 * d12 - d02 * d10;
+                        const double mn12 = d01 * d12 - d02 * d11;
+                        const double lpd = (double)lp;
+                        // Cauchy-Binet: det(M M^T + lp I), every term non-negative
+                        const double det64 = mn01 * mn01 + mn02 * mn02 + mn12 * mn12 + lpd * (s00 + s11) + lpd * lpd;
+                        ca = (float)((s11 + lpd) / det64);
+                        cb = (float)(-s01 / det64);
+                        cc = (float)((s00 + lpd) / det64);
+                    } else {
+                        float dd = det > 0.0f ? det : 1e-30f;
+                        ca = c / dd;
+                        cb = -b / dd;
+                        cc = a / dd;
+                    }
+                    r0 = make_float4(u, vv, ca, cb);
+                    r1.x = cc;
+                    r1.y = op;
+                    float fk0 = ceilf((u - r) - 0.5f), fk1 = floorf((u + r) - 0.5f);
+                    float fj0 = ceilf((vv - r) - 0.5f), fj1 = floorf((vv + r) - 0.5f);
+                    if (!(fk1 < 0.0f || fk0 > (float)(C.W - 1) || fj1 < 0.0f || fj0 > (float)(C.H - 1) ||
+                          fk0 > fk1 || fj0 > fj1)) {
+                        int kmin = (int)fmaxf(fk0, 0.0f), kmax = (int)fminf(fk1, (float)(C.W - 1));
+                        int jmin = (int)fmaxf(fj0, 0.0f), jmax = (int)fminf(fj1, (float)(C.H - 1));
+                        int x0 = kmin / P.tile_w, y0 = jmin / P.tile_h, x1 = kmax / P.tile_w, y1 = jmax / P.tile_h;
+                        rc = make_short4((short)x0, (short)y0, (short)x1, (short)y1);
+                        nt = (x1 - x0 + 1) * (y1 - y0 + 1);
+                    }
+                }
+            }
+        }
+        if (live) {
+            rec[idx * 2 + 0] = r0;
+            rec[idx * 2 + 1] = r1;
+            rect[idx] = rc;
+            ntiles[idx] = nt;
+            flags[idx] = f;
+        }
+    }
+    // one atomic per wave for the counters
+    unsigned long long bi = __ballot(n_invalid != 0);
+    unsigned long long bf = __ballot(n_fp64 != 0);
+    if (bi | bf) {
+        int tot_i = n_invalid, tot_f = n_fp64;
+        for (int off = 32; off > 0; off >>= 1) {
+            tot_i += __shfl_xor(tot_i, off);
+            tot_f += __shfl_xor(tot_f, off);
+        }
+        if ((threadIdx.x & 63) == 0) {
+            if (tot_i) {
+                atomicAdd(&status[ST_INVALID], (unsigned long long)tot_i);
+                atomicOr(&status[ST_FLAGS], (unsigned long long)FS_DEV_INVALID_GAUSS);
+            }
+            if (tot_f) atomicAdd(&status[ST_FP64], (unsigned long long)tot_f);
+        }
+    }
+}
+
+}  // namespace
+
+hipError_t launch_project(hipStream_t s, const GaussPtrs &g, int64_t n, const CamDev *cams_dev,
+                          int32_t n_views, const ProjParams &p, float *rec, int16_t *rect,
+                          int32_t *ntiles, uint8_t *flags, unsigned long long *status)
+{
+    if (n == 0 || n_views == 0) return hipSuccess;
+    dim3 grid((unsigned)((n + 255) / 256), (unsigned)((n_views + kViewsPerThread - 1) / kViewsPerThread));
+    hipLaunchKernelGGL(k_project, grid, dim3(256), 0, s, g, n, cams_dev, n_views, p,
+                       reinterpret_cast<float4 *>(rec), reinterpret_cast<short4 *>(rect), ntiles, flags, status);
+    return hipGetLastError();
+}
+
+}  // namespace fs

@@ -1,0 +1,401 @@
+// a2-a5: pair counting, scan, emission, stable sort and tile ranges (paper
+// Sec. 3.1: the pixels of a 16x16 tile share one subset of Gaussians, which
+// are blended in depth order).
+//
+// Order contract: within a tile, entries are ordered by depth, then by
+// Gaussian id. It is reached in two stable sorts: the visible Gaussians of
+// every view are sorted by the float bits of their depth (positive floats
+// order like their bit patterns; ties keep id order because the input is in
+// id order and the sort is stable), their tile pairs are emitted in that
+// order, and the pairs are then sorted stably by tile id. Sorting N depth
+// keys plus P 16-bit tile keys moves far fewer bytes than sorting P
+// (tile, depth) 48-bit keys.
+#include "fs_internal.h"
+
+namespace fs {
+namespace {
+
+constexpr int kThreads = 256;
+constexpr int kItems = 16;
+constexpr int kTile = kThreads * kItems;  // 4096 items per block tile
+constexpr int kWaves = kThreads / 64;
+
+__global__ void k_fill_u32(uint32_t *p, uint32_t v, int64_t count)
+{
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (; i < count; i += stride) p[i] = v;
+}
+
+// ---------------------------------------------------------------- scan ----
+__device__ __forceinline__ uint32_t wave_incl_scan_u32(uint32_t x)
+{
+    const int lane = threadIdx.x & 63;
+#pragma unroll
+    for (int off = 1; off < 64; off <<= 1) {
+        uint32_t y = __shfl_up(x, off);
+        if (lane >= off) x += y;
+    }
+    return x;
+}
+
+// exclusive scan of the block's values (one per thread), returns block total
+__device__ __forceinline__ uint32_t block_excl_scan(uint32_t x, uint32_t *s_wsum, uint32_t &total)
+{
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    uint32_t inc = wave_incl_scan_u32(x);
+    if (lane == 63) s_wsum[w] = inc;
+    __syncthreads();
+    uint32_t wbase = 0, tot = 0;
+    for (int i = 0; i < kWaves; ++i) {
+        uint32_t s = s_wsum[i];
+        if (i < w) wbase += s;
+        tot += s;
+    }
+    __syncthreads();
+    total = tot;
+    return wbase + inc - x;
+}
+
+__global__ __launch_bounds__(kThreads) void k_scan_reduce(const uint32_t *__restrict__ in, int64_t n,
+                                                          uint32_t *__restrict__ sums)
+{
+    __shared__ uint32_t s_wsum[kWaves];
+    const int64_t base = (int64_t)blockIdx.x * kTile;
+    uint32_t acc = 0;
+#pragma unroll
+    for (int k = 0; k < kItems; ++k) {
+        int64_t i = base + k * kThreads + threadIdx.x;
+        if (i < n) acc += in[i];
+    }
+    uint32_t tot;
+    block_excl_scan(acc, s_wsum, tot);
+    if (threadIdx.x == 0) sums[blockIdx.x] = tot;
+}
+
+__global__ __launch_bounds__(kThreads) void k_scan_down(const uint32_t *__restrict__ in, uint32_t *__restrict__ out,
+                                                        int64_t n, const uint32_t *__restrict__ offs,
+                                                        uint32_t *__restrict__ total_out)
+{
+    __shared__ uint32_t s_wsum[kWaves];
+    const int64_t base = (int64_t)blockIdx.x * kTile + (int64_t)threadIdx.x * kItems;
+    uint32_t v[kItems];
+    uint32_t acc = 0;
+#pragma unroll
+    for (int k = 0; k < kItems; ++k) {
+        int64_t i = base + k;
+        v[k] = i < n ? in[i] : 0u;
+        acc += v[k];
+    }
+    uint32_t tot;
+    uint32_t ex = block_excl_scan(acc, s_wsum, tot) + (offs ? offs[blockIdx.x] : 0u);
+#pragma unroll
+    for (int k = 0; k < kItems; ++k) {
+        int64_t i = base + k;
+        if (i < n) out[i] = ex;
+        ex += v[k];
+    }
+    if (total_out && blockIdx.x == gridDim.x - 1 && threadIdx.x == kThreads - 1) *total_out = ex;
+}
+
+// ------------------------------------------------------------ radix sort --
+__global__ __launch_bounds__(kThreads) void k_radix_hist(const uint32_t *__restrict__ keys, int64_t seg_len,
+                                                         int32_t blocks_per_seg, int32_t shift,
+                                                         uint32_t *__restrict__ hist)
+{
+    __shared__ uint32_t s_h[kWaves][256];
+    const int seg = blockIdx.x / blocks_per_seg, b = blockIdx.x % blocks_per_seg;
+    const int w = threadIdx.x >> 6;
+    for (int i = threadIdx.x; i < kWaves * 256; i += kThreads) (&s_h[0][0])[i] = 0;
+    __syncthreads();
+    const int64_t t0 = (int64_t)b * kTile;
+    const uint32_t *k = keys + (int64_t)seg * seg_len;
+#pragma unroll 4
+    for (int it = 0; it < kItems; ++it) {
+        int64_t i = t0 + it * kThreads + threadIdx.x;
+        if (i < seg_len) atomicAdd(&s_h[w][(k[i] >> shift) & 255u], 1u);
+    }
+    __syncthreads();
+    const int d = threadIdx.x;
+    uint32_t c = 0;
+#pragma unroll
+    for (int i = 0; i < kWaves; ++i) c += s_h[i][d];
+    hist[((int64_t)seg * 256 + d) * blocks_per_seg + b] = c;
+}
+
+// Stable scatter: wave w ranks the contiguous items [w*1024, (w+1)*1024) of
+// the block tile in 16 rounds of 64; equal digits are matched with 8 ballots.
+__global__ __launch_bounds__(kThreads) void k_radix_scatter(const uint32_t *__restrict__ kin, const uint32_t *__restrict__ vin,
+                                                            uint32_t *__restrict__ kout, uint32_t *__restrict__ vout,
+                                                            int64_t seg_len, int32_t blocks_per_seg, int32_t shift,
+                                                            const uint32_t *__restrict__ offs)
+{
+    __shared__ uint32_t s_cnt[kWaves][256];
+    __shared__ uint32_t s_dstart[256];
+    __shared__ uint32_t s_gofs[256];
+    __shared__ uint32_t s_wsum[kWaves];
+    __shared__ uint32_t s_k[kTile];
+    __shared__ uint32_t s_v[kTile];
+
+    const int seg = blockIdx.x / blocks_per_seg, b = blockIdx.x % blocks_per_seg;
+    const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    for (int i = threadIdx.x; i < kWaves * 256; i += kThreads) (&s_cnt[0][0])[i] = 0;
+    s_gofs[threadIdx.x] = offs[((int64_t)seg * 256 + threadIdx.x) * blocks_per_seg + b];
+    __syncthreads();
+
+    const int64_t t0 = (int64_t)b * kTile;
+    const int64_t nvalid64 = seg_len - t0;
+    const int nvalid = nvalid64 < kTile ? (int)nvalid64 : kTile;
+    const uint32_t *kbase = kin + (int64_t)seg * seg_len + t0;
+    const uint32_t *vbase = vin + (int64_t)seg * seg_len + t0;
+    const unsigned long long lt = (1ull << lane) - 1ull;
+
+    uint32_t key[kItems], val[kItems], rnk[kItems];
+#pragma unroll
+    for (int r = 0; r < kItems; ++r) {
+        const int li = w * (kItems * 64) + r * 64 + lane;
+        const bool ok = li < nvalid;
+        key[r] = ok ? kbase[li] : 0xFFFFFFFFu;
+        val[r] = ok ? vbase[li] : 0u;
+    }
+#pragma unroll
+    for (int r = 0; r < kItems; ++r) {
+        const uint32_t d = (key[r] >> shift) & 255u;
+        unsigned long long peers = ~0ull;
+#pragma unroll
+        for (int bit = 0; bit < 8; ++bit) {
+            const bool on = (d >> bit) & 1u;
+            const unsigned long long bb = __ballot(on);
+            peers &= on ? bb : ~bb;
+        }
+        const uint32_t before = s_cnt[w][d];
+        rnk[r] = before + (uint32_t)__popcll(peers & lt);
+        __builtin_amdgcn_wave_barrier();
+        if ((peers & lt) == 0ull) s_cnt[w][d] = before + (uint32_t)__popcll(peers);
+        __builtin_amdgcn_wave_barrier();
+    }
+    __syncthreads();
+    // per-digit totals, wave prefixes and the digit starts inside the tile
+    {
+        const int d = threadIdx.x;
+        uint32_t run = 0;
+#pragma unroll
+        for (int i = 0; i < kWaves; ++i) {
+            const uint32_t c = s_cnt[i][d];
+            s_cnt[i][d] = run;
+            run += c;
+        }
+        uint32_t tot;
+        const uint32_t ex = block_excl_scan(run, s_wsum, tot);
+        s_dstart[d] = ex;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int r = 0; r < kItems; ++r) {
+        const uint32_t d = (key[r] >> shift) & 255u;
+        const uint32_t pos = s_dstart[d] + s_cnt[w][d] + rnk[r];
+        s_k[pos] = key[r];
+        s_v[pos] = val[r];
+    }
+    __syncthreads();
+    // s_gofs comes from one exclusive scan over the [segment][digit][block]
+    // counts of all segments, so it is already a position in the whole array
+    for (int i = threadIdx.x; i < nvalid; i += kThreads) {
+        const uint32_t k = s_k[i];
+        const uint32_t d = (k >> shift) & 255u;
+        const int64_t p = (int64_t)s_gofs[d] + (i - (int64_t)s_dstart[d]);
+        kout[p] = k;
+        vout[p] = s_v[i];
+    }
+}
+
+// ------------------------------------------------------------- binning ---
+__global__ void k_depth_keys(const float4 *__restrict__ rec, const int32_t *__restrict__ ntiles,
+                             const uint8_t *__restrict__ flags, int64_t total, int64_t n,
+                             uint32_t *__restrict__ keys, uint32_t *__restrict__ vals)
+{
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= total) return;
+    const bool emits = (flags[i] & 1u) && ntiles[i] > 0;
+    keys[i] = emits ? __float_as_uint(rec[2 * i + 1].z) : 0xFFFFFFFFu;
+    vals[i] = (uint32_t)(i % n);
+}
+
+__global__ void k_gather_counts(const uint32_t *__restrict__ skeys, const uint32_t *__restrict__ svals,
+                                const int32_t *__restrict__ ntiles, int64_t total, int64_t n,
+                                uint32_t *__restrict__ counts)
+{
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= total) return;
+    const int64_t v = i / n;
+    counts[i] = skeys[i] == 0xFFFFFFFFu ? 0u : (uint32_t)ntiles[v * n + svals[i]];
+}
+
+__global__ void k_emit(const uint32_t *__restrict__ skeys, const uint32_t *__restrict__ svals,
+                       const uint32_t *__restrict__ offsets, const short4 *__restrict__ rect,
+                       const CamDev *__restrict__ cams, int64_t total, int64_t n, uint32_t capacity,
+                       uint32_t *__restrict__ tiles_out, uint32_t *__restrict__ vals_out,
+                       unsigned long long *__restrict__ status)
+{
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    uint32_t dropped = 0;
+    if (i < total && skeys[i] != 0xFFFFFFFFu) {
+        const int64_t v = i / n;
+        const uint32_t g = svals[i];
+        const short4 rc = rect[v * n + g];
+        const CamDev &C = cams[v];
+        uint32_t p = offsets[i];
+        for (int ty = rc.y; ty <= rc.w; ++ty) {
+            const uint32_t rowbase = C.tile_base + (uint32_t)ty * (uint32_t)C.tiles_x;
+            for (int tx = rc.x; tx <= rc.z; ++tx, ++p) {
+                if (p < capacity) {
+                    tiles_out[p] = rowbase + (uint32_t)tx;
+                    vals_out[p] = g;
+                } else {
+                    dropped++;
+                }
+            }
+        }
+    }
+    if (__ballot(dropped != 0)) {
+        if (dropped) {
+            atomicAdd(&status[ST_DROPPED], (unsigned long long)dropped);
+            atomicOr(&status[ST_FLAGS], (unsigned long long)FS_DEV_PAIR_OVERFLOW);
+        }
+    }
+}
+
+__global__ void k_ranges(const uint32_t *__restrict__ tiles, const uint32_t *__restrict__ n_pairs_dev,
+                         uint32_t capacity, int64_t max_pairs, uint2 *__restrict__ ranges)
+{
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    uint32_t np = *n_pairs_dev;
+    if (np > capacity) np = capacity;
+    if (i >= (int64_t)np || i >= max_pairs) return;
+    const uint32_t t = tiles[i];
+    if (i == 0 || tiles[i - 1] != t) ranges[t].x = (uint32_t)i;
+    if (i == (int64_t)np - 1 || tiles[i + 1] != t) ranges[t].y = (uint32_t)(i + 1);
+}
+
+inline unsigned grid_for(int64_t n, int threads) { return (unsigned)((n + threads - 1) / threads); }
+
+}  // namespace
+
+hipError_t launch_fill_u32(hipStream_t s, uint32_t *p, uint32_t v, int64_t count)
+{
+    if (count <= 0) return hipSuccess;
+    int64_t blocks = (count + 255) / 256;
+    if (blocks > 65536) blocks = 65536;
+    hipLaunchKernelGGL(k_fill_u32, dim3((unsigned)blocks), dim3(256), 0, s, p, v, count);
+    return hipGetLastError();
+}
+
+// ---- scan ----
+static int64_t scan_levels_bytes(int64_t n)
+{
+    int64_t bytes = 0;
+    while (n > kTile) {
+        n = (n + kTile - 1) / kTile;
+        bytes += (n + 64) * 4;
+    }
+    return bytes + 256;
+}
+
+size_t scan_ws_bytes(int64_t n) { return (size_t)scan_levels_bytes(n); }
+
+hipError_t scan_exclusive(hipStream_t s, const uint32_t *in, uint32_t *out, int64_t n, uint32_t *total_out, void *ws)
+{
+    if (n <= 0) {
+        if (total_out) return launch_fill_u32(s, total_out, 0u, 1);
+        return hipSuccess;
+    }
+    const int64_t blocks = (n + kTile - 1) / kTile;
+    if (blocks == 1) {
+        hipLaunchKernelGGL(k_scan_down, dim3(1), dim3(kThreads), 0, s, in, out, n, (const uint32_t *)nullptr, total_out);
+        return hipGetLastError();
+    }
+    uint32_t *sums = (uint32_t *)ws;
+    uint32_t *rest = sums + ((blocks + 64) & ~int64_t(63));
+    hipLaunchKernelGGL(k_scan_reduce, dim3((unsigned)blocks), dim3(kThreads), 0, s, in, n, sums);
+    hipError_t e = scan_exclusive(s, sums, sums, blocks, nullptr, rest);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_scan_down, dim3((unsigned)blocks), dim3(kThreads), 0, s, in, out, n, (const uint32_t *)sums, total_out);
+    return hipGetLastError();
+}
+
+// ---- radix sort ----
+size_t radix_ws_bytes(int64_t seg_len, int32_t segs)
+{
+    const int64_t bps = (seg_len + kTile - 1) / kTile;
+    const int64_t hist = (int64_t)segs * 256 * bps;
+    return (size_t)(2 * hist * 4 + scan_levels_bytes(hist) + 512);
+}
+
+hipError_t radix_sort(hipStream_t s, uint32_t *keys, uint32_t *vals, uint32_t *keys_alt, uint32_t *vals_alt,
+                      int64_t seg_len, int32_t segs, int32_t bits, void *ws)
+{
+    if (seg_len <= 0 || segs <= 0) return hipSuccess;
+    const int32_t bps = (int32_t)((seg_len + kTile - 1) / kTile);
+    const int64_t hist_n = (int64_t)segs * 256 * bps;
+    uint32_t *hist = (uint32_t *)ws;
+    uint32_t *offs = hist + hist_n;
+    void *scan_ws = offs + hist_n;
+    uint32_t *ki = keys, *vi = vals, *ko = keys_alt, *vo = vals_alt;
+    const unsigned grid = (unsigned)(segs * bps);
+    for (int shift = 0; shift < bits; shift += 8) {
+        hipLaunchKernelGGL(k_radix_hist, dim3(grid), dim3(kThreads), 0, s, ki, seg_len, bps, shift, hist);
+        hipError_t e = scan_exclusive(s, hist, offs, hist_n, nullptr, scan_ws);
+        if (e != hipSuccess) return e;
+        hipLaunchKernelGGL(k_radix_scatter, dim3(grid), dim3(kThreads), 0, s, ki, vi, ko, vo, seg_len, bps, shift,
+                           (const uint32_t *)offs);
+        e = hipGetLastError();
+        if (e != hipSuccess) return e;
+        uint32_t *tk = ki, *tv = vi;
+        ki = ko; vi = vo; ko = tk; vo = tv;
+    }
+    return hipSuccess;
+}
+
+hipError_t launch_depth_keys(hipStream_t s, const float *rec, const int32_t *ntiles, const uint8_t *flags,
+                             int64_t n, int32_t n_views, uint32_t *keys, uint32_t *vals)
+{
+    const int64_t total = n * n_views;
+    if (total == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_depth_keys, dim3(grid_for(total, 256)), dim3(256), 0, s,
+                       reinterpret_cast<const float4 *>(rec), ntiles, flags, total, n, keys, vals);
+    return hipGetLastError();
+}
+
+hipError_t launch_gather_counts(hipStream_t s, const uint32_t *sorted_keys, const uint32_t *sorted_vals,
+                                const int32_t *ntiles, int64_t n, int32_t n_views, uint32_t *counts)
+{
+    const int64_t total = n * n_views;
+    if (total == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_gather_counts, dim3(grid_for(total, 256)), dim3(256), 0, s, sorted_keys, sorted_vals,
+                       ntiles, total, n, counts);
+    return hipGetLastError();
+}
+
+hipError_t launch_emit(hipStream_t s, const uint32_t *sorted_keys, const uint32_t *sorted_vals,
+                       const uint32_t *offsets, const int16_t *rect, const CamDev *cams_dev, int64_t n,
+                       int32_t n_views, uint32_t capacity, uint32_t *tiles_out, uint32_t *vals_out,
+                       unsigned long long *status)
+{
+    const int64_t total = n * n_views;
+    if (total == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_emit, dim3(grid_for(total, 256)), dim3(256), 0, s, sorted_keys, sorted_vals, offsets,
+                       reinterpret_cast<const short4 *>(rect), cams_dev, total, n, capacity, tiles_out, vals_out,
+                       status);
+    return hipGetLastError();
+}
+
+hipError_t launch_ranges(hipStream_t s, const uint32_t *tiles, const uint32_t *n_pairs_dev, uint32_t capacity,
+                         int64_t n_pairs_max, uint32_t *ranges)
+{
+    if (n_pairs_max <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_ranges, dim3(grid_for(n_pairs_max, 256)), dim3(256), 0, s, tiles, n_pairs_dev, capacity,
+                       n_pairs_max, reinterpret_cast<uint2 *>(ranges));
+    return hipGetLastError();
+}
+
+}  // namespace fs

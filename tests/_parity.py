@@ -1,0 +1,78 @@
+"""Comparison rules between the GPU library and the CPU oracle (tests only).
+
+A (per-Gaussian, per-class contribution sums): for every row g,
+    |A_gpu[g] - A64[g]|_1 <= REL * |A64[g]|_1 + slack[g] + ABS
+where slack[g] is the oracle's budget for float32-vs-float64 threshold
+decisions (alpha_min, t_min, support) that lie within its band; the
+aggregate |dA|_1 / |A64|_1 must also stay within REL. REL = 1e-4 is the
+acceptance tolerance for A.
+
+Labels: S_gpu == S64 wherever the oracle's margin >= 1e-4 (and, for rows
+whose slack is significant, wherever the margin exceeds the normalised
+slack); the excluded entries are counted and reported.
+"""
+import sys
+
+import numpy as np
+
+REL = 1e-4
+ABS = 1e-9
+MARGIN = 1e-4
+
+
+def log(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+def compare_A(A_gpu: np.ndarray, A64: np.ndarray, slack: np.ndarray, rel: float = REL):
+    A_gpu = np.asarray(A_gpu, np.float64)
+    d = np.abs(A_gpu - A64).sum(axis=1)
+    s = np.abs(A64).sum(axis=1)
+    tol = rel * s + slack + ABS
+    bad = d > tol
+    seen = s > 0
+    r = np.zeros_like(d)
+    r[seen] = d[seen] / s[seen]
+    clean = seen & (slack <= 1e-6 * s)
+    stats = dict(rows=int(A64.shape[0]), seen=int(seen.sum()), rows_failing=int(bad.sum()),
+                 rows_with_slack=int((slack > 0).sum()),
+                 rows_over_rel_without_slack=int((d > rel * s + ABS).sum()),
+                 max_rel=float(r.max()) if r.size else 0.0,
+                 p99_rel=float(np.percentile(r[seen], 99)) if seen.any() else 0.0,
+                 median_rel=float(np.median(r[seen])) if seen.any() else 0.0,
+                 max_rel_clean=float(r[clean].max()) if clean.any() else 0.0,
+                 aggregate_rel=float(d.sum() / max(s.sum(), 1e-300)))
+    return stats, bad
+
+
+def assert_A(A_gpu, A64, slack, rel=REL, what=""):
+    st, bad = compare_A(A_gpu, A64, slack, rel)
+    log(f"[A parity{(' ' + what) if what else ''}] {st}")
+    if bad.any():
+        idx = np.nonzero(bad)[0][:10]
+        for g in idx:
+            log(f"  row {g}: gpu {A_gpu[g]} oracle {A64[g]} slack {slack[g]}")
+    assert st["rows_failing"] == 0, st
+    assert st["aggregate_rel"] <= rel, st
+    return st
+
+
+def compare_labels(S_gpu, S64, margin64, A64=None, slack=None):
+    S_gpu = np.asarray(S_gpu)
+    excl = margin64 < MARGIN
+    if A64 is not None and slack is not None:
+        s = np.abs(A64).sum(axis=1)
+        relslack = np.where(s > 0, slack / np.maximum(s, 1e-300), 0.0)
+        excl = excl | (margin64 < 4.0 * relslack[None, :])
+    mism = S_gpu != S64
+    st = dict(entries=int(S64.size), excluded_low_margin=int(excl.sum()),
+              mismatches=int((mism & ~excl).sum()), mismatches_in_excluded=int((mism & excl).sum()))
+    return st
+
+
+def assert_labels(S_gpu, S64, margin64, A64=None, slack=None, what=""):
+    st = compare_labels(S_gpu, S64, margin64, A64, slack)
+    log(f"[label parity{(' ' + what) if what else ''}] {st}")
+    assert st["mismatches"] == 0, st
+    return st
