@@ -33,11 +33,31 @@ def parse():
     ap.add_argument("--config", default="C2")
     ap.add_argument("--cpu-views", type=int, default=2, help="views of the CPU oracle sample (0: skip)")
     ap.add_argument("--no-plain", action="store_true")
+    ap.add_argument("--copy-probe", type=int, default=0, metavar="MIB",
+                    help="only run a device-to-device copy of this many MiB (HBM counter calibration)")
     return ap.parse_args()
+
+
+def copy_probe(mib: int):
+    """A plain copy of known size: its FETCH_SIZE / WRITE_SIZE readings give the
+    factor between those counters and real HBM bytes."""
+    import torch
+    torch.cuda.set_device(0)
+    n = mib * (1 << 20) // 4
+    src = torch.ones(n, dtype=torch.float32, device="cuda")
+    dst = torch.empty_like(src)
+    torch.cuda.synchronize()
+    for _ in range(3):
+        dst.copy_(src)
+    torch.cuda.synchronize()
+    print(json.dumps({"copy_probe_bytes_each_way": n * 4, "launches": 3}))
 
 
 def main():
     args = parse()
+    if args.copy_probe:
+        copy_probe(args.copy_probe)
+        return
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
         print(json.dumps({"error": "this build runs on exactly one GPU; multi-GPU runs are not supported "
                                    "(views would shard across GPUs with one reduce-scatter of A)"}))
@@ -101,7 +121,9 @@ def main():
         print(f"[bench] plain: {dt_p * 1e3:.2f} ms/step", file=sys.stderr, flush=True)
 
     # ---- roofline of the compositing kernel (one launch over all views) -----
-    ops = 16.0 * evals + 5.0 * blends
+    # algorithmic fp32 ops: 15 per (pixel, Gaussian) pair inside the support (offset, quadratic form,
+    # support test, exp, opacity, clamp, alpha test) + 5 per blend (1-alpha, T update, stop test, w, add)
+    ops = 15.0 * evals + 5.0 * blends
     acc_s = float(np.mean(acc_ms)) * 1e-3
     achieved = ops / acc_s
     roof = {"bound": "alu", "achieved": achieved / 1e12, "peak": PEAK_ALU_OPS / 1e12, "unit": "TFLOP/s",

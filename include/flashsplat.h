@@ -109,7 +109,8 @@ typedef struct {
  * element (v, g) lives at index v*n + g. */
 typedef struct {
     float *rec;       /* float32 [n_views][n][8]: u, v (pixel), conic_xx, conic_xy, conic_yy
-                         (inverse 2D covariance), opacity, depth (camera z), 0 */
+                         (inverse 2D covariance), opacity, depth (camera z), and 1 if the
+                         conic was inverted in float64 else 0 */
     int16_t *rect;    /* int16 [n_views][n][4]: tile rectangle x0, y0, x1, y1, inclusive */
     int32_t *ntiles;  /* int32 [n_views][n]: tiles in the rectangle, 0 if not visible */
     uint8_t *flags;   /* uint8 [n_views][n]: bit0 visible, bit1 float64 conic, bit2 invalid input */
@@ -141,7 +142,8 @@ typedef struct {
     int64_t fp64_splats;     /* (Gaussian, view) pairs inverted in float64 */
     int64_t pairs_dropped;   /* tile pairs beyond capacity */
     int64_t blends;          /* (pixel, Gaussian) weights added into A */
-    int64_t evaluated;       /* (pixel, Gaussian) pairs evaluated before each pixel's compositing ended */
+    int64_t evaluated;       /* (pixel, Gaussian) pairs with the pixel inside the Gaussian's support,
+                                evaluated before the pixel's compositing ended */
     int64_t unseen;          /* fs_assign: rows of A that are all zero */
     int64_t multi_member;    /* fs_assign: Gaussians assigned to more than one object */
     int64_t low_margin;      /* fs_assign: (object, Gaussian) entries with margin < 1e-4 */

@@ -66,7 +66,7 @@ def lib():
         I32 = ctypes.c_int32
         L.or_project32.argtypes = [I64, P, P, P, P, P, P, P, P, P]
         L.or_project32.restype = None
-        L.or_bin.argtypes = [I64, P, P, P, P, I32, I32, P, P, P]
+        L.or_bin.argtypes = [I64, P, P, P, P, P, P, P, P, I32, I32, P, P, P]
         L.or_bin.restype = I64
         L.or_project64.argtypes = [I64, P, P, P, P]
         L.or_project64.restype = None
@@ -127,8 +127,9 @@ def bin_view(scene, v: int, prm: np.ndarray, proj: Optional[dict] = None) -> Dic
     gid = np.zeros(max(total, 1), np.uint32)
     ranges = np.zeros((tx * ty, 2), np.uint32)
     n = pr["flags"].shape[0]
-    got = lib().or_bin(n, _p(pr["flags"]), _p(pr["rect"]), _p(pr["ntiles"]), _p(pr["depth"]),
-                       tx, ty, _p(tile), _p(gid), _p(ranges))
+    cam = np.ascontiguousarray(scene.camera_rows()[v])
+    got = lib().or_bin(n, _p(pr["flags"]), _p(pr["rect"]), _p(pr["ntiles"]), _p(pr["depth"]), _p(pr["cov"]),
+                       _p(pr["mean2d"]), _p(cam), _p(prm), tx, ty, _p(tile), _p(gid), _p(ranges))
     assert got == total
     return dict(tile=tile[:total], g=gid[:total], ranges=ranges, proj=pr, tiles_x=tx, tiles_y=ty)
 

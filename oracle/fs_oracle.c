@@ -40,13 +40,81 @@ enum { P_TW, P_TH, P_K, P_LP, P_ZN, P_GUARD, P_AMIN, P_AMAX, P_TMIN, P_COND, P_E
 /* camera row, float32 [18]: R (row-major 9), t (3), fx, fy, cx, cy, W, H */
 
 /* ------------------------------------------------------------------------
+ * Which tiles of a Gaussian's rectangle are listed (strict binary32, fixed
+ * order). A tile can hold a pixel centre inside the support ellipse
+ * q(d) = A dx^2 + 2B dx dy + C dy^2 <= k^2 (A, B, C = the float32 conic
+ * c/det, -b/det, a/det) only if the minimum of q over the bounding box of its
+ * pixel centres is <= k^2; that minimum is zero when the mean is inside the
+ * box and otherwise the least of the four edge minima, each at the clamped
+ * vertex of a 1D parabola (vertex offsets use the reciprocals 1/A and 1/C,
+ * rounded once). A tile passes when the minimum is <= k^2 (1 + 2^-9), a
+ * margin far above the rounding of a float32 conic that passed the
+ * conditioning predicate. In each tile row the listed tiles are the span from
+ * the first to the last passing tile (the ellipse meets a row in a convex set,
+ * so the passing tiles are contiguous up to rounding). Splats that fail the
+ * predicate (flag bit 1) list every tile of their rectangle.
+ * ---------------------------------------------------------------------- */
+typedef struct { float u, v, A, B, C, iA, iC; int full; } conic32_t;
+
+static conic32_t conic32(float u, float v, float a, float b, float c, uint8_t f)
+{
+    conic32_t q;
+    q.u = u; q.v = v;
+    q.full = (f & 2) != 0;
+    float det = a * c - b * b;
+    q.A = c / det; q.B = -b / det; q.C = a / det;
+    q.iA = 1.0f / q.A; q.iC = 1.0f / q.C;
+    return q;
+}
+
+static int tile_hit32(const conic32_t *q, int tx, int ty, int tw, int th, int W, int H, float k)
+{
+    int x1 = tx * tw + tw - 1, y1 = ty * th + th - 1;
+    if (x1 > W - 1) x1 = W - 1;
+    if (y1 > H - 1) y1 = H - 1;
+    float xl = ((float)(tx * tw) + 0.5f) - q->u, xh = ((float)x1 + 0.5f) - q->u;
+    float yl = ((float)(ty * th) + 0.5f) - q->v, yh = ((float)y1 + 0.5f) - q->v;
+    if (xl <= 0.0f && xh >= 0.0f && yl <= 0.0f && yh >= 0.0f) return 1;
+    float lim = (k * k) * 1.001953125f;
+    float ex[2] = {xl, xh}, ey[2] = {yl, yh};
+    for (int i = 0; i < 2; ++i) {
+        /* edge dx = ex[i], dy in [yl, yh] */
+        float x = ex[i];
+        float y = fminf(fmaxf(-(q->B * x) * q->iC, yl), yh);
+        float e = (q->A * x) * x + (2.0f * (q->B * x)) * y + (q->C * y) * y;
+        if (e <= lim) return 1;
+        /* edge dy = ey[i], dx in [xl, xh] */
+        float y2 = ey[i];
+        float x2 = fminf(fmaxf(-(q->B * y2) * q->iA, xl), xh);
+        float e2 = (q->A * x2) * x2 + (2.0f * (q->B * x2)) * y2 + (q->C * y2) * y2;
+        if (e2 <= lim) return 1;
+    }
+    return 0;
+}
+
+/* listed span [*l, *r] of tile row ty within columns [x0, x1]; returns 0 if empty */
+static int row_span32(const conic32_t *q, int ty, int x0, int x1, int tw, int th, int W, int H, float k,
+                      int *l, int *r)
+{
+    if (q->full) { *l = x0; *r = x1; return 1; }
+    int a = x0;
+    while (a <= x1 && !tile_hit32(q, a, ty, tw, th, W, H, k)) ++a;
+    if (a > x1) return 0;
+    int b = x1;
+    while (b > a && !tile_hit32(q, b, ty, tw, th, W, H, k)) --b;
+    *l = a; *r = b;
+    return 1;
+}
+
+/* ------------------------------------------------------------------------
  * Strict binary32 projection of one Gaussian into one view.
  * Follows EWA splatting as used by 3DGS (the paper's Sec. 3.1 projects each
  * 3D Gaussian to a 2D Gaussian (m2D, Sigma2D)); every operation is written
  * out in a fixed order so the GPU can reproduce it bit for bit.
  * Outputs: flags bit0 visible, bit1 fp64-conic predicate, bit2 culled for
- * invalid input; rect = tile rectangle [x0,y0,x1,y1] (inclusive);
- * ntiles; depth; cov = (a, b, c) of the 2D covariance incl. low-pass.
+ * invalid input; rect = tile rectangle [x0,y0,x1,y1] (inclusive) of the
+ * support ellipse's pixel bounding box; ntiles = tiles of the rectangle that
+ * row_span32 lists; depth; cov = (a, b, c) of the 2D covariance incl. low-pass.
  * ---------------------------------------------------------------------- */
 static void proj32_one(const float *gin /*11*/, const float *cam, const float *prm,
                        uint8_t *flags, int32_t *rect, int32_t *ntiles, float *depth,
@@ -126,27 +194,32 @@ static void proj32_one(const float *gin /*11*/, const float *cam, const float *p
     float v = fy * yr + cy;
     mean2d[0] = u; mean2d[1] = v;
 
-    /* bounding radius from the largest eigenvalue */
-    float mid = 0.5f * (a + c);
-    float hd = 0.5f * (a - c);
-    float lam = mid + sqrtf(hd * hd + b * b);
-    float r = ceilf(prm[P_K] * sqrtf(lam));
-    if (!isfinite(u) || !isfinite(v) || !isfinite(r) || !isfinite(a) || !isfinite(b) || !isfinite(c)) return;
+    /* bounding box of the support ellipse d^T Sigma^-1 d <= k^2: its half
+     * extents are k*sqrt(a) and k*sqrt(c), rounded up to whole pixels */
+    float rx = ceilf(prm[P_K] * sqrtf(a));
+    float ry = ceilf(prm[P_K] * sqrtf(c));
+    if (!isfinite(u) || !isfinite(v) || !isfinite(rx) || !isfinite(ry) || !isfinite(a) || !isfinite(b) || !isfinite(c)) return;
 
     float det = a * c - b * b;
     uint8_t f = 1;
     if (!(det > 0.0f) || (a * c >= prm[P_COND] * det)) f |= 2;
     *flags = f;
 
-    float fk0 = ceilf((u - r) - 0.5f), fk1 = floorf((u + r) - 0.5f);
-    float fj0 = ceilf((v - r) - 0.5f), fj1 = floorf((v + r) - 0.5f);
+    float fk0 = ceilf((u - rx) - 0.5f), fk1 = floorf((u + rx) - 0.5f);
+    float fj0 = ceilf((v - ry) - 0.5f), fj1 = floorf((v + ry) - 0.5f);
     if (fk1 < 0.0f || fk0 > (float)(W - 1) || fj1 < 0.0f || fj0 > (float)(H - 1) || fk0 > fk1 || fj0 > fj1)
         return;
     int kmin = (int)fmaxf(fk0, 0.0f), kmax = (int)fminf(fk1, (float)(W - 1));
     int jmin = (int)fmaxf(fj0, 0.0f), jmax = (int)fminf(fj1, (float)(H - 1));
     int tw = (int)prm[P_TW], th = (int)prm[P_TH];
     rect[0] = kmin / tw; rect[1] = jmin / th; rect[2] = kmax / tw; rect[3] = jmax / th;
-    *ntiles = (rect[2] - rect[0] + 1) * (rect[3] - rect[1] + 1);
+    conic32_t q32 = conic32(u, v, a, b, c, f);
+    int nt = 0;
+    for (int ty = rect[1]; ty <= rect[3]; ++ty) {
+        int l, r;
+        if (row_span32(&q32, ty, rect[0], rect[2], tw, th, W, H, prm[P_K], &l, &r)) nt += r - l + 1;
+    }
+    *ntiles = nt;
 }
 
 /* gauss: float32 [11][n] structure of arrays (mx,my,mz,qw,qx,qy,qz,sx,sy,sz,op). */
@@ -177,12 +250,15 @@ static int cmp_pair(const void *pa, const void *pb)
     return 0;
 }
 
-/* Returns the number of pairs. out_tile/out_g must hold sum(ntiles) entries;
+/* Returns the number of pairs (-1 if the rectangle enumeration disagrees with
+ * ntiles). out_tile/out_g must hold sum(ntiles) entries;
  * ranges: uint32 [tiles_x*tiles_y][2], empty tiles get [0,0). */
 int64_t or_bin(int64_t n, const uint8_t *flags, const int32_t *rect, const int32_t *ntiles,
-               const float *depth, int32_t tiles_x, int32_t tiles_y,
-               int32_t *out_tile, uint32_t *out_g, uint32_t *ranges)
+               const float *depth, const float *cov, const float *mean2d, const float *cam, const float *prm,
+               int32_t tiles_x, int32_t tiles_y, int32_t *out_tile, uint32_t *out_g, uint32_t *ranges)
 {
+    int W = (int)cam[16], H = (int)cam[17];
+    int tw = (int)prm[P_TW], th = (int)prm[P_TH];
     int64_t total = 0;
     for (int64_t g = 0; g < n; ++g)
         if (flags[g] & 1) total += ntiles[g];
@@ -190,14 +266,19 @@ int64_t or_bin(int64_t n, const uint8_t *flags, const int32_t *rect, const int32
     int64_t k = 0;
     for (int64_t g = 0; g < n; ++g) {
         if (!(flags[g] & 1) || ntiles[g] == 0) continue;
-        for (int ty = rect[4 * g + 1]; ty <= rect[4 * g + 3]; ++ty)
-            for (int tx = rect[4 * g + 0]; tx <= rect[4 * g + 2]; ++tx) {
+        conic32_t q32 = conic32(mean2d[2 * g], mean2d[2 * g + 1], cov[3 * g], cov[3 * g + 1], cov[3 * g + 2], flags[g]);
+        for (int ty = rect[4 * g + 1]; ty <= rect[4 * g + 3]; ++ty) {
+            int l, r;
+            if (!row_span32(&q32, ty, rect[4 * g + 0], rect[4 * g + 2], tw, th, W, H, prm[P_K], &l, &r)) continue;
+            for (int tx = l; tx <= r; ++tx) {
                 p[k].tile = ty * tiles_x + tx;
                 p[k].depth = depth[g];
                 p[k].g = (uint32_t)g;
                 ++k;
             }
+        }
     }
+    if (k != total) { free(p); return -1; }
     qsort(p, (size_t)total, sizeof(pair_t), cmp_pair);
     int64_t T = (int64_t)tiles_x * tiles_y;
     memset(ranges, 0, sizeof(uint32_t) * 2 * (size_t)T);
@@ -293,7 +374,8 @@ void or_project64(int64_t n, const float *gauss, const float *cam, const float *
  * Inputs: list (out_g of or_bin) + ranges, p64 from or_project64, mask
  * uint8 [H][W]. Accumulates into A (double [n][E]) and slack (double [n]);
  * writes tfinal (double [H][W]) and nblend (int32 [H][W]) when non-NULL.
- * stats (int64 [4]) += {blends, flagged decisions, bad labels, evaluated pairs}.
+ * stats (int64 [4]) += {blends, flagged decisions, bad labels, pairs evaluated
+ * inside the support before the pixel's compositing ended}.
  * ---------------------------------------------------------------------- */
 void or_composite64(int64_t n, const double *p64, const float *opacity, const float *cam,
                     const float *prm, const uint32_t *list, const uint32_t *ranges,
@@ -331,7 +413,7 @@ void or_composite64(int64_t n, const double *p64, const float *opacity, const fl
                     double dx = pxc - q[0], dy = pyc - q[1];
                     double power = -0.5 * (q[2] * dx * dx + q[4] * dy * dy) - q[3] * dx * dy;
                     double alpha = fmin(amax, (double)opacity[g] * exp(power));
-                    s_eval++;
+                    if (power >= cut) s_eval++;
                     int f_sup = fabs(power - cut) <= eps * (-cut);
                     int f_amin = amin > 0.0 && fabs(alpha - amin) <= eps * amin;
                     int flip = f_sup || f_amin;

@@ -21,7 +21,7 @@ ARCH = "gfx950"
 
 SOURCES = {
     "fs_project.hip": ["-ffp-contract=off"],
-    "fs_sort.hip": [],
+    "fs_sort.hip": ["-ffp-contract=off"],
     "fs_accum.hip": ["-ffp-contract=fast"],
     "fs_assign.hip": [],
     "fs_api.hip": [],

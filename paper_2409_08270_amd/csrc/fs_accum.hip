@@ -56,6 +56,30 @@ __device__ __forceinline__ void add_global(float *hi, float *lo, int64_t idx, fl
     if (err != 0.0f) unsafeAtomicAdd(lo + idx, err);
 }
 
+// Can any pixel centre of the 8x8 block with corner (bx, by) lie inside the
+// ellipse A dx^2 + 2B dx dy + C dy^2 <= lim around (u, v)? Minimum of the
+// quadratic over the block's pixel-centre box: zero if the mean is inside,
+// else the least edge minimum (clamped parabola vertex). Conservative through
+// the margin folded into lim; used only to skip work, never to decide a weight.
+__device__ __forceinline__ bool block_hit(float u, float v, float A, float B, float C, float bx, float by, float lim)
+{
+    const float xl = bx + 0.5f - u, xh = bx + 7.5f - u;
+    const float yl = by + 0.5f - v, yh = by + 7.5f - v;
+    if (xl <= 0.0f && xh >= 0.0f && yl <= 0.0f && yh >= 0.0f) return true;
+    const float iA = 1.0f / A, iC = 1.0f / C;
+    float qmin = 3.4e38f;
+#pragma unroll
+    for (int i = 0; i < 2; ++i) {
+        const float x = i ? xh : xl;
+        const float y = fminf(fmaxf(-(B * x) * iC, yl), yh);
+        qmin = fminf(qmin, A * x * x + 2.0f * B * x * y + C * y * y);
+        const float y2 = i ? yh : yl;
+        const float x2 = fminf(fmaxf(-(B * y2) * iA, xl), xh);
+        qmin = fminf(qmin, A * x2 * x2 + 2.0f * B * x2 * y2 + C * y2 * y2);
+    }
+    return qmin <= lim;
+}
+
 __global__ __launch_bounds__(256) void k_accum(const float4 *__restrict__ rec, const uint32_t *__restrict__ vals,
                                                const uint2 *__restrict__ ranges, const CamDev *__restrict__ cams,
                                                int32_t n_views, const uint32_t *__restrict__ items, int64_t n,
@@ -64,10 +88,12 @@ __global__ __launch_bounds__(256) void k_accum(const float4 *__restrict__ rec, c
                                                float *__restrict__ t_final, int32_t *__restrict__ n_blend,
                                                unsigned long long *__restrict__ status)
 {
-    __shared__ float4 s_rec[kBatch];       // u, v, a', b'
+    __shared__ float4 s_rec[kBatch];       // u, v, a', b' (conic scaled to log2 units)
     __shared__ float2 s_rec2[kBatch];      // c', opacity
     __shared__ uint32_t s_g[kBatch];
     __shared__ float s_part[kBatch][kSlots];
+    __shared__ uint8_t s_wmask[kBatch];    // bit w: wave w's 8x8 block can be reached
+    __shared__ uint8_t s_list[4][kBatch];  // per-wave compacted batch indices
     __shared__ uint32_t s_bits[8];
     __shared__ int32_t s_slot_label[kSlots];
     __shared__ uint32_t s_wslots[4];
@@ -102,9 +128,7 @@ __global__ __launch_bounds__(256) void k_accum(const float4 *__restrict__ rec, c
     if (tid < 4) s_wslots[tid] = 0;
     if (tid < 2) s_misc[tid] = 0;
     __syncthreads();
-    if (inside && !active) {
-        atomicAdd(&s_misc[0], 1u);
-    }
+    if (inside && !active) atomicAdd(&s_misc[0], 1u);
     if (active) atomicOr(&s_bits[lab >> 5], 1u << (lab & 31));
     __syncthreads();
     int slot = 0, nslot = 0;
@@ -137,6 +161,9 @@ __global__ __launch_bounds__(256) void k_accum(const float4 *__restrict__ rec, c
     const uint2 rg = ranges[tile];
     const float pxc = (float)x + 0.5f, pyc = (float)y + 0.5f;
     const float LOG2E = 1.4426950408889634f;
+    // block-reach margin: 1/64 relative on k^2 (the weights use their own test)
+    const float lim = -2.0f * P.cut2 / LOG2E * 1.015625f;
+    const float tx0 = (float)(tx * P.tile_w), ty0 = (float)(ty * P.tile_h);
     float T = 1.0f;
     int nb = 0, ne = 0;
     bool done = !active;
@@ -153,18 +180,40 @@ __global__ __launch_bounds__(256) void k_accum(const float4 *__restrict__ rec, c
             s_rec[tid] = make_float4(r0.x, r0.y, -0.5f * LOG2E * r0.z, -LOG2E * r0.w);
             s_rec2[tid] = make_float2(-0.5f * LOG2E * r1.x, r1.y);
             s_g[tid] = g;
+            uint32_t m = 0xFu;
+            if (r1.w == 0.0f) {  // float32 conic: cull the 8x8 blocks the support cannot reach
+                m = 0;
+#pragma unroll
+                for (int b = 0; b < 4; ++b) {
+                    const float bx = tx0 + (float)((b % bpr) * 8), by = ty0 + (float)((b / bpr) * 8);
+                    if (block_hit(r0.x, r0.y, r0.z, r0.w, r1.x, bx, by, lim)) m |= 1u << b;
+                }
+            }
+            s_wmask[tid] = (uint8_t)m;
         }
         __syncthreads();
+        // each wave compacts the batch entries that can reach its block, in order
+        int nlist = 0;
+#pragma unroll
+        for (int c = 0; c < kBatch / 64; ++c) {
+            const int e = c * 64 + lane;
+            const bool hit = (uint32_t)e < cnt && ((s_wmask[e] >> w) & 1u);
+            const unsigned long long bm = __ballot(hit);
+            if (hit) s_list[w][nlist + __popcll(bm & ((1ull << lane) - 1ull))] = (uint8_t)e;
+            nlist += __popcll(bm);
+        }
+        __builtin_amdgcn_wave_barrier();
         if (__ballot(!done) != 0ull) {
-            for (uint32_t j = 0; j < cnt; ++j) {
+            for (int it = 0; it < nlist; ++it) {
+                const uint32_t j = s_list[w][it];
                 float wgt = 0.0f;
                 if (!done) {
-                    ne++;
                     const float4 q = s_rec[j];
                     const float2 q2 = s_rec2[j];
                     const float dx = pxc - q.x, dy = pyc - q.y;
                     const float pw = (q.z * dx * dx + q2.x * dy * dy) + q.w * dx * dy;
                     if (pw >= P.cut2) {
+                        ne++;
                         const float alpha = fminf(P.alpha_max, q2.y * __builtin_amdgcn_exp2f(pw));
                         if (alpha >= P.alpha_min) {
                             const float Tn = T * (1.0f - alpha);
@@ -192,7 +241,7 @@ __global__ __launch_bounds__(256) void k_accum(const float4 *__restrict__ rec, c
                         }
                     }
                 }
-                if ((j & 15u) == 15u && __ballot(!done) == 0ull) break;
+                if ((it & 15) == 15 && __ballot(!done) == 0ull) break;
             }
         }
         __syncthreads();

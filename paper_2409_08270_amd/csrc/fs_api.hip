@@ -431,8 +431,9 @@ int fs_bin_sort(fs_ctx *ctx, const fs_proj *proj, const fs_camera *cams, const f
         k0 = (uint32_t *)ctx->pk_alt.p; v0 = (uint32_t *)ctx->pv_alt.p; k1 = out->tiles; v1 = out->vals;
     }
     if (!n_pairs) HIPCHECK(ctx, launch_fill_u32(s, k0, 0xFFFFFFFFu, sort_len));  // tail beyond the real count sorts last
-    HIPCHECK(ctx, launch_emit(s, dk, dv, (const uint32_t *)ctx->offsets.p, proj->rect, (const CamDev *)ctx->cams.p, n, V,
-                              (uint32_t)out->capacity, k0, v0, ctx->status_dev));
+    HIPCHECK(ctx, launch_emit(s, dk, dv, (const uint32_t *)ctx->offsets.p, (const uint32_t *)ctx->counts.p, proj->rec,
+                              proj->rect, proj->flags, (const CamDev *)ctx->cams.p, n, V, (uint32_t)out->capacity,
+                              p->tile_w, p->tile_h, p->sigma_k, k0, v0, ctx->status_dev));
     HIPCHECK(ctx, radix_sort(s, k0, v0, k1, v1, sort_len, 1, passes * 8, ctx->sort_ws.p));
     HIPCHECK(ctx, launch_ranges(s, out->tiles, ctx->npairs_dev, (uint32_t)out->capacity, sort_len, out->ranges));
     return FS_OK;

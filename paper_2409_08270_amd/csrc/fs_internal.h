@@ -75,10 +75,13 @@ hipError_t scan_exclusive(hipStream_t s, const uint32_t *in, uint32_t *out, int6
 hipError_t launch_gather_counts(hipStream_t s, const uint32_t *sorted_keys, const uint32_t *sorted_vals,
                                 const int32_t *ntiles, int64_t n, int32_t n_views, uint32_t *counts);
 
+// emits, for every depth-sorted item, one (tile, id) pair per tile that passes
+// tile_hit, at offsets[i]; pairs at or beyond `capacity` are dropped and latched
 hipError_t launch_emit(hipStream_t s, const uint32_t *sorted_keys, const uint32_t *sorted_vals,
-                       const uint32_t *offsets, const int16_t *rect, const CamDev *cams_dev,
-                       int64_t n, int32_t n_views, uint32_t capacity, uint32_t *tiles_out,
-                       uint32_t *vals_out, unsigned long long *status);
+                       const uint32_t *offsets, const uint32_t *counts, const float *rec, const int16_t *rect,
+                       const uint8_t *flags, const CamDev *cams_dev, int64_t n, int32_t n_views, uint32_t capacity,
+                       int32_t tile_w, int32_t tile_h, float sigma_k, uint32_t *tiles_out, uint32_t *vals_out,
+                       unsigned long long *status);
 
 hipError_t launch_ranges(hipStream_t s, const uint32_t *tiles, const uint32_t *n_pairs_dev,
                          uint32_t capacity, int64_t n_pairs_max, uint32_t *ranges);

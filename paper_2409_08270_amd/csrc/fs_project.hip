@@ -7,6 +7,7 @@
 // exactly as written, in the order written (products rounded, sums left to
 // right, correctly rounded division and square root).
 #include "fs_internal.h"
+#include "fs_tiles.h"
 
 namespace fs {
 namespace {
@@ -105,11 +106,10 @@ __global__ __launch_bounds__(256) void k_project(GaussPtrs G, int64_t n, const C
                 float c = ((m1[0] * m1[0] + m1[1] * m1[1]) + m1[2] * m1[2]) + lp;
                 float u = C.fx * xr + C.cx;
                 float vv = C.fy * yr + C.cy;
-                float mid = 0.5f * (a + c);
-                float hd = 0.5f * (a - c);
-                float lam = mid + sqrtf(hd * hd + b * b);
-                float r = ceilf(P.sigma_k * sqrtf(lam));
-                if (finite32(u) && finite32(vv) && finite32(r) && finite32(a) && finite32(b) && finite32(c)) {
+                // pixel bounding box of the support ellipse: half extents k*sqrt(a), k*sqrt(c)
+                float rx = ceilf(P.sigma_k * sqrtf(a));
+                float ry = ceilf(P.sigma_k * sqrtf(c));
+                if (finite32(u) && finite32(vv) && finite32(rx) && finite32(ry) && finite32(a) && finite32(b) && finite32(c)) {
                     float det = a * c - b * b;
                     bool deg = !(det > 0.0f) || (a * c >= P.fp64_cond * det);
                     f = deg ? 3 : 1;
@@ -140,15 +140,23 @@ __global__ __launch_bounds__(256) void k_project(GaussPtrs G, int64_t n, const C
                     r0 = make_float4(u, vv, ca, cb);
                     r1.x = cc;
                     r1.y = op;
-                    float fk0 = ceilf((u - r) - 0.5f), fk1 = floorf((u + r) - 0.5f);
-                    float fj0 = ceilf((vv - r) - 0.5f), fj1 = floorf((vv + r) - 0.5f);
+                    r1.w = (deg && P.fp64_conic) ? 1.0f : 0.0f;
+                    float fk0 = ceilf((u - rx) - 0.5f), fk1 = floorf((u + rx) - 0.5f);
+                    float fj0 = ceilf((vv - ry) - 0.5f), fj1 = floorf((vv + ry) - 0.5f);
                     if (!(fk1 < 0.0f || fk0 > (float)(C.W - 1) || fj1 < 0.0f || fj0 > (float)(C.H - 1) ||
                           fk0 > fk1 || fj0 > fj1)) {
                         int kmin = (int)fmaxf(fk0, 0.0f), kmax = (int)fminf(fk1, (float)(C.W - 1));
                         int jmin = (int)fmaxf(fj0, 0.0f), jmax = (int)fminf(fj1, (float)(C.H - 1));
                         int x0 = kmin / P.tile_w, y0 = jmin / P.tile_h, x1 = kmax / P.tile_w, y1 = jmax / P.tile_h;
                         rc = make_short4((short)x0, (short)y0, (short)x1, (short)y1);
-                        nt = (x1 - x0 + 1) * (y1 - y0 + 1);
+                        // tiles of the rectangle that the support ellipse reaches; the test
+                        // uses the float32 conic computed above (c/det, -b/det, a/det)
+                        const Conic32 q32 = make_conic32(u, vv, ca, cb, cc, deg);
+                        const float lim = support_limit(P.sigma_k);
+                        for (int ty = y0; ty <= y1; ++ty) {
+                            int l, r;
+                            if (row_span(q32, ty, x0, x1, P.tile_w, P.tile_h, C.W, C.H, lim, l, r)) nt += r - l + 1;
+                        }
                     }
                 }
             }

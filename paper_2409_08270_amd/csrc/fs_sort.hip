@@ -11,6 +11,7 @@
 // keys plus P 16-bit tile keys moves far fewer bytes than sorting P
 // (tile, depth) 48-bit keys.
 #include "fs_internal.h"
+#include "fs_tiles.h"
 
 namespace fs {
 namespace {
@@ -99,6 +100,10 @@ __global__ __launch_bounds__(kThreads) void k_scan_down(const uint32_t *__restri
 }
 
 // ------------------------------------------------------------ radix sort --
+// Digit histogram of one block tile. Each thread reads 16 consecutive keys and
+// adds runs of equal digits with one LDS atomic per run: keys emitted per
+// Gaussian in tile order repeat their high digit, which would otherwise
+// serialise the atomics.
 __global__ __launch_bounds__(kThreads) void k_radix_hist(const uint32_t *__restrict__ keys, int64_t seg_len,
                                                          int32_t blocks_per_seg, int32_t shift,
                                                          uint32_t *__restrict__ hist)
@@ -108,13 +113,43 @@ __global__ __launch_bounds__(kThreads) void k_radix_hist(const uint32_t *__restr
     const int w = threadIdx.x >> 6;
     for (int i = threadIdx.x; i < kWaves * 256; i += kThreads) (&s_h[0][0])[i] = 0;
     __syncthreads();
-    const int64_t t0 = (int64_t)b * kTile;
+    const int64_t t0 = (int64_t)b * kTile + (int64_t)threadIdx.x * kItems;
     const uint32_t *k = keys + (int64_t)seg * seg_len;
-#pragma unroll 4
-    for (int it = 0; it < kItems; ++it) {
-        int64_t i = t0 + it * kThreads + threadIdx.x;
-        if (i < seg_len) atomicAdd(&s_h[w][(k[i] >> shift) & 255u], 1u);
+    uint32_t run_d = 0xFFFFFFFFu, run_n = 0;
+    if (t0 + kItems <= seg_len) {
+        const uint4 *k4 = reinterpret_cast<const uint4 *>(k + t0);
+        const bool aligned = ((reinterpret_cast<uintptr_t>(k + t0) & 15u) == 0);
+#pragma unroll
+        for (int q = 0; q < kItems / 4; ++q) {
+            uint4 x;
+            if (aligned) x = k4[q];
+            else x = make_uint4(k[t0 + 4 * q], k[t0 + 4 * q + 1], k[t0 + 4 * q + 2], k[t0 + 4 * q + 3]);
+            const uint32_t xs[4] = {x.x, x.y, x.z, x.w};
+#pragma unroll
+            for (int e = 0; e < 4; ++e) {
+                const uint32_t d = (xs[e] >> shift) & 255u;
+                if (d != run_d) {
+                    if (run_n) atomicAdd(&s_h[w][run_d], run_n);
+                    run_d = d;
+                    run_n = 0;
+                }
+                run_n++;
+            }
+        }
+    } else {
+        for (int it = 0; it < kItems; ++it) {
+            const int64_t i = t0 + it;
+            if (i >= seg_len) break;
+            const uint32_t d = (k[i] >> shift) & 255u;
+            if (d != run_d) {
+                if (run_n) atomicAdd(&s_h[w][run_d], run_n);
+                run_d = d;
+                run_n = 0;
+            }
+            run_n++;
+        }
     }
+    if (run_n) atomicAdd(&s_h[w][run_d], run_n);
     __syncthreads();
     const int d = threadIdx.x;
     uint32_t c = 0;
@@ -231,37 +266,90 @@ __global__ void k_gather_counts(const uint32_t *__restrict__ skeys, const uint32
     counts[i] = skeys[i] == 0xFFFFFFFFu ? 0u : (uint32_t)ntiles[v * n + svals[i]];
 }
 
-__global__ void k_emit(const uint32_t *__restrict__ skeys, const uint32_t *__restrict__ svals,
-                       const uint32_t *__restrict__ offsets, const short4 *__restrict__ rect,
-                       const CamDev *__restrict__ cams, int64_t total, int64_t n, uint32_t capacity,
-                       uint32_t *__restrict__ tiles_out, uint32_t *__restrict__ vals_out,
-                       unsigned long long *__restrict__ status)
+// Emission of the (tile, Gaussian) pairs. Block b handles the depth-sorted
+// items [256 b, 256 b + 256), whose outputs form one contiguous range. Each
+// thread enumerates its Gaussian's tiles (the row_span rule, as in the count)
+// into an LDS window of kEmitWin pairs, and the block writes the window out
+// with consecutive threads on consecutive addresses.
+constexpr int kEmitWin = 4096;
+
+__global__ __launch_bounds__(kThreads) void k_emit(const uint32_t *__restrict__ skeys, const uint32_t *__restrict__ svals,
+                                                   const uint32_t *__restrict__ offsets, const uint32_t *__restrict__ counts,
+                                                   const float4 *__restrict__ rec, const short4 *__restrict__ rect,
+                                                   const uint8_t *__restrict__ flags, const CamDev *__restrict__ cams,
+                                                   int64_t total, int64_t n, uint32_t capacity, int32_t tw, int32_t th,
+                                                   float sigma_k, uint32_t *__restrict__ tiles_out,
+                                                   uint32_t *__restrict__ vals_out, unsigned long long *__restrict__ status)
 {
-    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    __shared__ uint32_t s_t[kEmitWin];
+    __shared__ uint32_t s_g[kEmitWin];
+    __shared__ uint32_t s_lo, s_hi;
+    const int64_t b0 = (int64_t)blockIdx.x * kThreads;
+    const int64_t last = min(total, b0 + kThreads) - 1;
+    const int64_t i = b0 + threadIdx.x;
+    const bool live = i < total && skeys[i] != 0xFFFFFFFFu;
+    const uint32_t off = i < total ? offsets[i] : 0u;
+    const uint32_t cnt = live ? counts[i] : 0u;
+    if (threadIdx.x == 0) s_lo = offsets[b0];
+    if (i == last) s_hi = off + cnt;
+    __syncthreads();
+    const uint32_t lo = s_lo, hi = s_hi;
+
+    uint32_t g = 0, tbase = 0, tiles_x = 0;
+    short4 rc = make_short4(0, 0, -1, -1);
+    Conic32 q32 = make_conic32(0.f, 0.f, 1.f, 0.f, 1.f, true);
+    int W = 0, H = 0;
+    const float lim = support_limit(sigma_k);
+    if (cnt > 0) {
+        const int64_t vw = i / n;
+        g = svals[i];
+        const int64_t idx = vw * n + g;
+        rc = rect[idx];
+        const float4 r0 = rec[2 * idx];
+        const float4 r1 = rec[2 * idx + 1];
+        q32 = make_conic32(r0.x, r0.y, r0.z, r0.w, r1.x, (flags[idx] & 2u) != 0);
+        const CamDev &C = cams[vw];
+        tbase = C.tile_base;
+        tiles_x = (uint32_t)C.tiles_x;
+        W = C.W;
+        H = C.H;
+    }
     uint32_t dropped = 0;
-    if (i < total && skeys[i] != 0xFFFFFFFFu) {
-        const int64_t v = i / n;
-        const uint32_t g = svals[i];
-        const short4 rc = rect[v * n + g];
-        const CamDev &C = cams[v];
-        uint32_t p = offsets[i];
-        for (int ty = rc.y; ty <= rc.w; ++ty) {
-            const uint32_t rowbase = C.tile_base + (uint32_t)ty * (uint32_t)C.tiles_x;
-            for (int tx = rc.x; tx <= rc.z; ++tx, ++p) {
-                if (p < capacity) {
-                    tiles_out[p] = rowbase + (uint32_t)tx;
-                    vals_out[p] = g;
-                } else {
-                    dropped++;
+    for (uint32_t w0 = lo; w0 < hi; w0 += kEmitWin) {
+        const uint32_t wend = min(hi, w0 + (uint32_t)kEmitWin);
+        if (cnt > 0 && off < wend && off + cnt > w0) {
+            uint32_t p = off;
+            for (int ty = rc.y; ty <= rc.w && p < wend; ++ty) {
+                int l, r;
+                if (!row_span(q32, ty, rc.x, rc.z, tw, th, W, H, lim, l, r)) continue;
+                const uint32_t n_row = (uint32_t)(r - l + 1);
+                if (p + n_row > w0) {
+                    const uint32_t rowbase = tbase + (uint32_t)ty * tiles_x + (uint32_t)l;
+                    const uint32_t a = p < w0 ? w0 - p : 0u;
+                    const uint32_t b = min(n_row, wend - p);
+                    for (uint32_t e = a; e < b; ++e) {
+                        s_t[p + e - w0] = rowbase + e;
+                        s_g[p + e - w0] = g;
+                    }
                 }
+                p += n_row;
             }
         }
-    }
-    if (__ballot(dropped != 0)) {
-        if (dropped) {
-            atomicAdd(&status[ST_DROPPED], (unsigned long long)dropped);
-            atomicOr(&status[ST_FLAGS], (unsigned long long)FS_DEV_PAIR_OVERFLOW);
+        __syncthreads();
+        for (uint32_t q = threadIdx.x; q < wend - w0; q += kThreads) {
+            const uint32_t p = w0 + q;
+            if (p < capacity) {
+                tiles_out[p] = s_t[q];
+                vals_out[p] = s_g[q];
+            } else {
+                dropped++;
+            }
         }
+        __syncthreads();
+    }
+    if (__ballot(dropped != 0) && dropped) {
+        atomicAdd(&status[ST_DROPPED], (unsigned long long)dropped);
+        atomicOr(&status[ST_FLAGS], (unsigned long long)FS_DEV_PAIR_OVERFLOW);
     }
 }
 
@@ -377,15 +465,16 @@ hipError_t launch_gather_counts(hipStream_t s, const uint32_t *sorted_keys, cons
 }
 
 hipError_t launch_emit(hipStream_t s, const uint32_t *sorted_keys, const uint32_t *sorted_vals,
-                       const uint32_t *offsets, const int16_t *rect, const CamDev *cams_dev, int64_t n,
-                       int32_t n_views, uint32_t capacity, uint32_t *tiles_out, uint32_t *vals_out,
+                       const uint32_t *offsets, const uint32_t *counts, const float *rec, const int16_t *rect,
+                       const uint8_t *flags, const CamDev *cams_dev, int64_t n, int32_t n_views, uint32_t capacity,
+                       int32_t tile_w, int32_t tile_h, float sigma_k, uint32_t *tiles_out, uint32_t *vals_out,
                        unsigned long long *status)
 {
     const int64_t total = n * n_views;
     if (total == 0) return hipSuccess;
-    hipLaunchKernelGGL(k_emit, dim3(grid_for(total, 256)), dim3(256), 0, s, sorted_keys, sorted_vals, offsets,
-                       reinterpret_cast<const short4 *>(rect), cams_dev, total, n, capacity, tiles_out, vals_out,
-                       status);
+    hipLaunchKernelGGL(k_emit, dim3(grid_for(total, kThreads)), dim3(kThreads), 0, s, sorted_keys, sorted_vals, offsets,
+                       counts, reinterpret_cast<const float4 *>(rec), reinterpret_cast<const short4 *>(rect), flags,
+                       cams_dev, total, n, capacity, tile_w, tile_h, sigma_k, tiles_out, vals_out, status);
     return hipGetLastError();
 }
 

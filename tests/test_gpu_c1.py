@@ -110,6 +110,9 @@ def test_accumulate_matches_oracle(c1, reduction, compensated):
     log(f"[c1] pixels with a different blend count: {int((~same).sum())} of {px}; blends gpu {st['blends']} oracle {ref['blends']}")
     assert (~same).sum() <= 0.002 * px
     assert np.max(np.abs(tf.cpu().numpy()[same] - tf_o[same])) < 1e-5
+    # pairs evaluated inside the support agree with the oracle's count
+    log(f"[c1] in-support evaluations gpu {st['evaluated']} oracle {ref['evaluated']}")
+    assert abs(st["evaluated"] - ref["evaluated"]) <= 2e-3 * ref["evaluated"]
 
 
 def test_assign_matches_oracle(c1):

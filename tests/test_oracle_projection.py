@@ -96,7 +96,8 @@ def test_guard_band_clamp_freezes_jacobian():
     assert not np.allclose(S2[0], S2[1], rtol=1e-3)
 
 
-def test_radius_and_rect_against_eigensolver_and_brute_force():
+def test_rect_is_the_support_bounding_box_by_brute_force():
+    # tile rectangle = tiles holding a pixel centre within u +- ceil(3 sqrt(a)), v +- ceil(3 sqrt(c))
     sc = sg.make_tiny(3, n=12, views=3, res=48, spread=0.6)
     for v in range(sc.n_views):
         pr = O.project32(sc, v, PRM)
@@ -104,20 +105,61 @@ def test_radius_and_rect_against_eigensolver_and_brute_force():
         for g in range(sc.n):
             if not (pr["flags"][g] & 1):
                 continue
-            a, b, c = [float(x) for x in pr["cov"][g]]
-            lam = float(np.linalg.eigvalsh(np.array([[a, b], [b, c]]))[-1])
-            r = math.ceil(3.0 * math.sqrt(lam))
+            a, b, c = [np.float32(x) for x in pr["cov"][g]]
+            rx = float(np.ceil(np.float32(3.0) * np.sqrt(a)))
+            ry = float(np.ceil(np.float32(3.0) * np.sqrt(c)))
+            # the box holds the whole k-sigma ellipse: its x half-extent is 3 sqrt(a) (eigen form)
+            lam = np.linalg.eigvalsh(np.array([[a, b], [b, c]], np.float64))
+            assert 3.0 * math.sqrt(lam[-1]) >= 3.0 * math.sqrt(float(a)) - 1e-6
             u, vv = [float(x) for x in pr["mean2d"][g]]
-            # brute force: tiles holding at least one pixel centre inside the square u +- r, v +- r
             tiles = set()
             for j in range(H):
                 for k in range(W):
-                    if abs(k + 0.5 - u) <= r and abs(j + 0.5 - vv) <= r:
+                    if abs(k + 0.5 - u) <= rx and abs(j + 0.5 - vv) <= ry:
                         tiles.add((k // 16, j // 16))
             x0, y0, x1, y1 = pr["rect"][g]
-            got = {(tx, ty) for ty in range(y0, y1 + 1) for tx in range(x0, x1 + 1)} if pr["ntiles"][g] else set()
+            got = {(tx, ty) for ty in range(y0, y1 + 1) for tx in range(x0, x1 + 1)} if tiles else set()
             assert got == tiles, (v, g)
-            assert pr["ntiles"][g] == len(tiles)
+
+
+def _pairs_by_tile(b):
+    out = {}
+    for t, g in zip(b["tile"], b["g"]):
+        out.setdefault(int(g), set()).add(int(t))
+    return out
+
+
+@pytest.mark.parametrize("cfg", ["tiny", "C1"])
+def test_tile_lists_lose_no_support_pixel_and_are_tight(cfg):
+    sc = sg.make_tiny(4, n=12, views=3, res=64, spread=0.5) if cfg == "tiny" else sg.make_config("C1")
+    for v in range(min(3, sc.n_views)):
+        b = O.bin_view(sc, v, PRM)
+        p64 = O.project64(sc, v, PRM)
+        pr = b["proj"]
+        tx = b["tiles_x"]
+        W, H = int(sc.W[v]), int(sc.H[v])
+        listed = _pairs_by_tile(b)
+        jj, kk = np.mgrid[0:H, 0:W]
+        for g in np.nonzero((pr["flags"] & 1) != 0)[0]:
+            u, vv, A, B, C = p64[g]
+            dx = kk + 0.5 - u
+            dy = jj + 0.5 - vv
+            q = A * dx * dx + 2 * B * dx * dy + C * dy * dy
+            need = {int((j // 16) * tx + (k // 16)) for j, k in zip(*np.nonzero(q <= 9.0))}
+            have = listed.get(int(g), set())
+            # no pixel centre inside the support ellipse is lost
+            assert need <= have, (v, g)
+            if pr["flags"][g] & 2:
+                continue
+            # every listed tile comes close: a dense sample of its pixel-centre box reaches q <= 9 (1 + 1%)
+            for t in have:
+                ty_, tx_ = divmod(t, tx)
+                xs = np.linspace(tx_ * 16 + 0.5, min(tx_ * 16 + 15, W - 1) + 0.5, 61) - u
+                ys = np.linspace(ty_ * 16 + 0.5, min(ty_ * 16 + 15, H - 1) + 0.5, 61) - vv
+                X, Y = np.meshgrid(xs, ys)
+                qmin = (A * X * X + 2 * B * X * Y + C * Y * Y).min()
+                assert qmin <= 9.0 * 1.01, (v, g, t, qmin)
+            assert pr["ntiles"][g] == len(have)
 
 
 def test_culling_and_visibility():
@@ -165,26 +207,18 @@ def test_bin_order_matches_lexsort():
     for v in (0, 5):
         b = O.bin_view(sc, v, PRM)
         pr = b["proj"]
-        tx = b["tiles_x"]
-        tiles, depth, gid = [], [], []
-        for g in np.nonzero((pr["flags"] & 1) != 0)[0]:
-            x0, y0, x1, y1 = pr["rect"][g]
-            if pr["ntiles"][g] == 0:
-                continue
-            for ty in range(y0, y1 + 1):
-                for txx in range(x0, x1 + 1):
-                    tiles.append(ty * tx + txx)
-                    depth.append(pr["depth"][g])
-                    gid.append(g)
-        tiles = np.array(tiles)
-        depth = np.array(depth, np.float32)
-        gid = np.array(gid)
+        tiles = b["tile"].astype(np.int64)
+        gid = b["g"].astype(np.int64)
+        depth = pr["depth"][gid]
+        # the pairs re-sorted by (tile, depth, id) with numpy come out unchanged
         order = np.lexsort((gid, depth, tiles))
-        assert np.array_equal(b["tile"], tiles[order])
-        assert np.array_equal(b["g"], gid[order].astype(np.uint32))
+        assert np.array_equal(order, np.arange(order.size))
+        # every visible Gaussian appears exactly ntiles times
+        cnt = np.bincount(gid, minlength=sc.n)
+        assert np.array_equal(cnt, np.where((pr["flags"] & 1) != 0, pr["ntiles"], 0))
         T = b["ranges"].shape[0]
-        st = np.searchsorted(tiles[order], np.arange(T), side="left")
-        en = np.searchsorted(tiles[order], np.arange(T), side="right")
+        st = np.searchsorted(tiles, np.arange(T), side="left")
+        en = np.searchsorted(tiles, np.arange(T), side="right")
         nonempty = en > st
         assert np.array_equal(b["ranges"][nonempty, 0], st[nonempty])
         assert np.array_equal(b["ranges"][nonempty, 1], en[nonempty])
