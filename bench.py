@@ -103,8 +103,35 @@ def main():
     blends = st["blends"] / args.steps
     evals = st["evaluated"] / args.steps
     pairs = sum(out["pairs"])
+    wsteps, wsteps_max = st["wave_steps"] / args.steps, st["wave_steps_max"] / args.steps
     print(f"[bench] batched: {dt_b * 1e3:.2f} ms/step, pairs {pairs}, blends {blends:.3e}, evaluated {evals:.3e}, "
-          f"accumulate kernel {np.mean(acc_ms):.3f} ms", file=sys.stderr, flush=True)
+          f"accumulate kernel {np.mean(acc_ms):.3f} ms; wave steps {wsteps:.3e}, 4 x per-tile max {4 * wsteps_max:.3e}",
+          file=sys.stderr, flush=True)
+
+    # ---- compositing kernel alone, per reduction strategy (same bins) --------
+    strat = {}
+    cams, nv = ds.cams()
+    prm_lin = L.params(tile_order=1)
+    prm_xcd = L.params(tile_order=2)
+    for name, red, comp, prm in (("plain_atomics", L.FS_RED_PLAIN, False, solver.prm),
+                                 ("lds", L.FS_RED_LDS, False, solver.prm),
+                                 ("lds_two_sum", L.FS_RED_LDS2SUM, True, solver.prm),
+                                 ("lds_two_sum_linear_order", L.FS_RED_LDS2SUM, True, prm_lin),
+                                 ("lds_two_sum_xcd_runs", L.FS_RED_LDS2SUM, True, prm_xcd)):
+        n, E = sc.n, sc.E
+        A_hi = torch.zeros((n, E), dtype=torch.float32, device="cuda")
+        A_lo = torch.zeros((n, E), dtype=torch.float32, device="cuda") if comp else None
+        ts = []
+        for _ in range(3):
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record(ctx.stream)
+            ctx.fs_accumulate(solver.proj, solver.bins, cams, ds.masks, E, prm, A_hi, A_lo, red)
+            e1.record(ctx.stream)
+            e1.synchronize()
+            ts.append(e0.elapsed_time(e1))
+        strat[name] = float(np.median(ts))
+    ctx.status()
+    print(f"[bench] compositing kernel per strategy (ms): {strat}", file=sys.stderr, flush=True)
 
     # ---- plain (per view) ---------------------------------------------------
     dt_p = None
@@ -128,7 +155,8 @@ def main():
     achieved = ops / acc_s
     roof = {"bound": "alu", "achieved": achieved / 1e12, "peak": PEAK_ALU_OPS / 1e12, "unit": "TFLOP/s",
             "frac": achieved / PEAK_ALU_OPS, "traffic": None, "kernel": "k_accum",
-            "ops_per_launch": ops, "launch_ms": acc_s * 1e3}
+            "ops_per_launch": ops, "launch_ms": acc_s * 1e3,
+            "wave_steps": wsteps, "wave_balance": wsteps / max(1.0, 4 * wsteps_max)}
 
     # ---- CPU oracle on a bounded sample of views -----------------------------
     cpu = None
@@ -183,6 +211,7 @@ def main():
         "pairs_per_step": pairs,
         "plain_views_per_sec": (V / dt_p) if dt_p else None,
         "batched_over_plain": (dt_p / dt_b) if dt_p else None,
+        "accumulate_ms_by_strategy": strat,
         "roofline": roof,
         "cpu_baseline": cpu,
         "parity_sample": parity,

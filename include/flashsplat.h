@@ -102,7 +102,9 @@ typedef struct {
     float fp64_cond;         /* a splat whose float32 2D covariance has a*c >= fp64_cond*det
                                 (or det <= 0) gets its conic inverted in float64 (64) */
     int32_t fp64_conic;      /* 1 (default): use the float64 inversion for such splats */
-    int32_t reserved;
+    int32_t tile_order;      /* fs_accumulate work order: 0 (default) longest tile list first;
+                                1 = plain tile order; 2 = each of the chip's 8 XCDs (each with
+                                its own L2) gets a contiguous run of tiles */
 } fs_params;
 
 /* Projected Gaussians, caller-owned device buffers, one plane per view:
@@ -144,6 +146,8 @@ typedef struct {
     int64_t blends;          /* (pixel, Gaussian) weights added into A */
     int64_t evaluated;       /* (pixel, Gaussian) pairs with the pixel inside the Gaussian's support,
                                 evaluated before the pixel's compositing ended */
+    int64_t wave_steps;      /* diagnostic: list entries walked by the compositing waves, summed */
+    int64_t wave_steps_max;  /* diagnostic: per tile, the longest walk of its waves, summed over tiles */
     int64_t unseen;          /* fs_assign: rows of A that are all zero */
     int64_t multi_member;    /* fs_assign: Gaussians assigned to more than one object */
     int64_t low_margin;      /* fs_assign: (object, Gaussian) entries with margin < 1e-4 */

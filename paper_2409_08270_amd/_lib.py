@@ -52,7 +52,7 @@ class FsCamera(ctypes.Structure):
 class FsParams(ctypes.Structure):
     _fields_ = [("tile_w", _I32), ("tile_h", _I32), ("sigma_k", _F), ("lowpass", _F), ("znear", _F),
                 ("guard", _F), ("alpha_min", _F), ("alpha_max", _F), ("t_min", _F), ("fp64_cond", _F),
-                ("fp64_conic", _I32), ("reserved", _I32)]
+                ("fp64_conic", _I32), ("tile_order", _I32)]
 
 
 class FsProj(ctypes.Structure):
@@ -69,7 +69,8 @@ class FsPixelOut(ctypes.Structure):
 
 class FsStatus(ctypes.Structure):
     _fields_ = [("flags", ctypes.c_uint32), ("bad_labels", _I64), ("invalid_gauss", _I64),
-                ("fp64_splats", _I64), ("pairs_dropped", _I64), ("blends", _I64), ("evaluated", _I64), ("unseen", _I64),
+                ("fp64_splats", _I64), ("pairs_dropped", _I64), ("blends", _I64), ("evaluated", _I64), ("wave_steps", _I64),
+                ("wave_steps_max", _I64), ("unseen", _I64),
                 ("multi_member", _I64), ("low_margin", _I64)]
 
     def as_dict(self):

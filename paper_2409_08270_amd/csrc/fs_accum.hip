@@ -28,6 +28,19 @@ __device__ __forceinline__ float dpp_mov(float x)
     return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(x), CTRL, 0xF, 0xF, false));
 }
 
+// value of lane (lane ^ 8), within each 16-lane row (row rotate by 8)
+__device__ __forceinline__ float dpp_xor8(float x) { return dpp_mov<0x128>(x); }
+
+// value of lane (lane ^ 4): lanes in 4-lane banks 0 and 2 of a row take lane + 4
+// (row shift left by 4), banks 1 and 3 take lane - 4 (row shift right by 4)
+__device__ __forceinline__ float dpp_xor4(float x)
+{
+    const int xi = __float_as_int(x);
+    int r = __builtin_amdgcn_update_dpp(xi, xi, 0x104, 0xF, 0x5, false);
+    r = __builtin_amdgcn_update_dpp(r, xi, 0x114, 0xF, 0xA, false);
+    return __int_as_float(r);
+}
+
 // sum over the 64 lanes; the result is returned in every lane
 __device__ __forceinline__ float wave_sum(float x)
 {
@@ -40,6 +53,38 @@ __device__ __forceinline__ float wave_sum(float x)
     const float r2 = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(x), 32));
     const float r3 = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(x), 48));
     return (r0 + r1) + (r2 + r3);
+}
+
+// Butterfly reduce-scatter of 8 per-lane values over the 64 lanes: on return,
+// the eight lanes of octet e = lane >> 3 hold the sum over all lanes of x[e].
+// Two halvings use the gfx950 lane-swap instructions (v_permlane32_swap:
+// upper 32 lanes of the first operand <-> lower 32 lanes of the second;
+// v_permlane16_swap: odd 16-lane rows of the first <-> even rows of the
+// second), the rest are DPP lane moves (no LDS traffic). About 2.5
+// instructions per value, against 11 for a full wave sum.
+__device__ __forceinline__ float reduce_scatter8(const float (&x)[8])
+{
+    const int lane = threadIdx.x & 63;
+    float s1[4];
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+        const auto r = __builtin_amdgcn_permlane32_swap(__float_as_uint(x[k]), __float_as_uint(x[k + 4]), false, false);
+        s1[k] = __uint_as_float(r[0]) + __uint_as_float(r[1]);  // entry k + 4*bit5(lane)
+    }
+    float s2[2];
+#pragma unroll
+    for (int k = 0; k < 2; ++k) {
+        const auto r = __builtin_amdgcn_permlane16_swap(__float_as_uint(s1[k]), __float_as_uint(s1[k + 2]), false, false);
+        s2[k] = __uint_as_float(r[0]) + __uint_as_float(r[1]);  // entry k + 2*bit4 + 4*bit5
+    }
+    const bool b3 = (lane >> 3) & 1;
+    const float keep = b3 ? s2[1] : s2[0];
+    const float send = b3 ? s2[0] : s2[1];
+    float t = keep + dpp_xor8(send);                             // entry lane >> 3, 8 lanes summed
+    t += dpp_xor4(t);
+    t += dpp_mov<0xB1>(t);                                       // xor 1
+    t += dpp_mov<0x4E>(t);                                       // xor 2
+    return t;
 }
 
 __device__ __forceinline__ void add_global(float *hi, float *lo, int64_t idx, float x)
@@ -80,7 +125,8 @@ __device__ __forceinline__ bool block_hit(float u, float v, float A, float B, fl
     return qmin <= lim;
 }
 
-__global__ __launch_bounds__(256) void k_accum(const float4 *__restrict__ rec, const uint32_t *__restrict__ vals,
+template <bool PIX>
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(7, 7))) void k_accum(const float4 *__restrict__ rec, const uint32_t *__restrict__ vals,
                                                const uint2 *__restrict__ ranges, const CamDev *__restrict__ cams,
                                                int32_t n_views, const uint32_t *__restrict__ items, int64_t n,
                                                const uint8_t *__restrict__ masks, AccParams P,
@@ -88,12 +134,12 @@ __global__ __launch_bounds__(256) void k_accum(const float4 *__restrict__ rec, c
                                                float *__restrict__ t_final, int32_t *__restrict__ n_blend,
                                                unsigned long long *__restrict__ status)
 {
-    __shared__ float4 s_rec[kBatch];       // u, v, a', b' (conic scaled to log2 units)
-    __shared__ float2 s_rec2[kBatch];      // c', opacity
+    __shared__ float4 s_rec[kBatch + 1];   // u, v, a', b' (conic scaled to log2 units); [kBatch] = null
+    __shared__ float2 s_rec2[kBatch + 1];  // c', opacity
     __shared__ uint32_t s_g[kBatch];
     __shared__ float s_part[kBatch][kSlots];
     __shared__ uint8_t s_wmask[kBatch];    // bit w: wave w's 8x8 block can be reached
-    __shared__ uint8_t s_list[4][kBatch];  // per-wave compacted batch indices
+    __shared__ uint16_t s_list[4][kBatch + 16];  // per-wave compacted batch indices, padded with the null record
     __shared__ uint32_t s_bits[8];
     __shared__ int32_t s_slot_label[kSlots];
     __shared__ uint32_t s_wslots[4];
@@ -157,6 +203,10 @@ __global__ __launch_bounds__(256) void k_accum(const float4 *__restrict__ rec, c
         if (nslot > kSlots && P.reduction != FS_RED_PLAIN) atomicOr(&status[ST_FLAGS], (unsigned long long)FS_DEV_MANY_LABELS);
     }
     for (int i = tid; i < kBatch * kSlots; i += 256) (&s_part[0][0])[i] = 0.0f;
+    if (tid == 0) {  // null record: far away, zero opacity, contributes nothing
+        s_rec[kBatch] = make_float4(-1.0e6f, -1.0e6f, -1.0f, 0.0f);
+        s_rec2[kBatch] = make_float2(-1.0f, 0.0f);
+    }
 
     const uint2 rg = ranges[tile];
     const float pxc = (float)x + 0.5f, pyc = (float)y + 0.5f;
@@ -165,7 +215,9 @@ __global__ __launch_bounds__(256) void k_accum(const float4 *__restrict__ rec, c
     const float lim = -2.0f * P.cut2 / LOG2E * 1.015625f;
     const float tx0 = (float)(tx * P.tile_w), ty0 = (float)(ty * P.tile_h);
     float T = 1.0f;
-    int nb = 0, ne = 0;
+    int nb = 0;                       // per-pixel blend count (only kept for the per-pixel outputs)
+    uint32_t nb_w = 0, ne_w = 0;      // wave totals of blends and in-support evaluations (scalar)
+    uint32_t steps_w = 0;             // list entries this wave walked
     bool done = !active;
     const int64_t rec_base = (int64_t)view * n;
     const int E = P.E;
@@ -199,49 +251,82 @@ __global__ __launch_bounds__(256) void k_accum(const float4 *__restrict__ rec, c
             const int e = c * 64 + lane;
             const bool hit = (uint32_t)e < cnt && ((s_wmask[e] >> w) & 1u);
             const unsigned long long bm = __ballot(hit);
-            if (hit) s_list[w][nlist + __popcll(bm & ((1ull << lane) - 1ull))] = (uint8_t)e;
+            if (hit) s_list[w][nlist + __popcll(bm & ((1ull << lane) - 1ull))] = (uint16_t)e;
             nlist += __popcll(bm);
         }
+        if (lane < 16) s_list[w][nlist + lane] = (uint16_t)kBatch;  // pad the last group with the null record
         __builtin_amdgcn_wave_barrier();
+
+        // one front-to-back step of this lane's pixel over a staged entry (branch-free):
+        // power in log2 units via Horner, alpha, transmittance test, weight
+        auto step = [&](const float4 q, const float2 q2) -> float {
+            const float dx = pxc - q.x, dy = pyc - q.y;
+            const float pw = fmaf(fmaf(q.z, dx, q.w * dy), dx, (q2.x * dy) * dy);
+            const bool insup = pw >= P.cut2;
+            const float alpha = fminf(P.alpha_max, q2.y * __builtin_amdgcn_exp2f(pw));
+            const bool ok = !done && insup && alpha >= P.alpha_min;
+            const float Tn = fmaf(-T, alpha, T);
+            const bool stop = ok && Tn < P.t_min;
+            const bool take = ok && !stop;
+            ne_w += (uint32_t)__popcll(__ballot(!done && insup));
+            nb_w += (uint32_t)__popcll(__ballot(take));
+            if (PIX) nb += take ? 1 : 0;
+            const float wv = take ? alpha * T : 0.0f;
+            T = take ? Tn : T;
+            done = done || stop;
+            return wv;
+        };
+
         if (__ballot(!done) != 0ull) {
-            for (int it = 0; it < nlist; ++it) {
-                const uint32_t j = s_list[w][it];
-                float wgt = 0.0f;
-                if (!done) {
-                    const float4 q = s_rec[j];
-                    const float2 q2 = s_rec2[j];
-                    const float dx = pxc - q.x, dy = pyc - q.y;
-                    const float pw = (q.z * dx * dx + q2.x * dy * dy) + q.w * dx * dy;
-                    if (pw >= P.cut2) {
-                        ne++;
-                        const float alpha = fminf(P.alpha_max, q2.y * __builtin_amdgcn_exp2f(pw));
-                        if (alpha >= P.alpha_min) {
-                            const float Tn = T * (1.0f - alpha);
-                            if (Tn < P.t_min) {
-                                done = true;
-                            } else {
-                                wgt = alpha * T;
-                                T = Tn;
-                                nb++;
+            if (!plain && __popc(wslots) == 1) {
+                // single label in this wave: the weights of 8 entries are summed at once
+                const int slot0 = __ffs(wslots) - 1;
+                for (int g0 = 0; g0 < nlist; g0 += 8) {
+                    steps_w += 8;
+                    float wr[8];
+                    uint32_t jj[8];
+#pragma unroll
+                    for (int k = 0; k < 8; ++k) jj[k] = s_list[w][g0 + k];
+                    // the next entry's record is read from LDS while this one is composited
+                    float4 q = s_rec[jj[0]];
+                    float2 q2 = s_rec2[jj[0]];
+#pragma unroll
+                    for (int k = 0; k < 8; ++k) {
+                        float4 qn = q;
+                        float2 qn2 = q2;
+                        if (k + 1 < 8) {
+                            qn = s_rec[jj[k + 1]];
+                            qn2 = s_rec2[jj[k + 1]];
+                        }
+                        wr[k] = step(q, q2);
+                        q = qn;
+                        q2 = qn2;
+                    }
+                    const float tot = reduce_scatter8(wr);
+                    const int e = lane >> 3;
+                    if ((lane & 7) == 0 && g0 + e < nlist && tot != 0.0f) atomicAdd(&s_part[s_list[w][g0 + e]][slot0], tot);
+                    if (__ballot(!done) == 0ull) break;
+                }
+            } else {
+                for (int it = 0; it < nlist; ++it) {
+                    steps_w += 1;
+                    const uint32_t j = s_list[w][it];
+                    const float wgt = step(s_rec[j], s_rec2[j]);
+                    if (__ballot(wgt != 0.0f)) {
+                        if (plain) {
+                            if (wgt != 0.0f) add_global(A_hi, A_lo, (int64_t)s_g[j] * E + lab, wgt);
+                        } else {
+                            uint32_t sl = wslots;
+                            while (sl) {
+                                const int sidx = __ffs(sl) - 1;
+                                sl &= sl - 1u;
+                                const float part = wave_sum(slot == sidx ? wgt : 0.0f);
+                                if (lane == 0 && part != 0.0f) atomicAdd(&s_part[j][sidx], part);
                             }
                         }
                     }
+                    if ((it & 15) == 15 && __ballot(!done) == 0ull) break;
                 }
-                const unsigned long long any = __ballot(wgt != 0.0f);
-                if (any) {
-                    if (plain) {
-                        if (wgt != 0.0f) add_global(A_hi, A_lo, (int64_t)s_g[j] * E + lab, wgt);
-                    } else {
-                        uint32_t sl = wslots;
-                        while (sl) {
-                            const int sidx = __ffs(sl) - 1;
-                            sl &= sl - 1u;
-                            const float part = wave_sum(slot == sidx ? wgt : 0.0f);
-                            if (lane == 0 && part != 0.0f) atomicAdd(&s_part[j][sidx], part);
-                        }
-                    }
-                }
-                if ((it & 15) == 15 && __ballot(!done) == 0ull) break;
             }
         }
         __syncthreads();
@@ -260,16 +345,17 @@ __global__ __launch_bounds__(256) void k_accum(const float4 *__restrict__ rec, c
 
     if (inside) {
         if (t_final) t_final[pix] = T;
-        if (n_blend) n_blend[pix] = nb;
+        if (PIX && n_blend) n_blend[pix] = nb;
     }
-    // blend and evaluation counters: one atomic per wave
-    int tot = nb, tev = ne;
-    for (int off = 32; off > 0; off >>= 1) {
-        tot += __shfl_xor(tot, off);
-        tev += __shfl_xor(tev, off);
+    // counters: one atomic per wave; the block's largest wave walk for the balance diagnostic
+    if (lane == 0) {
+        if (nb_w) atomicAdd(&status[ST_BLENDS], (unsigned long long)nb_w);
+        if (ne_w) atomicAdd(&status[ST_EVALS], (unsigned long long)ne_w);
+        if (steps_w) atomicAdd(&status[ST_WSTEPS], (unsigned long long)steps_w);
+        atomicMax(&s_misc[1], steps_w);
     }
-    if (lane == 0 && tot) atomicAdd(&status[ST_BLENDS], (unsigned long long)tot);
-    if (lane == 0 && tev) atomicAdd(&status[ST_EVALS], (unsigned long long)tev);
+    __syncthreads();
+    if (tid == 0 && s_misc[1]) atomicAdd(&status[ST_WSTEPS_MAX], (unsigned long long)s_misc[1]);
 }
 
 }  // namespace
@@ -280,7 +366,8 @@ hipError_t launch_accumulate(hipStream_t s, const float *rec, const uint32_t *va
                              float *t_final, int32_t *n_blend, unsigned long long *status)
 {
     if (n_items == 0) return hipSuccess;
-    hipLaunchKernelGGL(k_accum, dim3(n_items), dim3(256), 0, s, reinterpret_cast<const float4 *>(rec), vals,
+    auto kern = (t_final || n_blend) ? k_accum<true> : k_accum<false>;
+    hipLaunchKernelGGL(kern, dim3(n_items), dim3(256), 0, s, reinterpret_cast<const float4 *>(rec), vals,
                        reinterpret_cast<const uint2 *>(ranges), cams_dev, n_views, items, n, masks, p, A_hi,
                        p.reduction == FS_RED_LDS2SUM ? A_lo : nullptr, t_final, n_blend, status);
     return hipGetLastError();

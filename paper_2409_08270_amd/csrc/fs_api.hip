@@ -38,6 +38,8 @@ struct fs_ctx {
     DevBuf cams;
     DevBuf dkeys, dvals, dkeys2, dvals2, counts, offsets;
     DevBuf pk_alt, pv_alt, sort_ws, scan_ws;
+    DevBuf items, items_k, items_k2, items_v2, items_ws;
+    uint64_t items_tiles = 0;  // tile count the XCD-run table was built for
     Staging stage[4];
     int stage_next = 0;
     std::string last_error;
@@ -131,6 +133,7 @@ int check_params(fs_ctx *ctx, const fs_params *p, bool for_accum)
         return set_err(ctx, FS_ERR_ARG, "need 0 <= alpha_min <= alpha_max <= 1");
     if (!finite_f(p->t_min) || p->t_min < 0.f || p->t_min >= 1.f) return set_err(ctx, FS_ERR_ARG, "need 0 <= t_min < 1");
     if (!finite_f(p->fp64_cond) || p->fp64_cond < 1.f) return set_err(ctx, FS_ERR_ARG, "fp64_cond must be >= 1");
+    if (p->tile_order < 0 || p->tile_order > 2) return set_err(ctx, FS_ERR_ARG, "tile_order must be 0, 1 or 2");
     return FS_OK;
 }
 
@@ -178,6 +181,32 @@ int build_cams(fs_ctx *ctx, const fs_camera *cams, int32_t n_views, const fs_par
     if (pixels_out) *pixels_out = px;
     if (n_views == 0) return FS_OK;
     return upload(ctx, ctx->cams, cd.data(), cd.size() * sizeof(CamDev));
+}
+
+// Work order of fs_accumulate. Workgroups are handed to the chip's 8 XCDs in
+// round-robin order of their index, and every XCD has its own L2. The table
+// maps workgroup b to tile (b % 8) * run + b / 8 (with the remainder spread
+// over the first XCDs), so XCD x composites one contiguous run of tiles: the
+// Gaussian records that neighbouring tiles share stay in one L2.
+constexpr int kXcds = 8;
+
+int build_items(fs_ctx *ctx, uint64_t n_tiles)
+{
+    if (ctx->items_tiles == n_tiles && ctx->items.p) return FS_OK;
+    ctx->items_tiles = 0;
+    std::vector<uint32_t> it((size_t)n_tiles);
+    const uint64_t base = n_tiles / kXcds, rem = n_tiles % kXcds;
+    uint64_t start[kXcds];
+    uint64_t acc = 0;
+    for (int x = 0; x < kXcds; ++x) {
+        start[x] = acc;
+        acc += base + ((uint64_t)x < rem ? 1 : 0);
+    }
+    for (uint64_t b = 0; b < n_tiles; ++b) it[b] = (uint32_t)(start[b % kXcds] + b / kXcds);
+    int rc = upload(ctx, ctx->items, it.data(), it.size() * sizeof(uint32_t));
+    if (rc) return rc;
+    ctx->items_tiles = n_tiles;
+    return FS_OK;
 }
 
 ProjParams proj_params(const fs_params *p)
@@ -247,7 +276,7 @@ void fs_params_default(fs_params *p)
     p->t_min = 1e-4f;
     p->fp64_cond = 64.0f;
     p->fp64_conic = 1;
-    p->reserved = 0;
+    p->tile_order = 0;
 }
 
 void fs_params_exact(fs_params *p)
@@ -299,7 +328,8 @@ int fs_ctx_destroy(fs_ctx *ctx)
     if (!ctx) return FS_ERR_ARG;
     (void)hipStreamSynchronize(ctx->stream);
     DevBuf *bufs[] = {&ctx->cams, &ctx->dkeys, &ctx->dvals, &ctx->dkeys2, &ctx->dvals2, &ctx->counts,
-                      &ctx->offsets, &ctx->pk_alt, &ctx->pv_alt, &ctx->sort_ws, &ctx->scan_ws};
+                      &ctx->offsets, &ctx->pk_alt, &ctx->pv_alt, &ctx->sort_ws, &ctx->scan_ws, &ctx->items,
+                      &ctx->items_k, &ctx->items_k2, &ctx->items_v2, &ctx->items_ws};
     for (DevBuf *b : bufs)
         if (b->p) (void)hipFree(b->p);
     for (int i = 0; i < 4; ++i) {
@@ -330,6 +360,8 @@ int fs_status_get(fs_ctx *ctx, fs_status *out, int32_t clear)
     out->pairs_dropped = (int64_t)h[ST_DROPPED];
     out->blends = (int64_t)h[ST_BLENDS];
     out->evaluated = (int64_t)h[ST_EVALS];
+    out->wave_steps = (int64_t)h[ST_WSTEPS];
+    out->wave_steps_max = (int64_t)h[ST_WSTEPS_MAX];
     out->unseen = (int64_t)h[ST_UNSEEN];
     out->multi_member = (int64_t)h[ST_MULTI];
     out->low_margin = (int64_t)h[ST_LOWMARGIN];
@@ -469,8 +501,27 @@ int fs_accumulate(fs_ctx *ctx, const fs_proj *proj, const fs_bins *bins, const f
     ap.tile_w = p->tile_w;
     ap.tile_h = p->tile_h;
     ap.reduction = reduction;
+    const uint32_t *items = nullptr;
+    if (p->tile_order == 0) {
+        // longest lists first, so that the longest-running workgroups start early
+        const size_t tb = (size_t)total_tiles * 4;
+        if ((rc = ensure(ctx, ctx->items, tb)) || (rc = ensure(ctx, ctx->items_k, tb)) ||
+            (rc = ensure(ctx, ctx->items_k2, tb)) || (rc = ensure(ctx, ctx->items_v2, tb)) ||
+            (rc = ensure(ctx, ctx->items_ws, radix_ws_bytes((int64_t)total_tiles, 1))))
+            return rc;
+        ctx->items_tiles = 0;  // the XCD-run table (tile_order 2) shares the buffer
+        HIPCHECK(ctx, launch_tile_keys(ctx->stream, bins->ranges, (int64_t)total_tiles, (uint32_t *)ctx->items_k.p,
+                                       (uint32_t *)ctx->items.p));
+        HIPCHECK(ctx, radix_sort(ctx->stream, (uint32_t *)ctx->items_k.p, (uint32_t *)ctx->items.p,
+                                 (uint32_t *)ctx->items_k2.p, (uint32_t *)ctx->items_v2.p, (int64_t)total_tiles, 1, 16,
+                                 ctx->items_ws.p));
+        items = (const uint32_t *)ctx->items.p;
+    } else if (p->tile_order == 2) {
+        if ((rc = build_items(ctx, total_tiles))) return rc;
+        items = (const uint32_t *)ctx->items.p;
+    }
     HIPCHECK(ctx, launch_accumulate(ctx->stream, proj->rec, bins->vals, bins->ranges, (const CamDev *)ctx->cams.p, V,
-                                    nullptr, (uint32_t)total_tiles, proj->n, masks, ap, A_hi,
+                                    items, (uint32_t)total_tiles, proj->n, masks, ap, A_hi,
                                     reduction == FS_RED_LDS2SUM ? A_lo : nullptr, pix ? pix->t_final : nullptr,
                                     pix ? pix->n_blend : nullptr, ctx->status_dev));
     return FS_OK;

@@ -43,6 +43,8 @@ enum StatusIdx {
     ST_LOWMARGIN,
     ST_PAIRS,       // total pairs of the last bin_sort (device-side count)
     ST_EVALS,
+    ST_WSTEPS,      // list entries walked, summed over waves (diagnostic)
+    ST_WSTEPS_MAX,  // per tile, the longest walk of its waves, summed over tiles (diagnostic)
     ST_COUNT = 16
 };
 
@@ -82,6 +84,9 @@ hipError_t launch_emit(hipStream_t s, const uint32_t *sorted_keys, const uint32_
                        const uint8_t *flags, const CamDev *cams_dev, int64_t n, int32_t n_views, uint32_t capacity,
                        int32_t tile_w, int32_t tile_h, float sigma_k, uint32_t *tiles_out, uint32_t *vals_out,
                        unsigned long long *status);
+
+// keys[t] = 65535 - min(list length of tile t, 65535), vals[t] = t
+hipError_t launch_tile_keys(hipStream_t s, const uint32_t *ranges, int64_t n_tiles, uint32_t *keys, uint32_t *vals);
 
 hipError_t launch_ranges(hipStream_t s, const uint32_t *tiles, const uint32_t *n_pairs_dev,
                          uint32_t capacity, int64_t n_pairs_max, uint32_t *ranges);

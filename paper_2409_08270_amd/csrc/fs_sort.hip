@@ -365,6 +365,19 @@ __global__ void k_ranges(const uint32_t *__restrict__ tiles, const uint32_t *__r
     if (i == (int64_t)np - 1 || tiles[i + 1] != t) ranges[t].y = (uint32_t)(i + 1);
 }
 
+// Work-order keys: tiles with longer lists get smaller keys (lengths clamp
+// at 65535), so an ascending stable sort puts the longest lists first.
+__global__ void k_tile_keys(const uint2 *__restrict__ ranges, int64_t n_tiles, uint32_t *__restrict__ keys,
+                            uint32_t *__restrict__ vals)
+{
+    int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= n_tiles) return;
+    const uint2 r = ranges[t];
+    const uint32_t len = r.y - r.x;
+    keys[t] = 0xFFFFu - (len < 0xFFFFu ? len : 0xFFFFu);
+    vals[t] = (uint32_t)t;
+}
+
 inline unsigned grid_for(int64_t n, int threads) { return (unsigned)((n + threads - 1) / threads); }
 
 }  // namespace
@@ -475,6 +488,14 @@ hipError_t launch_emit(hipStream_t s, const uint32_t *sorted_keys, const uint32_
     hipLaunchKernelGGL(k_emit, dim3(grid_for(total, kThreads)), dim3(kThreads), 0, s, sorted_keys, sorted_vals, offsets,
                        counts, reinterpret_cast<const float4 *>(rec), reinterpret_cast<const short4 *>(rect), flags,
                        cams_dev, total, n, capacity, tile_w, tile_h, sigma_k, tiles_out, vals_out, status);
+    return hipGetLastError();
+}
+
+hipError_t launch_tile_keys(hipStream_t s, const uint32_t *ranges, int64_t n_tiles, uint32_t *keys, uint32_t *vals)
+{
+    if (n_tiles <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_tile_keys, dim3(grid_for(n_tiles, 256)), dim3(256), 0, s,
+                       reinterpret_cast<const uint2 *>(ranges), n_tiles, keys, vals);
     return hipGetLastError();
 }
 
