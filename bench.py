@@ -31,8 +31,10 @@ def parse():
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--config", default="C2")
-    ap.add_argument("--cpu-views", type=int, default=2, help="views of the CPU oracle sample (0: skip)")
+    ap.add_argument("--cpu-views", type=int, default=24, help="views of the CPU oracle sample (0: skip)")
     ap.add_argument("--no-plain", action="store_true")
+    ap.add_argument("--no-strategies", action="store_true",
+                    help="skip the per-strategy compositing comparison (keeps one launch shape per kernel)")
     ap.add_argument("--copy-probe", type=int, default=0, metavar="MIB",
                     help="only run a device-to-device copy of this many MiB (HBM counter calibration)")
     return ap.parse_args()
@@ -78,46 +80,59 @@ def main():
     ctx = L.Context()
     V = sc.n_views
 
-    # ---- batched (all views per call) --------------------------------------
-    acc_ms = []
-    solver = Solver(ctx, ds)
-
-    def step_batched(record):
-        ev = (torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) if record else None
-        out = solver.solve(chunk=V, want_margin=False, acc_events=ev)
-        if record:
-            ev[1].synchronize()
-            acc_ms.append(ev[0].elapsed_time(ev[1]))
-        return out
-
+    # ---- batched: the whole solve (all views, assignment included) as one graph launch ----
+    prm = L.params()
+    batch = L.Batch(ctx, [ds], prm, gammas=[0.0])
+    binfo = batch.info()
+    print(f"[bench] batch planned: {binfo}", file=sys.stderr, flush=True)
     for _ in range(args.warmup):
-        step_batched(False)
+        batch.run()
+    torch.cuda.synchronize()
     ctx.status()
     torch.cuda.synchronize()
     t = time.perf_counter()
     for _ in range(args.steps):
-        out = step_batched(True)
+        batch.run()
     torch.cuda.synchronize()
     dt_b = (time.perf_counter() - t) / args.steps
     st = ctx.status()
     blends = st["blends"] / args.steps
     evals = st["evaluated"] / args.steps
-    pairs = sum(out["pairs"])
+    pairs = binfo["pairs"]
     wsteps, wsteps_max = st["wave_steps"] / args.steps, st["wave_steps_max"] / args.steps
-    print(f"[bench] batched: {dt_b * 1e3:.2f} ms/step, pairs {pairs}, blends {blends:.3e}, evaluated {evals:.3e}, "
-          f"accumulate kernel {np.mean(acc_ms):.3f} ms; wave steps {wsteps:.3e}, 4 x per-tile max {4 * wsteps_max:.3e}",
-          file=sys.stderr, flush=True)
+
+    # ---- the compositing kernel alone, same launch as inside the graph, timed with HIP events
+    # recorded on the stream it runs on
+    solver = Solver(ctx, ds, prm)
+    solver.solve(chunk=V, want_margin=False)
+    cams, nv = ds.cams()
+    n, E = sc.n, sc.E
+    A_hi = torch.zeros((n, E), dtype=torch.float32, device="cuda")
+    A_lo = torch.zeros((n, E), dtype=torch.float32, device="cuda")
+    acc_ms = []
+    ctx.status()
+    for _ in range(args.steps):
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(ctx.stream)
+        ctx.fs_accumulate(solver.proj, solver.bins, cams, ds.masks, E, prm, A_hi, A_lo, L.FS_RED_LDS2SUM)
+        e1.record(ctx.stream)
+        e1.synchronize()
+        acc_ms.append(e0.elapsed_time(e1))
+    st_acc = ctx.status()
+    assert st_acc["blends"] == st["blends"], "standalone compositing saw different work than the graph"
+    print(f"[bench] batched graph: {dt_b * 1e3:.2f} ms/step, pairs {pairs}, blends {blends:.3e}, "
+          f"evaluated {evals:.3e}, accumulate kernel {np.mean(acc_ms):.3f} ms; wave steps {wsteps:.3e}, "
+          f"4 x per-tile max {4 * wsteps_max:.3e}", file=sys.stderr, flush=True)
 
     # ---- compositing kernel alone, per reduction strategy (same bins) --------
     strat = {}
-    cams, nv = ds.cams()
     prm_lin = L.params(tile_order=1)
     prm_xcd = L.params(tile_order=2)
-    for name, red, comp, prm in (("plain_atomics", L.FS_RED_PLAIN, False, solver.prm),
-                                 ("lds", L.FS_RED_LDS, False, solver.prm),
-                                 ("lds_two_sum", L.FS_RED_LDS2SUM, True, solver.prm),
+    for name, red, comp, prm_s in (() if args.no_strategies else (("plain_atomics", L.FS_RED_PLAIN, False, prm),
+                                 ("lds", L.FS_RED_LDS, False, prm),
+                                 ("lds_two_sum", L.FS_RED_LDS2SUM, True, prm),
                                  ("lds_two_sum_linear_order", L.FS_RED_LDS2SUM, True, prm_lin),
-                                 ("lds_two_sum_xcd_runs", L.FS_RED_LDS2SUM, True, prm_xcd)):
+                                 ("lds_two_sum_xcd_runs", L.FS_RED_LDS2SUM, True, prm_xcd))):
         n, E = sc.n, sc.E
         A_hi = torch.zeros((n, E), dtype=torch.float32, device="cuda")
         A_lo = torch.zeros((n, E), dtype=torch.float32, device="cuda") if comp else None
@@ -125,7 +140,7 @@ def main():
         for _ in range(3):
             e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
             e0.record(ctx.stream)
-            ctx.fs_accumulate(solver.proj, solver.bins, cams, ds.masks, E, prm, A_hi, A_lo, red)
+            ctx.fs_accumulate(solver.proj, solver.bins, cams, ds.masks, E, prm_s, A_hi, A_lo, red)
             e1.record(ctx.stream)
             e1.synchronize()
             ts.append(e0.elapsed_time(e1))
@@ -205,8 +220,8 @@ def main():
         "dtype": "f32",
         "data": "synthetic",
         "config": {"workload": f"{args.config}: {sc.n} Gaussians (4 clusters + shell), {V} views "
-                               f"{int(sc.W[0])}x{int(sc.H[0])}, E={sc.E}, gamma=0", "mode": "batched",
-                   "reduction": "lds+two-sum"},
+                               f"{int(sc.W[0])}x{int(sc.H[0])}, E={sc.E}, gamma=0", "mode": "batched, one hipGraph",
+                   "reduction": "lds+two-sum", "chunks": binfo["n_chunks"]},
         "blends_per_sec": blends / dt_b,
         "pairs_per_step": pairs,
         "plain_views_per_sec": (V / dt_p) if dt_p else None,

@@ -222,6 +222,59 @@ int fs_accumulate(fs_ctx *ctx, const fs_proj *proj, const fs_bins *bins, const f
 int fs_assign(fs_ctx *ctx, const float *A_hi, const float *A_lo, int64_t n, int32_t n_classes,
               float gamma, uint8_t *S, float *margin);
 
+/* Batched solve ------------------------------------------------------------
+ * Many scenes of uneven size, all their views, in one graph launch: the
+ * splat-and-accumulate pass is a sum over views (Eq. (6)), so views of all
+ * scenes are projected, binned and composited together, in chunks that fit a
+ * bounded workspace, and every scene's assignment follows (Eq. (7)).
+ * fs_batch_create plans the work (one exact counting pass and one read-back of
+ * the per-view pair counts), allocates the workspace and captures the whole
+ * solve into a hipGraph; fs_batch_run replays it on the context's stream.
+ * The buffers named in the scene descriptors are borrowed: they must stay
+ * valid and keep their addresses until fs_batch_destroy. If the inputs change
+ * so that a chunk needs more pairs than planned, the excess is dropped and
+ * FS_DEV_PAIR_OVERFLOW is latched; create a new batch then. */
+typedef struct fs_batch fs_batch;
+
+typedef struct {
+    fs_gaussians gauss;        /* device */
+    const fs_camera *cams;     /* host [n_views] (copied at creation) */
+    int32_t n_views;
+    const uint8_t *masks;      /* device, this scene's views concatenated */
+    int32_t n_classes;         /* [2, 256] */
+    float *A_hi;               /* device float32 [n][n_classes] */
+    float *A_lo;               /* device float32 [n][n_classes], or NULL */
+    uint8_t *S;                /* device uint8 [n_classes][n], or NULL to skip the assignment */
+    float *margin;             /* device float32 [n_classes][n], or NULL */
+    float gamma;               /* background bias in [-1, 1] */
+} fs_scene;
+
+typedef struct {
+    int64_t pair_budget;       /* max tile pairs per chunk (0: 2^28) */
+    int64_t elem_budget;       /* max (Gaussian, view) elements per chunk (0: 2^26) */
+    int32_t zero_accumulators; /* 1: each run starts from A = 0 (default 1) */
+    int32_t use_graph;         /* 1 (default): capture into a hipGraph; 0: enqueue the kernels per run */
+    int32_t reduction;         /* FS_RED_* for the compositing (default FS_RED_AUTO) */
+    int32_t reserved;
+} fs_batch_opts;
+
+typedef struct {
+    int32_t n_chunks;
+    int32_t n_views;
+    int64_t pairs;             /* tile pairs planned, all chunks */
+    int64_t pair_capacity;     /* pair slots of the workspace (largest chunk plus slack) */
+    int64_t elements;          /* (Gaussian, view) elements, all chunks */
+    int64_t tiles;             /* tiles, all chunks */
+    int64_t workspace_bytes;   /* device memory held by the batch */
+} fs_batch_info;
+
+void fs_batch_opts_default(fs_batch_opts *o);
+int fs_batch_create(fs_ctx *ctx, const fs_scene *scenes, int32_t n_scenes, const fs_params *p,
+                    const fs_batch_opts *opts, fs_batch **out);
+int fs_batch_run(fs_batch *b);
+int fs_batch_get_info(fs_batch *b, fs_batch_info *out);
+int fs_batch_destroy(fs_batch *b);
+
 #ifdef __cplusplus
 }
 #endif

@@ -77,10 +77,29 @@ class FsStatus(ctypes.Structure):
         return {k: int(getattr(self, k)) for k, _ in self._fields_}
 
 
+class FsScene(ctypes.Structure):
+    _fields_ = [("gauss", FsGaussians), ("cams", ctypes.POINTER(FsCamera)), ("n_views", _I32), ("masks", _P),
+                ("n_classes", _I32), ("A_hi", _P), ("A_lo", _P), ("S", _P), ("margin", _P), ("gamma", _F)]
+
+
+class FsBatchOpts(ctypes.Structure):
+    _fields_ = [("pair_budget", _I64), ("elem_budget", _I64), ("zero_accumulators", _I32), ("use_graph", _I32),
+                ("reduction", _I32), ("reserved", _I32)]
+
+
+class FsBatchInfo(ctypes.Structure):
+    _fields_ = [("n_chunks", _I32), ("n_views", _I32), ("pairs", _I64), ("pair_capacity", _I64),
+                ("elements", _I64), ("tiles", _I64), ("workspace_bytes", _I64)]
+
+    def as_dict(self):
+        return {k: int(getattr(self, k)) for k, _ in self._fields_}
+
+
 # every symbol the header declares (checked by the CPU test)
 EXPORTS = ["fs_version", "fs_error_string", "fs_params_default", "fs_params_exact", "fs_ctx_create",
            "fs_ctx_set_stream", "fs_ctx_destroy", "fs_ctx_last_error", "fs_status_get", "fs_project",
-           "fs_bin_sort", "fs_accumulate", "fs_assign"]
+           "fs_bin_sort", "fs_accumulate", "fs_assign", "fs_batch_opts_default", "fs_batch_create",
+           "fs_batch_run", "fs_batch_get_info", "fs_batch_destroy"]
 
 _lib = None
 
@@ -111,6 +130,12 @@ def load(path: str = LIB_PATH):
         "fs_accumulate": ([_P, ctypes.POINTER(FsProj), ctypes.POINTER(FsBins), ctypes.POINTER(FsCamera), _P, _I32,
                            ctypes.POINTER(FsParams), _P, _P, _I32, ctypes.POINTER(FsPixelOut)], _I32),
         "fs_assign": ([_P, _P, _P, _I64, _I32, _F, _P, _P], _I32),
+        "fs_batch_opts_default": ([ctypes.POINTER(FsBatchOpts)], None),
+        "fs_batch_create": ([_P, ctypes.POINTER(FsScene), _I32, ctypes.POINTER(FsParams),
+                             ctypes.POINTER(FsBatchOpts), ctypes.POINTER(_P)], _I32),
+        "fs_batch_run": ([_P], _I32),
+        "fs_batch_get_info": ([_P, ctypes.POINTER(FsBatchInfo)], _I32),
+        "fs_batch_destroy": ([_P], _I32),
     }
     for name, (args, res) in sig.items():
         f = getattr(L, name)
@@ -280,3 +305,65 @@ class Bins:
 
     def struct(self) -> FsBins:
         return FsBins(_ptr(self.vals), _ptr(self.tiles), _ptr(self.ranges), self.capacity)
+
+
+def batch_opts(**over) -> FsBatchOpts:
+    o = FsBatchOpts()
+    load().fs_batch_opts_default(ctypes.byref(o))
+    for k, v in over.items():
+        setattr(o, k, v)
+    return o
+
+
+class Batch:
+    """An fs_batch: many scenes solved by one graph launch.
+
+    `scenes` are DeviceScene objects; the accumulators (A_hi, A_lo [n][E]),
+    labels S [E][n] and optional margins are allocated here and borrowed by
+    the library until close(). `gammas` gives one background bias per scene.
+    """
+
+    def __init__(self, ctx: Context, scenes: Sequence["DeviceScene"], prm: FsParams,
+                 gammas: Optional[Sequence[float]] = None, compensated: bool = True, want_labels: bool = True,
+                 want_margin: bool = False, **opts):
+        self.ctx = ctx
+        self.L = ctx.L
+        self.scenes = list(scenes)
+        dev = ctx.stream.device
+        self.A_hi, self.A_lo, self.S, self.margin, self._cams = [], [], [], [], []
+        arr = (FsScene * len(self.scenes))()
+        for i, ds in enumerate(self.scenes):
+            n, E = ds.n, ds.E
+            self.A_hi.append(torch.zeros((n, E), dtype=torch.float32, device=dev))
+            self.A_lo.append(torch.zeros((n, E), dtype=torch.float32, device=dev) if compensated else None)
+            self.S.append(torch.zeros((E, n), dtype=torch.uint8, device=dev) if want_labels else None)
+            self.margin.append(torch.zeros((E, n), dtype=torch.float32, device=dev) if want_margin else None)
+            cams, nv = ds.cams()
+            self._cams.append(cams)
+            g = 0.0 if gammas is None else float(gammas[i])
+            arr[i] = FsScene(ds.struct(), ctypes.cast(cams, ctypes.POINTER(FsCamera)), nv, _ptr(ds.masks), E,
+                             _ptr(self.A_hi[i]), _ptr(self.A_lo[i]), _ptr(self.S[i]), _ptr(self.margin[i]), g)
+        o = batch_opts(**opts)
+        h = _P()
+        ctx._check(self.L.fs_batch_create(ctx.h, arr, len(self.scenes), ctypes.byref(prm), ctypes.byref(o),
+                                          ctypes.byref(h)))
+        self.h = h
+
+    def run(self):
+        self.ctx._check(self.L.fs_batch_run(self.h))
+
+    def info(self) -> dict:
+        inf = FsBatchInfo()
+        self.ctx._check(self.L.fs_batch_get_info(self.h, ctypes.byref(inf)))
+        return inf.as_dict()
+
+    def close(self):
+        if getattr(self, "h", None) is not None:
+            self.L.fs_batch_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

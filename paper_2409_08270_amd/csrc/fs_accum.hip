@@ -127,10 +127,9 @@ __device__ __forceinline__ bool block_hit(float u, float v, float A, float B, fl
 
 template <bool PIX>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(7, 7))) void k_accum(const float4 *__restrict__ rec, const uint32_t *__restrict__ vals,
-                                               const uint2 *__restrict__ ranges, const CamDev *__restrict__ cams,
-                                               int32_t n_views, const uint32_t *__restrict__ items, int64_t n,
-                                               const uint8_t *__restrict__ masks, AccParams P,
-                                               float *__restrict__ A_hi, float *__restrict__ A_lo,
+                                               const uint2 *__restrict__ ranges, const ViewDev *__restrict__ views,
+                                               int32_t n_views, const SceneDev *__restrict__ scenes,
+                                               const uint32_t *__restrict__ items, AccParams P,
                                                float *__restrict__ t_final, int32_t *__restrict__ n_blend,
                                                unsigned long long *__restrict__ status)
 {
@@ -146,14 +145,13 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(7, 7))) voi
     __shared__ uint32_t s_misc[2];
 
     const uint32_t tile = items ? items[blockIdx.x] : blockIdx.x;
-    // view of this tile: last view whose tile_base <= tile
-    int lo = 0, hi = n_views - 1;
-    while (lo < hi) {
-        const int mid = (lo + hi + 1) >> 1;
-        if (cams[mid].tile_base <= tile) lo = mid; else hi = mid - 1;
-    }
-    const int view = lo;
-    const CamDev &C = cams[view];
+    const int view = find_view_of_tile(views, n_views, tile);
+    const ViewDev &C = views[view];
+    const SceneDev &SC = scenes[C.scene];
+    const uint8_t *__restrict__ masks = SC.masks;
+    float *__restrict__ A_hi = SC.A_hi;
+    float *__restrict__ A_lo = P.reduction == FS_RED_LDS2SUM ? SC.A_lo : nullptr;
+    const int E = SC.E;
     const uint32_t local = tile - C.tile_base;
     const int tx = (int)(local % (uint32_t)C.tiles_x), ty = (int)(local / (uint32_t)C.tiles_x);
 
@@ -162,13 +160,13 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(7, 7))) voi
     const int x = tx * P.tile_w + (w % bpr) * 8 + (lane & 7);
     const int y = ty * P.tile_h + (w / bpr) * 8 + (lane >> 3);
     const bool inside = x < C.W && y < C.H;
-    const int64_t pix = (int64_t)C.mask_off + (int64_t)y * C.W + x;
+    const int64_t pix = (int64_t)C.mask_off + (int64_t)y * C.W + x;  // within the scene's masks
 
     int lab = 0;
     bool active = inside;
     if (inside) {
         lab = masks[pix];
-        if (lab >= P.E) active = false;
+        if (lab >= E) active = false;
     }
     if (tid < 8) s_bits[tid] = 0;
     if (tid < 4) s_wslots[tid] = 0;
@@ -219,8 +217,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(7, 7))) voi
     uint32_t nb_w = 0, ne_w = 0;      // wave totals of blends and in-support evaluations (scalar)
     uint32_t steps_w = 0;             // list entries this wave walked
     bool done = !active;
-    const int64_t rec_base = (int64_t)view * n;
-    const int E = P.E;
+    const int64_t rec_base = (int64_t)C.elem_off;
 
     for (uint32_t base = rg.x; base < rg.y; base += kBatch) {
         const uint32_t cnt = min((uint32_t)kBatch, rg.y - base);
@@ -361,15 +358,15 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(7, 7))) voi
 }  // namespace
 
 hipError_t launch_accumulate(hipStream_t s, const float *rec, const uint32_t *vals, const uint32_t *ranges,
-                             const CamDev *cams_dev, int32_t n_views, const uint32_t *items, uint32_t n_items,
-                             int64_t n, const uint8_t *masks, const AccParams &p, float *A_hi, float *A_lo,
-                             float *t_final, int32_t *n_blend, unsigned long long *status)
+                             const ViewDev *views, int32_t n_views, const SceneDev *scenes, const uint32_t *items,
+                             uint32_t n_items, const AccParams &p, float *t_final, int32_t *n_blend,
+                             unsigned long long *status)
 {
     if (n_items == 0) return hipSuccess;
     auto kern = (t_final || n_blend) ? k_accum<true> : k_accum<false>;
     hipLaunchKernelGGL(kern, dim3(n_items), dim3(256), 0, s, reinterpret_cast<const float4 *>(rec), vals,
-                       reinterpret_cast<const uint2 *>(ranges), cams_dev, n_views, items, n, masks, p, A_hi,
-                       p.reduction == FS_RED_LDS2SUM ? A_lo : nullptr, t_final, n_blend, status);
+                       reinterpret_cast<const uint2 *>(ranges), views, n_views, scenes, items, p, t_final, n_blend,
+                       status);
     return hipGetLastError();
 }
 

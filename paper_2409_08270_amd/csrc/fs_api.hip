@@ -1,10 +1,18 @@
-// C ABI of the library: context, argument validation, workspace and the four
-// calls of the splat-and-accumulate path (declared in include/flashsplat.h).
+// C ABI of the library (include/flashsplat.h): context, argument validation,
+// workspace, the four calls of the splat-and-accumulate path and the batched
+// multi-scene solve captured into a hipGraph.
+//
+// All calls share one planning step: the views of the call (of one scene for
+// the single-scene calls, of many for a batch) are laid out in small device
+// tables (ViewDev, SceneDev, projection tasks, sort segments) that the kernels
+// index; see fs_internal.h.
 #include <math.h>
 #include <stdarg.h>
 #include <stdio.h>
 #include <string.h>
 
+#include <algorithm>
+#include <new>
 #include <string>
 #include <vector>
 
@@ -26,6 +34,8 @@ struct Staging {
     bool pending = false;
 };
 
+constexpr int kStaging = 8;
+
 }  // namespace
 
 struct fs_ctx {
@@ -35,12 +45,14 @@ struct fs_ctx {
     unsigned long long *status_host = nullptr;  // pinned
     uint32_t *npairs_dev = nullptr;
     uint32_t *npairs_host = nullptr;            // pinned
-    DevBuf cams;
+    // per-call tables
+    DevBuf views, scenes, tasks, dsegs, psegs, lsegs;
+    // per-call workspace (grow-only)
     DevBuf dkeys, dvals, dkeys2, dvals2, counts, offsets;
     DevBuf pk_alt, pv_alt, sort_ws, scan_ws;
     DevBuf items, items_k, items_k2, items_v2, items_ws;
-    uint64_t items_tiles = 0;  // tile count the XCD-run table was built for
-    Staging stage[4];
+    uint64_t items_tiles = 0;  // tile count the XCD-run table in `items` was built for
+    Staging stage[kStaging];
     int stage_next = 0;
     std::string last_error;
 };
@@ -67,33 +79,49 @@ int set_err(fs_ctx *ctx, int code, const char *fmt, ...)
             return set_err((ctx), FS_ERR_HIP, "%s failed: %s", #expr, hipGetErrorString(_e));    \
     } while (0)
 
-int ensure(fs_ctx *ctx, DevBuf &b, size_t bytes)
+#define RCHECK(expr)            \
+    do {                        \
+        int _rc = (expr);       \
+        if (_rc) return _rc;    \
+    } while (0)
+
+int alloc_buf(fs_ctx *ctx, DevBuf &b, size_t bytes)
 {
-    if (bytes <= b.cap) return FS_OK;
     if (b.p) {
-        // the stream may still use the old buffer
-        HIPCHECK(ctx, hipStreamSynchronize(ctx->stream));
+        HIPCHECK(ctx, hipStreamSynchronize(ctx->stream));  // the stream may still use the old buffer
         HIPCHECK(ctx, hipFree(b.p));
         b.p = nullptr;
         b.cap = 0;
     }
-    size_t want = bytes + bytes / 4 + 4096;
-    if (hipMalloc(&b.p, want) != hipSuccess) {
+    if (hipMalloc(&b.p, bytes) != hipSuccess) {
         b.p = nullptr;
-        return set_err(ctx, FS_ERR_ALLOC, "device allocation of %zu bytes failed", want);
+        return set_err(ctx, FS_ERR_ALLOC, "device allocation of %zu bytes failed", bytes);
     }
-    b.cap = want;
+    b.cap = bytes;
     return FS_OK;
+}
+
+int ensure(fs_ctx *ctx, DevBuf &b, size_t bytes)
+{
+    if (bytes <= b.cap && b.p) return FS_OK;
+    return alloc_buf(ctx, b, bytes + bytes / 4 + 4096);
+}
+
+void free_buf(DevBuf &b)
+{
+    if (b.p) (void)hipFree(b.p);
+    b.p = nullptr;
+    b.cap = 0;
 }
 
 // Copies host bytes to a device buffer asynchronously through a ring of
 // pinned staging buffers (a slot is reused only after its copy completed).
 int upload(fs_ctx *ctx, DevBuf &dst, const void *src, size_t bytes)
 {
-    int rc = ensure(ctx, dst, bytes);
-    if (rc) return rc;
+    RCHECK(ensure(ctx, dst, bytes));
+    if (bytes == 0) return FS_OK;
     Staging &st = ctx->stage[ctx->stage_next];
-    ctx->stage_next = (ctx->stage_next + 1) % 4;
+    ctx->stage_next = (ctx->stage_next + 1) % kStaging;
     if (st.pending) {
         HIPCHECK(ctx, hipEventSynchronize(st.ev));
         st.pending = false;
@@ -112,6 +140,12 @@ int upload(fs_ctx *ctx, DevBuf &dst, const void *src, size_t bytes)
     HIPCHECK(ctx, hipEventRecord(st.ev, ctx->stream));
     st.pending = true;
     return FS_OK;
+}
+
+template <class T>
+int upload_vec(fs_ctx *ctx, DevBuf &dst, const std::vector<T> &v)
+{
+    return upload(ctx, dst, v.data(), v.size() * sizeof(T));
 }
 
 bool finite_f(float x) { return isfinite(x); }
@@ -155,58 +189,32 @@ int check_cams(fs_ctx *ctx, const fs_camera *cams, int32_t n_views)
     return FS_OK;
 }
 
-// Device camera table; returns the total number of tiles and pixels.
-int build_cams(fs_ctx *ctx, const fs_camera *cams, int32_t n_views, const fs_params *p, uint64_t *tiles_out,
-               uint64_t *pixels_out)
+int check_gauss(fs_ctx *ctx, const fs_gaussians *g)
 {
-    std::vector<CamDev> cd((size_t)n_views);
-    uint64_t tb = 0, px = 0;
-    for (int v = 0; v < n_views; ++v) {
-        const fs_camera &c = cams[v];
-        CamDev &d = cd[v];
-        memcpy(d.R, c.R, sizeof(d.R));
-        memcpy(d.t, c.t, sizeof(d.t));
-        d.fx = c.fx; d.fy = c.fy; d.cx = c.cx; d.cy = c.cy;
-        d.W = c.width; d.H = c.height;
-        d.tiles_x = (c.width + p->tile_w - 1) / p->tile_w;
-        d.tiles_y = (c.height + p->tile_h - 1) / p->tile_h;
-        d.tile_base = (uint32_t)tb;
-        d.pad = 0;
-        d.mask_off = px;
-        tb += (uint64_t)d.tiles_x * d.tiles_y;
-        px += (uint64_t)c.width * c.height;
-    }
-    if (tb >= 0xFFFFFFFFull) return set_err(ctx, FS_ERR_ARG, "too many tiles in one call (%llu)", (unsigned long long)tb);
-    if (tiles_out) *tiles_out = tb;
-    if (pixels_out) *pixels_out = px;
-    if (n_views == 0) return FS_OK;
-    return upload(ctx, ctx->cams, cd.data(), cd.size() * sizeof(CamDev));
+    if (!g) return set_err(ctx, FS_ERR_ARG, "Gaussians are NULL");
+    if (g->n < 0 || g->n >= 0xFFFFFFFFll) return set_err(ctx, FS_ERR_ARG, "Gaussian count %lld out of range", (long long)g->n);
+    if (g->n > 0 && (!g->mx || !g->my || !g->mz || !g->qw || !g->qx || !g->qy || !g->qz || !g->sx || !g->sy ||
+                     !g->sz || !g->opacity))
+        return set_err(ctx, FS_ERR_ARG, "Gaussian array is NULL");
+    return FS_OK;
 }
 
-// Work order of fs_accumulate. Workgroups are handed to the chip's 8 XCDs in
-// round-robin order of their index, and every XCD has its own L2. The table
-// maps workgroup b to tile (b % 8) * run + b / 8 (with the remainder spread
-// over the first XCDs), so XCD x composites one contiguous run of tiles: the
-// Gaussian records that neighbouring tiles share stay in one L2.
-constexpr int kXcds = 8;
-
-int build_items(fs_ctx *ctx, uint64_t n_tiles)
+int check_proj(fs_ctx *ctx, const fs_proj *pr)
 {
-    if (ctx->items_tiles == n_tiles && ctx->items.p) return FS_OK;
-    ctx->items_tiles = 0;
-    std::vector<uint32_t> it((size_t)n_tiles);
-    const uint64_t base = n_tiles / kXcds, rem = n_tiles % kXcds;
-    uint64_t start[kXcds];
-    uint64_t acc = 0;
-    for (int x = 0; x < kXcds; ++x) {
-        start[x] = acc;
-        acc += base + ((uint64_t)x < rem ? 1 : 0);
-    }
-    for (uint64_t b = 0; b < n_tiles; ++b) it[b] = (uint32_t)(start[b % kXcds] + b / kXcds);
-    int rc = upload(ctx, ctx->items, it.data(), it.size() * sizeof(uint32_t));
-    if (rc) return rc;
-    ctx->items_tiles = n_tiles;
+    if (!pr) return set_err(ctx, FS_ERR_ARG, "proj is NULL");
+    if (pr->n < 0 || pr->n_views < 0) return set_err(ctx, FS_ERR_ARG, "proj sizes negative");
+    if (pr->n >= 0xFFFFFFFFll) return set_err(ctx, FS_ERR_ARG, "too many Gaussians (%lld)", (long long)pr->n);
+    if ((int64_t)pr->n * pr->n_views >= 0xFFFFFFFFll) return set_err(ctx, FS_ERR_ARG, "n * n_views too large for one call");
+    if (pr->n > 0 && pr->n_views > 0 && (!pr->rec || !pr->rect || !pr->ntiles || !pr->flags))
+        return set_err(ctx, FS_ERR_ARG, "proj has NULL planes");
     return FS_OK;
+}
+
+int bits_for(uint64_t count)
+{
+    int b = 1;
+    while (b < 32 && (1ull << b) < count) ++b;
+    return b;
 }
 
 ProjParams proj_params(const fs_params *p)
@@ -223,30 +231,137 @@ ProjParams proj_params(const fs_params *p)
     return q;
 }
 
-int check_proj(fs_ctx *ctx, const fs_proj *pr)
+AccParams acc_params(const fs_params *p, int32_t reduction)
 {
-    if (!pr) return set_err(ctx, FS_ERR_ARG, "proj is NULL");
-    if (pr->n < 0 || pr->n_views < 0) return set_err(ctx, FS_ERR_ARG, "proj sizes negative");
-    if (pr->n >= 0xFFFFFFFFll) return set_err(ctx, FS_ERR_ARG, "too many Gaussians (%lld)", (long long)pr->n);
-    if ((int64_t)pr->n * pr->n_views >= 0x7FFFFFFFll * 2)
-        return set_err(ctx, FS_ERR_ARG, "n * n_views too large for one call");
-    if (pr->n > 0 && pr->n_views > 0 && (!pr->rec || !pr->rect || !pr->ntiles || !pr->flags))
-        return set_err(ctx, FS_ERR_ARG, "proj has NULL planes");
+    AccParams ap;
+    const double LOG2E = 1.4426950408889634;
+    ap.cut2 = (float)(-0.5 * (double)p->sigma_k * (double)p->sigma_k * LOG2E);
+    ap.alpha_min = p->alpha_min;
+    ap.alpha_max = p->alpha_max;
+    ap.t_min = p->t_min;
+    ap.tile_w = p->tile_w;
+    ap.tile_h = p->tile_h;
+    ap.reduction = reduction;
+    ap.pad = 0;
+    return ap;
+}
+
+GaussPtrs gauss_ptrs(const fs_gaussians *g)
+{
+    GaussPtrs gp{nullptr, nullptr, nullptr, nullptr, nullptr, nullptr, nullptr, nullptr, nullptr, nullptr, nullptr};
+    if (g) gp = GaussPtrs{g->mx, g->my, g->mz, g->qw, g->qx, g->qy, g->qz, g->sx, g->sy, g->sz, g->opacity};
+    return gp;
+}
+
+// ---- planning -------------------------------------------------------------
+// Host tables for a run of views (one call, or one chunk of a batch).
+struct Plan {
+    std::vector<ViewDev> views;
+    std::vector<ProjTask> tasks;
+    std::vector<SegDev> dsegs;     // depth sort: one segment per view
+    uint32_t proj_blocks = 0;
+    uint32_t dblocks = 0;
+    uint64_t elems = 0;
+    uint64_t tiles = 0;
+};
+
+// Appends views [v0, v1) of a scene with n Gaussians; mask_off0 is the mask
+// offset of view v0 within the scene's masks.
+void plan_add(Plan &pl, const fs_params *p, uint32_t scene, int64_t n, const fs_camera *cams, int v0, int v1,
+              uint64_t mask_off0)
+{
+    uint64_t moff = mask_off0;
+    const int first = (int)pl.views.size();
+    for (int v = v0; v < v1; ++v) {
+        const fs_camera &c = cams[v];
+        ViewDev d;
+        memcpy(d.R, c.R, sizeof(d.R));
+        memcpy(d.t, c.t, sizeof(d.t));
+        d.fx = c.fx; d.fy = c.fy; d.cx = c.cx; d.cy = c.cy;
+        d.W = c.width; d.H = c.height;
+        d.tiles_x = (c.width + p->tile_w - 1) / p->tile_w;
+        d.tiles_y = (c.height + p->tile_h - 1) / p->tile_h;
+        d.tile_base = (uint32_t)pl.tiles;
+        d.scene = scene;
+        d.mask_off = moff;
+        d.elem_off = pl.elems;
+        d.n = (uint32_t)n;
+        d.pad = 0;
+        pl.views.push_back(d);
+        SegDev sg;
+        sg.off = pl.elems;
+        sg.len = (uint32_t)n;
+        sg.blk0 = pl.dblocks;
+        pl.dsegs.push_back(sg);
+        pl.dblocks += (uint32_t)((n + kSortTile - 1) / kSortTile);
+        pl.elems += (uint64_t)n;
+        pl.tiles += (uint64_t)d.tiles_x * d.tiles_y;
+        moff += (uint64_t)c.width * c.height;
+    }
+    const uint32_t bpv = (uint32_t)((n + 255) / 256);
+    for (int v = first; v < (int)pl.views.size(); v += kProjViews) {
+        ProjTask t;
+        t.blk0 = pl.proj_blocks;
+        t.scene = scene;
+        t.v0 = (uint32_t)v;
+        t.nv = (uint32_t)std::min<int>(kProjViews, (int)pl.views.size() - v);
+        pl.tasks.push_back(t);
+        pl.proj_blocks += bpv;
+    }
+}
+
+SceneDev scene_dev(const fs_gaussians *g, int64_t n, const uint8_t *masks, float *A_hi, float *A_lo, int32_t E)
+{
+    SceneDev s;
+    s.g = gauss_ptrs(g);
+    s.masks = masks;
+    s.A_hi = A_hi;
+    s.A_lo = A_lo;
+    s.n = (uint32_t)n;
+    s.E = E;
+    return s;
+}
+
+// XCD-run work order (tile_order 2). Workgroups are handed to the chip's 8
+// XCDs round-robin by index and every XCD has its own L2: the table maps
+// workgroup b to tile (b % 8) * run + b / 8, so XCD x composites one
+// contiguous run of tiles.
+constexpr int kXcds = 8;
+
+int build_xcd_items(fs_ctx *ctx, uint64_t n_tiles)
+{
+    if (ctx->items_tiles == n_tiles && ctx->items.p) return FS_OK;
+    std::vector<uint32_t> it((size_t)n_tiles);
+    const uint64_t base = n_tiles / kXcds, rem = n_tiles % kXcds;
+    uint64_t start[kXcds];
+    uint64_t acc = 0;
+    for (int x = 0; x < kXcds; ++x) {
+        start[x] = acc;
+        acc += base + ((uint64_t)x < rem ? 1 : 0);
+    }
+    for (uint64_t b = 0; b < n_tiles; ++b) it[b] = (uint32_t)(start[b % kXcds] + b / kXcds);
+    ctx->items_tiles = 0;
+    RCHECK(upload(ctx, ctx->items, it.data(), it.size() * sizeof(uint32_t)));
+    ctx->items_tiles = n_tiles;
     return FS_OK;
 }
 
-int bits_for(uint64_t count)
+// Longest-list-first work order (tile_order 0) of `n_tiles` tiles into
+// `items`, from their ranges; `lseg` is one segment covering all tiles.
+int enqueue_lpt(fs_ctx *ctx, hipStream_t s, const uint32_t *ranges, uint64_t n_tiles, const SegDev *lseg,
+                uint32_t *items, uint32_t *k, uint32_t *k2, uint32_t *v2, void *ws)
 {
-    int b = 1;
-    while (b < 32 && (1ull << b) < count) ++b;
-    return b;
+    HIPCHECK(ctx, launch_tile_keys(s, ranges, (int64_t)n_tiles, k, items));
+    const uint32_t blocks = (uint32_t)((n_tiles + kSortTile - 1) / kSortTile);
+    HIPCHECK(ctx, radix_sort(s, k, items, k2, v2, lseg, 1, blocks, 16, ws, nullptr));
+    return FS_OK;
 }
 
 }  // namespace
 
 extern "C" {
 
-const char *fs_version(void) { return "flashsplat-gfx950 0.1"; }
+const char *fs_version(void) { return "flashsplat-gfx950 0.2"; }
 
 const char *fs_error_string(int code)
 {
@@ -302,7 +417,7 @@ int fs_ctx_create(fs_ctx **out, void *stream)
     if (!rc && hipHostMalloc((void **)&ctx->status_host, ST_COUNT * sizeof(unsigned long long), hipHostMallocDefault) != hipSuccess)
         rc = FS_ERR_ALLOC;
     if (!rc && hipHostMalloc((void **)&ctx->npairs_host, 64, hipHostMallocDefault) != hipSuccess) rc = FS_ERR_ALLOC;
-    for (int i = 0; !rc && i < 4; ++i)
+    for (int i = 0; !rc && i < kStaging; ++i)
         if (hipEventCreateWithFlags(&ctx->stage[i].ev, hipEventDisableTiming) != hipSuccess) rc = FS_ERR_HIP;
     if (!rc && launch_fill_u32(ctx->stream, (uint32_t *)ctx->status_dev, 0u, ST_COUNT * 2) != hipSuccess) rc = FS_ERR_HIP;
     if (!rc && launch_fill_u32(ctx->stream, ctx->npairs_dev, 0u, 16) != hipSuccess) rc = FS_ERR_HIP;
@@ -327,12 +442,12 @@ int fs_ctx_destroy(fs_ctx *ctx)
 {
     if (!ctx) return FS_ERR_ARG;
     (void)hipStreamSynchronize(ctx->stream);
-    DevBuf *bufs[] = {&ctx->cams, &ctx->dkeys, &ctx->dvals, &ctx->dkeys2, &ctx->dvals2, &ctx->counts,
-                      &ctx->offsets, &ctx->pk_alt, &ctx->pv_alt, &ctx->sort_ws, &ctx->scan_ws, &ctx->items,
-                      &ctx->items_k, &ctx->items_k2, &ctx->items_v2, &ctx->items_ws};
-    for (DevBuf *b : bufs)
-        if (b->p) (void)hipFree(b->p);
-    for (int i = 0; i < 4; ++i) {
+    DevBuf *bufs[] = {&ctx->views, &ctx->scenes, &ctx->tasks, &ctx->dsegs, &ctx->psegs, &ctx->lsegs,
+                      &ctx->dkeys, &ctx->dvals, &ctx->dkeys2, &ctx->dvals2, &ctx->counts, &ctx->offsets,
+                      &ctx->pk_alt, &ctx->pv_alt, &ctx->sort_ws, &ctx->scan_ws, &ctx->items, &ctx->items_k,
+                      &ctx->items_k2, &ctx->items_v2, &ctx->items_ws};
+    for (DevBuf *b : bufs) free_buf(*b);
+    for (int i = 0; i < kStaging; ++i) {
         if (ctx->stage[i].host) (void)hipHostFree(ctx->stage[i].host);
         if (ctx->stage[i].ev) (void)hipEventDestroy(ctx->stage[i].ev);
     }
@@ -365,9 +480,7 @@ int fs_status_get(fs_ctx *ctx, fs_status *out, int32_t clear)
     out->unseen = (int64_t)h[ST_UNSEEN];
     out->multi_member = (int64_t)h[ST_MULTI];
     out->low_margin = (int64_t)h[ST_LOWMARGIN];
-    if (clear) {
-        HIPCHECK(ctx, launch_fill_u32(ctx->stream, (uint32_t *)ctx->status_dev, 0u, ST_COUNT * 2));
-    }
+    if (clear) HIPCHECK(ctx, launch_fill_u32(ctx->stream, (uint32_t *)ctx->status_dev, 0u, ST_COUNT * 2));
     const uint32_t errbits = FS_DEV_BAD_LABEL | FS_DEV_PAIR_OVERFLOW | FS_DEV_INVALID_GAUSS;
     if (out->flags & errbits) return set_err(ctx, FS_ERR_DEVICE, "device status flags 0x%x", out->flags);
     return FS_OK;
@@ -377,23 +490,24 @@ int fs_project(fs_ctx *ctx, const fs_gaussians *g, const fs_camera *cams, int32_
                const fs_proj *out)
 {
     if (!ctx) return FS_ERR_ARG;
-    if (!g || !out) return set_err(ctx, FS_ERR_ARG, "NULL argument");
-    int rc = check_params(ctx, p, false);
-    if (rc) return rc;
-    if ((rc = check_cams(ctx, cams, n_views))) return rc;
-    if ((rc = check_proj(ctx, out))) return rc;
-    if (g->n < 0) return set_err(ctx, FS_ERR_ARG, "n < 0");
+    if (!out) return set_err(ctx, FS_ERR_ARG, "NULL argument");
+    RCHECK(check_params(ctx, p, false));
+    RCHECK(check_cams(ctx, cams, n_views));
+    RCHECK(check_proj(ctx, out));
+    RCHECK(check_gauss(ctx, g));
     if (out->n != g->n || out->n_views != n_views)
         return set_err(ctx, FS_ERR_ARG, "proj sized for n=%lld, views=%d; need n=%lld, views=%d", (long long)out->n,
                        out->n_views, (long long)g->n, n_views);
-    if (g->n > 0 && (!g->mx || !g->my || !g->mz || !g->qw || !g->qx || !g->qy || !g->qz || !g->sx || !g->sy ||
-                     !g->sz || !g->opacity))
-        return set_err(ctx, FS_ERR_ARG, "Gaussian array is NULL");
     if (g->n == 0 || n_views == 0) return FS_OK;
-    if ((rc = build_cams(ctx, cams, n_views, p, nullptr, nullptr))) return rc;
-    GaussPtrs gp{g->mx, g->my, g->mz, g->qw, g->qx, g->qy, g->qz, g->sx, g->sy, g->sz, g->opacity};
-    HIPCHECK(ctx, launch_project(ctx->stream, gp, g->n, (const CamDev *)ctx->cams.p, n_views, proj_params(p), out->rec,
-                                 out->rect, out->ntiles, out->flags, ctx->status_dev));
+    Plan pl;
+    plan_add(pl, p, 0, g->n, cams, 0, n_views, 0);
+    std::vector<SceneDev> sc{scene_dev(g, g->n, nullptr, nullptr, nullptr, 2)};
+    RCHECK(upload_vec(ctx, ctx->views, pl.views));
+    RCHECK(upload_vec(ctx, ctx->scenes, sc));
+    RCHECK(upload_vec(ctx, ctx->tasks, pl.tasks));
+    HIPCHECK(ctx, launch_project(ctx->stream, (const ProjTask *)ctx->tasks.p, (int32_t)pl.tasks.size(), pl.proj_blocks,
+                                 (const SceneDev *)ctx->scenes.p, (const ViewDev *)ctx->views.p, proj_params(p),
+                                 out->rec, out->rect, out->ntiles, out->flags, nullptr, nullptr, ctx->status_dev));
     return FS_OK;
 }
 
@@ -401,39 +515,44 @@ int fs_bin_sort(fs_ctx *ctx, const fs_proj *proj, const fs_camera *cams, const f
                 int64_t *n_pairs)
 {
     if (!ctx) return FS_ERR_ARG;
-    int rc = check_params(ctx, p, false);
-    if (rc) return rc;
-    if ((rc = check_proj(ctx, proj))) return rc;
+    RCHECK(check_params(ctx, p, false));
+    RCHECK(check_proj(ctx, proj));
     if (!out) return set_err(ctx, FS_ERR_ARG, "bins is NULL");
-    if ((rc = check_cams(ctx, cams, proj->n_views))) return rc;
+    RCHECK(check_cams(ctx, cams, proj->n_views));
     if (out->capacity < 0 || out->capacity >= 0xFFFFFFFFll) return set_err(ctx, FS_ERR_ARG, "bad bins capacity");
     if (!out->ranges || (out->capacity > 0 && (!out->vals || !out->tiles)))
         return set_err(ctx, FS_ERR_ARG, "bins has NULL arrays");
     const int64_t n = proj->n;
     const int32_t V = proj->n_views;
-    uint64_t total_tiles = 0;
-    if ((rc = build_cams(ctx, cams, V, p, &total_tiles, nullptr))) return rc;
+    Plan pl;
+    plan_add(pl, p, 0, n, cams, 0, V, 0);
+    if (pl.tiles >= 0xFFFFFFFFull) return set_err(ctx, FS_ERR_ARG, "too many tiles in one call");
     hipStream_t s = ctx->stream;
-    HIPCHECK(ctx, launch_fill_u32(s, out->ranges, 0u, (int64_t)total_tiles * 2));
-    const int64_t total = n * V;
+    HIPCHECK(ctx, launch_fill_u32(s, out->ranges, 0u, (int64_t)pl.tiles * 2));
+    const int64_t total = (int64_t)pl.elems;
     if (total == 0) {
         if (n_pairs) *n_pairs = 0;
         HIPCHECK(ctx, launch_fill_u32(s, ctx->npairs_dev, 0u, 1));
         return FS_OK;
     }
+    RCHECK(upload_vec(ctx, ctx->views, pl.views));
+    RCHECK(upload_vec(ctx, ctx->dsegs, pl.dsegs));
     const size_t tb = (size_t)total * 4;
-    if ((rc = ensure(ctx, ctx->dkeys, tb)) || (rc = ensure(ctx, ctx->dvals, tb)) || (rc = ensure(ctx, ctx->dkeys2, tb)) ||
-        (rc = ensure(ctx, ctx->dvals2, tb)) || (rc = ensure(ctx, ctx->counts, tb)) || (rc = ensure(ctx, ctx->offsets, tb)))
-        return rc;
-    size_t ws = radix_ws_bytes(n, V);
-    if ((rc = ensure(ctx, ctx->sort_ws, ws))) return rc;
-    if ((rc = ensure(ctx, ctx->scan_ws, scan_ws_bytes(total)))) return rc;
+    RCHECK(ensure(ctx, ctx->dkeys, tb));
+    RCHECK(ensure(ctx, ctx->dvals, tb));
+    RCHECK(ensure(ctx, ctx->dkeys2, tb));
+    RCHECK(ensure(ctx, ctx->dvals2, tb));
+    RCHECK(ensure(ctx, ctx->counts, tb));
+    RCHECK(ensure(ctx, ctx->offsets, tb));
+    RCHECK(ensure(ctx, ctx->sort_ws, radix_ws_bytes(pl.dblocks)));
+    RCHECK(ensure(ctx, ctx->scan_ws, scan_ws_bytes(total)));
     uint32_t *dk = (uint32_t *)ctx->dkeys.p, *dv = (uint32_t *)ctx->dvals.p;
-    uint32_t *dk2 = (uint32_t *)ctx->dkeys2.p, *dv2 = (uint32_t *)ctx->dvals2.p;
+    const ViewDev *views = (const ViewDev *)ctx->views.p;
     // depth order of each view's emitting Gaussians (4 passes: result back in dk/dv)
-    HIPCHECK(ctx, launch_depth_keys(s, proj->rec, proj->ntiles, proj->flags, n, V, dk, dv));
-    HIPCHECK(ctx, radix_sort(s, dk, dv, dk2, dv2, n, V, 32, ctx->sort_ws.p));
-    HIPCHECK(ctx, launch_gather_counts(s, dk, dv, proj->ntiles, n, V, (uint32_t *)ctx->counts.p));
+    HIPCHECK(ctx, launch_depth_keys(s, proj->rec, proj->ntiles, proj->flags, views, V, total, dk, dv));
+    HIPCHECK(ctx, radix_sort(s, dk, dv, (uint32_t *)ctx->dkeys2.p, (uint32_t *)ctx->dvals2.p,
+                             (const SegDev *)ctx->dsegs.p, V, pl.dblocks, 32, ctx->sort_ws.p, nullptr));
+    HIPCHECK(ctx, launch_gather_counts(s, dk, dv, proj->ntiles, views, V, total, (uint32_t *)ctx->counts.p));
     HIPCHECK(ctx, scan_exclusive(s, (const uint32_t *)ctx->counts.p, (uint32_t *)ctx->offsets.p, total, ctx->npairs_dev,
                                  ctx->scan_ws.p));
     int64_t sort_len = out->capacity;
@@ -450,23 +569,25 @@ int fs_bin_sort(fs_ctx *ctx, const fs_proj *proj, const fs_camera *cams, const f
     if (sort_len == 0) return FS_OK;
     // stable sort of the pairs by tile id; the emit target is chosen so that
     // the final pass lands in the caller's buffers
-    const int bits = bits_for(total_tiles);
-    const int passes = (bits + 7) / 8;
-    if ((rc = ensure(ctx, ctx->pk_alt, (size_t)sort_len * 4)) || (rc = ensure(ctx, ctx->pv_alt, (size_t)sort_len * 4)))
-        return rc;
-    ws = radix_ws_bytes(sort_len, 1);
-    if ((rc = ensure(ctx, ctx->sort_ws, ws))) return rc;
+    const int passes = (bits_for(pl.tiles) + 7) / 8;
+    RCHECK(ensure(ctx, ctx->pk_alt, (size_t)sort_len * 4));
+    RCHECK(ensure(ctx, ctx->pv_alt, (size_t)sort_len * 4));
+    const uint32_t pblocks = (uint32_t)((sort_len + kSortTile - 1) / kSortTile);
+    RCHECK(ensure(ctx, ctx->sort_ws, radix_ws_bytes(pblocks)));
+    std::vector<SegDev> ps{SegDev{0, (uint32_t)sort_len, 0}};
+    RCHECK(upload_vec(ctx, ctx->psegs, ps));
     uint32_t *k0, *v0, *k1, *v1;
     if (passes % 2 == 0) {
         k0 = out->tiles; v0 = out->vals; k1 = (uint32_t *)ctx->pk_alt.p; v1 = (uint32_t *)ctx->pv_alt.p;
     } else {
         k0 = (uint32_t *)ctx->pk_alt.p; v0 = (uint32_t *)ctx->pv_alt.p; k1 = out->tiles; v1 = out->vals;
     }
-    if (!n_pairs) HIPCHECK(ctx, launch_fill_u32(s, k0, 0xFFFFFFFFu, sort_len));  // tail beyond the real count sorts last
     HIPCHECK(ctx, launch_emit(s, dk, dv, (const uint32_t *)ctx->offsets.p, (const uint32_t *)ctx->counts.p, proj->rec,
-                              proj->rect, proj->flags, (const CamDev *)ctx->cams.p, n, V, (uint32_t)out->capacity,
-                              p->tile_w, p->tile_h, p->sigma_k, k0, v0, ctx->status_dev));
-    HIPCHECK(ctx, radix_sort(s, k0, v0, k1, v1, sort_len, 1, passes * 8, ctx->sort_ws.p));
+                              proj->rect, proj->flags, views, V, total, (uint32_t)out->capacity, p->tile_w, p->tile_h,
+                              p->sigma_k, k0, v0, ctx->status_dev));
+    // without a host count, the device count caps the sort (entries past it are never read)
+    HIPCHECK(ctx, radix_sort(s, k0, v0, k1, v1, (const SegDev *)ctx->psegs.p, 1, pblocks, passes * 8, ctx->sort_ws.p,
+                             n_pairs ? nullptr : ctx->npairs_dev));
     HIPCHECK(ctx, launch_ranges(s, out->tiles, ctx->npairs_dev, (uint32_t)out->capacity, sort_len, out->ranges));
     return FS_OK;
 }
@@ -476,54 +597,45 @@ int fs_accumulate(fs_ctx *ctx, const fs_proj *proj, const fs_bins *bins, const f
                   const fs_pixel_out *pix)
 {
     if (!ctx) return FS_ERR_ARG;
-    int rc = check_params(ctx, p, true);
-    if (rc) return rc;
-    if ((rc = check_proj(ctx, proj))) return rc;
+    RCHECK(check_params(ctx, p, true));
+    RCHECK(check_proj(ctx, proj));
     if (!bins || !bins->ranges) return set_err(ctx, FS_ERR_ARG, "bins is NULL");
-    if ((rc = check_cams(ctx, cams, proj->n_views))) return rc;
+    RCHECK(check_cams(ctx, cams, proj->n_views));
     if (n_classes < 2 || n_classes > 256) return set_err(ctx, FS_ERR_ARG, "n_classes %d not in [2, 256]", n_classes);
     if (reduction < FS_RED_AUTO || reduction > FS_RED_LDS2SUM) return set_err(ctx, FS_ERR_ARG, "unknown reduction %d", reduction);
     if (reduction == FS_RED_AUTO) reduction = A_lo ? FS_RED_LDS2SUM : FS_RED_LDS;
     if (reduction == FS_RED_LDS2SUM && !A_lo) return set_err(ctx, FS_ERR_ARG, "FS_RED_LDS2SUM needs A_lo");
     if (proj->n > 0 && proj->n_views > 0 && (!masks || !A_hi)) return set_err(ctx, FS_ERR_ARG, "masks or A_hi is NULL");
-    if (!finite_f(p->alpha_min)) return set_err(ctx, FS_ERR_ARG, "bad alpha_min");
     const int32_t V = proj->n_views;
     if (proj->n == 0 || V == 0) return FS_OK;
-    uint64_t total_tiles = 0;
-    if ((rc = build_cams(ctx, cams, V, p, &total_tiles, nullptr))) return rc;
-    AccParams ap;
-    const double LOG2E = 1.4426950408889634;
-    ap.cut2 = (float)(-0.5 * (double)p->sigma_k * (double)p->sigma_k * LOG2E);
-    ap.alpha_min = p->alpha_min;
-    ap.alpha_max = p->alpha_max;
-    ap.t_min = p->t_min;
-    ap.E = n_classes;
-    ap.tile_w = p->tile_w;
-    ap.tile_h = p->tile_h;
-    ap.reduction = reduction;
+    Plan pl;
+    plan_add(pl, p, 0, proj->n, cams, 0, V, 0);
+    std::vector<SceneDev> sc{scene_dev(nullptr, proj->n, masks, A_hi, A_lo, n_classes)};
+    RCHECK(upload_vec(ctx, ctx->views, pl.views));
+    RCHECK(upload_vec(ctx, ctx->scenes, sc));
     const uint32_t *items = nullptr;
     if (p->tile_order == 0) {
-        // longest lists first, so that the longest-running workgroups start early
-        const size_t tb = (size_t)total_tiles * 4;
-        if ((rc = ensure(ctx, ctx->items, tb)) || (rc = ensure(ctx, ctx->items_k, tb)) ||
-            (rc = ensure(ctx, ctx->items_k2, tb)) || (rc = ensure(ctx, ctx->items_v2, tb)) ||
-            (rc = ensure(ctx, ctx->items_ws, radix_ws_bytes((int64_t)total_tiles, 1))))
-            return rc;
+        const size_t tb = (size_t)pl.tiles * 4;
+        const uint32_t lblocks = (uint32_t)((pl.tiles + kSortTile - 1) / kSortTile);
+        RCHECK(ensure(ctx, ctx->items, tb));
+        RCHECK(ensure(ctx, ctx->items_k, tb));
+        RCHECK(ensure(ctx, ctx->items_k2, tb));
+        RCHECK(ensure(ctx, ctx->items_v2, tb));
+        RCHECK(ensure(ctx, ctx->items_ws, radix_ws_bytes(lblocks)));
+        std::vector<SegDev> ls{SegDev{0, (uint32_t)pl.tiles, 0}};
+        RCHECK(upload_vec(ctx, ctx->lsegs, ls));
         ctx->items_tiles = 0;  // the XCD-run table (tile_order 2) shares the buffer
-        HIPCHECK(ctx, launch_tile_keys(ctx->stream, bins->ranges, (int64_t)total_tiles, (uint32_t *)ctx->items_k.p,
-                                       (uint32_t *)ctx->items.p));
-        HIPCHECK(ctx, radix_sort(ctx->stream, (uint32_t *)ctx->items_k.p, (uint32_t *)ctx->items.p,
-                                 (uint32_t *)ctx->items_k2.p, (uint32_t *)ctx->items_v2.p, (int64_t)total_tiles, 1, 16,
-                                 ctx->items_ws.p));
+        RCHECK(enqueue_lpt(ctx, ctx->stream, bins->ranges, pl.tiles, (const SegDev *)ctx->lsegs.p,
+                           (uint32_t *)ctx->items.p, (uint32_t *)ctx->items_k.p, (uint32_t *)ctx->items_k2.p,
+                           (uint32_t *)ctx->items_v2.p, ctx->items_ws.p));
         items = (const uint32_t *)ctx->items.p;
     } else if (p->tile_order == 2) {
-        if ((rc = build_items(ctx, total_tiles))) return rc;
+        RCHECK(build_xcd_items(ctx, pl.tiles));
         items = (const uint32_t *)ctx->items.p;
     }
-    HIPCHECK(ctx, launch_accumulate(ctx->stream, proj->rec, bins->vals, bins->ranges, (const CamDev *)ctx->cams.p, V,
-                                    items, (uint32_t)total_tiles, proj->n, masks, ap, A_hi,
-                                    reduction == FS_RED_LDS2SUM ? A_lo : nullptr, pix ? pix->t_final : nullptr,
-                                    pix ? pix->n_blend : nullptr, ctx->status_dev));
+    HIPCHECK(ctx, launch_accumulate(ctx->stream, proj->rec, bins->vals, bins->ranges, (const ViewDev *)ctx->views.p, V,
+                                    (const SceneDev *)ctx->scenes.p, items, (uint32_t)pl.tiles, acc_params(p, reduction),
+                                    pix ? pix->t_final : nullptr, pix ? pix->n_blend : nullptr, ctx->status_dev));
     return FS_OK;
 }
 
@@ -536,6 +648,488 @@ int fs_assign(fs_ctx *ctx, const float *A_hi, const float *A_lo, int64_t n, int3
     if (!finite_f(gamma) || gamma < -1.f || gamma > 1.f) return set_err(ctx, FS_ERR_ARG, "gamma must be finite in [-1, 1]");
     if (n > 0 && (!A_hi || !S)) return set_err(ctx, FS_ERR_ARG, "A_hi or S is NULL");
     HIPCHECK(ctx, launch_assign(ctx->stream, A_hi, A_lo, n, n_classes, gamma, S, margin, ctx->status_dev));
+    return FS_OK;
+}
+
+}  // extern "C"
+
+// ===========================================================================
+// Batched solve
+// ===========================================================================
+namespace {
+
+struct SceneIn {
+    fs_gaussians g;
+    std::vector<fs_camera> cams;
+    std::vector<uint64_t> mask_off;  // per view, within the scene's masks
+    const uint8_t *masks;
+    int32_t E;
+    float *A_hi, *A_lo;
+    uint8_t *S;
+    float *margin;
+    float gamma;
+};
+
+struct ViewRef {
+    uint32_t scene;
+    int32_t v;
+};
+
+struct Chunk {
+    Plan plan;
+    std::vector<ViewRef> refs;
+    uint64_t pairs = 0;       // planned (exact at creation)
+    uint32_t pair_cap = 0;    // slots used by this chunk
+    uint32_t pblocks = 0;
+    uint32_t lblocks = 0;
+    int passes = 0;
+    DevBuf views, tasks, dsegs, psegs, lsegs;
+};
+
+}  // namespace
+
+struct fs_batch {
+    fs_ctx *ctx = nullptr;
+    fs_params p;
+    fs_batch_opts o;
+    std::vector<SceneIn> scenes;
+    std::vector<Chunk> chunks;
+    DevBuf scenes_d;
+    // workspace shared by the chunks
+    DevBuf rec, rect, ntiles, flags, dkeys, dvals, dkeys2, dvals2, counts, offsets;
+    DevBuf ptiles, pvals, pk_alt, pv_alt, ranges, items, items_k, items_k2, items_v2;
+    DevBuf sort_ws, scan_ws, npairs, view_offs;
+    uint64_t max_elems = 0, max_tiles = 0, max_pairs = 0;
+    uint32_t max_dblocks = 0, max_pblocks = 0, max_lblocks = 0;
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+    int64_t ws_bytes = 0;
+    int64_t total_pairs = 0, total_elems = 0, total_tiles = 0;
+};
+
+namespace {
+
+std::vector<DevBuf *> batch_bufs(fs_batch *b)
+{
+    std::vector<DevBuf *> v = {&b->scenes_d, &b->rec, &b->rect, &b->ntiles, &b->flags, &b->dkeys, &b->dvals,
+                               &b->dkeys2, &b->dvals2, &b->counts, &b->offsets, &b->ptiles, &b->pvals, &b->pk_alt,
+                               &b->pv_alt, &b->ranges, &b->items, &b->items_k, &b->items_k2, &b->items_v2,
+                               &b->sort_ws, &b->scan_ws, &b->npairs, &b->view_offs};
+    for (Chunk &c : b->chunks) {
+        v.push_back(&c.views);
+        v.push_back(&c.tasks);
+        v.push_back(&c.dsegs);
+        v.push_back(&c.psegs);
+        v.push_back(&c.lsegs);
+    }
+    return v;
+}
+
+void chunk_plan(fs_batch *b, Chunk &c)
+{
+    c.plan = Plan();
+    // consecutive views of one scene form one run of plan_add
+    size_t i = 0;
+    while (i < c.refs.size()) {
+        size_t j = i;
+        while (j + 1 < c.refs.size() && c.refs[j + 1].scene == c.refs[i].scene && c.refs[j + 1].v == c.refs[j].v + 1) ++j;
+        const SceneIn &s = b->scenes[c.refs[i].scene];
+        plan_add(c.plan, &b->p, c.refs[i].scene, s.g.n, s.cams.data(), c.refs[i].v, c.refs[j].v + 1,
+                 s.mask_off[c.refs[i].v]);
+        i = j + 1;
+    }
+}
+
+// projection, depth sort, counts and scan of one chunk (the first half of binning)
+int enqueue_count(fs_batch *b, Chunk &c, int chunk_idx, hipStream_t s)
+{
+    fs_ctx *ctx = b->ctx;
+    const Plan &pl = c.plan;
+    const int64_t total = (int64_t)pl.elems;
+    const int32_t V = (int32_t)pl.views.size();
+    uint32_t *np = (uint32_t *)b->npairs.p + chunk_idx;
+    if (total == 0) {
+        HIPCHECK(ctx, launch_fill_u32(s, np, 0u, 1));
+        return FS_OK;
+    }
+    uint32_t *dk = (uint32_t *)b->dkeys.p, *dv = (uint32_t *)b->dvals.p;
+    HIPCHECK(ctx, launch_project(s, (const ProjTask *)c.tasks.p, (int32_t)pl.tasks.size(), pl.proj_blocks,
+                                 (const SceneDev *)b->scenes_d.p, (const ViewDev *)c.views.p, proj_params(&b->p),
+                                 (float *)b->rec.p, (int16_t *)b->rect.p, (int32_t *)b->ntiles.p, (uint8_t *)b->flags.p,
+                                 dk, dv, ctx->status_dev));
+    HIPCHECK(ctx, radix_sort(s, dk, dv, (uint32_t *)b->dkeys2.p, (uint32_t *)b->dvals2.p, (const SegDev *)c.dsegs.p, V,
+                             pl.dblocks, 32, b->sort_ws.p, nullptr));
+    HIPCHECK(ctx, launch_gather_counts(s, dk, dv, (const int32_t *)b->ntiles.p, (const ViewDev *)c.views.p, V, total,
+                                       (uint32_t *)b->counts.p));
+    HIPCHECK(ctx, scan_exclusive(s, (const uint32_t *)b->counts.p, (uint32_t *)b->offsets.p, total, np, b->scan_ws.p));
+    return FS_OK;
+}
+
+// the rest of one chunk: emission, pair sort, ranges, work order, compositing
+int enqueue_finish(fs_batch *b, Chunk &c, int chunk_idx, hipStream_t s)
+{
+    fs_ctx *ctx = b->ctx;
+    const Plan &pl = c.plan;
+    const int64_t total = (int64_t)pl.elems;
+    const int32_t V = (int32_t)pl.views.size();
+    if (total == 0 || c.pair_cap == 0 || pl.tiles == 0) return FS_OK;
+    const uint32_t *np = (const uint32_t *)b->npairs.p + chunk_idx;
+    uint32_t *dk = (uint32_t *)b->dkeys.p, *dv = (uint32_t *)b->dvals.p;
+    uint32_t *k0, *v0, *k1, *v1;
+    uint32_t *pt = (uint32_t *)b->ptiles.p, *pv = (uint32_t *)b->pvals.p;
+    uint32_t *pta = (uint32_t *)b->pk_alt.p, *pva = (uint32_t *)b->pv_alt.p;
+    if (c.passes % 2 == 0) {
+        k0 = pt; v0 = pv; k1 = pta; v1 = pva;
+    } else {
+        k0 = pta; v0 = pva; k1 = pt; v1 = pv;
+    }
+    HIPCHECK(ctx, launch_emit(s, dk, dv, (const uint32_t *)b->offsets.p, (const uint32_t *)b->counts.p,
+                              (const float *)b->rec.p, (const int16_t *)b->rect.p, (const uint8_t *)b->flags.p,
+                              (const ViewDev *)c.views.p, V, total, c.pair_cap, b->p.tile_w, b->p.tile_h, b->p.sigma_k,
+                              k0, v0, ctx->status_dev));
+    HIPCHECK(ctx, radix_sort(s, k0, v0, k1, v1, (const SegDev *)c.psegs.p, 1, c.pblocks, c.passes * 8, b->sort_ws.p, np));
+    HIPCHECK(ctx, launch_fill_u32(s, (uint32_t *)b->ranges.p, 0u, (int64_t)pl.tiles * 2));
+    HIPCHECK(ctx, launch_ranges(s, pt, np, c.pair_cap, c.pair_cap, (uint32_t *)b->ranges.p));
+    const uint32_t *items = nullptr;
+    if (b->p.tile_order == 0) {
+        RCHECK(enqueue_lpt(ctx, s, (const uint32_t *)b->ranges.p, pl.tiles, (const SegDev *)c.lsegs.p,
+                           (uint32_t *)b->items.p, (uint32_t *)b->items_k.p, (uint32_t *)b->items_k2.p,
+                           (uint32_t *)b->items_v2.p, b->sort_ws.p));
+        items = (const uint32_t *)b->items.p;
+    }
+    HIPCHECK(ctx, launch_accumulate(s, (const float *)b->rec.p, pv, (const uint32_t *)b->ranges.p,
+                                    (const ViewDev *)c.views.p, V, (const SceneDev *)b->scenes_d.p, items,
+                                    (uint32_t)pl.tiles, acc_params(&b->p, b->o.reduction), nullptr, nullptr,
+                                    ctx->status_dev));
+    return FS_OK;
+}
+
+// the whole solve: optional zeroing, every chunk, every scene's assignment
+int enqueue_run(fs_batch *b, hipStream_t s)
+{
+    fs_ctx *ctx = b->ctx;
+    if (b->o.zero_accumulators) {
+        for (const SceneIn &sc : b->scenes) {
+            const int64_t cnt = (int64_t)sc.g.n * sc.E;
+            HIPCHECK(ctx, launch_fill_u32(s, (uint32_t *)sc.A_hi, 0u, cnt));
+            if (sc.A_lo) HIPCHECK(ctx, launch_fill_u32(s, (uint32_t *)sc.A_lo, 0u, cnt));
+        }
+    }
+    for (size_t i = 0; i < b->chunks.size(); ++i) {
+        RCHECK(enqueue_count(b, b->chunks[i], (int)i, s));
+        RCHECK(enqueue_finish(b, b->chunks[i], (int)i, s));
+    }
+    for (const SceneIn &sc : b->scenes)
+        if (sc.S)
+            HIPCHECK(ctx, launch_assign(s, sc.A_hi, sc.A_lo, sc.g.n, sc.E, sc.gamma, sc.S, sc.margin, ctx->status_dev));
+    return FS_OK;
+}
+
+int batch_alloc(fs_batch *b, DevBuf &buf, size_t bytes)
+{
+    RCHECK(alloc_buf(b->ctx, buf, bytes < 256 ? 256 : bytes));
+    b->ws_bytes += (int64_t)buf.cap;
+    return FS_OK;
+}
+
+int batch_build(fs_batch *b, const fs_scene *scenes, int32_t n_scenes)
+{
+    fs_ctx *ctx = b->ctx;
+    const int64_t pair_budget = b->o.pair_budget > 0 ? b->o.pair_budget : (int64_t)1 << 28;
+    const int64_t elem_budget = b->o.elem_budget > 0 ? b->o.elem_budget : (int64_t)1 << 26;
+    // scenes
+    std::vector<SceneDev> sd;
+    for (int i = 0; i < n_scenes; ++i) {
+        const fs_scene &in = scenes[i];
+        SceneIn s;
+        s.g = in.gauss;
+        s.cams.assign(in.cams, in.cams + in.n_views);
+        s.mask_off.resize((size_t)in.n_views);
+        uint64_t m = 0;
+        for (int v = 0; v < in.n_views; ++v) {
+            s.mask_off[v] = m;
+            m += (uint64_t)in.cams[v].width * in.cams[v].height;
+        }
+        s.masks = in.masks;
+        s.E = in.n_classes;
+        s.A_hi = in.A_hi;
+        s.A_lo = in.A_lo;
+        s.S = in.S;
+        s.margin = in.margin;
+        s.gamma = in.gamma;
+        b->scenes.push_back(s);
+        sd.push_back(scene_dev(&in.gauss, in.gauss.n, in.masks, in.A_hi, in.A_lo, in.n_classes));
+    }
+    RCHECK(batch_alloc(b, b->scenes_d, sd.size() * sizeof(SceneDev)));
+    RCHECK(upload_vec(ctx, b->scenes_d, sd));
+
+    // 1. provisional chunks by element budget, for the exact count
+    std::vector<ViewRef> all;
+    for (int i = 0; i < n_scenes; ++i)
+        for (int v = 0; v < scenes[i].n_views; ++v) all.push_back(ViewRef{(uint32_t)i, v});
+    auto chunk_by = [&](const std::vector<int64_t> *pairs) {
+        std::vector<Chunk> out;
+        Chunk cur;
+        int64_t ce = 0, cp = 0;
+        uint64_t ct = 0;
+        for (size_t k = 0; k < all.size(); ++k) {
+            const SceneIn &s = b->scenes[all[k].scene];
+            const int64_t e = s.g.n;
+            const int64_t p = pairs ? (*pairs)[k] : 0;
+            const fs_camera &c = s.cams[all[k].v];
+            const uint64_t t = (uint64_t)((c.width + b->p.tile_w - 1) / b->p.tile_w) *
+                               (uint64_t)((c.height + b->p.tile_h - 1) / b->p.tile_h);
+            if (!cur.refs.empty() && (ce + e > elem_budget || cp + p > pair_budget || ct + t > 0x7FFFFFFFull)) {
+                out.push_back(std::move(cur));
+                cur = Chunk();
+                ce = cp = 0;
+                ct = 0;
+            }
+            cur.refs.push_back(all[k]);
+            ce += e;
+            cp += p;
+            ct += t;
+        }
+        if (!cur.refs.empty()) out.push_back(std::move(cur));
+        return out;
+    };
+    std::vector<Chunk> prov = chunk_by(nullptr);
+    uint64_t max_e = 0;
+    uint32_t max_db = 0;
+    size_t max_v = 0;
+    for (Chunk &c : prov) {
+        chunk_plan(b, c);
+        max_e = std::max<uint64_t>(max_e, c.plan.elems);
+        max_db = std::max(max_db, c.plan.dblocks);
+        max_v = std::max(max_v, c.plan.views.size());
+    }
+    if (max_e >= 0xFFFFFFFFull) return set_err(ctx, FS_ERR_ARG, "a single view holds too many Gaussians");
+    // projection and depth-sort workspace (sized for the element budget)
+    const size_t E4 = (size_t)std::max<uint64_t>(max_e, 1) * 4;
+    RCHECK(batch_alloc(b, b->rec, E4 * 8));
+    RCHECK(batch_alloc(b, b->rect, E4 * 2));
+    RCHECK(batch_alloc(b, b->ntiles, E4));
+    RCHECK(batch_alloc(b, b->flags, E4 / 4 + 256));
+    RCHECK(batch_alloc(b, b->dkeys, E4));
+    RCHECK(batch_alloc(b, b->dvals, E4));
+    RCHECK(batch_alloc(b, b->dkeys2, E4));
+    RCHECK(batch_alloc(b, b->dvals2, E4));
+    RCHECK(batch_alloc(b, b->counts, E4));
+    RCHECK(batch_alloc(b, b->offsets, E4));
+    RCHECK(batch_alloc(b, b->scan_ws, scan_ws_bytes((int64_t)max_e)));
+    RCHECK(batch_alloc(b, b->npairs, 4 * (all.size() + 64)));
+    RCHECK(batch_alloc(b, b->view_offs, 4 * (max_v + 64)));
+    DevBuf tmp_sort;
+    RCHECK(alloc_buf(ctx, tmp_sort, radix_ws_bytes(std::max<uint32_t>(max_db, 1))));
+
+    // 2. exact pair count of every view
+    std::vector<int64_t> vpairs(all.size(), 0);
+    std::vector<uint32_t> hoff;
+    size_t k0 = 0;
+    int rc = FS_OK;
+    for (size_t ci = 0; ci < prov.size() && !rc; ++ci) {
+        Chunk &c = prov[ci];
+        const int32_t V = (int32_t)c.plan.views.size();
+        if ((rc = upload_vec(ctx, c.views, c.plan.views)) || (rc = upload_vec(ctx, c.tasks, c.plan.tasks)) ||
+            (rc = upload_vec(ctx, c.dsegs, c.plan.dsegs)))
+            break;
+        std::swap(b->sort_ws, tmp_sort);
+        rc = enqueue_count(b, c, 0, ctx->stream);
+        std::swap(b->sort_ws, tmp_sort);
+        if (rc) break;
+        hipError_t e = c.plan.elems > 0
+                           ? launch_view_offsets(ctx->stream, (const uint32_t *)b->offsets.p, (const ViewDev *)c.views.p,
+                                                 V, (int64_t)c.plan.elems, (const uint32_t *)b->npairs.p,
+                                                 (uint32_t *)b->view_offs.p)
+                           : launch_fill_u32(ctx->stream, (uint32_t *)b->view_offs.p, 0u, V + 1);
+        hoff.assign((size_t)V + 1, 0);
+        if (e == hipSuccess)
+            e = hipMemcpyAsync(hoff.data(), b->view_offs.p, 4 * (size_t)(V + 1), hipMemcpyDeviceToHost, ctx->stream);
+        if (e == hipSuccess) e = hipStreamSynchronize(ctx->stream);
+        if (e != hipSuccess) {
+            rc = set_err(ctx, FS_ERR_HIP, "batch count failed: %s", hipGetErrorString(e));
+            break;
+        }
+        for (int v = 0; v < V; ++v) vpairs[k0 + v] = (int64_t)hoff[v + 1] - (int64_t)hoff[v];
+        k0 += (size_t)V;
+        free_buf(c.views);
+        free_buf(c.tasks);
+        free_buf(c.dsegs);
+    }
+    for (Chunk &c : prov) {
+        free_buf(c.views);
+        free_buf(c.tasks);
+        free_buf(c.dsegs);
+    }
+    free_buf(tmp_sort);
+    if (rc) return rc;
+
+    // 3. final chunks by elements and pairs; per-chunk tables
+    b->chunks = chunk_by(&vpairs);
+    size_t k = 0;
+    for (Chunk &c : b->chunks) {
+        chunk_plan(b, c);
+        for (size_t j = 0; j < c.refs.size(); ++j) c.pairs += (uint64_t)vpairs[k + j];
+        k += c.refs.size();
+        if (c.pairs >= 0xFFFFF000ull) return set_err(ctx, FS_ERR_CAPACITY, "a single view needs too many tile pairs");
+        b->max_pairs = std::max<uint64_t>(b->max_pairs, c.pairs);
+        b->max_tiles = std::max<uint64_t>(b->max_tiles, c.plan.tiles);
+        b->max_elems = std::max<uint64_t>(b->max_elems, c.plan.elems);
+        b->max_dblocks = std::max(b->max_dblocks, c.plan.dblocks);
+        b->total_pairs += (int64_t)c.pairs;
+        b->total_elems += (int64_t)c.plan.elems;
+        b->total_tiles += (int64_t)c.plan.tiles;
+    }
+    const uint64_t cap = std::min<uint64_t>(0xFFFFF000ull, b->max_pairs + b->max_pairs / 64 + 4096);
+    for (Chunk &c : b->chunks) {
+        c.pair_cap = (uint32_t)std::min<uint64_t>(cap, c.pairs + c.pairs / 64 + 4096);
+        c.pblocks = (c.pair_cap + kSortTile - 1) / kSortTile;
+        c.lblocks = (uint32_t)((c.plan.tiles + kSortTile - 1) / kSortTile);
+        c.passes = (bits_for(std::max<uint64_t>(c.plan.tiles, 2)) + 7) / 8;
+        b->max_pblocks = std::max(b->max_pblocks, c.pblocks);
+        b->max_lblocks = std::max(b->max_lblocks, c.lblocks);
+        RCHECK(upload_vec(ctx, c.views, c.plan.views));
+        RCHECK(upload_vec(ctx, c.tasks, c.plan.tasks));
+        RCHECK(upload_vec(ctx, c.dsegs, c.plan.dsegs));
+        std::vector<SegDev> ps{SegDev{0, c.pair_cap, 0}};
+        RCHECK(upload_vec(ctx, c.psegs, ps));
+        std::vector<SegDev> ls{SegDev{0, (uint32_t)c.plan.tiles, 0}};
+        RCHECK(upload_vec(ctx, c.lsegs, ls));
+        for (DevBuf *d : {&c.views, &c.tasks, &c.dsegs, &c.psegs, &c.lsegs}) b->ws_bytes += (int64_t)d->cap;
+    }
+    const size_t P4 = (size_t)std::max<uint64_t>(cap, 1) * 4;
+    RCHECK(batch_alloc(b, b->ptiles, P4));
+    RCHECK(batch_alloc(b, b->pvals, P4));
+    RCHECK(batch_alloc(b, b->pk_alt, P4));
+    RCHECK(batch_alloc(b, b->pv_alt, P4));
+    const size_t T4 = (size_t)std::max<uint64_t>(b->max_tiles, 1) * 4;
+    RCHECK(batch_alloc(b, b->ranges, T4 * 2));
+    RCHECK(batch_alloc(b, b->items, T4));
+    RCHECK(batch_alloc(b, b->items_k, T4));
+    RCHECK(batch_alloc(b, b->items_k2, T4));
+    RCHECK(batch_alloc(b, b->items_v2, T4));
+    const uint32_t sb = std::max(std::max(b->max_dblocks, b->max_pblocks), std::max<uint32_t>(b->max_lblocks, 1));
+    RCHECK(batch_alloc(b, b->sort_ws, radix_ws_bytes(sb)));
+    HIPCHECK(ctx, hipStreamSynchronize(ctx->stream));
+
+    // 4. capture the whole solve into one graph
+    if (b->o.use_graph) {
+        hipStream_t s = ctx->stream;
+        bool own_stream = false;
+        if (s == nullptr) {  // the null stream cannot be captured: record on a private stream
+            HIPCHECK(ctx, hipStreamCreateWithFlags(&s, hipStreamNonBlocking));
+            own_stream = true;
+        }
+        hipError_t e = hipStreamBeginCapture(s, hipStreamCaptureModeRelaxed);
+        if (e != hipSuccess) {
+            if (own_stream) (void)hipStreamDestroy(s);
+            return set_err(ctx, FS_ERR_HIP, "graph capture could not start: %s", hipGetErrorString(e));
+        }
+        rc = enqueue_run(b, s);
+        hipGraph_t g = nullptr;
+        e = hipStreamEndCapture(s, &g);
+        if (own_stream) (void)hipStreamDestroy(s);
+        if (rc) {
+            if (g) (void)hipGraphDestroy(g);
+            return rc;
+        }
+        if (e != hipSuccess) return set_err(ctx, FS_ERR_HIP, "graph capture failed: %s", hipGetErrorString(e));
+        b->graph = g;
+        HIPCHECK(ctx, hipGraphInstantiate(&b->exec, b->graph, nullptr, nullptr, 0));
+    }
+    return FS_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+void fs_batch_opts_default(fs_batch_opts *o)
+{
+    if (!o) return;
+    o->pair_budget = 0;
+    o->elem_budget = 0;
+    o->zero_accumulators = 1;
+    o->use_graph = 1;
+    o->reduction = FS_RED_AUTO;
+    o->reserved = 0;
+}
+
+int fs_batch_create(fs_ctx *ctx, const fs_scene *scenes, int32_t n_scenes, const fs_params *p,
+                    const fs_batch_opts *opts, fs_batch **out)
+{
+    if (!ctx) return FS_ERR_ARG;
+    if (!out) return set_err(ctx, FS_ERR_ARG, "out is NULL");
+    *out = nullptr;
+    RCHECK(check_params(ctx, p, true));
+    if (p->tile_order == 2) return set_err(ctx, FS_ERR_ARG, "batches support tile_order 0 and 1");
+    if (n_scenes <= 0 || !scenes) return set_err(ctx, FS_ERR_ARG, "need at least one scene");
+    fs_batch_opts o;
+    fs_batch_opts_default(&o);
+    if (opts) o = *opts;
+    if (o.reduction < FS_RED_AUTO || o.reduction > FS_RED_LDS2SUM) return set_err(ctx, FS_ERR_ARG, "unknown reduction");
+    bool all_lo = true;
+    for (int i = 0; i < n_scenes; ++i) {
+        const fs_scene &s = scenes[i];
+        RCHECK(check_gauss(ctx, &s.gauss));
+        RCHECK(check_cams(ctx, s.cams, s.n_views));
+        if (s.n_classes < 2 || s.n_classes > 256) return set_err(ctx, FS_ERR_ARG, "scene %d: n_classes not in [2, 256]", i);
+        if (s.gauss.n > 0 && (!s.A_hi || (s.n_views > 0 && !s.masks)))
+            return set_err(ctx, FS_ERR_ARG, "scene %d: A_hi or masks is NULL", i);
+        if (s.S && (!finite_f(s.gamma) || s.gamma < -1.f || s.gamma > 1.f))
+            return set_err(ctx, FS_ERR_ARG, "scene %d: gamma must be finite in [-1, 1]", i);
+        all_lo = all_lo && s.A_lo != nullptr;
+    }
+    if (o.reduction == FS_RED_AUTO) o.reduction = all_lo ? FS_RED_LDS2SUM : FS_RED_LDS;
+    if (o.reduction == FS_RED_LDS2SUM && !all_lo) return set_err(ctx, FS_ERR_ARG, "FS_RED_LDS2SUM needs A_lo in every scene");
+    fs_batch *b = new (std::nothrow) fs_batch();
+    if (!b) return FS_ERR_ALLOC;
+    b->ctx = ctx;
+    b->p = *p;
+    b->o = o;
+    int rc = batch_build(b, scenes, n_scenes);
+    if (rc) {
+        fs_batch_destroy(b);
+        return rc;
+    }
+    *out = b;
+    return FS_OK;
+}
+
+int fs_batch_run(fs_batch *b)
+{
+    if (!b) return FS_ERR_ARG;
+    fs_ctx *ctx = b->ctx;
+    if (b->exec) {
+        HIPCHECK(ctx, hipGraphLaunch(b->exec, ctx->stream));
+        return FS_OK;
+    }
+    return enqueue_run(b, ctx->stream);
+}
+
+int fs_batch_get_info(fs_batch *b, fs_batch_info *out)
+{
+    if (!b || !out) return FS_ERR_ARG;
+    out->n_chunks = (int32_t)b->chunks.size();
+    int32_t nv = 0;
+    for (const SceneIn &s : b->scenes) nv += (int32_t)s.cams.size();
+    out->n_views = nv;
+    out->pairs = b->total_pairs;
+    out->pair_capacity = (int64_t)(b->ptiles.cap / 4);
+    out->elements = b->total_elems;
+    out->tiles = b->total_tiles;
+    out->workspace_bytes = b->ws_bytes;
+    return FS_OK;
+}
+
+int fs_batch_destroy(fs_batch *b)
+{
+    if (!b) return FS_ERR_ARG;
+    if (b->ctx) (void)hipStreamSynchronize(b->ctx->stream);
+    if (b->exec) (void)hipGraphExecDestroy(b->exec);
+    if (b->graph) (void)hipGraphDestroy(b->graph);
+    for (DevBuf *d : batch_bufs(b)) free_buf(*d);
+    delete b;
     return FS_OK;
 }
 

@@ -1,4 +1,12 @@
 // Internal declarations shared by the library's translation units.
+//
+// Every call works on a set of views that may belong to several scenes. The
+// host builds small device tables for it:
+//   ViewDev   one per view: camera, tile numbering, where the view's
+//             projection plane and mask live, and its scene;
+//   SceneDev  one per scene: Gaussian arrays, masks, accumulators, classes;
+//   ProjTask / SegDev  work lists of the projection and of the sorts.
+// Element (v, g) of the projection planes lives at views[v].elem_off + g.
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -8,26 +16,53 @@
 
 namespace fs {
 
-// Camera as the kernels see it (one per view of a call).
-struct CamDev {
+struct GaussPtrs {
+    const float *mx, *my, *mz, *qw, *qx, *qy, *qz, *sx, *sy, *sz, *op;
+};
+
+struct ViewDev {
     float R[9];
     float t[3];
     float fx, fy, cx, cy;
     int32_t W, H;
     int32_t tiles_x, tiles_y;
-    uint32_t tile_base;   // first global tile id of this view
+    uint32_t tile_base;   // global id of this view's tile (0, 0)
+    uint32_t scene;       // index into the scene table
+    uint64_t mask_off;    // offset of this view's mask inside its scene's masks
+    uint64_t elem_off;    // first element of this view's projection plane
+    uint32_t n;           // Gaussians in the scene (= plane length)
     uint32_t pad;
-    uint64_t mask_off;    // offset of this view's mask in the concatenated masks
+};
+
+struct SceneDev {
+    GaussPtrs g;
+    const uint8_t *masks;
+    float *A_hi;
+    float *A_lo;          // NULL: no compensation
+    uint32_t n;
+    int32_t E;
+};
+
+// projection work: blocks [blk0, blk0 + ceil(n/256)) project the Gaussians of
+// `scene` into views [v0, v0 + nv) (all of that scene)
+struct ProjTask {
+    uint32_t blk0;
+    uint32_t scene;
+    uint32_t v0;
+    uint32_t nv;
+};
+
+// radix-sort segment: elements [off, off + len), block tiles from blk0
+struct SegDev {
+    uint64_t off;
+    uint32_t len;
+    uint32_t blk0;
 };
 
 struct ProjParams {
     int32_t tile_w, tile_h;
     float sigma_k, lowpass, znear, guard, fp64_cond;
     int32_t fp64_conic;
-};
-
-struct GaussPtrs {
-    const float *mx, *my, *mz, *qw, *qx, *qy, *qz, *sx, *sy, *sz, *op;
 };
 
 // Device status block (ctx-owned): counters are 64-bit, flags in word 0.
@@ -48,64 +83,105 @@ enum StatusIdx {
     ST_COUNT = 16
 };
 
-// ---- launchers (all enqueue on `s`, return hipError_t) ----
-hipError_t launch_project(hipStream_t s, const GaussPtrs &g, int64_t n, const CamDev *cams_dev,
-                          int32_t n_views, const ProjParams &p, float *rec, int16_t *rect,
-                          int32_t *ntiles, uint8_t *flags, unsigned long long *status);
+constexpr int kSortTile = 4096;  // items per radix-sort block tile
+constexpr int kProjViews = 8;    // views projected per Gaussian load
 
+// ---- launchers (all enqueue on `s`, return hipError_t) ----
 hipError_t launch_fill_u32(hipStream_t s, uint32_t *p, uint32_t v, int64_t count);
 
-// depth keys for the per-view depth sort: key = float bits of depth for
-// Gaussians that emit at least one pair, 0xFFFFFFFF otherwise; val = id.
-hipError_t launch_depth_keys(hipStream_t s, const float *rec, const int32_t *ntiles,
-                             const uint8_t *flags, int64_t n, int32_t n_views,
-                             uint32_t *keys, uint32_t *vals);
+// a1: projection of every task; optionally also writes the depth-sort keys
+// (float bits of depth for elements that emit pairs, 0xFFFFFFFF otherwise) and
+// values (Gaussian id within its scene) of every element.
+hipError_t launch_project(hipStream_t s, const ProjTask *tasks, int32_t n_tasks, uint32_t n_blocks,
+                          const SceneDev *scenes, const ViewDev *views, const ProjParams &p, float *rec,
+                          int16_t *rect, int32_t *ntiles, uint8_t *flags, uint32_t *dkeys, uint32_t *dvals,
+                          unsigned long long *status);
 
-// Stable LSD radix sort of (key, val) u32 pairs over `segs` equal segments of
-// `seg_len` items, sorting on bits [0, bits). Result in (keys, vals); the
-// alt buffers are scratch of the same size. Workspace from radix_ws_bytes.
-size_t radix_ws_bytes(int64_t seg_len, int32_t segs);
-hipError_t radix_sort(hipStream_t s, uint32_t *keys, uint32_t *vals, uint32_t *keys_alt,
-                      uint32_t *vals_alt, int64_t seg_len, int32_t segs, int32_t bits, void *ws);
+// depth-sort keys from existing projection planes (same rule as above)
+hipError_t launch_depth_keys(hipStream_t s, const float *rec, const int32_t *ntiles, const uint8_t *flags,
+                             const ViewDev *views, int32_t n_views, int64_t total, uint32_t *keys, uint32_t *vals);
+
+// Stable LSD radix sort of (key, val) u32 pairs over segments, on bits
+// [0, bits) in 8-bit passes; len_dev (optional, single-segment sorts only)
+// caps the length on the device. After an even number of passes the result
+// is in (keys, vals), after an odd number in (keys_alt, vals_alt).
+size_t radix_ws_bytes(uint32_t n_blocks);
+hipError_t radix_sort(hipStream_t s, uint32_t *keys, uint32_t *vals, uint32_t *keys_alt, uint32_t *vals_alt,
+                      const SegDev *segs, int32_t n_segs, uint32_t n_blocks, int32_t bits, void *ws,
+                      const uint32_t *len_dev);
 
 // Exclusive scan of u32 -> u32 (device-wide), total written to *total_out.
 size_t scan_ws_bytes(int64_t n);
-hipError_t scan_exclusive(hipStream_t s, const uint32_t *in, uint32_t *out, int64_t n,
-                          uint32_t *total_out, void *ws);
+hipError_t scan_exclusive(hipStream_t s, const uint32_t *in, uint32_t *out, int64_t n, uint32_t *total_out, void *ws);
 
-// counts[v*n + s] = ntiles of the s-th depth-sorted Gaussian of view v (0 if key invalid)
+// counts[i] = ntiles of depth-sorted element i (0 if its key is the sentinel)
 hipError_t launch_gather_counts(hipStream_t s, const uint32_t *sorted_keys, const uint32_t *sorted_vals,
-                                const int32_t *ntiles, int64_t n, int32_t n_views, uint32_t *counts);
+                                const int32_t *ntiles, const ViewDev *views, int32_t n_views, int64_t total,
+                                uint32_t *counts);
 
-// emits, for every depth-sorted item, one (tile, id) pair per tile that passes
-// tile_hit, at offsets[i]; pairs at or beyond `capacity` are dropped and latched
+// emits, for every depth-sorted element, one (tile, id) pair per listed tile
+// (the row_span rule) at offsets[i]; pairs at or beyond `capacity` are
+// dropped and latched
 hipError_t launch_emit(hipStream_t s, const uint32_t *sorted_keys, const uint32_t *sorted_vals,
                        const uint32_t *offsets, const uint32_t *counts, const float *rec, const int16_t *rect,
-                       const uint8_t *flags, const CamDev *cams_dev, int64_t n, int32_t n_views, uint32_t capacity,
-                       int32_t tile_w, int32_t tile_h, float sigma_k, uint32_t *tiles_out, uint32_t *vals_out,
-                       unsigned long long *status);
+                       const uint8_t *flags, const ViewDev *views, int32_t n_views, int64_t total,
+                       uint32_t capacity, int32_t tile_w, int32_t tile_h, float sigma_k, uint32_t *tiles_out,
+                       uint32_t *vals_out, unsigned long long *status);
+
+hipError_t launch_ranges(hipStream_t s, const uint32_t *tiles, const uint32_t *n_pairs_dev, uint32_t capacity,
+                         int64_t n_pairs_max, uint32_t *ranges);
+
+// out[v] = offsets[views[v].elem_off] (first pair of view v), out[n_views] = total
+hipError_t launch_view_offsets(hipStream_t s, const uint32_t *offsets, const ViewDev *views, int32_t n_views,
+                               int64_t total_elems, const uint32_t *total_pairs, uint32_t *out);
 
 // keys[t] = 65535 - min(list length of tile t, 65535), vals[t] = t
 hipError_t launch_tile_keys(hipStream_t s, const uint32_t *ranges, int64_t n_tiles, uint32_t *keys, uint32_t *vals);
 
-hipError_t launch_ranges(hipStream_t s, const uint32_t *tiles, const uint32_t *n_pairs_dev,
-                         uint32_t capacity, int64_t n_pairs_max, uint32_t *ranges);
-
 struct AccParams {
     float cut2;       // -0.5*k^2*log2(e): support bound on the log2-scaled power
     float alpha_min, alpha_max, t_min;
-    int32_t E;
     int32_t tile_w, tile_h;
     int32_t reduction;
+    int32_t pad;
 };
 
-hipError_t launch_accumulate(hipStream_t s, const float *rec, const uint32_t *vals,
-                             const uint32_t *ranges, const CamDev *cams_dev, int32_t n_views,
-                             const uint32_t *item_view, uint32_t n_items, int64_t n,
-                             const uint8_t *masks, const AccParams &p, float *A_hi, float *A_lo,
-                             float *t_final, int32_t *n_blend, unsigned long long *status);
+hipError_t launch_accumulate(hipStream_t s, const float *rec, const uint32_t *vals, const uint32_t *ranges,
+                             const ViewDev *views, int32_t n_views, const SceneDev *scenes, const uint32_t *items,
+                             uint32_t n_items, const AccParams &p, float *t_final, int32_t *n_blend,
+                             unsigned long long *status);
 
-hipError_t launch_assign(hipStream_t s, const float *A_hi, const float *A_lo, int64_t n, int32_t E,
-                         float gamma, uint8_t *S, float *margin, unsigned long long *status);
+hipError_t launch_assign(hipStream_t s, const float *A_hi, const float *A_lo, int64_t n, int32_t E, float gamma,
+                         uint8_t *S, float *margin, unsigned long long *status);
+
+// ---- device helpers ------------------------------------------------------
+// View holding element i: the wave searches once (scalar) for its first
+// lane's element, then each lane steps forward while its element lies beyond
+// the view (a wave's 64 consecutive elements span few views).
+__device__ __forceinline__ int find_view_of_elem(const ViewDev *__restrict__ views, int32_t n_views, int64_t i)
+{
+    const uint32_t lo32 = __builtin_amdgcn_readfirstlane((uint32_t)(i & 0xFFFFFFFFll));
+    const uint32_t hi32 = __builtin_amdgcn_readfirstlane((uint32_t)((uint64_t)i >> 32));
+    const int64_t i0 = (int64_t)(((uint64_t)hi32 << 32) | lo32);
+    int lo = 0, hi = n_views - 1;
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if ((int64_t)views[mid].elem_off <= i0) lo = mid; else hi = mid - 1;
+    }
+    int v = lo;
+    while (v + 1 < n_views && (int64_t)views[v + 1].elem_off <= i) ++v;
+    return v;
+}
+
+// View holding global tile id t (views ordered by tile_base).
+__device__ __forceinline__ int find_view_of_tile(const ViewDev *__restrict__ views, int32_t n_views, uint32_t t)
+{
+    int lo = 0, hi = n_views - 1;
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (views[mid].tile_base <= t) lo = mid; else hi = mid - 1;
+    }
+    return lo;
+}
 
 }  // namespace fs

@@ -12,19 +12,29 @@
 namespace fs {
 namespace {
 
-constexpr int kViewsPerThread = 8;
-
 __device__ __forceinline__ bool finite32(float x) { return __builtin_isfinite(x); }
 
-__global__ __launch_bounds__(256) void k_project(GaussPtrs G, int64_t n, const CamDev *__restrict__ cams,
-                                                 int32_t n_views, ProjParams P, float4 *__restrict__ rec,
-                                                 short4 *__restrict__ rect, int32_t *__restrict__ ntiles,
-                                                 uint8_t *__restrict__ flags,
+// Block b belongs to the task whose [blk0, next blk0) holds b; the task's
+// Gaussians are loaded once and projected into its (up to kProjViews) views.
+__global__ __launch_bounds__(256) void k_project(const ProjTask *__restrict__ tasks, int32_t n_tasks,
+                                                 const SceneDev *__restrict__ scenes, const ViewDev *__restrict__ views,
+                                                 ProjParams P, float4 *__restrict__ rec, short4 *__restrict__ rect,
+                                                 int32_t *__restrict__ ntiles, uint8_t *__restrict__ flags,
+                                                 uint32_t *__restrict__ dkeys, uint32_t *__restrict__ dvals,
                                                  unsigned long long *__restrict__ status)
 {
-    const int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    const int v0 = blockIdx.y * kViewsPerThread;
-    const int v1 = min(n_views, v0 + kViewsPerThread);
+    int lo = 0, hi = n_tasks - 1;
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (tasks[mid].blk0 <= blockIdx.x) lo = mid; else hi = mid - 1;
+    }
+    const ProjTask task = tasks[lo];
+    const SceneDev &S = scenes[task.scene];
+    const GaussPtrs G = S.g;
+    const int64_t n = S.n;
+    const int64_t g = (int64_t)(blockIdx.x - task.blk0) * blockDim.x + threadIdx.x;
+    const int v0 = (int)task.v0;
+    const int v1 = (int)(task.v0 + task.nv);
     const bool live = g < n;
 
     float mx = 0.f, my = 0.f, mz = 0.f, qw = 1.f, qx = 0.f, qy = 0.f, qz = 0.f, sx = 1.f, sy = 1.f, sz = 1.f, op = 0.f;
@@ -64,9 +74,9 @@ __global__ __launch_bounds__(256) void k_project(GaussPtrs G, int64_t n, const C
 
     int n_invalid = 0, n_fp64 = 0;
     for (int v = v0; v < v1; ++v) {
-        const CamDev &C = cams[v];
+        const ViewDev &C = views[v];
         const float *R = C.R;
-        const int64_t idx = (int64_t)v * n + g;
+        const int64_t idx = (int64_t)C.elem_off + g;
         uint8_t f = 0;
         int nt = 0;
         short4 rc = make_short4(0, 0, 0, 0);
@@ -167,6 +177,12 @@ __global__ __launch_bounds__(256) void k_project(GaussPtrs G, int64_t n, const C
             rect[idx] = rc;
             ntiles[idx] = nt;
             flags[idx] = f;
+            if (dkeys) {
+                // depth-sort key: positive float bits order like the depths; the
+                // sentinel puts elements without pairs last
+                dkeys[idx] = ((f & 1u) && nt > 0) ? __float_as_uint(r1.z) : 0xFFFFFFFFu;
+                dvals[idx] = (uint32_t)g;
+            }
         }
     }
     // one atomic per wave for the counters
@@ -190,14 +206,15 @@ __global__ __launch_bounds__(256) void k_project(GaussPtrs G, int64_t n, const C
 
 }  // namespace
 
-hipError_t launch_project(hipStream_t s, const GaussPtrs &g, int64_t n, const CamDev *cams_dev,
-                          int32_t n_views, const ProjParams &p, float *rec, int16_t *rect,
-                          int32_t *ntiles, uint8_t *flags, unsigned long long *status)
+hipError_t launch_project(hipStream_t s, const ProjTask *tasks, int32_t n_tasks, uint32_t n_blocks,
+                          const SceneDev *scenes, const ViewDev *views, const ProjParams &p, float *rec,
+                          int16_t *rect, int32_t *ntiles, uint8_t *flags, uint32_t *dkeys, uint32_t *dvals,
+                          unsigned long long *status)
 {
-    if (n == 0 || n_views == 0) return hipSuccess;
-    dim3 grid((unsigned)((n + 255) / 256), (unsigned)((n_views + kViewsPerThread - 1) / kViewsPerThread));
-    hipLaunchKernelGGL(k_project, grid, dim3(256), 0, s, g, n, cams_dev, n_views, p,
-                       reinterpret_cast<float4 *>(rec), reinterpret_cast<short4 *>(rect), ntiles, flags, status);
+    if (n_blocks == 0 || n_tasks == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_project, dim3(n_blocks), dim3(256), 0, s, tasks, n_tasks, scenes, views, p,
+                       reinterpret_cast<float4 *>(rec), reinterpret_cast<short4 *>(rect), ntiles, flags, dkeys, dvals,
+                       status);
     return hipGetLastError();
 }
 

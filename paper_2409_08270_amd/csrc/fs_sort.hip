@@ -104,19 +104,55 @@ __global__ __launch_bounds__(kThreads) void k_scan_down(const uint32_t *__restri
 // adds runs of equal digits with one LDS atomic per run: keys emitted per
 // Gaussian in tile order repeat their high digit, which would otherwise
 // serialise the atomics.
-__global__ __launch_bounds__(kThreads) void k_radix_hist(const uint32_t *__restrict__ keys, int64_t seg_len,
-                                                         int32_t blocks_per_seg, int32_t shift,
-                                                         uint32_t *__restrict__ hist)
+// Segment of block b: the last segment whose first block tile is <= b.
+struct SegInfo {
+    int64_t base;     // first element of this block tile
+    int nvalid;       // valid items in the tile
+    uint32_t bps;     // block tiles of the segment
+    uint32_t lb;      // tile index inside the segment
+    uint32_t blk0;
+};
+
+__device__ __forceinline__ SegInfo seg_of_block(const SegDev *__restrict__ segs, int32_t n_segs, uint32_t b,
+                                                const uint32_t *__restrict__ len_dev)
+{
+    int lo = 0, hi = n_segs - 1;
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (segs[mid].blk0 <= b) lo = mid; else hi = mid - 1;
+    }
+    const SegDev sg = segs[lo];
+    SegInfo r;
+    r.blk0 = sg.blk0;
+    r.lb = b - sg.blk0;
+    r.bps = (sg.len + kTile - 1) / kTile;
+    uint32_t len = sg.len;
+    if (len_dev) len = min(len, *len_dev);
+    const int64_t rem = (int64_t)len - (int64_t)r.lb * kTile;
+    r.nvalid = rem <= 0 ? 0 : (rem < kTile ? (int)rem : kTile);
+    r.base = (int64_t)sg.off + (int64_t)r.lb * kTile;
+    return r;
+}
+
+// Digit histogram of one block tile. Each thread reads 16 consecutive keys and
+// adds runs of equal digits with one LDS atomic per run: keys emitted per
+// Gaussian in tile order repeat their high digit, which would otherwise
+// serialise the atomics. Counts are stored [segment][digit][tile] so that one
+// exclusive scan over the whole table gives every tile's output positions.
+__global__ __launch_bounds__(kThreads) void k_radix_hist(const uint32_t *__restrict__ keys,
+                                                         const SegDev *__restrict__ segs, int32_t n_segs,
+                                                         int32_t shift, uint32_t *__restrict__ hist,
+                                                         const uint32_t *__restrict__ len_dev)
 {
     __shared__ uint32_t s_h[kWaves][256];
-    const int seg = blockIdx.x / blocks_per_seg, b = blockIdx.x % blocks_per_seg;
+    const SegInfo si = seg_of_block(segs, n_segs, blockIdx.x, len_dev);
     const int w = threadIdx.x >> 6;
     for (int i = threadIdx.x; i < kWaves * 256; i += kThreads) (&s_h[0][0])[i] = 0;
     __syncthreads();
-    const int64_t t0 = (int64_t)b * kTile + (int64_t)threadIdx.x * kItems;
-    const uint32_t *k = keys + (int64_t)seg * seg_len;
+    const int t0 = threadIdx.x * kItems;
+    const uint32_t *k = keys + si.base;
     uint32_t run_d = 0xFFFFFFFFu, run_n = 0;
-    if (t0 + kItems <= seg_len) {
+    if (t0 + kItems <= si.nvalid) {
         const uint4 *k4 = reinterpret_cast<const uint4 *>(k + t0);
         const bool aligned = ((reinterpret_cast<uintptr_t>(k + t0) & 15u) == 0);
 #pragma unroll
@@ -138,8 +174,8 @@ __global__ __launch_bounds__(kThreads) void k_radix_hist(const uint32_t *__restr
         }
     } else {
         for (int it = 0; it < kItems; ++it) {
-            const int64_t i = t0 + it;
-            if (i >= seg_len) break;
+            const int i = t0 + it;
+            if (i >= si.nvalid) break;
             const uint32_t d = (k[i] >> shift) & 255u;
             if (d != run_d) {
                 if (run_n) atomicAdd(&s_h[w][run_d], run_n);
@@ -155,15 +191,16 @@ __global__ __launch_bounds__(kThreads) void k_radix_hist(const uint32_t *__restr
     uint32_t c = 0;
 #pragma unroll
     for (int i = 0; i < kWaves; ++i) c += s_h[i][d];
-    hist[((int64_t)seg * 256 + d) * blocks_per_seg + b] = c;
+    hist[(int64_t)si.blk0 * 256 + (int64_t)d * si.bps + si.lb] = c;
 }
 
 // Stable scatter: wave w ranks the contiguous items [w*1024, (w+1)*1024) of
 // the block tile in 16 rounds of 64; equal digits are matched with 8 ballots.
 __global__ __launch_bounds__(kThreads) void k_radix_scatter(const uint32_t *__restrict__ kin, const uint32_t *__restrict__ vin,
                                                             uint32_t *__restrict__ kout, uint32_t *__restrict__ vout,
-                                                            int64_t seg_len, int32_t blocks_per_seg, int32_t shift,
-                                                            const uint32_t *__restrict__ offs)
+                                                            const SegDev *__restrict__ segs, int32_t n_segs,
+                                                            int32_t shift, const uint32_t *__restrict__ offs,
+                                                            const uint32_t *__restrict__ len_dev)
 {
     __shared__ uint32_t s_cnt[kWaves][256];
     __shared__ uint32_t s_dstart[256];
@@ -172,17 +209,15 @@ __global__ __launch_bounds__(kThreads) void k_radix_scatter(const uint32_t *__re
     __shared__ uint32_t s_k[kTile];
     __shared__ uint32_t s_v[kTile];
 
-    const int seg = blockIdx.x / blocks_per_seg, b = blockIdx.x % blocks_per_seg;
+    const SegInfo si = seg_of_block(segs, n_segs, blockIdx.x, len_dev);
     const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
     for (int i = threadIdx.x; i < kWaves * 256; i += kThreads) (&s_cnt[0][0])[i] = 0;
-    s_gofs[threadIdx.x] = offs[((int64_t)seg * 256 + threadIdx.x) * blocks_per_seg + b];
+    s_gofs[threadIdx.x] = offs[(int64_t)si.blk0 * 256 + (int64_t)threadIdx.x * si.bps + si.lb];
     __syncthreads();
 
-    const int64_t t0 = (int64_t)b * kTile;
-    const int64_t nvalid64 = seg_len - t0;
-    const int nvalid = nvalid64 < kTile ? (int)nvalid64 : kTile;
-    const uint32_t *kbase = kin + (int64_t)seg * seg_len + t0;
-    const uint32_t *vbase = vin + (int64_t)seg * seg_len + t0;
+    const int nvalid = si.nvalid;
+    const uint32_t *kbase = kin + si.base;
+    const uint32_t *vbase = vin + si.base;
     const unsigned long long lt = (1ull << lane) - 1ull;
 
     uint32_t key[kItems], val[kItems], rnk[kItems];
@@ -246,24 +281,29 @@ __global__ __launch_bounds__(kThreads) void k_radix_scatter(const uint32_t *__re
 
 // ------------------------------------------------------------- binning ---
 __global__ void k_depth_keys(const float4 *__restrict__ rec, const int32_t *__restrict__ ntiles,
-                             const uint8_t *__restrict__ flags, int64_t total, int64_t n,
-                             uint32_t *__restrict__ keys, uint32_t *__restrict__ vals)
+                             const uint8_t *__restrict__ flags, const ViewDev *__restrict__ views, int32_t n_views,
+                             int64_t total, uint32_t *__restrict__ keys, uint32_t *__restrict__ vals)
 {
     int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= total) return;
-    const bool emits = (flags[i] & 1u) && ntiles[i] > 0;
+    const int v = find_view_of_elem(views, n_views, i);
+    const bool emits = (flags[i] & 1) && ntiles[i] > 0;
     keys[i] = emits ? __float_as_uint(rec[2 * i + 1].z) : 0xFFFFFFFFu;
-    vals[i] = (uint32_t)(i % n);
+    vals[i] = (uint32_t)(i - (int64_t)views[v].elem_off);
 }
 
 __global__ void k_gather_counts(const uint32_t *__restrict__ skeys, const uint32_t *__restrict__ svals,
-                                const int32_t *__restrict__ ntiles, int64_t total, int64_t n,
-                                uint32_t *__restrict__ counts)
+                                const int32_t *__restrict__ ntiles, const ViewDev *__restrict__ views,
+                                int32_t n_views, int64_t total, uint32_t *__restrict__ counts)
 {
     int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= total) return;
-    const int64_t v = i / n;
-    counts[i] = skeys[i] == 0xFFFFFFFFu ? 0u : (uint32_t)ntiles[v * n + svals[i]];
+    if (skeys[i] == 0xFFFFFFFFu) {
+        counts[i] = 0u;
+        return;
+    }
+    const int v = find_view_of_elem(views, n_views, i);
+    counts[i] = (uint32_t)ntiles[(int64_t)views[v].elem_off + svals[i]];
 }
 
 // Emission of the (tile, Gaussian) pairs. Block b handles the depth-sorted
@@ -276,8 +316,8 @@ constexpr int kEmitWin = 4096;
 __global__ __launch_bounds__(kThreads) void k_emit(const uint32_t *__restrict__ skeys, const uint32_t *__restrict__ svals,
                                                    const uint32_t *__restrict__ offsets, const uint32_t *__restrict__ counts,
                                                    const float4 *__restrict__ rec, const short4 *__restrict__ rect,
-                                                   const uint8_t *__restrict__ flags, const CamDev *__restrict__ cams,
-                                                   int64_t total, int64_t n, uint32_t capacity, int32_t tw, int32_t th,
+                                                   const uint8_t *__restrict__ flags, const ViewDev *__restrict__ views,
+                                                   int32_t n_views, int64_t total, uint32_t capacity, int32_t tw, int32_t th,
                                                    float sigma_k, uint32_t *__restrict__ tiles_out,
                                                    uint32_t *__restrict__ vals_out, unsigned long long *__restrict__ status)
 {
@@ -301,14 +341,14 @@ __global__ __launch_bounds__(kThreads) void k_emit(const uint32_t *__restrict__ 
     int W = 0, H = 0;
     const float lim = support_limit(sigma_k);
     if (cnt > 0) {
-        const int64_t vw = i / n;
+        const int vw = find_view_of_elem(views, n_views, i);
         g = svals[i];
-        const int64_t idx = vw * n + g;
+        const ViewDev &C = views[vw];
+        const int64_t idx = (int64_t)C.elem_off + g;
         rc = rect[idx];
         const float4 r0 = rec[2 * idx];
         const float4 r1 = rec[2 * idx + 1];
         q32 = make_conic32(r0.x, r0.y, r0.z, r0.w, r1.x, (flags[idx] & 2u) != 0);
-        const CamDev &C = cams[vw];
         tbase = C.tile_base;
         tiles_x = (uint32_t)C.tiles_x;
         W = C.W;
@@ -378,6 +418,21 @@ __global__ void k_tile_keys(const uint2 *__restrict__ ranges, int64_t n_tiles, u
     vals[t] = (uint32_t)t;
 }
 
+// out[v] = first pair index of view v (offsets at the view's first element),
+// out[n_views] = total pairs; used to plan chunks from one exact count
+__global__ void k_view_offsets(const uint32_t *__restrict__ offsets, const ViewDev *__restrict__ views, int32_t n_views,
+                               int64_t total_elems, const uint32_t *__restrict__ total_pairs, uint32_t *__restrict__ out)
+{
+    const int v = blockIdx.x * blockDim.x + threadIdx.x;
+    if (v > n_views) return;
+    if (v == n_views) {
+        out[v] = *total_pairs;
+        return;
+    }
+    const int64_t e = (int64_t)views[v].elem_off;
+    out[v] = e < total_elems ? offsets[e] : *total_pairs;
+}
+
 inline unsigned grid_for(int64_t n, int threads) { return (unsigned)((n + threads - 1) / threads); }
 
 }  // namespace
@@ -425,30 +480,28 @@ hipError_t scan_exclusive(hipStream_t s, const uint32_t *in, uint32_t *out, int6
 }
 
 // ---- radix sort ----
-size_t radix_ws_bytes(int64_t seg_len, int32_t segs)
+size_t radix_ws_bytes(uint32_t n_blocks)
 {
-    const int64_t bps = (seg_len + kTile - 1) / kTile;
-    const int64_t hist = (int64_t)segs * 256 * bps;
+    const int64_t hist = (int64_t)n_blocks * 256;
     return (size_t)(2 * hist * 4 + scan_levels_bytes(hist) + 512);
 }
 
 hipError_t radix_sort(hipStream_t s, uint32_t *keys, uint32_t *vals, uint32_t *keys_alt, uint32_t *vals_alt,
-                      int64_t seg_len, int32_t segs, int32_t bits, void *ws)
+                      const SegDev *segs, int32_t n_segs, uint32_t n_blocks, int32_t bits, void *ws,
+                      const uint32_t *len_dev)
 {
-    if (seg_len <= 0 || segs <= 0) return hipSuccess;
-    const int32_t bps = (int32_t)((seg_len + kTile - 1) / kTile);
-    const int64_t hist_n = (int64_t)segs * 256 * bps;
+    if (n_blocks == 0 || n_segs == 0) return hipSuccess;
+    const int64_t hist_n = (int64_t)n_blocks * 256;
     uint32_t *hist = (uint32_t *)ws;
     uint32_t *offs = hist + hist_n;
     void *scan_ws = offs + hist_n;
     uint32_t *ki = keys, *vi = vals, *ko = keys_alt, *vo = vals_alt;
-    const unsigned grid = (unsigned)(segs * bps);
     for (int shift = 0; shift < bits; shift += 8) {
-        hipLaunchKernelGGL(k_radix_hist, dim3(grid), dim3(kThreads), 0, s, ki, seg_len, bps, shift, hist);
+        hipLaunchKernelGGL(k_radix_hist, dim3(n_blocks), dim3(kThreads), 0, s, ki, segs, n_segs, shift, hist, len_dev);
         hipError_t e = scan_exclusive(s, hist, offs, hist_n, nullptr, scan_ws);
         if (e != hipSuccess) return e;
-        hipLaunchKernelGGL(k_radix_scatter, dim3(grid), dim3(kThreads), 0, s, ki, vi, ko, vo, seg_len, bps, shift,
-                           (const uint32_t *)offs);
+        hipLaunchKernelGGL(k_radix_scatter, dim3(n_blocks), dim3(kThreads), 0, s, ki, vi, ko, vo, segs, n_segs, shift,
+                           (const uint32_t *)offs, len_dev);
         e = hipGetLastError();
         if (e != hipSuccess) return e;
         uint32_t *tk = ki, *tv = vi;
@@ -458,36 +511,42 @@ hipError_t radix_sort(hipStream_t s, uint32_t *keys, uint32_t *vals, uint32_t *k
 }
 
 hipError_t launch_depth_keys(hipStream_t s, const float *rec, const int32_t *ntiles, const uint8_t *flags,
-                             int64_t n, int32_t n_views, uint32_t *keys, uint32_t *vals)
+                             const ViewDev *views, int32_t n_views, int64_t total, uint32_t *keys, uint32_t *vals)
 {
-    const int64_t total = n * n_views;
     if (total == 0) return hipSuccess;
     hipLaunchKernelGGL(k_depth_keys, dim3(grid_for(total, 256)), dim3(256), 0, s,
-                       reinterpret_cast<const float4 *>(rec), ntiles, flags, total, n, keys, vals);
+                       reinterpret_cast<const float4 *>(rec), ntiles, flags, views, n_views, total, keys, vals);
     return hipGetLastError();
 }
 
 hipError_t launch_gather_counts(hipStream_t s, const uint32_t *sorted_keys, const uint32_t *sorted_vals,
-                                const int32_t *ntiles, int64_t n, int32_t n_views, uint32_t *counts)
+                                const int32_t *ntiles, const ViewDev *views, int32_t n_views, int64_t total,
+                                uint32_t *counts)
 {
-    const int64_t total = n * n_views;
     if (total == 0) return hipSuccess;
     hipLaunchKernelGGL(k_gather_counts, dim3(grid_for(total, 256)), dim3(256), 0, s, sorted_keys, sorted_vals,
-                       ntiles, total, n, counts);
+                       ntiles, views, n_views, total, counts);
     return hipGetLastError();
 }
 
 hipError_t launch_emit(hipStream_t s, const uint32_t *sorted_keys, const uint32_t *sorted_vals,
                        const uint32_t *offsets, const uint32_t *counts, const float *rec, const int16_t *rect,
-                       const uint8_t *flags, const CamDev *cams_dev, int64_t n, int32_t n_views, uint32_t capacity,
-                       int32_t tile_w, int32_t tile_h, float sigma_k, uint32_t *tiles_out, uint32_t *vals_out,
-                       unsigned long long *status)
+                       const uint8_t *flags, const ViewDev *views, int32_t n_views, int64_t total,
+                       uint32_t capacity, int32_t tile_w, int32_t tile_h, float sigma_k, uint32_t *tiles_out,
+                       uint32_t *vals_out, unsigned long long *status)
 {
-    const int64_t total = n * n_views;
     if (total == 0) return hipSuccess;
     hipLaunchKernelGGL(k_emit, dim3(grid_for(total, kThreads)), dim3(kThreads), 0, s, sorted_keys, sorted_vals, offsets,
                        counts, reinterpret_cast<const float4 *>(rec), reinterpret_cast<const short4 *>(rect), flags,
-                       cams_dev, total, n, capacity, tile_w, tile_h, sigma_k, tiles_out, vals_out, status);
+                       views, n_views, total, capacity, tile_w, tile_h, sigma_k, tiles_out, vals_out, status);
+    return hipGetLastError();
+}
+
+hipError_t launch_view_offsets(hipStream_t s, const uint32_t *offsets, const ViewDev *views, int32_t n_views,
+                               int64_t total_elems, const uint32_t *total_pairs, uint32_t *out)
+{
+    hipLaunchKernelGGL(k_view_offsets, dim3(grid_for(n_views + 1, 256)), dim3(256), 0, s, offsets, views, n_views,
+                       total_elems, total_pairs, out);
     return hipGetLastError();
 }
 

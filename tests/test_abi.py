@@ -47,3 +47,40 @@ def test_defaults_and_host_side_validation(lib):
     assert lib.fs_error_string(L.FS_ERR_CAPACITY) == b"output capacity too small"
     st = L.FsStatus()
     assert lib.fs_status_get(None, ctypes.byref(st), 0) == L.FS_ERR_ARG
+
+
+def test_batch_defaults_and_null_handling(lib):
+    from paper_2409_08270_amd import _lib as L
+    o = L.batch_opts()
+    assert (o.pair_budget, o.elem_budget, o.zero_accumulators, o.use_graph, o.reduction) == (0, 0, 1, 1, L.FS_RED_AUTO)
+    out = ctypes.c_void_p()
+    assert lib.fs_batch_create(None, None, 0, None, None, ctypes.byref(out)) == L.FS_ERR_ARG
+    assert lib.fs_batch_run(None) == L.FS_ERR_ARG
+    assert lib.fs_batch_destroy(None) == L.FS_ERR_ARG
+    inf = L.FsBatchInfo()
+    assert lib.fs_batch_get_info(None, ctypes.byref(inf)) == L.FS_ERR_ARG
+
+
+def test_struct_layouts_match_the_header(tmp_path):
+    """sizeof/offsetof of every public struct, from a C compiler, against the ctypes mirror."""
+    import subprocess
+    from paper_2409_08270_amd import _lib as L
+    structs = {"fs_gaussians": L.FsGaussians, "fs_camera": L.FsCamera, "fs_params": L.FsParams,
+               "fs_proj": L.FsProj, "fs_bins": L.FsBins, "fs_pixel_out": L.FsPixelOut, "fs_status": L.FsStatus,
+               "fs_scene": L.FsScene, "fs_batch_opts": L.FsBatchOpts, "fs_batch_info": L.FsBatchInfo}
+    lines = ['#include <stdio.h>', '#include <stddef.h>', f'#include "{HEADER}"', "int main(void) {"]
+    for cname, cls in structs.items():
+        lines.append(f'printf("{cname} %zu\\n", sizeof({cname}));')
+        for f, _ in cls._fields_:
+            lines.append(f'printf("{cname}.{f} %zu\\n", offsetof({cname}, {f}));')
+    lines.append("return 0; }")
+    src = tmp_path / "layout.c"
+    src.write_text("\n".join(lines))
+    exe = tmp_path / "layout"
+    subprocess.run(["gcc", "-std=c99", "-o", str(exe), str(src)], check=True)
+    got = dict(l.rsplit(" ", 1) for l in subprocess.run([str(exe)], check=True, capture_output=True,
+                                                       text=True).stdout.split("\n") if l)
+    for cname, cls in structs.items():
+        assert int(got[cname]) == ctypes.sizeof(cls), cname
+        for f, _ in cls._fields_:
+            assert int(got[f"{cname}.{f}"]) == getattr(cls, f).offset, f"{cname}.{f}"

@@ -1,0 +1,169 @@
+"""The batched solve (fs_batch_*): many scenes of uneven size, every view, the
+assignment included, in one hipGraph launch. Checked against the oracle per
+scene, against itself across chunkings and graph replays, and against the
+single-scene calls."""
+import numpy as np
+import pytest
+import torch
+
+import oracle as O
+import scenegen as sg
+from paper_2409_08270_amd import _lib as L
+from paper_2409_08270_amd.solve import Solver
+from tests._parity import assert_A, assert_labels, log
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    return L.Context()
+
+
+def _uneven_scenes():
+    """Three small scenes: different Gaussian counts, view counts, image sizes
+    (one ragged) and class counts."""
+    a = sg.make_config("C1", n=900, views=2, res=64)
+    b = sg.make_config("C1", seed=11, n=2300, views=4, res=100)
+    c = sg.make_config("C1", seed=12, n=1500, views=3, res=80)
+    rng = np.random.default_rng(7)
+    # scene c: 5 classes in blocks, plus 1% relabels
+    for i, m in enumerate(c.masks):
+        base = ((np.arange(80)[None, :] // 20) + (np.arange(80)[:, None] // 40) + i) % 5
+        noise = rng.random(m.shape) < 0.01
+        c.masks[i] = np.where(noise, rng.integers(0, 5, size=m.shape), base).astype(np.uint8)
+    c.E = 5
+    return [a, b, c]
+
+
+def _A(batch, i):
+    A = batch.A_hi[i].double()
+    if batch.A_lo[i] is not None:
+        A = A + batch.A_lo[i].double()
+    return A.cpu().numpy()
+
+
+def test_multi_scene_batch_matches_the_oracle(ctx):
+    scenes = _uneven_scenes()
+    gammas = [0.0, 0.3, -0.2]
+    dss = [L.DeviceScene(s) for s in scenes]
+    log("[batch] 3 scenes, one graph")
+    b = L.Batch(ctx, dss, L.params(), gammas=gammas, want_margin=True)
+    b.run()
+    torch.cuda.synchronize()
+    st = ctx.status()
+    info = b.info()
+    assert info["n_chunks"] == 1 and info["n_views"] == 9
+    blends = 0
+    for i, sc in enumerate(scenes):
+        ref = O.solve64(sc, O.params())
+        blends += ref["blends"]
+        assert_A(_A(b, i), ref["A"], ref["slack"], what=f"batch scene {i}")
+        S64, m64 = O.assign64(ref["A"], gammas[i])
+        assert_labels(b.S[i].cpu().numpy(), S64, m64, ref["A"], ref["slack"], what=f"batch scene {i}")
+        # margins are |a_n - o_n - gamma| of the normalised sums (Eq. (7)), within the A tolerance
+        mg = b.margin[i].cpu().numpy()
+        assert np.all(mg >= 0)
+        assert np.quantile(np.abs(mg - m64), 0.99) <= 1e-3
+    assert abs(st["blends"] - blends) <= 1e-3 * blends
+
+
+def test_chunked_batch_equals_one_chunk(ctx):
+    scenes = _uneven_scenes()
+    dss = [L.DeviceScene(s) for s in scenes]
+    one = L.Batch(ctx, dss, L.params())
+    one.run()
+    # budgets that force a chunk boundary inside scenes
+    many = L.Batch(ctx, dss, L.params(), elem_budget=5000, pair_budget=20000)
+    many.run()
+    torch.cuda.synchronize()
+    ctx.status()
+    assert many.info()["n_chunks"] >= 3
+    assert many.info()["pairs"] == one.info()["pairs"]
+    for i in range(len(scenes)):
+        a, c = _A(one, i), _A(many, i)
+        d = np.abs(a - c).sum(1)
+        s = np.abs(a).sum(1)
+        assert np.all(d <= 1e-5 * s + 1e-9), f"scene {i}"
+        # summation order differs between chunkings: labels may differ only where the margin is in the last bits
+        diff = one.S[i].cpu().numpy() != many.S[i].cpu().numpy()
+        assert diff.sum() <= 2, f"scene {i}: {int(diff.sum())} label flips"
+
+
+def test_graph_replays_match_the_eager_enqueue(ctx):
+    scenes = _uneven_scenes()[:2]
+    dss = [L.DeviceScene(s) for s in scenes]
+    eager = L.Batch(ctx, dss, L.params(), use_graph=0)
+    eager.run()
+    torch.cuda.synchronize()
+    want = [_A(eager, i) for i in range(2)]
+    want_S = [eager.S[i].cpu().numpy() for i in range(2)]
+    g = L.Batch(ctx, dss, L.params(), use_graph=1)
+    for rep in range(4):
+        # unrelated eager work and synchronisations between the replays
+        x = torch.randn(1 << 20, device="cuda")
+        (x * 2).sum().item()
+        g.run()
+        torch.cuda.synchronize()
+        for i in range(2):
+            a = _A(g, i)
+            d = np.abs(a - want[i]).sum(1)
+            s = np.abs(want[i]).sum(1)
+            assert np.all(d <= 1e-5 * s + 1e-9), f"replay {rep} scene {i}"
+            # labels differ only where the bias-free margin sits in the last bits
+            diff = g.S[i].cpu().numpy() != want_S[i]
+            assert diff.sum() <= 2, f"replay {rep} scene {i}: {int(diff.sum())} label flips"
+    st = ctx.status()
+    assert st["flags"] & (L.FS_DEV_PAIR_OVERFLOW | L.FS_DEV_BAD_LABEL) == 0
+
+
+def test_accumulating_runs_add_up(ctx):
+    sc = sg.make_config("C1", n=1200, views=3, res=72)
+    ds = L.DeviceScene(sc)
+    b = L.Batch(ctx, [ds], L.params(), zero_accumulators=0, want_labels=False)
+    b.run()
+    torch.cuda.synchronize()
+    once = _A(b, 0)
+    b.run()
+    torch.cuda.synchronize()
+    twice = _A(b, 0)
+    d = np.abs(twice - 2 * once).sum(1)
+    assert np.all(d <= 1e-5 * np.abs(once).sum(1) + 1e-9)
+
+
+def test_batch_equals_single_scene_calls(ctx):
+    sc = sg.make_config("C1", n=2000, views=5, res=96)
+    ds = L.DeviceScene(sc)
+    b = L.Batch(ctx, [ds], L.params(), gammas=[0.2])
+    b.run()
+    out = Solver(ctx, ds).solve(chunk=5, gamma=0.2)
+    torch.cuda.synchronize()
+    ctx.status()
+    a = _A(b, 0)
+    c = (out["A_hi"].double() + out["A_lo"].double()).cpu().numpy()
+    d = np.abs(a - c).sum(1)
+    assert np.all(d <= 1e-5 * np.abs(c).sum(1) + 1e-9)
+
+
+def test_batch_with_an_empty_scene(ctx):
+    empty = sg.make_custom(np.zeros((0, 3)), np.zeros((0, 3)), np.zeros((0, 4)), np.zeros(0),
+                           [(np.eye(3), np.zeros(3))], W=40, H=24)
+    sc = sg.make_config("C1", n=800, views=2, res=64)
+    dss = [L.DeviceScene(empty), L.DeviceScene(sc)]
+    b = L.Batch(ctx, dss, L.params())
+    b.run()
+    torch.cuda.synchronize()
+    ctx.status()
+    ref = O.solve64(sc, O.params())
+    assert_A(_A(b, 1), ref["A"], ref["slack"], what="next to an empty scene")
+
+
+def test_batch_rejects_bad_arguments(ctx):
+    sc = sg.make_config("C1", n=300, views=1, res=32)
+    ds = L.DeviceScene(sc)
+    with pytest.raises(L.FlashSplatError):
+        L.Batch(ctx, [ds], L.params(tile_order=2))
+    with pytest.raises(L.FlashSplatError):
+        L.Batch(ctx, [ds], L.params(), gammas=[1.5])
+    with pytest.raises(L.FlashSplatError):
+        L.Batch(ctx, [ds], L.params(), compensated=False, reduction=L.FS_RED_LDS2SUM)
