@@ -9,9 +9,9 @@
  *   fs_bin_sort    16x16 tile lists in depth order (Sec. 3.1)
  *   fs_accumulate  front-to-back alpha compositing (Eq. (1)); every weight
  *                  w = alpha*T is added into A[g][label(pixel)]
- *                  (Eq. (6), Eq. (7), Supp. Sec. 6)
+ *                  (Eq. (7), Eq. (8), Listing 1 of the supplement)
  *   fs_assign      closed-form, L1-normalised, background-biased argmax per
- *                  object (Sec. 3.2 "Regularized ILP", Eq. (7), Supp. Sec. 6)
+ *                  object (Sec. 3.2 "Regularized ILP", Eq. (8), Listing 1 of the supplement)
  *
  * Conventions shared by all calls
  *  - Memory: every array argument documented as "device" is device memory
@@ -195,7 +195,7 @@ int fs_project(fs_ctx *ctx, const fs_gaussians *g, const fs_camera *cams, int32_
 int fs_bin_sort(fs_ctx *ctx, const fs_proj *proj, const fs_camera *cams, const fs_params *p,
                 const fs_bins *out, int64_t *n_pairs);
 
-/* a6: compositing and accumulation (Eq. (1), Eq. (6)-(7), Supp. Sec. 6).
+/* a6: compositing and accumulation (Eq. (1), Eq. (7)-(8), Listing 1 of the supplement).
  * For every pixel of every view, front to back over its tile's list:
  * alpha = min(alpha_max, o*exp(-d^T conic d / 2)) for pixels within the
  * support; Gaussians with alpha < alpha_min are skipped; compositing stops
@@ -210,8 +210,8 @@ int fs_accumulate(fs_ctx *ctx, const fs_proj *proj, const fs_bins *bins, const f
                   const uint8_t *masks, int32_t n_classes, const fs_params *p,
                   float *A_hi, float *A_lo, int32_t reduction, const fs_pixel_out *pix);
 
-/* a7: assignment (Sec. 3.2 Eq. (6) and "Regularized ILP"; Sec. 3.3 Eq. (7);
- * Supp. Sec. 6 and its listing). For every Gaussian g and object t:
+/* a7: assignment (Sec. 3.2 Eq. (7) and "Regularized ILP"; Sec. 3.3 Eq. (8);
+ * Listing 1 of the supplement). For every Gaussian g and object t:
  * a = A[g][t], o = sum_{e != t} A[g][e] (prefix + suffix sums, no
  * subtraction), (o_n, a_n) = (o, a) / max(o + a, 1e-12);
  * S[t][g] = a_n > o_n + gamma (ties go to "others"); margin[t][g] =
@@ -224,9 +224,9 @@ int fs_assign(fs_ctx *ctx, const float *A_hi, const float *A_lo, int64_t n, int3
 
 /* Batched solve ------------------------------------------------------------
  * Many scenes of uneven size, all their views, in one graph launch: the
- * splat-and-accumulate pass is a sum over views (Eq. (6)), so views of all
+ * splat-and-accumulate pass is a sum over views (Eq. (7)), so views of all
  * scenes are projected, binned and composited together, in chunks that fit a
- * bounded workspace, and every scene's assignment follows (Eq. (7)).
+ * bounded workspace, and every scene's assignment follows (Eq. (8)).
  * fs_batch_create plans the work (one exact counting pass and one read-back of
  * the per-view pair counts), allocates the workspace and captures the whole
  * solve into a hipGraph; fs_batch_run replays it on the context's stream.

@@ -9,13 +9,13 @@ Pieces (paper sections in brackets):
                          [Sec. 3.1]; the reference of the bit-exact contract
   project64              binary64 mean2D / conic [Sec. 3.1]
   composite64 / solve64  binary64 alpha compositing, A = sum of alpha*T per
-                         (Gaussian, pixel label) [Eq. (1), Eq. (6), Eq. (7),
-                         Supp. Sec. 6]
+                         (Gaussian, pixel label) [Eq. (1), Eq. (7), Eq. (8),
+                         Listing 1 of the supplement]
   render64               Eq. (1) with an arbitrary per-Gaussian property
   weights64              dense per-pixel weights (tiny scenes only)
   assign64               L1-normalised, background-biased argmax per object
-                         [Sec. 3.2 "Regularized ILP", Eq. (7), Supp. Sec. 6]
-  objective_eq2 / brute_force_binary   exhaustive checks of Eq. (2)/(5)
+                         [Sec. 3.2 "Regularized ILP", Eq. (8), Listing 1 of the supplement]
+  objective_eq2 / brute_force_binary   exhaustive checks of Eq. (2)/(6)
 """
 from __future__ import annotations
 
@@ -218,7 +218,7 @@ def weights64(scene, v: int, prm: np.ndarray) -> np.ndarray:
 # assignment
 
 def assign64(A: np.ndarray, gamma: float = 0.0):
-    """Closed-form assignment for every object t (Eq. (7), Sec. 3.2 bias).
+    """Closed-form assignment for every object t (Eq. (8), Sec. 3.2 bias).
 
     For row g and object t: a = A[g,t], o = sum_{e != t} A[g,e] (others);
     normalise (o, a) by max(o + a, 1e-12) (L1 normalisation as in the

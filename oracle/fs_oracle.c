@@ -7,7 +7,7 @@
  * It shares no source with the GPU library.
  *
  * What it computes (paper: Sec. 3.1 "Preliminary: Rasterization of 3DGS",
- * Eq. (1); Sec. 3.2 Eq. (6); Sec. 3.3 Eq. (7); Supp. Sec. 6):
+ * Eq. (1); Sec. 3.2 Eq. (7); Sec. 3.3 Eq. (8); Listing 1 of the supplement):
  *
  *   A[g][e] = sum over views v, pixels (j,k) with M^v[j][k] == e of
  *             alpha_g(v,j,k) * T_g(v,j,k)
@@ -354,7 +354,7 @@ void or_project64(int64_t n, const float *gauss, const float *cam, const float *
 
 /* ------------------------------------------------------------------------
  * binary64 compositing of one view with accumulation into A (Eq. (1),
- * Eq. (6)-(7), Supp. Sec. 6). For every pixel, front to back over its
+ * Eq. (7)-(8), Listing 1 of the supplement). For every pixel, front to back over its
  * tile's list:
  *   d = pixel_centre - mean2D
  *   power = -0.5 (cxx dx^2 + cyy dy^2) - cxy dx dy
@@ -526,7 +526,7 @@ void or_render64(int64_t n, const double *p64, const float *opacity, const float
 /* ------------------------------------------------------------------------
  * Dense per-pixel weights for tiny scenes: wout double [H*W][n] receives
  * alpha_i T_i for every Gaussian added at every pixel (same rules as
- * or_composite64). Used by the exhaustive checks of Eq. (2) and Eq. (5).
+ * or_composite64). Used by the exhaustive checks of Eq. (2) and Eq. (6).
  * ---------------------------------------------------------------------- */
 void or_weights64(int64_t n, const double *p64, const float *opacity, const float *cam,
                   const float *prm, const uint32_t *list, const uint32_t *ranges, double *wout)

@@ -25,7 +25,6 @@ SOURCES = {
     "fs_accum.hip": ["-ffp-contract=fast"],
     "fs_assign.hip": [],
     "fs_api.hip": [],
-    "fs_batch.hip": [],
 }
 
 COMMON = [

@@ -1,6 +1,6 @@
 // a6: front-to-back alpha compositing with accumulation of every weight
-// w = alpha * T into A[g][label(pixel)] (paper Eq. (1), Eq. (6)-(7),
-// Supp. Sec. 6).
+// w = alpha * T into A[g][label(pixel)] (paper Eq. (1), Eq. (7)-(8),
+// Listing 1 of the supplement).
 //
 // One workgroup of 256 threads composites one tile of 256 pixels; each wave
 // owns an 8x8 block of the tile. The tile's depth-ordered list is staged

@@ -1,6 +1,6 @@
-// a7: closed-form assignment (paper Sec. 3.2 Eq. (6) and the background
-// bias of "Regularized ILP for Noise Reduction"; Sec. 3.3 Eq. (7); Supp.
-// Sec. 6). For Gaussian g and object t: a = A[g][t], o = sum of the other
+// a7: closed-form assignment (paper Sec. 3.2 Eq. (7) and the background
+// bias of "Regularized ILP for Noise Reduction"; Sec. 3.3 Eq. (8); Listing 1
+// of the supplement). For Gaussian g and object t: a = A[g][t], o = sum of the other
 // objects' contributions, (o_n, a_n) = (o, a) / max(o + a, 1e-12);
 // S[t][g] = a_n > o_n + gamma (ties go to "others", the first index of the
 // argmax); margin = |a_n - o_n - gamma|.

@@ -5,7 +5,7 @@ plain:   one fs_project / fs_bin_sort / fs_accumulate per view, with the
 chunked: the same calls over a chunk of views at once: Gaussians are read once
          per chunk and every kernel covers all tiles of the chunk.
 
-Both add into the same A (A is a sum over views, Eq. (6)), then fs_assign
+Both add into the same A (A is a sum over views, Eq. (7)), then fs_assign
 produces the labels. Only argument marshalling and the loop over views or
 chunks live here; all arithmetic runs in the library's kernels.
 """

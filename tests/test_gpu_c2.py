@@ -91,7 +91,7 @@ def test_batched_equals_per_view(c2):
 
 
 def test_column_sums_equal_accumulated_alpha_per_label(c2):
-    # Eq. (6): column e of A = sum over pixels labelled e of (1 - T_final)
+    # Eq. (7): column e of A = sum over pixels labelled e of (1 - T_final)
     sc, ds, ctx, solver, out, st = c2
     n, E = sc.n, sc.E
     A_hi = torch.zeros((n, E), dtype=torch.float32, device="cuda")

@@ -1,6 +1,6 @@
 """Pins of the oracle's closed-form assignment (CPU only).
 
-The closed form (Eq. (6); Eq. (7) per object; L1 normalisation and the
+The closed form (Eq. (7); Eq. (8) per object; L1 normalisation and the
 background bias of Sec. 3.2) is checked against an exhaustive search over
 every labelling of Eq. (2) on tiny scenes, against an independent PyTorch
 formulation built from library routines (L1 normalize, argmax with
@@ -27,7 +27,7 @@ def test_closed_form_attains_the_exhaustive_optimum_of_eq2(seed, masks):
     S, margin = O.assign64(A, 0.0)
     P = S[1].astype(np.float64)
     assert O.objective_eq2(Ws, sc.masks, P) == pytest.approx(best, rel=1e-12, abs=1e-12)
-    # every labelling's objective is C + sum_i P_i (A0 - A1)  (Eq. (5))
+    # every labelling's objective is C + sum_i P_i (A0 - A1)  (Eq. (6))
     C = sum(float(m.sum()) for m in sc.masks)
     n = sc.n
     codes = np.arange(1 << n)
@@ -37,7 +37,7 @@ def test_closed_form_attains_the_exhaustive_optimum_of_eq2(seed, masks):
 
 def test_multi_object_closed_form_is_optimal_per_object():
     # scene segmentation: for object t, S[t] minimises Eq. (2) against the
-    # binary mask 1(M == t) (Eq. (7) with A_0 = A_others)
+    # binary mask 1(M == t) (Eq. (8) with A_0 = A_others)
     sc = sg.make_tiny(31, n=10, views=3, res=32, E=4, masks="random")
     Ws = [O.weights64(sc, v, PRM) for v in range(sc.n_views)]
     A = O.solve64(sc, PRM)["A"]

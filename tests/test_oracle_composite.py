@@ -3,7 +3,7 @@
 Expected values come from closed forms (one or two Gaussians, with alpha from
 an explicit matrix inverse), from invariants that the paper's formulation
 implies (Eq. (1): the blend weights and the final transmittance telescope to
-one; Lemma 1; Eq. (6): the columns of A partition the accumulated alpha by
+one; Lemma 1; Eq. (7): the columns of A partition the accumulated alpha by
 label; A is a sum over views), and from an independent rendering of Eq. (1).
 """
 import math
@@ -99,7 +99,7 @@ def test_partition_of_unity_and_all_ones_render():
         # rendering Eq. (1) with x_i = 1 reproduces the accumulated alpha
         ones = O.render64(sc, v, PRM, np.ones(sc.n), bins=b, p64=p64)
         assert np.allclose(ones, 1.0 - tf, rtol=0, atol=1e-12)
-        # Eq. (6): column e of A = accumulated alpha over pixels labelled e
+        # Eq. (7): column e of A = accumulated alpha over pixels labelled e
         for e in range(sc.E):
             assert A[:, e].sum() == pytest.approx((1.0 - tf)[sc.masks[v] == e].sum(), rel=1e-10)
         # the same weights, aggregated per Gaussian, give A
@@ -120,7 +120,7 @@ def test_view_additivity_and_label_permutation():
 
 
 def test_eq2_equals_eq5_for_random_labellings():
-    # Eq. (2) evaluated by rendering the labelling equals C + sum_i P_i (A0 - A1) (Eq. (5))
+    # Eq. (2) evaluated by rendering the labelling equals C + sum_i P_i (A0 - A1) (Eq. (6))
     for seed in (11, 12):
         sc = sg.make_tiny(seed, n=10, views=3, res=32, masks="raycast")
         Ws = [O.weights64(sc, v, PRM) for v in range(sc.n_views)]
