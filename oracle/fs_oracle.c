@@ -41,67 +41,69 @@ enum { P_TW, P_TH, P_K, P_LP, P_ZN, P_GUARD, P_AMIN, P_AMAX, P_TMIN, P_COND, P_E
 
 /* ------------------------------------------------------------------------
  * Which tiles of a Gaussian's rectangle are listed (strict binary32, fixed
- * order). A tile can hold a pixel centre inside the support ellipse
- * q(d) = A dx^2 + 2B dx dy + C dy^2 <= k^2 (A, B, C = the float32 conic
- * c/det, -b/det, a/det) only if the minimum of q over the bounding box of its
- * pixel centres is <= k^2; that minimum is zero when the mean is inside the
- * box and otherwise the least of the four edge minima, each at the clamped
- * vertex of a 1D parabola (vertex offsets use the reciprocals 1/A and 1/C,
- * rounded once). A tile passes when the minimum is <= k^2 (1 + 2^-9), a
- * margin far above the rounding of a float32 conic that passed the
- * conditioning predicate. In each tile row the listed tiles are the span from
- * the first to the last passing tile (the ellipse meets a row in a convex set,
- * so the passing tiles are contiguous up to rounding). Splats that fail the
- * predicate (flag bit 1) list every tile of their rectangle.
+ * order). The support is the ellipse q(d) = A dx^2 + 2B dx dy + C dy^2 <= L,
+ * with (A, B, C) the float32 conic (c/det, -b/det, a/det) and
+ * L = k^2 (1 + 2^-7), a margin far above the rounding of a float32 conic that
+ * passed the conditioning predicate.
+ *
+ * Tile row ty covers pixel-centre offsets y in [y0, y1] from the mean. The
+ * ellipse reaches |y| <= ye = sqrt(L A / dt) (dt = AC - B^2); its left-most
+ * point is (-xe, yx) with xe = sqrt(L C / dt), yx = B xe / C, its right-most
+ * point (xe, -yx). At height y it spans x = (-B y -/+ sqrt(A L - dt y^2)) / A.
+ * The left edge is convex in y and the right edge concave, so over the band
+ * (clipped to |y| <= ye) the least x is -xe if yx lies in the band, else the
+ * left edge at the band end nearer to yx; the greatest x likewise. The row
+ * lists the tiles holding a pixel-centre column k with k + 0.5 - u in
+ * [Xmin, Xmax], inside the image and the tile rectangle. Splats that fail the
+ * conditioning predicate (flag bit 1) list their whole rectangle.
  * ---------------------------------------------------------------------- */
-typedef struct { float u, v, A, B, C, iA, iC; int full; } conic32_t;
+typedef struct { float u, v, A, B, dt, lim, xe, ye, yx; int full; } span32_t;
 
-static conic32_t conic32(float u, float v, float a, float b, float c, uint8_t f)
+static span32_t span32(float u, float v, float a, float b, float c, uint8_t f, float k)
 {
-    conic32_t q;
-    q.u = u; q.v = v;
-    q.full = (f & 2) != 0;
+    span32_t s;
+    s.u = u; s.v = v;
+    s.full = (f & 2) != 0;
     float det = a * c - b * b;
-    q.A = c / det; q.B = -b / det; q.C = a / det;
-    q.iA = 1.0f / q.A; q.iC = 1.0f / q.C;
-    return q;
+    float A = c / det, B = -b / det, C = a / det;
+    s.A = A; s.B = B;
+    s.lim = (k * k) * 1.0078125f;
+    s.dt = A * C - B * B;
+    s.xe = sqrtf((s.lim * C) / s.dt);
+    s.ye = sqrtf((s.lim * A) / s.dt);
+    s.yx = (B * s.xe) / C;
+    return s;
 }
 
-static int tile_hit32(const conic32_t *q, int tx, int ty, int tw, int th, int W, int H, float k)
+/* x of the ellipse boundary at offset y: left edge (sgn -1) or right (+1) */
+static float edge_x32(const span32_t *s, float y, float sgn)
 {
-    int x1 = tx * tw + tw - 1, y1 = ty * th + th - 1;
-    if (x1 > W - 1) x1 = W - 1;
-    if (y1 > H - 1) y1 = H - 1;
-    float xl = ((float)(tx * tw) + 0.5f) - q->u, xh = ((float)x1 + 0.5f) - q->u;
-    float yl = ((float)(ty * th) + 0.5f) - q->v, yh = ((float)y1 + 0.5f) - q->v;
-    if (xl <= 0.0f && xh >= 0.0f && yl <= 0.0f && yh >= 0.0f) return 1;
-    float lim = (k * k) * 1.001953125f;
-    float ex[2] = {xl, xh}, ey[2] = {yl, yh};
-    for (int i = 0; i < 2; ++i) {
-        /* edge dx = ex[i], dy in [yl, yh] */
-        float x = ex[i];
-        float y = fminf(fmaxf(-(q->B * x) * q->iC, yl), yh);
-        float e = (q->A * x) * x + (2.0f * (q->B * x)) * y + (q->C * y) * y;
-        if (e <= lim) return 1;
-        /* edge dy = ey[i], dx in [xl, xh] */
-        float y2 = ey[i];
-        float x2 = fminf(fmaxf(-(q->B * y2) * q->iA, xl), xh);
-        float e2 = (q->A * x2) * x2 + (2.0f * (q->B * x2)) * y2 + (q->C * y2) * y2;
-        if (e2 <= lim) return 1;
-    }
-    return 0;
+    float r = sqrtf(fmaxf((s->A * s->lim) - (s->dt * y) * y, 0.0f));
+    return (-(s->B * y) + sgn * r) / s->A;
 }
 
-/* listed span [*l, *r] of tile row ty within columns [x0, x1]; returns 0 if empty */
-static int row_span32(const conic32_t *q, int ty, int x0, int x1, int tw, int th, int W, int H, float k,
-                      int *l, int *r)
+/* listed span [*l, *r] of tile row ty within tile columns [x0, x1]; returns 0 if empty */
+static int row_span32(const span32_t *s, int ty, int x0, int x1, int tw, int th, int W, int H, int *l, int *r)
 {
-    if (q->full) { *l = x0; *r = x1; return 1; }
-    int a = x0;
-    while (a <= x1 && !tile_hit32(q, a, ty, tw, th, W, H, k)) ++a;
-    if (a > x1) return 0;
-    int b = x1;
-    while (b > a && !tile_hit32(q, b, ty, tw, th, W, H, k)) --b;
+    if (s->full) { *l = x0; *r = x1; return 1; }
+    int j1 = ty * th + th - 1;
+    if (j1 > H - 1) j1 = H - 1;
+    float y0 = ((float)(ty * th) + 0.5f) - s->v;
+    float y1 = ((float)j1 + 0.5f) - s->v;
+    float lo = fmaxf(y0, -s->ye), hi = fminf(y1, s->ye);
+    if (!(lo <= hi)) return 0;
+    float yl = s->yx, yr = -s->yx, xmin, xmax;
+    if (yl >= lo && yl <= hi) xmin = -s->xe;
+    else xmin = edge_x32(s, yl < lo ? lo : hi, -1.0f);
+    if (yr >= lo && yr <= hi) xmax = s->xe;
+    else xmax = edge_x32(s, yr < lo ? lo : hi, 1.0f);
+    float kl = fmaxf(ceilf((s->u + xmin) - 0.5f), 0.0f);
+    float kr = fminf(floorf((s->u + xmax) - 0.5f), (float)(W - 1));
+    if (!(kl <= kr)) return 0;
+    int a = (int)kl / tw, b = (int)kr / tw;
+    if (a < x0) a = x0;
+    if (b > x1) b = x1;
+    if (a > b) return 0;
     *l = a; *r = b;
     return 1;
 }
@@ -213,11 +215,11 @@ static void proj32_one(const float *gin /*11*/, const float *cam, const float *p
     int jmin = (int)fmaxf(fj0, 0.0f), jmax = (int)fminf(fj1, (float)(H - 1));
     int tw = (int)prm[P_TW], th = (int)prm[P_TH];
     rect[0] = kmin / tw; rect[1] = jmin / th; rect[2] = kmax / tw; rect[3] = jmax / th;
-    conic32_t q32 = conic32(u, v, a, b, c, f);
+    span32_t sp = span32(u, v, a, b, c, f, prm[P_K]);
     int nt = 0;
     for (int ty = rect[1]; ty <= rect[3]; ++ty) {
         int l, r;
-        if (row_span32(&q32, ty, rect[0], rect[2], tw, th, W, H, prm[P_K], &l, &r)) nt += r - l + 1;
+        if (row_span32(&sp, ty, rect[0], rect[2], tw, th, W, H, &l, &r)) nt += r - l + 1;
     }
     *ntiles = nt;
 }
@@ -266,10 +268,10 @@ int64_t or_bin(int64_t n, const uint8_t *flags, const int32_t *rect, const int32
     int64_t k = 0;
     for (int64_t g = 0; g < n; ++g) {
         if (!(flags[g] & 1) || ntiles[g] == 0) continue;
-        conic32_t q32 = conic32(mean2d[2 * g], mean2d[2 * g + 1], cov[3 * g], cov[3 * g + 1], cov[3 * g + 2], flags[g]);
+        span32_t sp = span32(mean2d[2 * g], mean2d[2 * g + 1], cov[3 * g], cov[3 * g + 1], cov[3 * g + 2], flags[g], prm[P_K]);
         for (int ty = rect[4 * g + 1]; ty <= rect[4 * g + 3]; ++ty) {
             int l, r;
-            if (!row_span32(&q32, ty, rect[4 * g + 0], rect[4 * g + 2], tw, th, W, H, prm[P_K], &l, &r)) continue;
+            if (!row_span32(&sp, ty, rect[4 * g + 0], rect[4 * g + 2], tw, th, W, H, &l, &r)) continue;
             for (int tx = l; tx <= r; ++tx) {
                 p[k].tile = ty * tiles_x + tx;
                 p[k].depth = depth[g];

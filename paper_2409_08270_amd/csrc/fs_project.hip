@@ -159,13 +159,12 @@ __global__ __launch_bounds__(256) void k_project(const ProjTask *__restrict__ ta
                         int jmin = (int)fmaxf(fj0, 0.0f), jmax = (int)fminf(fj1, (float)(C.H - 1));
                         int x0 = kmin / P.tile_w, y0 = jmin / P.tile_h, x1 = kmax / P.tile_w, y1 = jmax / P.tile_h;
                         rc = make_short4((short)x0, (short)y0, (short)x1, (short)y1);
-                        // tiles of the rectangle that the support ellipse reaches; the test
-                        // uses the float32 conic computed above (c/det, -b/det, a/det)
-                        const Conic32 q32 = make_conic32(u, vv, ca, cb, cc, deg);
-                        const float lim = support_limit(P.sigma_k);
+                        // tiles of the rectangle that the support ellipse reaches, row by row,
+                        // from the float32 conic computed above (c/det, -b/det, a/det)
+                        const Span32 sp = make_span32(u, vv, ca, cb, cc, deg, support_limit(P.sigma_k));
                         for (int ty = y0; ty <= y1; ++ty) {
                             int l, r;
-                            if (row_span(q32, ty, x0, x1, P.tile_w, P.tile_h, C.W, C.H, lim, l, r)) nt += r - l + 1;
+                            if (row_span(sp, ty, x0, x1, P.tile_w, P.tile_h, C.W, C.H, l, r)) nt += r - l + 1;
                         }
                     }
                 }

@@ -337,9 +337,8 @@ __global__ __launch_bounds__(kThreads) void k_emit(const uint32_t *__restrict__ 
 
     uint32_t g = 0, tbase = 0, tiles_x = 0;
     short4 rc = make_short4(0, 0, -1, -1);
-    Conic32 q32 = make_conic32(0.f, 0.f, 1.f, 0.f, 1.f, true);
+    Span32 sp = make_span32(0.f, 0.f, 1.f, 0.f, 1.f, true, 1.0f);
     int W = 0, H = 0;
-    const float lim = support_limit(sigma_k);
     if (cnt > 0) {
         const int vw = find_view_of_elem(views, n_views, i);
         g = svals[i];
@@ -348,7 +347,7 @@ __global__ __launch_bounds__(kThreads) void k_emit(const uint32_t *__restrict__ 
         rc = rect[idx];
         const float4 r0 = rec[2 * idx];
         const float4 r1 = rec[2 * idx + 1];
-        q32 = make_conic32(r0.x, r0.y, r0.z, r0.w, r1.x, (flags[idx] & 2u) != 0);
+        sp = make_span32(r0.x, r0.y, r0.z, r0.w, r1.x, (flags[idx] & 2u) != 0, support_limit(sigma_k));
         tbase = C.tile_base;
         tiles_x = (uint32_t)C.tiles_x;
         W = C.W;
@@ -361,7 +360,7 @@ __global__ __launch_bounds__(kThreads) void k_emit(const uint32_t *__restrict__ 
             uint32_t p = off;
             for (int ty = rc.y; ty <= rc.w && p < wend; ++ty) {
                 int l, r;
-                if (!row_span(q32, ty, rc.x, rc.z, tw, th, W, H, lim, l, r)) continue;
+                if (!row_span(sp, ty, rc.x, rc.z, tw, th, W, H, l, r)) continue;
                 const uint32_t n_row = (uint32_t)(r - l + 1);
                 if (p + n_row > w0) {
                     const uint32_t rowbase = tbase + (uint32_t)ty * tiles_x + (uint32_t)l;
