@@ -81,6 +81,8 @@ def test_A_and_labels_match_the_oracle_at_full_size(c2, ref):
 def test_batched_equals_per_view(c2):
     sc, ds, ctx, solver, out, st = c2
     per = Solver(ctx, ds).solve(chunk=1)
+    torch.cuda.synchronize()
+    ctx.status()
     a = (out["A_hi"].double() + out["A_lo"].double()).cpu().numpy()
     b = (per["A_hi"].double() + per["A_lo"].double()).cpu().numpy()
     d = np.abs(a - b).sum(1)
@@ -99,6 +101,7 @@ def test_column_sums_equal_accumulated_alpha_per_label(c2):
     px = sc.pixels()
     tf = torch.empty(px, dtype=torch.float32, device="cuda")
     nb = torch.empty(px, dtype=torch.int32, device="cuda")
+    ctx.status()  # start the counters from zero
     solver.accumulate_views(range(sc.n_views), A_hi, A_lo, L.FS_RED_AUTO, tf, nb)
     st2 = ctx.status()
     A = (A_hi.double() + A_lo.double()).cpu().numpy()
