@@ -227,5 +227,6 @@ def test_near_degenerate_splats_use_the_float64_conic(ctx):
 def test_threshold_free_preset(ctx):
     sc = sg.make_config("C1", n=1500, views=3, res=96)
     stats, _, ref = _solve_and_compare(ctx, sc, L.params_exact(), "exact preset")
-    # without alpha_min / t_min, almost no decision is ambiguous
-    assert stats["rows_with_slack"] <= 0.2 * stats["seen"]
+    # without alpha_min / t_min only the support cutoff can be decided differently in float32 and
+    # float64; every row then meets the 1e-4 bound without drawing on the oracle's slack at all
+    assert stats["rows_over_rel_without_slack"] == 0
