@@ -126,12 +126,12 @@ def main():
 
     # ---- compositing kernel alone, per reduction strategy (same bins) --------
     strat = {}
-    prm_lin = L.params(tile_order=1)
+    prm_img = L.params(tile_order=1)
     prm_xcd = L.params(tile_order=2)
     for name, red, comp, prm_s in (() if args.no_strategies else (("plain_atomics", L.FS_RED_PLAIN, False, prm),
                                  ("lds", L.FS_RED_LDS, False, prm),
                                  ("lds_two_sum", L.FS_RED_LDS2SUM, True, prm),
-                                 ("lds_two_sum_linear_order", L.FS_RED_LDS2SUM, True, prm_lin),
+                                 ("lds_two_sum_image_order", L.FS_RED_LDS2SUM, True, prm_img),
                                  ("lds_two_sum_xcd_runs", L.FS_RED_LDS2SUM, True, prm_xcd))):
         n, E = sc.n, sc.E
         A_hi = torch.zeros((n, E), dtype=torch.float32, device="cuda")

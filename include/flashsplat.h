@@ -103,8 +103,8 @@ typedef struct {
                                 (or det <= 0) gets its conic inverted in float64 (64) */
     int32_t fp64_conic;      /* 1 (default): use the float64 inversion for such splats */
     int32_t tile_order;      /* fs_accumulate work order: 0 (default) longest tile list first;
-                                1 = plain tile order; 2 = each of the chip's 8 XCDs (each with
-                                its own L2) gets a contiguous run of tiles */
+                                1 = image order; 2 = each of the chip's 8 XCDs (each with its
+                                own L2) gets a contiguous run of tiles */
 } fs_params;
 
 /* Projected Gaussians, caller-owned device buffers, one plane per view:

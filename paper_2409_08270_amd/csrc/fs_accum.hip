@@ -142,7 +142,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(7, 7))) voi
     __shared__ uint32_t s_bits[8];
     __shared__ int32_t s_slot_label[kSlots];
     __shared__ uint32_t s_wslots[4];
-    __shared__ uint32_t s_misc[2];
+    __shared__ uint32_t s_misc[5];      // bad labels, longest wave walk, blends, evaluations, walked entries
 
     const uint32_t tile = items ? items[blockIdx.x] : blockIdx.x;
     const int view = find_view_of_tile(views, n_views, tile);
@@ -170,7 +170,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(7, 7))) voi
     }
     if (tid < 8) s_bits[tid] = 0;
     if (tid < 4) s_wslots[tid] = 0;
-    if (tid < 2) s_misc[tid] = 0;
+    if (tid < 5) s_misc[tid] = 0;
     __syncthreads();
     if (inside && !active) atomicAdd(&s_misc[0], 1u);
     if (active) atomicOr(&s_bits[lab >> 5], 1u << (lab & 31));
@@ -195,10 +195,10 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(7, 7))) voi
     const uint32_t wslots = s_wslots[w];
     if (tid == 0) {
         if (s_misc[0]) {
-            atomicAdd(&status[ST_BAD_LABELS], (unsigned long long)s_misc[0]);
-            atomicOr(&status[ST_FLAGS], (unsigned long long)FS_DEV_BAD_LABEL);
+            status_add(status, ST_BAD_LABELS, (unsigned long long)s_misc[0]);
+            status_flag(status, (unsigned long long)FS_DEV_BAD_LABEL);
         }
-        if (nslot > kSlots && P.reduction != FS_RED_PLAIN) atomicOr(&status[ST_FLAGS], (unsigned long long)FS_DEV_MANY_LABELS);
+        if (nslot > kSlots && P.reduction != FS_RED_PLAIN) status_flag(status, (unsigned long long)FS_DEV_MANY_LABELS);
     }
     for (int i = tid; i < kBatch * kSlots; i += 256) (&s_part[0][0])[i] = 0.0f;
     if (tid == 0) {  // null record: far away, zero opacity, contributes nothing
@@ -344,15 +344,20 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(7, 7))) voi
         if (t_final) t_final[pix] = T;
         if (PIX && n_blend) n_blend[pix] = nb;
     }
-    // counters: one atomic per wave; the block's largest wave walk for the balance diagnostic
+    // counters: summed over the block in LDS, then one striped global atomic per counter
     if (lane == 0) {
-        if (nb_w) atomicAdd(&status[ST_BLENDS], (unsigned long long)nb_w);
-        if (ne_w) atomicAdd(&status[ST_EVALS], (unsigned long long)ne_w);
-        if (steps_w) atomicAdd(&status[ST_WSTEPS], (unsigned long long)steps_w);
+        atomicAdd(&s_misc[2], nb_w);
+        atomicAdd(&s_misc[3], ne_w);
+        atomicAdd(&s_misc[4], steps_w);
         atomicMax(&s_misc[1], steps_w);
     }
     __syncthreads();
-    if (tid == 0 && s_misc[1]) atomicAdd(&status[ST_WSTEPS_MAX], (unsigned long long)s_misc[1]);
+    if (tid == 0) {
+        if (s_misc[2]) status_add(status, ST_BLENDS, (unsigned long long)s_misc[2]);
+        if (s_misc[3]) status_add(status, ST_EVALS, (unsigned long long)s_misc[3]);
+        if (s_misc[4]) status_add(status, ST_WSTEPS, (unsigned long long)s_misc[4]);
+        if (s_misc[1]) status_add(status, ST_WSTEPS_MAX, (unsigned long long)s_misc[1]);
+    }
 }
 
 }  // namespace

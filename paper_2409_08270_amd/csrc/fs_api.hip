@@ -42,7 +42,7 @@ struct fs_ctx {
     hipStream_t stream = nullptr;
     int device = 0;
     unsigned long long *status_dev = nullptr;
-    unsigned long long *status_host = nullptr;  // pinned
+    unsigned long long *status_host = nullptr;  // pinned, kStatusWords
     uint32_t *npairs_dev = nullptr;
     uint32_t *npairs_host = nullptr;            // pinned
     // per-call tables
@@ -412,14 +412,14 @@ int fs_ctx_create(fs_ctx **out, void *stream)
     ctx->stream = (hipStream_t)stream;
     int rc = FS_OK;
     if (hipGetDevice(&ctx->device) != hipSuccess) rc = FS_ERR_HIP;
-    if (!rc && hipMalloc((void **)&ctx->status_dev, ST_COUNT * sizeof(unsigned long long)) != hipSuccess) rc = FS_ERR_ALLOC;
+    if (!rc && hipMalloc((void **)&ctx->status_dev, kStatusWords * sizeof(unsigned long long)) != hipSuccess) rc = FS_ERR_ALLOC;
     if (!rc && hipMalloc((void **)&ctx->npairs_dev, 64) != hipSuccess) rc = FS_ERR_ALLOC;
-    if (!rc && hipHostMalloc((void **)&ctx->status_host, ST_COUNT * sizeof(unsigned long long), hipHostMallocDefault) != hipSuccess)
+    if (!rc && hipHostMalloc((void **)&ctx->status_host, kStatusWords * sizeof(unsigned long long), hipHostMallocDefault) != hipSuccess)
         rc = FS_ERR_ALLOC;
     if (!rc && hipHostMalloc((void **)&ctx->npairs_host, 64, hipHostMallocDefault) != hipSuccess) rc = FS_ERR_ALLOC;
     for (int i = 0; !rc && i < kStaging; ++i)
         if (hipEventCreateWithFlags(&ctx->stage[i].ev, hipEventDisableTiming) != hipSuccess) rc = FS_ERR_HIP;
-    if (!rc && launch_fill_u32(ctx->stream, (uint32_t *)ctx->status_dev, 0u, ST_COUNT * 2) != hipSuccess) rc = FS_ERR_HIP;
+    if (!rc && launch_fill_u32(ctx->stream, (uint32_t *)ctx->status_dev, 0u, kStatusWords * 2) != hipSuccess) rc = FS_ERR_HIP;
     if (!rc && launch_fill_u32(ctx->stream, ctx->npairs_dev, 0u, 16) != hipSuccess) rc = FS_ERR_HIP;
     if (!rc && hipStreamSynchronize(ctx->stream) != hipSuccess) rc = FS_ERR_HIP;
     if (rc) {
@@ -464,10 +464,16 @@ const char *fs_ctx_last_error(fs_ctx *ctx) { return ctx ? ctx->last_error.c_str(
 int fs_status_get(fs_ctx *ctx, fs_status *out, int32_t clear)
 {
     if (!ctx || !out) return set_err(ctx, FS_ERR_ARG, "NULL argument");
-    HIPCHECK(ctx, hipMemcpyAsync(ctx->status_host, ctx->status_dev, ST_COUNT * sizeof(unsigned long long),
+    HIPCHECK(ctx, hipMemcpyAsync(ctx->status_host, ctx->status_dev, kStatusWords * sizeof(unsigned long long),
                                  hipMemcpyDeviceToHost, ctx->stream));
     HIPCHECK(ctx, hipStreamSynchronize(ctx->stream));
-    const unsigned long long *h = ctx->status_host;
+    unsigned long long h[ST_COUNT];
+    for (int c = 0; c < ST_COUNT; ++c) {
+        unsigned long long acc = 0;
+        for (int l = 0; l < kStatusLanes; ++l) acc += ctx->status_host[c * kStatusLanes + l];
+        h[c] = acc;
+    }
+    h[ST_FLAGS] = ctx->status_host[ST_FLAGS * kStatusLanes];
     out->flags = (uint32_t)h[ST_FLAGS];
     out->bad_labels = (int64_t)h[ST_BAD_LABELS];
     out->invalid_gauss = (int64_t)h[ST_INVALID];
@@ -480,7 +486,7 @@ int fs_status_get(fs_ctx *ctx, fs_status *out, int32_t clear)
     out->unseen = (int64_t)h[ST_UNSEEN];
     out->multi_member = (int64_t)h[ST_MULTI];
     out->low_margin = (int64_t)h[ST_LOWMARGIN];
-    if (clear) HIPCHECK(ctx, launch_fill_u32(ctx->stream, (uint32_t *)ctx->status_dev, 0u, ST_COUNT * 2));
+    if (clear) HIPCHECK(ctx, launch_fill_u32(ctx->stream, (uint32_t *)ctx->status_dev, 0u, kStatusWords * 2));
     const uint32_t errbits = FS_DEV_BAD_LABEL | FS_DEV_PAIR_OVERFLOW | FS_DEV_INVALID_GAUSS;
     if (out->flags & errbits) return set_err(ctx, FS_ERR_DEVICE, "device status flags 0x%x", out->flags);
     return FS_OK;

@@ -69,9 +69,9 @@ __global__ __launch_bounds__(256) void k_assign(const float *__restrict__ A_hi, 
     if (tid < R && s_members[tid] > 1) atomicAdd(&s_cnt[1], 1u);
     __syncthreads();
     if (tid == 0) {
-        if (s_cnt[0]) atomicAdd(&status[ST_UNSEEN], (unsigned long long)s_cnt[0]);
-        if (s_cnt[1]) atomicAdd(&status[ST_MULTI], (unsigned long long)s_cnt[1]);
-        if (s_cnt[2]) atomicAdd(&status[ST_LOWMARGIN], (unsigned long long)s_cnt[2]);
+        if (s_cnt[0]) status_add(status, ST_UNSEEN, (unsigned long long)s_cnt[0]);
+        if (s_cnt[1]) status_add(status, ST_MULTI, (unsigned long long)s_cnt[1]);
+        if (s_cnt[2]) status_add(status, ST_LOWMARGIN, (unsigned long long)s_cnt[2]);
     }
 }
 

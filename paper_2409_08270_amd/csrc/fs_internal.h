@@ -65,7 +65,10 @@ struct ProjParams {
     int32_t fp64_conic;
 };
 
-// Device status block (ctx-owned): counters are 64-bit, flags in word 0.
+// Device status block (ctx-owned): 64-bit counters, each striped over
+// kStatusLanes words (indexed by the updating block) so that many blocks
+// adding to one counter do not serialise on a single address; flags live in
+// the first word of ST_FLAGS. The host sums the stripes.
 enum StatusIdx {
     ST_FLAGS = 0,
     ST_BAD_LABELS,
@@ -82,6 +85,19 @@ enum StatusIdx {
     ST_WSTEPS_MAX,  // per tile, the longest walk of its waves, summed over tiles (diagnostic)
     ST_COUNT = 16
 };
+
+constexpr int kStatusLanes = 64;
+constexpr int kStatusWords = ST_COUNT * kStatusLanes;
+
+__device__ __forceinline__ void status_add(unsigned long long *status, int idx, unsigned long long v)
+{
+    atomicAdd(&status[idx * kStatusLanes + (blockIdx.x & (kStatusLanes - 1))], v);
+}
+
+__device__ __forceinline__ void status_flag(unsigned long long *status, unsigned long long bits)
+{
+    atomicOr(&status[ST_FLAGS * kStatusLanes], bits);
+}
 
 constexpr int kSortTile = 4096;  // items per radix-sort block tile
 constexpr int kProjViews = 8;    // views projected per Gaussian load

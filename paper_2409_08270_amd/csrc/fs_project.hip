@@ -195,10 +195,10 @@ __global__ __launch_bounds__(256) void k_project(const ProjTask *__restrict__ ta
         }
         if ((threadIdx.x & 63) == 0) {
             if (tot_i) {
-                atomicAdd(&status[ST_INVALID], (unsigned long long)tot_i);
-                atomicOr(&status[ST_FLAGS], (unsigned long long)FS_DEV_INVALID_GAUSS);
+                status_add(status, ST_INVALID, (unsigned long long)tot_i);
+                status_flag(status, (unsigned long long)FS_DEV_INVALID_GAUSS);
             }
-            if (tot_f) atomicAdd(&status[ST_FP64], (unsigned long long)tot_f);
+            if (tot_f) status_add(status, ST_FP64, (unsigned long long)tot_f);
         }
     }
 }

@@ -387,8 +387,8 @@ __global__ __launch_bounds__(kThreads) void k_emit(const uint32_t *__restrict__ 
         __syncthreads();
     }
     if (__ballot(dropped != 0) && dropped) {
-        atomicAdd(&status[ST_DROPPED], (unsigned long long)dropped);
-        atomicOr(&status[ST_FLAGS], (unsigned long long)FS_DEV_PAIR_OVERFLOW);
+        status_add(status, ST_DROPPED, (unsigned long long)dropped);
+        status_flag(status, (unsigned long long)FS_DEV_PAIR_OVERFLOW);
     }
 }
 
