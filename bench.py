@@ -40,6 +40,23 @@ def parse():
     return ap.parse_args()
 
 
+def recorded_traffic():
+    """HBM bytes per compositing launch from the committed rocprofv3 FETCH_SIZE / WRITE_SIZE
+    summary (scaled by the copy-probe calibration), or None when the kernel source has changed
+    since the counters were taken."""
+    import hashlib
+    path = os.path.join(ROOT, "profiles", "k_accum_c2_traffic.json")
+    try:
+        rec = json.load(open(path))
+    except (OSError, ValueError):
+        return None
+    csrc = os.path.join(ROOT, "paper_2409_08270_amd", "csrc")
+    src = open(os.path.join(csrc, "fs_accum.hip"), "rb").read() + open(os.path.join(csrc, "fs_internal.h"), "rb").read()
+    if hashlib.sha256(src).hexdigest() != rec.get("kernel_source_sha256"):
+        return None
+    return float(rec["hbm_bytes_per_launch"])
+
+
 def copy_probe(mib: int):
     """A plain copy of known size: its FETCH_SIZE / WRITE_SIZE readings give the
     factor between those counters and real HBM bytes."""
@@ -169,7 +186,8 @@ def main():
     acc_s = float(np.mean(acc_ms)) * 1e-3
     achieved = ops / acc_s
     roof = {"bound": "alu", "achieved": achieved / 1e12, "peak": PEAK_ALU_OPS / 1e12, "unit": "TFLOP/s",
-            "frac": achieved / PEAK_ALU_OPS, "traffic": None, "kernel": "k_accum",
+            "frac": achieved / PEAK_ALU_OPS, "traffic": recorded_traffic(), "traffic_unit": "bytes per launch (HBM)",
+            "kernel": "k_accum",
             "ops_per_launch": ops, "launch_ms": acc_s * 1e3,
             "wave_steps": wsteps, "wave_balance": wsteps / max(1.0, 4 * wsteps_max)}
 

@@ -21,6 +21,7 @@ namespace {
 
 constexpr int kSlots = 8;     // distinct labels per tile handled by pre-reduction
 constexpr int kBatch = 256;   // Gaussians staged per batch
+constexpr float kLoFloor = -200.0f;  // floor of log2(opacity): 2^-200 is zero in float32
 
 template <int CTRL>
 __device__ __forceinline__ float dpp_mov(float x)
@@ -133,12 +134,14 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(7, 7))) voi
                                                float *__restrict__ t_final, int32_t *__restrict__ n_blend,
                                                unsigned long long *__restrict__ status)
 {
-    __shared__ float4 s_rec[kBatch + 1];   // u, v, a', b' (conic scaled to log2 units); [kBatch] = null
-    __shared__ float2 s_rec2[kBatch + 1];  // c', opacity
+    // staged entry e: s_rec[e] = (u, v, a', b'), (c', lo, thr, 0), with the conic scaled to log2
+    // units, lo = log2(opacity) and thr = cut2 + lo; entry kBatch is a null record
+    __shared__ float4 s_rec[2 * (kBatch + 1)];
     __shared__ uint32_t s_g[kBatch];
     __shared__ float s_part[kBatch][kSlots];
     __shared__ uint8_t s_wmask[kBatch];    // bit w: wave w's 8x8 block can be reached
-    __shared__ uint16_t s_list[4][kBatch + 16];  // per-wave compacted batch indices, padded with the null record
+    __shared__ __align__(16) uint32_t s_list[4][kBatch + 16];  // per-wave compacted entries (byte offsets
+                                                               // into s_rec), padded with the null record
     __shared__ uint32_t s_bits[8];
     __shared__ int32_t s_slot_label[kSlots];
     __shared__ uint32_t s_wslots[4];
@@ -201,9 +204,9 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(7, 7))) voi
         if (nslot > kSlots && P.reduction != FS_RED_PLAIN) status_flag(status, (unsigned long long)FS_DEV_MANY_LABELS);
     }
     for (int i = tid; i < kBatch * kSlots; i += 256) (&s_part[0][0])[i] = 0.0f;
-    if (tid == 0) {  // null record: far away, zero opacity, contributes nothing
-        s_rec[kBatch] = make_float4(-1.0e6f, -1.0e6f, -1.0f, 0.0f);
-        s_rec2[kBatch] = make_float2(-1.0f, 0.0f);
+    if (tid == 0) {  // null record: far away, never inside its support, zero opacity
+        s_rec[2 * kBatch] = make_float4(-1.0e6f, -1.0e6f, 0.0f, 0.0f);
+        s_rec[2 * kBatch + 1] = make_float4(0.0f, kLoFloor, 3.0e38f, 0.0f);
     }
 
     const uint2 rg = ranges[tile];
@@ -213,10 +216,9 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(7, 7))) voi
     const float lim = -2.0f * P.cut2 / LOG2E * 1.015625f;
     const float tx0 = (float)(tx * P.tile_w), ty0 = (float)(ty * P.tile_h);
     float T = 1.0f;
-    int nb = 0;                       // per-pixel blend count (only kept for the per-pixel outputs)
-    uint32_t nb_w = 0, ne_w = 0;      // wave totals of blends and in-support evaluations (scalar)
+    uint32_t nb_l = 0, ne_l = 0;      // this pixel's blends and in-support evaluations
     uint32_t steps_w = 0;             // list entries this wave walked
-    bool done = !active;
+    bool live = active;
     const int64_t rec_base = (int64_t)C.elem_off;
 
     for (uint32_t base = rg.x; base < rg.y; base += kBatch) {
@@ -226,8 +228,9 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(7, 7))) voi
             const uint32_t g = vals[base + tid];
             const float4 r0 = rec[(rec_base + g) * 2];
             const float4 r1 = rec[(rec_base + g) * 2 + 1];
-            s_rec[tid] = make_float4(r0.x, r0.y, -0.5f * LOG2E * r0.z, -LOG2E * r0.w);
-            s_rec2[tid] = make_float2(-0.5f * LOG2E * r1.x, r1.y);
+            const float lo = fmaxf(__builtin_amdgcn_logf(r1.y), kLoFloor);
+            s_rec[2 * tid] = make_float4(r0.x, r0.y, -0.5f * LOG2E * r0.z, -LOG2E * r0.w);
+            s_rec[2 * tid + 1] = make_float4(-0.5f * LOG2E * r1.x, lo, P.cut2 + lo, 0.0f);
             s_g[tid] = g;
             uint32_t m = 0xFu;
             if (r1.w == 0.0f) {  // float32 conic: cull the 8x8 blocks the support cannot reach
@@ -248,52 +251,55 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(7, 7))) voi
             const int e = c * 64 + lane;
             const bool hit = (uint32_t)e < cnt && ((s_wmask[e] >> w) & 1u);
             const unsigned long long bm = __ballot(hit);
-            if (hit) s_list[w][nlist + __popcll(bm & ((1ull << lane) - 1ull))] = (uint16_t)e;
+            if (hit) s_list[w][nlist + __popcll(bm & ((1ull << lane) - 1ull))] = (uint32_t)e * 32u;
             nlist += __popcll(bm);
         }
-        if (lane < 16) s_list[w][nlist + lane] = (uint16_t)kBatch;  // pad the last group with the null record
+        if (lane < 16) s_list[w][nlist + lane] = (uint32_t)kBatch * 32u;  // pad the last group with the null record
         __builtin_amdgcn_wave_barrier();
 
         // one front-to-back step of this lane's pixel over a staged entry (branch-free):
-        // power in log2 units via Horner, alpha, transmittance test, weight
-        auto step = [&](const float4 q, const float2 q2) -> float {
+        // power in log2 units via Horner with log2(opacity) folded in, so that
+        // alpha = min(alpha_max, 2^(power + lo)); the support test compares against thr
+        auto step = [&](const float4 q, const float4 q2) -> float {
             const float dx = pxc - q.x, dy = pyc - q.y;
-            const float pw = fmaf(fmaf(q.z, dx, q.w * dy), dx, (q2.x * dy) * dy);
-            const bool insup = pw >= P.cut2;
-            const float alpha = fminf(P.alpha_max, q2.y * __builtin_amdgcn_exp2f(pw));
-            const bool ok = !done && insup && alpha >= P.alpha_min;
+            const float pw = fmaf(fmaf(q.z, dx, q.w * dy), dx, fmaf(q2.x * dy, dy, q2.y));
+            const bool insup = live && pw >= q2.z;
+            const float alpha = fminf(P.alpha_max, __builtin_amdgcn_exp2f(pw));
+            const bool ok = insup && alpha >= P.alpha_min;
             const float Tn = fmaf(-T, alpha, T);
             const bool stop = ok && Tn < P.t_min;
             const bool take = ok && !stop;
-            ne_w += (uint32_t)__popcll(__ballot(!done && insup));
-            nb_w += (uint32_t)__popcll(__ballot(take));
-            if (PIX) nb += take ? 1 : 0;
+            ne_l += insup ? 1u : 0u;
+            nb_l += take ? 1u : 0u;
             const float wv = take ? alpha * T : 0.0f;
             T = take ? Tn : T;
-            done = done || stop;
+            live = live && !stop;
             return wv;
         };
+        auto rec_at = [&](uint32_t off) -> const float4 * {
+            return reinterpret_cast<const float4 *>(reinterpret_cast<const char *>(s_rec) + off);
+        };
 
-        if (__ballot(!done) != 0ull) {
+        if (__ballot(live) != 0ull) {
             if (!plain && __popc(wslots) == 1) {
                 // single label in this wave: the weights of 8 entries are summed at once
                 const int slot0 = __ffs(wslots) - 1;
                 for (int g0 = 0; g0 < nlist; g0 += 8) {
                     steps_w += 8;
                     float wr[8];
-                    uint32_t jj[8];
-#pragma unroll
-                    for (int k = 0; k < 8; ++k) jj[k] = s_list[w][g0 + k];
+                    const uint4 o0 = *reinterpret_cast<const uint4 *>(&s_list[w][g0]);
+                    const uint4 o1 = *reinterpret_cast<const uint4 *>(&s_list[w][g0 + 4]);
+                    const uint32_t jj[8] = {o0.x, o0.y, o0.z, o0.w, o1.x, o1.y, o1.z, o1.w};
                     // the next entry's record is read from LDS while this one is composited
-                    float4 q = s_rec[jj[0]];
-                    float2 q2 = s_rec2[jj[0]];
+                    float4 q = rec_at(jj[0])[0];
+                    float4 q2 = rec_at(jj[0])[1];
 #pragma unroll
                     for (int k = 0; k < 8; ++k) {
                         float4 qn = q;
-                        float2 qn2 = q2;
+                        float4 qn2 = q2;
                         if (k + 1 < 8) {
-                            qn = s_rec[jj[k + 1]];
-                            qn2 = s_rec2[jj[k + 1]];
+                            qn = rec_at(jj[k + 1])[0];
+                            qn2 = rec_at(jj[k + 1])[1];
                         }
                         wr[k] = step(q, q2);
                         q = qn;
@@ -301,14 +307,16 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(7, 7))) voi
                     }
                     const float tot = reduce_scatter8(wr);
                     const int e = lane >> 3;
-                    if ((lane & 7) == 0 && g0 + e < nlist && tot != 0.0f) atomicAdd(&s_part[s_list[w][g0 + e]][slot0], tot);
-                    if (__ballot(!done) == 0ull) break;
+                    if ((lane & 7) == 0 && g0 + e < nlist && tot != 0.0f)
+                        atomicAdd(&s_part[s_list[w][g0 + e] >> 5][slot0], tot);
+                    if (__ballot(live) == 0ull) break;
                 }
             } else {
                 for (int it = 0; it < nlist; ++it) {
                     steps_w += 1;
-                    const uint32_t j = s_list[w][it];
-                    const float wgt = step(s_rec[j], s_rec2[j]);
+                    const uint32_t off = s_list[w][it];
+                    const uint32_t j = off >> 5;
+                    const float wgt = step(rec_at(off)[0], rec_at(off)[1]);
                     if (__ballot(wgt != 0.0f)) {
                         if (plain) {
                             if (wgt != 0.0f) add_global(A_hi, A_lo, (int64_t)s_g[j] * E + lab, wgt);
@@ -322,7 +330,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(7, 7))) voi
                             }
                         }
                     }
-                    if ((it & 15) == 15 && __ballot(!done) == 0ull) break;
+                    if ((it & 15) == 15 && __ballot(live) == 0ull) break;
                 }
             }
         }
@@ -337,14 +345,20 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(7, 7))) voi
                 }
             }
         }
-        if (__syncthreads_or(!done) == 0) break;
+        if (__syncthreads_or(live) == 0) break;
     }
 
     if (inside) {
         if (t_final) t_final[pix] = T;
-        if (PIX && n_blend) n_blend[pix] = nb;
+        if (PIX && n_blend) n_blend[pix] = (int32_t)nb_l;
     }
-    // counters: summed over the block in LDS, then one striped global atomic per counter
+    // counters: summed over the wave, then the block in LDS, then one striped global atomic each
+    uint32_t nb_w = nb_l, ne_w = ne_l;
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) {
+        nb_w += __shfl_xor(nb_w, off);
+        ne_w += __shfl_xor(ne_w, off);
+    }
     if (lane == 0) {
         atomicAdd(&s_misc[2], nb_w);
         atomicAdd(&s_misc[3], ne_w);
