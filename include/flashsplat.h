@@ -151,6 +151,7 @@ typedef struct {
     int64_t unseen;          /* fs_assign: rows of A that are all zero */
     int64_t multi_member;    /* fs_assign: Gaussians assigned to more than one object */
     int64_t low_margin;      /* fs_assign: (object, Gaussian) entries with margin < 1e-4 */
+    int64_t pairs_emitted;   /* tile pairs written by fs_bin_sort and the batched solve */
 } fs_status;
 
 /* Library and context ---------------------------------------------------- */
@@ -255,7 +256,10 @@ typedef struct {
     int32_t zero_accumulators; /* 1: each run starts from A = 0 (default 1) */
     int32_t use_graph;         /* 1 (default): capture into a hipGraph; 0: enqueue the kernels per run */
     int32_t reduction;         /* FS_RED_* for the compositing (default FS_RED_AUTO) */
-    int32_t reserved;
+    int32_t depth_slabs;       /* 1..4: the Gaussians of each view are binned and composited in this
+                                  many depth slabs, front to back, and tiles whose pixels have all
+                                  finished get no pairs from later slabs; 0 (default): 1, one pass
+                                  over the full lists */
 } fs_batch_opts;
 
 typedef struct {

@@ -132,7 +132,8 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(7, 7))) voi
                                                int32_t n_views, const SceneDev *__restrict__ scenes,
                                                const uint32_t *__restrict__ items, AccParams P,
                                                float *__restrict__ t_final, int32_t *__restrict__ n_blend,
-                                               unsigned long long *__restrict__ status)
+                                               float *__restrict__ tstate, uint8_t *__restrict__ tile_done,
+                                               int32_t first, unsigned long long *__restrict__ status)
 {
     // staged entry e: s_rec[e] = (u, v, a', b'), (c', lo, thr, 0), with the conic scaled to log2
     // units, lo = log2(opacity) and thr = cut2 + lo; entry kBatch is a null record
@@ -148,6 +149,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(7, 7))) voi
     __shared__ uint32_t s_misc[5];      // bad labels, longest wave walk, blends, evaluations, walked entries
 
     const uint32_t tile = items ? items[blockIdx.x] : blockIdx.x;
+    if (tile_done && tile_done[tile]) return;  // every pixel of this tile has finished (whole block)
     const int view = find_view_of_tile(views, n_views, tile);
     const ViewDev &C = views[view];
     const SceneDev &SC = scenes[C.scene];
@@ -164,6 +166,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(7, 7))) voi
     const int y = ty * P.tile_h + (w / bpr) * 8 + (lane >> 3);
     const bool inside = x < C.W && y < C.H;
     const int64_t pix = (int64_t)C.mask_off + (int64_t)y * C.W + x;  // within the scene's masks
+    const int64_t spix = (int64_t)C.pix_off + (int64_t)y * C.W + x;  // within the call's pixel state
 
     int lab = 0;
     bool active = inside;
@@ -175,7 +178,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(7, 7))) voi
     if (tid < 4) s_wslots[tid] = 0;
     if (tid < 5) s_misc[tid] = 0;
     __syncthreads();
-    if (inside && !active) atomicAdd(&s_misc[0], 1u);
+    if (inside && !active && (first || tstate == nullptr)) atomicAdd(&s_misc[0], 1u);  // counted once per solve
     if (active) atomicOr(&s_bits[lab >> 5], 1u << (lab & 31));
     __syncthreads();
     int slot = 0, nslot = 0;
@@ -216,12 +219,18 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(7, 7))) voi
     const float lim = -2.0f * P.cut2 / LOG2E * 1.015625f;
     const float tx0 = (float)(tx * P.tile_w), ty0 = (float)(ty * P.tile_h);
     float T = 1.0f;
+    if (tstate && !first && active) {
+        const float ts = tstate[spix];
+        if (ts < 0.0f) active = false;  // this pixel's compositing ended in an earlier slab
+        else T = ts;
+    }
     uint32_t nb_l = 0, ne_l = 0;      // this pixel's blends and in-support evaluations
     uint32_t steps_w = 0;             // list entries this wave walked
     bool live = active;
+    const bool any_live = __syncthreads_or(live) != 0;
     const int64_t rec_base = (int64_t)C.elem_off;
 
-    for (uint32_t base = rg.x; base < rg.y; base += kBatch) {
+    for (uint32_t base = any_live ? rg.x : rg.y; base < rg.y; base += kBatch) {
         const uint32_t cnt = min((uint32_t)kBatch, rg.y - base);
         __syncthreads();  // previous batch fully consumed
         if ((uint32_t)tid < cnt) {
@@ -348,6 +357,11 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(7, 7))) voi
         if (__syncthreads_or(live) == 0) break;
     }
 
+    if (tile_done) {
+        const bool still = __syncthreads_or(live) != 0;
+        if (tid == 0 && !still) tile_done[tile] = 1;
+    }
+    if (inside && tstate) tstate[spix] = live ? T : -1.0f;
     if (inside) {
         if (t_final) t_final[pix] = T;
         if (PIX && n_blend) n_blend[pix] = (int32_t)nb_l;
@@ -379,13 +393,13 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(7, 7))) voi
 hipError_t launch_accumulate(hipStream_t s, const float *rec, const uint32_t *vals, const uint32_t *ranges,
                              const ViewDev *views, int32_t n_views, const SceneDev *scenes, const uint32_t *items,
                              uint32_t n_items, const AccParams &p, float *t_final, int32_t *n_blend,
-                             unsigned long long *status)
+                             float *tstate, uint8_t *tile_done, int32_t first, unsigned long long *status)
 {
     if (n_items == 0) return hipSuccess;
     auto kern = (t_final || n_blend) ? k_accum<true> : k_accum<false>;
     hipLaunchKernelGGL(kern, dim3(n_items), dim3(256), 0, s, reinterpret_cast<const float4 *>(rec), vals,
                        reinterpret_cast<const uint2 *>(ranges), views, n_views, scenes, items, p, t_final, n_blend,
-                       status);
+                       tstate, tile_done, first, status);
     return hipGetLastError();
 }
 

@@ -263,6 +263,7 @@ struct Plan {
     uint32_t dblocks = 0;
     uint64_t elems = 0;
     uint64_t tiles = 0;
+    uint64_t pixels = 0;
 };
 
 // Appends views [v0, v1) of a scene with n Gaussians; mask_off0 is the mask
@@ -285,6 +286,7 @@ void plan_add(Plan &pl, const fs_params *p, uint32_t scene, int64_t n, const fs_
         d.scene = scene;
         d.mask_off = moff;
         d.elem_off = pl.elems;
+        d.pix_off = pl.pixels;
         d.n = (uint32_t)n;
         d.pad = 0;
         pl.views.push_back(d);
@@ -296,6 +298,7 @@ void plan_add(Plan &pl, const fs_params *p, uint32_t scene, int64_t n, const fs_
         pl.dblocks += (uint32_t)((n + kSortTile - 1) / kSortTile);
         pl.elems += (uint64_t)n;
         pl.tiles += (uint64_t)d.tiles_x * d.tiles_y;
+        pl.pixels += (uint64_t)c.width * c.height;
         moff += (uint64_t)c.width * c.height;
     }
     const uint32_t bpv = (uint32_t)((n + 255) / 256);
@@ -486,6 +489,7 @@ int fs_status_get(fs_ctx *ctx, fs_status *out, int32_t clear)
     out->unseen = (int64_t)h[ST_UNSEEN];
     out->multi_member = (int64_t)h[ST_MULTI];
     out->low_margin = (int64_t)h[ST_LOWMARGIN];
+    out->pairs_emitted = (int64_t)h[ST_PAIRS];
     if (clear) HIPCHECK(ctx, launch_fill_u32(ctx->stream, (uint32_t *)ctx->status_dev, 0u, kStatusWords * 2));
     const uint32_t errbits = FS_DEV_BAD_LABEL | FS_DEV_PAIR_OVERFLOW | FS_DEV_INVALID_GAUSS;
     if (out->flags & errbits) return set_err(ctx, FS_ERR_DEVICE, "device status flags 0x%x", out->flags);
@@ -590,7 +594,7 @@ int fs_bin_sort(fs_ctx *ctx, const fs_proj *proj, const fs_camera *cams, const f
     }
     HIPCHECK(ctx, launch_emit(s, dk, dv, (const uint32_t *)ctx->offsets.p, (const uint32_t *)ctx->counts.p, proj->rec,
                               proj->rect, proj->flags, views, V, total, (uint32_t)out->capacity, p->tile_w, p->tile_h,
-                              p->sigma_k, k0, v0, ctx->status_dev));
+                              p->sigma_k, nullptr, k0, v0, ctx->status_dev));
     // without a host count, the device count caps the sort (entries past it are never read)
     HIPCHECK(ctx, radix_sort(s, k0, v0, k1, v1, (const SegDev *)ctx->psegs.p, 1, pblocks, passes * 8, ctx->sort_ws.p,
                              n_pairs ? nullptr : ctx->npairs_dev));
@@ -641,7 +645,8 @@ int fs_accumulate(fs_ctx *ctx, const fs_proj *proj, const fs_bins *bins, const f
     }
     HIPCHECK(ctx, launch_accumulate(ctx->stream, proj->rec, bins->vals, bins->ranges, (const ViewDev *)ctx->views.p, V,
                                     (const SceneDev *)ctx->scenes.p, items, (uint32_t)pl.tiles, acc_params(p, reduction),
-                                    pix ? pix->t_final : nullptr, pix ? pix->n_blend : nullptr, ctx->status_dev));
+                                    pix ? pix->t_final : nullptr, pix ? pix->n_blend : nullptr, nullptr, nullptr, 1,
+                                    ctx->status_dev));
     return FS_OK;
 }
 
@@ -685,6 +690,7 @@ struct Chunk {
     Plan plan;
     std::vector<ViewRef> refs;
     uint64_t pairs = 0;       // planned (exact at creation)
+    uint64_t slab_max = 0;    // largest pair count of one depth slab (before culling finished tiles)
     uint32_t pair_cap = 0;    // slots used by this chunk
     uint32_t pblocks = 0;
     uint32_t lblocks = 0;
@@ -704,8 +710,10 @@ struct fs_batch {
     // workspace shared by the chunks
     DevBuf rec, rect, ntiles, flags, dkeys, dvals, dkeys2, dvals2, counts, offsets;
     DevBuf ptiles, pvals, pk_alt, pv_alt, ranges, items, items_k, items_k2, items_v2;
-    DevBuf sort_ws, scan_ws, npairs, view_offs;
-    uint64_t max_elems = 0, max_tiles = 0, max_pairs = 0;
+    DevBuf sort_ws, scan_ws, npairs, view_offs, tstate, tile_done;
+    uint64_t max_elems = 0, max_tiles = 0, max_pairs = 0, max_pixels = 0;
+    int n_slabs = 1;
+    uint32_t slab_num[9] = {0, 1024};  // depth-slab boundaries, numerators over 1024
     uint32_t max_dblocks = 0, max_pblocks = 0, max_lblocks = 0;
     hipGraph_t graph = nullptr;
     hipGraphExec_t exec = nullptr;
@@ -720,7 +728,7 @@ std::vector<DevBuf *> batch_bufs(fs_batch *b)
     std::vector<DevBuf *> v = {&b->scenes_d, &b->rec, &b->rect, &b->ntiles, &b->flags, &b->dkeys, &b->dvals,
                                &b->dkeys2, &b->dvals2, &b->counts, &b->offsets, &b->ptiles, &b->pvals, &b->pk_alt,
                                &b->pv_alt, &b->ranges, &b->items, &b->items_k, &b->items_k2, &b->items_v2,
-                               &b->sort_ws, &b->scan_ws, &b->npairs, &b->view_offs};
+                               &b->sort_ws, &b->scan_ws, &b->npairs, &b->view_offs, &b->tstate, &b->tile_done};
     for (Chunk &c : b->chunks) {
         v.push_back(&c.views);
         v.push_back(&c.tasks);
@@ -746,40 +754,52 @@ void chunk_plan(fs_batch *b, Chunk &c)
     }
 }
 
-// projection, depth sort, counts and scan of one chunk (the first half of binning)
-int enqueue_count(fs_batch *b, Chunk &c, int chunk_idx, hipStream_t s)
+// projection and per-view depth sort of one chunk
+int enqueue_front(fs_batch *b, Chunk &c, hipStream_t s)
 {
     fs_ctx *ctx = b->ctx;
     const Plan &pl = c.plan;
-    const int64_t total = (int64_t)pl.elems;
-    const int32_t V = (int32_t)pl.views.size();
-    uint32_t *np = (uint32_t *)b->npairs.p + chunk_idx;
-    if (total == 0) {
-        HIPCHECK(ctx, launch_fill_u32(s, np, 0u, 1));
-        return FS_OK;
-    }
+    if (pl.elems == 0) return FS_OK;
     uint32_t *dk = (uint32_t *)b->dkeys.p, *dv = (uint32_t *)b->dvals.p;
     HIPCHECK(ctx, launch_project(s, (const ProjTask *)c.tasks.p, (int32_t)pl.tasks.size(), pl.proj_blocks,
                                  (const SceneDev *)b->scenes_d.p, (const ViewDev *)c.views.p, proj_params(&b->p),
                                  (float *)b->rec.p, (int16_t *)b->rect.p, (int32_t *)b->ntiles.p, (uint8_t *)b->flags.p,
                                  dk, dv, ctx->status_dev));
-    HIPCHECK(ctx, radix_sort(s, dk, dv, (uint32_t *)b->dkeys2.p, (uint32_t *)b->dvals2.p, (const SegDev *)c.dsegs.p, V,
-                             pl.dblocks, 32, b->sort_ws.p, nullptr));
-    HIPCHECK(ctx, launch_gather_counts(s, dk, dv, (const int32_t *)b->ntiles.p, (const ViewDev *)c.views.p, V, total,
-                                       (uint32_t *)b->counts.p));
+    HIPCHECK(ctx, radix_sort(s, dk, dv, (uint32_t *)b->dkeys2.p, (uint32_t *)b->dvals2.p, (const SegDev *)c.dsegs.p,
+                             (int32_t)pl.views.size(), pl.dblocks, 32, b->sort_ws.p, nullptr));
+    return FS_OK;
+}
+
+// pair counts of every element (no slab, no culling) and their exclusive scan; total into *np
+int enqueue_full_count(fs_batch *b, Chunk &c, uint32_t *np, hipStream_t s)
+{
+    fs_ctx *ctx = b->ctx;
+    const Plan &pl = c.plan;
+    const int64_t total = (int64_t)pl.elems;
+    if (total == 0) {
+        HIPCHECK(ctx, launch_fill_u32(s, np, 0u, 1));
+        return FS_OK;
+    }
+    HIPCHECK(ctx, launch_gather_counts(s, (const uint32_t *)b->dkeys.p, (const uint32_t *)b->dvals.p,
+                                       (const int32_t *)b->ntiles.p, (const ViewDev *)c.views.p,
+                                       (int32_t)pl.views.size(), total, (uint32_t *)b->counts.p));
     HIPCHECK(ctx, scan_exclusive(s, (const uint32_t *)b->counts.p, (uint32_t *)b->offsets.p, total, np, b->scan_ws.p));
     return FS_OK;
 }
 
-// the rest of one chunk: emission, pair sort, ranges, work order, compositing
-int enqueue_finish(fs_batch *b, Chunk &c, int chunk_idx, hipStream_t s)
+// Depth slabs of one chunk, front to back: the pairs of the Gaussians in slab k
+// (their depth ranks) are counted, emitted, sorted by tile and composited,
+// resuming every pixel's transmittance from the previous slab. Tiles whose
+// pixels have all finished are marked by the compositing and get no pairs in
+// later slabs, so the long tails of dense tiles are never sorted.
+int enqueue_slabs(fs_batch *b, Chunk &c, int chunk_idx, hipStream_t s)
 {
     fs_ctx *ctx = b->ctx;
     const Plan &pl = c.plan;
     const int64_t total = (int64_t)pl.elems;
     const int32_t V = (int32_t)pl.views.size();
     if (total == 0 || c.pair_cap == 0 || pl.tiles == 0) return FS_OK;
-    const uint32_t *np = (const uint32_t *)b->npairs.p + chunk_idx;
+    const int S = b->n_slabs;
     uint32_t *dk = (uint32_t *)b->dkeys.p, *dv = (uint32_t *)b->dvals.p;
     uint32_t *k0, *v0, *k1, *v1;
     uint32_t *pt = (uint32_t *)b->ptiles.p, *pv = (uint32_t *)b->pvals.p;
@@ -789,24 +809,39 @@ int enqueue_finish(fs_batch *b, Chunk &c, int chunk_idx, hipStream_t s)
     } else {
         k0 = pta; v0 = pva; k1 = pt; v1 = pv;
     }
-    HIPCHECK(ctx, launch_emit(s, dk, dv, (const uint32_t *)b->offsets.p, (const uint32_t *)b->counts.p,
-                              (const float *)b->rec.p, (const int16_t *)b->rect.p, (const uint8_t *)b->flags.p,
-                              (const ViewDev *)c.views.p, V, total, c.pair_cap, b->p.tile_w, b->p.tile_h, b->p.sigma_k,
-                              k0, v0, ctx->status_dev));
-    HIPCHECK(ctx, radix_sort(s, k0, v0, k1, v1, (const SegDev *)c.psegs.p, 1, c.pblocks, c.passes * 8, b->sort_ws.p, np));
-    HIPCHECK(ctx, launch_fill_u32(s, (uint32_t *)b->ranges.p, 0u, (int64_t)pl.tiles * 2));
-    HIPCHECK(ctx, launch_ranges(s, pt, np, c.pair_cap, c.pair_cap, (uint32_t *)b->ranges.p));
-    const uint32_t *items = nullptr;
-    if (b->p.tile_order == 0) {
-        RCHECK(enqueue_lpt(ctx, s, (const uint32_t *)b->ranges.p, pl.tiles, (const SegDev *)c.lsegs.p,
-                           (uint32_t *)b->items.p, (uint32_t *)b->items_k.p, (uint32_t *)b->items_k2.p,
-                           (uint32_t *)b->items_v2.p, b->sort_ws.p));
-        items = (const uint32_t *)b->items.p;
+    uint8_t *done = S > 1 ? (uint8_t *)b->tile_done.p : nullptr;
+    float *tstate = S > 1 ? (float *)b->tstate.p : nullptr;
+    if (done) HIPCHECK(ctx, launch_fill_u32(s, (uint32_t *)done, 0u, (int64_t)((pl.tiles + 3) / 4)));
+    for (int k = 0; k < S; ++k) {
+        uint32_t *np = (uint32_t *)b->npairs.p + (size_t)chunk_idx * S + k;
+        const Slab sl{b->slab_num[k], b->slab_num[k + 1]};
+        HIPCHECK(ctx, launch_slab_counts(s, dk, dv, (const float *)b->rec.p, (const int16_t *)b->rect.p,
+                                         (const uint8_t *)b->flags.p, (const int32_t *)b->ntiles.p,
+                                         (const ViewDev *)c.views.p, V, total, sl, k > 0 ? done : nullptr,
+                                         b->p.tile_w, b->p.tile_h, b->p.sigma_k, (uint32_t *)b->counts.p));
+        HIPCHECK(ctx, scan_exclusive(s, (const uint32_t *)b->counts.p, (uint32_t *)b->offsets.p, total, np,
+                                     b->scan_ws.p));
+        HIPCHECK(ctx, launch_emit(s, dk, dv, (const uint32_t *)b->offsets.p, (const uint32_t *)b->counts.p,
+                                  (const float *)b->rec.p, (const int16_t *)b->rect.p, (const uint8_t *)b->flags.p,
+                                  (const ViewDev *)c.views.p, V, total, c.pair_cap, b->p.tile_w, b->p.tile_h,
+                                  b->p.sigma_k, k > 0 ? done : nullptr, k0, v0, ctx->status_dev));
+        HIPCHECK(ctx, radix_sort(s, k0, v0, k1, v1, (const SegDev *)c.psegs.p, 1, c.pblocks, c.passes * 8,
+                                 b->sort_ws.p, np));
+        HIPCHECK(ctx, launch_fill_u32(s, (uint32_t *)b->ranges.p, 0u, (int64_t)pl.tiles * 2));
+        HIPCHECK(ctx, launch_ranges(s, pt, np, c.pair_cap, c.pair_cap, (uint32_t *)b->ranges.p));
+        const uint32_t *items = nullptr;
+        if (b->p.tile_order == 0) {
+            RCHECK(enqueue_lpt(ctx, s, (const uint32_t *)b->ranges.p, pl.tiles, (const SegDev *)c.lsegs.p,
+                               (uint32_t *)b->items.p, (uint32_t *)b->items_k.p, (uint32_t *)b->items_k2.p,
+                               (uint32_t *)b->items_v2.p, b->sort_ws.p));
+            items = (const uint32_t *)b->items.p;
+        }
+        HIPCHECK(ctx, launch_accumulate(s, (const float *)b->rec.p, pv, (const uint32_t *)b->ranges.p,
+                                        (const ViewDev *)c.views.p, V, (const SceneDev *)b->scenes_d.p, items,
+                                        (uint32_t)pl.tiles, acc_params(&b->p, b->o.reduction), nullptr, nullptr,
+                                        tstate, done, k == 0 ? 1 : 0,
+                                        ctx->status_dev));
     }
-    HIPCHECK(ctx, launch_accumulate(s, (const float *)b->rec.p, pv, (const uint32_t *)b->ranges.p,
-                                    (const ViewDev *)c.views.p, V, (const SceneDev *)b->scenes_d.p, items,
-                                    (uint32_t)pl.tiles, acc_params(&b->p, b->o.reduction), nullptr, nullptr,
-                                    ctx->status_dev));
     return FS_OK;
 }
 
@@ -822,8 +857,8 @@ int enqueue_run(fs_batch *b, hipStream_t s)
         }
     }
     for (size_t i = 0; i < b->chunks.size(); ++i) {
-        RCHECK(enqueue_count(b, b->chunks[i], (int)i, s));
-        RCHECK(enqueue_finish(b, b->chunks[i], (int)i, s));
+        RCHECK(enqueue_front(b, b->chunks[i], s));
+        RCHECK(enqueue_slabs(b, b->chunks[i], (int)i, s));
     }
     for (const SceneIn &sc : b->scenes)
         if (sc.S)
@@ -923,13 +958,18 @@ int batch_build(fs_batch *b, const fs_scene *scenes, int32_t n_scenes)
     RCHECK(batch_alloc(b, b->counts, E4));
     RCHECK(batch_alloc(b, b->offsets, E4));
     RCHECK(batch_alloc(b, b->scan_ws, scan_ws_bytes((int64_t)max_e)));
-    RCHECK(batch_alloc(b, b->npairs, 4 * (all.size() + 64)));
-    RCHECK(batch_alloc(b, b->view_offs, 4 * (max_v + 64)));
+    const int S = b->n_slabs, NB = S + 1;
+    RCHECK(batch_alloc(b, b->npairs, 4 * (all.size() * S + 64)));
+    RCHECK(batch_alloc(b, b->view_offs, 4 * (max_v * NB + 64)));
+    SlabBounds nb;
+    nb.n = (uint32_t)NB;
+    for (int i = 0; i < 9; ++i) nb.num[i] = i < NB ? b->slab_num[i] : 1024u;
     DevBuf tmp_sort;
     RCHECK(alloc_buf(ctx, tmp_sort, radix_ws_bytes(std::max<uint32_t>(max_db, 1))));
 
-    // 2. exact pair count of every view
+    // 2. exact pair count of every view and of each of its depth slabs
     std::vector<int64_t> vpairs(all.size(), 0);
+    std::vector<int64_t> vslab(all.size() * S, 0);
     std::vector<uint32_t> hoff;
     size_t k0 = 0;
     int rc = FS_OK;
@@ -940,23 +980,28 @@ int batch_build(fs_batch *b, const fs_scene *scenes, int32_t n_scenes)
             (rc = upload_vec(ctx, c.dsegs, c.plan.dsegs)))
             break;
         std::swap(b->sort_ws, tmp_sort);
-        rc = enqueue_count(b, c, 0, ctx->stream);
+        rc = enqueue_front(b, c, ctx->stream);
+        if (!rc) rc = enqueue_full_count(b, c, (uint32_t *)b->npairs.p, ctx->stream);
         std::swap(b->sort_ws, tmp_sort);
         if (rc) break;
         hipError_t e = c.plan.elems > 0
-                           ? launch_view_offsets(ctx->stream, (const uint32_t *)b->offsets.p, (const ViewDev *)c.views.p,
-                                                 V, (int64_t)c.plan.elems, (const uint32_t *)b->npairs.p,
+                           ? launch_slab_offsets(ctx->stream, (const uint32_t *)b->offsets.p, (const ViewDev *)c.views.p,
+                                                 V, (int64_t)c.plan.elems, (const uint32_t *)b->npairs.p, nb,
                                                  (uint32_t *)b->view_offs.p)
-                           : launch_fill_u32(ctx->stream, (uint32_t *)b->view_offs.p, 0u, V + 1);
-        hoff.assign((size_t)V + 1, 0);
+                           : launch_fill_u32(ctx->stream, (uint32_t *)b->view_offs.p, 0u, (int64_t)V * NB);
+        hoff.assign((size_t)V * NB, 0);
         if (e == hipSuccess)
-            e = hipMemcpyAsync(hoff.data(), b->view_offs.p, 4 * (size_t)(V + 1), hipMemcpyDeviceToHost, ctx->stream);
+            e = hipMemcpyAsync(hoff.data(), b->view_offs.p, 4 * hoff.size(), hipMemcpyDeviceToHost, ctx->stream);
         if (e == hipSuccess) e = hipStreamSynchronize(ctx->stream);
         if (e != hipSuccess) {
             rc = set_err(ctx, FS_ERR_HIP, "batch count failed: %s", hipGetErrorString(e));
             break;
         }
-        for (int v = 0; v < V; ++v) vpairs[k0 + v] = (int64_t)hoff[v + 1] - (int64_t)hoff[v];
+        for (int v = 0; v < V; ++v) {
+            const uint32_t *o = &hoff[(size_t)v * NB];
+            vpairs[k0 + v] = (int64_t)o[S] - (int64_t)o[0];
+            for (int q = 0; q < S; ++q) vslab[(k0 + v) * S + q] = (int64_t)o[q + 1] - (int64_t)o[q];
+        }
         k0 += (size_t)V;
         free_buf(c.views);
         free_buf(c.tasks);
@@ -976,10 +1021,16 @@ int batch_build(fs_batch *b, const fs_scene *scenes, int32_t n_scenes)
     for (Chunk &c : b->chunks) {
         chunk_plan(b, c);
         for (size_t j = 0; j < c.refs.size(); ++j) c.pairs += (uint64_t)vpairs[k + j];
+        for (int q = 0; q < S; ++q) {
+            uint64_t sum = 0;
+            for (size_t j = 0; j < c.refs.size(); ++j) sum += (uint64_t)vslab[(k + j) * S + q];
+            c.slab_max = std::max(c.slab_max, sum);
+        }
         k += c.refs.size();
         if (c.pairs >= 0xFFFFF000ull) return set_err(ctx, FS_ERR_CAPACITY, "a single view needs too many tile pairs");
-        b->max_pairs = std::max<uint64_t>(b->max_pairs, c.pairs);
+        b->max_pairs = std::max<uint64_t>(b->max_pairs, c.slab_max);
         b->max_tiles = std::max<uint64_t>(b->max_tiles, c.plan.tiles);
+        b->max_pixels = std::max<uint64_t>(b->max_pixels, c.plan.pixels);
         b->max_elems = std::max<uint64_t>(b->max_elems, c.plan.elems);
         b->max_dblocks = std::max(b->max_dblocks, c.plan.dblocks);
         b->total_pairs += (int64_t)c.pairs;
@@ -988,7 +1039,7 @@ int batch_build(fs_batch *b, const fs_scene *scenes, int32_t n_scenes)
     }
     const uint64_t cap = std::min<uint64_t>(0xFFFFF000ull, b->max_pairs + b->max_pairs / 64 + 4096);
     for (Chunk &c : b->chunks) {
-        c.pair_cap = (uint32_t)std::min<uint64_t>(cap, c.pairs + c.pairs / 64 + 4096);
+        c.pair_cap = (uint32_t)std::min<uint64_t>(cap, c.slab_max + c.slab_max / 64 + 4096);
         c.pblocks = (c.pair_cap + kSortTile - 1) / kSortTile;
         c.lblocks = (uint32_t)((c.plan.tiles + kSortTile - 1) / kSortTile);
         c.passes = (bits_for(std::max<uint64_t>(c.plan.tiles, 2)) + 7) / 8;
@@ -1016,6 +1067,10 @@ int batch_build(fs_batch *b, const fs_scene *scenes, int32_t n_scenes)
     RCHECK(batch_alloc(b, b->items_v2, T4));
     const uint32_t sb = std::max(std::max(b->max_dblocks, b->max_pblocks), std::max<uint32_t>(b->max_lblocks, 1));
     RCHECK(batch_alloc(b, b->sort_ws, radix_ws_bytes(sb)));
+    if (S > 1) {
+        RCHECK(batch_alloc(b, b->tstate, (size_t)std::max<uint64_t>(b->max_pixels, 1) * 4));
+        RCHECK(batch_alloc(b, b->tile_done, ((size_t)b->max_tiles + 3) / 4 * 4 + 4));
+    }
     HIPCHECK(ctx, hipStreamSynchronize(ctx->stream));
 
     // 4. capture the whole solve into one graph
@@ -1058,7 +1113,7 @@ void fs_batch_opts_default(fs_batch_opts *o)
     o->zero_accumulators = 1;
     o->use_graph = 1;
     o->reduction = FS_RED_AUTO;
-    o->reserved = 0;
+    o->depth_slabs = 0;
 }
 
 int fs_batch_create(fs_ctx *ctx, const fs_scene *scenes, int32_t n_scenes, const fs_params *p,
@@ -1074,6 +1129,7 @@ int fs_batch_create(fs_ctx *ctx, const fs_scene *scenes, int32_t n_scenes, const
     fs_batch_opts_default(&o);
     if (opts) o = *opts;
     if (o.reduction < FS_RED_AUTO || o.reduction > FS_RED_LDS2SUM) return set_err(ctx, FS_ERR_ARG, "unknown reduction");
+    if (o.depth_slabs < 0 || o.depth_slabs > 4) return set_err(ctx, FS_ERR_ARG, "depth_slabs must be in [0, 4]");
     bool all_lo = true;
     for (int i = 0; i < n_scenes; ++i) {
         const fs_scene &s = scenes[i];
@@ -1093,6 +1149,13 @@ int fs_batch_create(fs_ctx *ctx, const fs_scene *scenes, int32_t n_scenes, const
     b->ctx = ctx;
     b->p = *p;
     b->o = o;
+    {
+        static const uint32_t kSlabNum[5][5] = {
+            {0, 1024}, {0, 256, 1024}, {0, 102, 307, 1024}, {0, 51, 154, 410, 1024}, {0}};
+        const int S = o.depth_slabs == 0 ? 1 : o.depth_slabs;
+        b->n_slabs = S;
+        for (int i = 0; i <= S; ++i) b->slab_num[i] = kSlabNum[S - 1][i];
+    }
     int rc = batch_build(b, scenes, n_scenes);
     if (rc) {
         fs_batch_destroy(b);

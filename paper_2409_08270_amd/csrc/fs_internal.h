@@ -30,6 +30,7 @@ struct ViewDev {
     uint32_t scene;       // index into the scene table
     uint64_t mask_off;    // offset of this view's mask inside its scene's masks
     uint64_t elem_off;    // first element of this view's projection plane
+    uint64_t pix_off;     // first pixel of this view in the call's per-pixel state buffer
     uint32_t n;           // Gaussians in the scene (= plane length)
     uint32_t pad;
 };
@@ -79,7 +80,7 @@ enum StatusIdx {
     ST_UNSEEN,
     ST_MULTI,
     ST_LOWMARGIN,
-    ST_PAIRS,       // total pairs of the last bin_sort (device-side count)
+    ST_PAIRS,       // tile pairs emitted
     ST_EVALS,
     ST_WSTEPS,      // list entries walked, summed over waves (diagnostic)
     ST_WSTEPS_MAX,  // per tile, the longest walk of its waves, summed over tiles (diagnostic)
@@ -135,21 +136,42 @@ hipError_t launch_gather_counts(hipStream_t s, const uint32_t *sorted_keys, cons
                                 const int32_t *ntiles, const ViewDev *views, int32_t n_views, int64_t total,
                                 uint32_t *counts);
 
+// Depth slab [lo, hi) of a view holding n Gaussians, as fractions num/1024 of its
+// depth-sorted elements: ranks [(n*num_lo) >> 10, (n*num_hi) >> 10).
+struct Slab {
+    uint32_t num_lo, num_hi;
+};
+
+// counts[i] = listed tiles of depth-sorted element i that lie in the slab and
+// whose tile is not marked in `done` (NULL: no tile is done); 0 outside the slab
+hipError_t launch_slab_counts(hipStream_t s, const uint32_t *sorted_keys, const uint32_t *sorted_vals,
+                              const float *rec, const int16_t *rect, const uint8_t *flags, const int32_t *ntiles,
+                              const ViewDev *views, int32_t n_views, int64_t total, Slab slab, const uint8_t *done,
+                              int32_t tile_w, int32_t tile_h, float sigma_k, uint32_t *counts);
+
 // emits, for every depth-sorted element, one (tile, id) pair per listed tile
 // (the row_span rule) at offsets[i]; pairs at or beyond `capacity` are
 // dropped and latched
+// (tiles marked in `done`, if not NULL, are skipped, as in launch_slab_counts)
 hipError_t launch_emit(hipStream_t s, const uint32_t *sorted_keys, const uint32_t *sorted_vals,
                        const uint32_t *offsets, const uint32_t *counts, const float *rec, const int16_t *rect,
                        const uint8_t *flags, const ViewDev *views, int32_t n_views, int64_t total,
-                       uint32_t capacity, int32_t tile_w, int32_t tile_h, float sigma_k, uint32_t *tiles_out,
-                       uint32_t *vals_out, unsigned long long *status);
+                       uint32_t capacity, int32_t tile_w, int32_t tile_h, float sigma_k, const uint8_t *done,
+                       uint32_t *tiles_out, uint32_t *vals_out, unsigned long long *status);
 
 hipError_t launch_ranges(hipStream_t s, const uint32_t *tiles, const uint32_t *n_pairs_dev, uint32_t capacity,
                          int64_t n_pairs_max, uint32_t *ranges);
 
-// out[v] = offsets[views[v].elem_off] (first pair of view v), out[n_views] = total
-hipError_t launch_view_offsets(hipStream_t s, const uint32_t *offsets, const ViewDev *views, int32_t n_views,
-                               int64_t total_elems, const uint32_t *total_pairs, uint32_t *out);
+
+
+// Pair offsets at depth-slab boundaries: out[v * nb.n + b] = offsets at depth
+// rank (n_v * nb.num[b]) >> 10 of view v (total_pairs past the last element).
+struct SlabBounds {
+    uint32_t n;
+    uint32_t num[9];
+};
+hipError_t launch_slab_offsets(hipStream_t s, const uint32_t *offsets, const ViewDev *views, int32_t n_views,
+                               int64_t total_elems, const uint32_t *total_pairs, SlabBounds nb, uint32_t *out);
 
 // keys[t] = 65535 - min(list length of tile t, 65535), vals[t] = t
 hipError_t launch_tile_keys(hipStream_t s, const uint32_t *ranges, int64_t n_tiles, uint32_t *keys, uint32_t *vals);
@@ -162,10 +184,15 @@ struct AccParams {
     int32_t pad;
 };
 
+// Resumable compositing (depth slabs): with `tstate` set, each pixel's
+// transmittance is read from tstate[views[v].pix_off + y*W + x] (unless
+// `first`, which starts from T = 1) and written back at the end, -1 marking a
+// pixel whose compositing has ended; with `tile_done` set, tiles already marked
+// are skipped and tiles left without a live pixel are marked.
 hipError_t launch_accumulate(hipStream_t s, const float *rec, const uint32_t *vals, const uint32_t *ranges,
                              const ViewDev *views, int32_t n_views, const SceneDev *scenes, const uint32_t *items,
                              uint32_t n_items, const AccParams &p, float *t_final, int32_t *n_blend,
-                             unsigned long long *status);
+                             float *tstate, uint8_t *tile_done, int32_t first, unsigned long long *status);
 
 hipError_t launch_assign(hipStream_t s, const float *A_hi, const float *A_lo, int64_t n, int32_t E, float gamma,
                          uint8_t *S, float *margin, unsigned long long *status);

@@ -306,6 +306,50 @@ __global__ void k_gather_counts(const uint32_t *__restrict__ skeys, const uint32
     counts[i] = (uint32_t)ntiles[(int64_t)views[v].elem_off + svals[i]];
 }
 
+// Depth-slab pair counts. An element outside the slab counts 0; inside, its
+// listed tiles (the row_span rule) that are not yet marked done.
+__device__ __forceinline__ bool in_slab(const ViewDev &C, int64_t i, Slab sl)
+{
+    const uint64_t r = (uint64_t)(i - (int64_t)C.elem_off);
+    const uint64_t lo = ((uint64_t)C.n * sl.num_lo) >> 10, hi = ((uint64_t)C.n * sl.num_hi) >> 10;
+    return r >= lo && r < hi;
+}
+
+__global__ void k_slab_counts(const uint32_t *__restrict__ skeys, const uint32_t *__restrict__ svals,
+                              const float4 *__restrict__ rec, const short4 *__restrict__ rect,
+                              const uint8_t *__restrict__ flags, const int32_t *__restrict__ ntiles,
+                              const ViewDev *__restrict__ views, int32_t n_views, int64_t total, Slab sl,
+                              const uint8_t *__restrict__ done, int32_t tw, int32_t th, float sigma_k,
+                              uint32_t *__restrict__ counts)
+{
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= total) return;
+    uint32_t c = 0;
+    if (skeys[i] != 0xFFFFFFFFu) {
+        const int v = find_view_of_elem(views, n_views, i);
+        const ViewDev &C = views[v];
+        if (in_slab(C, i, sl)) {
+            const int64_t idx = (int64_t)C.elem_off + svals[i];
+            if (done == nullptr) {
+                c = (uint32_t)ntiles[idx];
+            } else {
+                const short4 rc = rect[idx];
+                const float4 r0 = rec[2 * idx];
+                const float4 r1 = rec[2 * idx + 1];
+                const Span32 sp = make_span32(r0.x, r0.y, r0.z, r0.w, r1.x, (flags[idx] & 2u) != 0,
+                                              support_limit(sigma_k));
+                for (int ty = rc.y; ty <= rc.w; ++ty) {
+                    int l, r;
+                    if (!row_span(sp, ty, rc.x, rc.z, tw, th, C.W, C.H, l, r)) continue;
+                    const uint8_t *d = done + C.tile_base + (uint32_t)ty * (uint32_t)C.tiles_x;
+                    for (int t = l; t <= r; ++t) c += d[t] ? 0u : 1u;
+                }
+            }
+        }
+    }
+    counts[i] = c;
+}
+
 // Emission of the (tile, Gaussian) pairs. Block b handles the depth-sorted
 // items [256 b, 256 b + 256), whose outputs form one contiguous range. Each
 // thread enumerates its Gaussian's tiles (the row_span rule, as in the count)
@@ -318,7 +362,8 @@ __global__ __launch_bounds__(kThreads) void k_emit(const uint32_t *__restrict__ 
                                                    const float4 *__restrict__ rec, const short4 *__restrict__ rect,
                                                    const uint8_t *__restrict__ flags, const ViewDev *__restrict__ views,
                                                    int32_t n_views, int64_t total, uint32_t capacity, int32_t tw, int32_t th,
-                                                   float sigma_k, uint32_t *__restrict__ tiles_out,
+                                                   float sigma_k, const uint8_t *__restrict__ done,
+                                                   uint32_t *__restrict__ tiles_out,
                                                    uint32_t *__restrict__ vals_out, unsigned long long *__restrict__ status)
 {
     __shared__ uint32_t s_t[kEmitWin];
@@ -361,17 +406,28 @@ __global__ __launch_bounds__(kThreads) void k_emit(const uint32_t *__restrict__ 
             for (int ty = rc.y; ty <= rc.w && p < wend; ++ty) {
                 int l, r;
                 if (!row_span(sp, ty, rc.x, rc.z, tw, th, W, H, l, r)) continue;
-                const uint32_t n_row = (uint32_t)(r - l + 1);
-                if (p + n_row > w0) {
-                    const uint32_t rowbase = tbase + (uint32_t)ty * tiles_x + (uint32_t)l;
-                    const uint32_t a = p < w0 ? w0 - p : 0u;
-                    const uint32_t b = min(n_row, wend - p);
-                    for (uint32_t e = a; e < b; ++e) {
-                        s_t[p + e - w0] = rowbase + e;
-                        s_g[p + e - w0] = g;
+                const uint32_t rowbase = tbase + (uint32_t)ty * tiles_x;
+                if (done == nullptr) {
+                    const uint32_t n_row = (uint32_t)(r - l + 1);
+                    if (p + n_row > w0) {
+                        const uint32_t a = p < w0 ? w0 - p : 0u;
+                        const uint32_t b = min(n_row, wend - p);
+                        for (uint32_t e = a; e < b; ++e) {
+                            s_t[p + e - w0] = rowbase + (uint32_t)l + e;
+                            s_g[p + e - w0] = g;
+                        }
+                    }
+                    p += n_row;
+                } else {
+                    for (int t = l; t <= r && p < wend; ++t) {
+                        if (done[rowbase + (uint32_t)t]) continue;
+                        if (p >= w0) {
+                            s_t[p - w0] = rowbase + (uint32_t)t;
+                            s_g[p - w0] = g;
+                        }
+                        ++p;
                     }
                 }
-                p += n_row;
             }
         }
         __syncthreads();
@@ -386,22 +442,44 @@ __global__ __launch_bounds__(kThreads) void k_emit(const uint32_t *__restrict__ 
         }
         __syncthreads();
     }
+    if (threadIdx.x == 0 && hi > lo) status_add(status, ST_PAIRS, (unsigned long long)(hi - lo));
     if (__ballot(dropped != 0) && dropped) {
         status_add(status, ST_DROPPED, (unsigned long long)dropped);
         status_flag(status, (unsigned long long)FS_DEV_PAIR_OVERFLOW);
     }
 }
 
-__global__ void k_ranges(const uint32_t *__restrict__ tiles, const uint32_t *__restrict__ n_pairs_dev,
-                         uint32_t capacity, int64_t max_pairs, uint2 *__restrict__ ranges)
+// Ranges of the sorted tile ids: each thread takes 4 consecutive entries (one
+// 16-byte load) plus the neighbours on either side, in a grid-stride loop.
+__global__ __launch_bounds__(256) void k_ranges(const uint32_t *__restrict__ tiles,
+                                                const uint32_t *__restrict__ n_pairs_dev, uint32_t capacity,
+                                                int64_t max_pairs, uint2 *__restrict__ ranges)
 {
-    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    uint32_t np = *n_pairs_dev;
-    if (np > capacity) np = capacity;
-    if (i >= (int64_t)np || i >= max_pairs) return;
-    const uint32_t t = tiles[i];
-    if (i == 0 || tiles[i - 1] != t) ranges[t].x = (uint32_t)i;
-    if (i == (int64_t)np - 1 || tiles[i + 1] != t) ranges[t].y = (uint32_t)(i + 1);
+    int64_t np = (int64_t)*n_pairs_dev;
+    if (np > (int64_t)capacity) np = capacity;
+    if (np > max_pairs) np = max_pairs;
+    const int64_t stride = 4 * (int64_t)gridDim.x * blockDim.x;
+    const bool aligned = (reinterpret_cast<uintptr_t>(tiles) & 15u) == 0;
+    for (int64_t i0 = 4 * ((int64_t)blockIdx.x * blockDim.x + threadIdx.x); i0 < np; i0 += stride) {
+        uint32_t t[6];
+        t[0] = i0 > 0 ? tiles[i0 - 1] : 0xFFFFFFFFu;
+        if (aligned && i0 + 4 <= np) {
+            const uint4 q = *reinterpret_cast<const uint4 *>(tiles + i0);
+            t[1] = q.x; t[2] = q.y; t[3] = q.z; t[4] = q.w;
+        } else {
+#pragma unroll
+            for (int k = 0; k < 4; ++k) t[1 + k] = i0 + k < np ? tiles[i0 + k] : 0xFFFFFFFFu;
+        }
+        t[5] = i0 + 4 < np ? tiles[i0 + 4] : 0xFFFFFFFFu;
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+            const int64_t i = i0 + k;
+            if (i >= np) break;
+            const uint32_t c = t[1 + k];
+            if (c != t[k]) ranges[c].x = (uint32_t)i;
+            if (c != t[2 + k]) ranges[c].y = (uint32_t)(i + 1);
+        }
+    }
 }
 
 // Work-order keys: tiles with longer lists get smaller keys (lengths clamp
@@ -417,19 +495,17 @@ __global__ void k_tile_keys(const uint2 *__restrict__ ranges, int64_t n_tiles, u
     vals[t] = (uint32_t)t;
 }
 
-// out[v] = first pair index of view v (offsets at the view's first element),
-// out[n_views] = total pairs; used to plan chunks from one exact count
-__global__ void k_view_offsets(const uint32_t *__restrict__ offsets, const ViewDev *__restrict__ views, int32_t n_views,
-                               int64_t total_elems, const uint32_t *__restrict__ total_pairs, uint32_t *__restrict__ out)
+// Pair offsets at depth-slab boundaries (used to plan chunks and slab capacities
+// from one exact count).
+__global__ void k_slab_offsets(const uint32_t *__restrict__ offsets, const ViewDev *__restrict__ views,
+                               int32_t n_views, int64_t total_elems, const uint32_t *__restrict__ total_pairs,
+                               SlabBounds nb, uint32_t *__restrict__ out)
 {
-    const int v = blockIdx.x * blockDim.x + threadIdx.x;
-    if (v > n_views) return;
-    if (v == n_views) {
-        out[v] = *total_pairs;
-        return;
-    }
-    const int64_t e = (int64_t)views[v].elem_off;
-    out[v] = e < total_elems ? offsets[e] : *total_pairs;
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n_views * (int)nb.n) return;
+    const int v = i / (int)nb.n, b = i % (int)nb.n;
+    const int64_t e = (int64_t)views[v].elem_off + (int64_t)(((uint64_t)views[v].n * nb.num[b]) >> 10);
+    out[i] = e < total_elems ? offsets[e] : *total_pairs;
 }
 
 inline unsigned grid_for(int64_t n, int threads) { return (unsigned)((n + threads - 1) / threads); }
@@ -531,23 +607,38 @@ hipError_t launch_gather_counts(hipStream_t s, const uint32_t *sorted_keys, cons
 hipError_t launch_emit(hipStream_t s, const uint32_t *sorted_keys, const uint32_t *sorted_vals,
                        const uint32_t *offsets, const uint32_t *counts, const float *rec, const int16_t *rect,
                        const uint8_t *flags, const ViewDev *views, int32_t n_views, int64_t total,
-                       uint32_t capacity, int32_t tile_w, int32_t tile_h, float sigma_k, uint32_t *tiles_out,
+                       uint32_t capacity, int32_t tile_w, int32_t tile_h, float sigma_k, const uint8_t *done,
+                       uint32_t *tiles_out,
                        uint32_t *vals_out, unsigned long long *status)
 {
     if (total == 0) return hipSuccess;
     hipLaunchKernelGGL(k_emit, dim3(grid_for(total, kThreads)), dim3(kThreads), 0, s, sorted_keys, sorted_vals, offsets,
                        counts, reinterpret_cast<const float4 *>(rec), reinterpret_cast<const short4 *>(rect), flags,
-                       views, n_views, total, capacity, tile_w, tile_h, sigma_k, tiles_out, vals_out, status);
+                       views, n_views, total, capacity, tile_w, tile_h, sigma_k, done, tiles_out, vals_out, status);
     return hipGetLastError();
 }
 
-hipError_t launch_view_offsets(hipStream_t s, const uint32_t *offsets, const ViewDev *views, int32_t n_views,
-                               int64_t total_elems, const uint32_t *total_pairs, uint32_t *out)
+hipError_t launch_slab_offsets(hipStream_t s, const uint32_t *offsets, const ViewDev *views, int32_t n_views,
+                               int64_t total_elems, const uint32_t *total_pairs, SlabBounds nb, uint32_t *out)
 {
-    hipLaunchKernelGGL(k_view_offsets, dim3(grid_for(n_views + 1, 256)), dim3(256), 0, s, offsets, views, n_views,
-                       total_elems, total_pairs, out);
+    if (n_views <= 0 || nb.n == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_slab_offsets, dim3(grid_for((int64_t)n_views * nb.n, 256)), dim3(256), 0, s, offsets, views,
+                       n_views, total_elems, total_pairs, nb, out);
     return hipGetLastError();
 }
+
+hipError_t launch_slab_counts(hipStream_t s, const uint32_t *sorted_keys, const uint32_t *sorted_vals,
+                              const float *rec, const int16_t *rect, const uint8_t *flags, const int32_t *ntiles,
+                              const ViewDev *views, int32_t n_views, int64_t total, Slab slab, const uint8_t *done,
+                              int32_t tile_w, int32_t tile_h, float sigma_k, uint32_t *counts)
+{
+    if (total == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_slab_counts, dim3(grid_for(total, 256)), dim3(256), 0, s, sorted_keys, sorted_vals,
+                       reinterpret_cast<const float4 *>(rec), reinterpret_cast<const short4 *>(rect), flags, ntiles,
+                       views, n_views, total, slab, done, tile_w, tile_h, sigma_k, counts);
+    return hipGetLastError();
+}
+
 
 hipError_t launch_tile_keys(hipStream_t s, const uint32_t *ranges, int64_t n_tiles, uint32_t *keys, uint32_t *vals)
 {
@@ -561,8 +652,10 @@ hipError_t launch_ranges(hipStream_t s, const uint32_t *tiles, const uint32_t *n
                          int64_t n_pairs_max, uint32_t *ranges)
 {
     if (n_pairs_max <= 0) return hipSuccess;
-    hipLaunchKernelGGL(k_ranges, dim3(grid_for(n_pairs_max, 256)), dim3(256), 0, s, tiles, n_pairs_dev, capacity,
-                       n_pairs_max, reinterpret_cast<uint2 *>(ranges));
+    int64_t blocks = (n_pairs_max + 1023) / 1024;
+    if (blocks > 4096) blocks = 4096;
+    hipLaunchKernelGGL(k_ranges, dim3((unsigned)blocks), dim3(256), 0, s, tiles, n_pairs_dev, capacity, n_pairs_max,
+                       reinterpret_cast<uint2 *>(ranges));
     return hipGetLastError();
 }
 

@@ -167,3 +167,30 @@ def test_batch_rejects_bad_arguments(ctx):
         L.Batch(ctx, [ds], L.params(), gammas=[1.5])
     with pytest.raises(L.FlashSplatError):
         L.Batch(ctx, [ds], L.params(), compensated=False, reduction=L.FS_RED_LDS2SUM)
+
+
+def test_depth_slabs_give_the_single_pass_result(ctx):
+    """Front-to-back depth slabs (tiles whose pixels have finished get no later pairs)
+    composite the same weights as one pass over the full lists."""
+    scenes = _uneven_scenes()
+    dss = [L.DeviceScene(s) for s in scenes]
+    ctx.status()
+    one = L.Batch(ctx, dss, L.params(), depth_slabs=1)
+    one.run()
+    torch.cuda.synchronize()
+    st1 = ctx.status()
+    assert st1["pairs_emitted"] == one.info()["pairs"]
+    for S in (2, 3, 4):
+        b = L.Batch(ctx, dss, L.params(), depth_slabs=S)
+        b.run()
+        torch.cuda.synchronize()
+        st = ctx.status()
+        log(f"[slabs] S={S}: pairs emitted {st['pairs_emitted']} of {one.info()['pairs']}; blends {st['blends']} "
+            f"vs {st1['blends']}")
+        assert st["pairs_emitted"] <= st1["pairs_emitted"]
+        assert abs(st["blends"] - st1["blends"]) <= 1e-4 * st1["blends"]
+        assert st["bad_labels"] == st1["bad_labels"]
+        for i in range(len(scenes)):
+            a, c = _A(one, i), _A(b, i)
+            d = np.abs(a - c).sum(1)
+            assert np.all(d <= 1e-5 * np.abs(a).sum(1) + 1e-9), f"S={S} scene {i}"

@@ -78,6 +78,21 @@ def test_A_and_labels_match_the_oracle_at_full_size(c2, ref):
         assert_labels(S.cpu().numpy(), S64, m64, ref["A"], ref["slack"], what=f"C2 gamma={gamma}")
 
 
+def test_graph_batch_matches_the_oracle_at_full_size(c2, ref):
+    # the launch configuration the benchmark times: the whole solve as one graph
+    sc, ds, ctx, solver, out, st = c2
+    b = L.Batch(ctx, [ds], solver.prm, gammas=[0.2])
+    b.run()
+    torch.cuda.synchronize()
+    st2 = ctx.status()
+    A = (b.A_hi[0].double() + b.A_lo[0].double()).cpu().numpy()
+    assert_A(A, ref["A"], ref["slack"], what="C2 graph batch")
+    log(f"[c2] graph batch: pairs emitted {st2['pairs_emitted']} of {b.info()['pairs']} planned")
+    assert abs(st2["blends"] - ref["blends"]) <= 1e-3 * ref["blends"]
+    S64, m64 = O.assign64(ref["A"], 0.2)
+    assert_labels(b.S[0].cpu().numpy(), S64, m64, ref["A"], ref["slack"], what="C2 graph batch gamma=0.2")
+
+
 def test_batched_equals_per_view(c2):
     sc, ds, ctx, solver, out, st = c2
     per = Solver(ctx, ds).solve(chunk=1)
