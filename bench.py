@@ -182,6 +182,28 @@ def main():
         ctx.status()
         print(f"[bench] plain: {dt_p * 1e3:.2f} ms/step", file=sys.stderr, flush=True)
 
+    # ---- follow-ups once A is known: bias sweep, object removal ----------------
+    def timed(fn, reps=5):
+        ts = []
+        for _ in range(reps):
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record(ctx.stream)
+            fn()
+            e1.record(ctx.stream)
+            e1.synchronize()
+            ts.append(e0.elapsed_time(e1))
+        return float(np.median(ts))
+
+    gam = [float(x) for x in np.linspace(-0.5, 0.5, 64)]
+    S_sw = torch.empty((64, sc.E, sc.n), dtype=torch.uint8, device="cuda")
+    sweep_ms = timed(lambda: ctx.fs_assign_sweep(batch.A_hi[0], batch.A_lo[0], sc.n, sc.E, gam, S_sw,
+                                                 want_counts=False))
+    sel = batch.S[0][1].contiguous()
+    compact_ms = timed(lambda: ctx.fs_compact(ds, sel, False))
+    followups = {"bias_sweep_64_gammas_ms": sweep_ms, "object_removal_compaction_ms": compact_ms,
+                 "gaussians": sc.n}
+    print(f"[bench] follow-ups: {followups}", file=sys.stderr, flush=True)
+
     # ---- roofline of the compositing kernel (one launch over all views) -----
     # algorithmic fp32 ops: 15 per (pixel, Gaussian) pair inside the support (offset, quadratic form,
     # support test, exp, opacity, clamp, alpha test) + 5 per blend (1-alpha, T update, stop test, w, add)
@@ -250,6 +272,7 @@ def main():
         "plain_views_per_sec": (V / dt_p) if dt_p else None,
         "batched_over_plain": (dt_p / dt_b) if dt_p else None,
         "accumulate_ms_by_strategy": strat,
+        "followups": followups,
         "roofline": roof,
         "cpu_baseline": cpu,
         "parity_sample": parity,

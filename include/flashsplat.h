@@ -223,6 +223,33 @@ int fs_accumulate(fs_ctx *ctx, const fs_proj *proj, const fs_bins *bins, const f
 int fs_assign(fs_ctx *ctx, const float *A_hi, const float *A_lo, int64_t n, int32_t n_classes,
               float gamma, uint8_t *S, float *margin);
 
+/* Interactive follow-ups of the assignment ---------------------------------
+ * Once A is known the background bias can be adjusted interactively (Sec. 3.2
+ * "Regularized ILP for Noise Reduction", Sec. 4.2), and the Gaussians of an
+ * object extracted or removed from the scene (Sec. 4.4 "Object Removal"). */
+
+/* Labels for several biases from one read of A: for k < n_gamma, S[k][t][g]
+ * is fs_assign's S[t][g] with gamma = gammas[k].
+ * gammas: host float [n_gamma], each finite in [-1, 1]; n_gamma in
+ *   [1, min(64, 4096 / n_classes)].
+ * S: device uint8 [n_gamma][n_classes][n], or NULL to count only.
+ * counts: host int64 [n_gamma][n_classes] (members of each object for each
+ *   bias), or NULL; when non-NULL the call synchronises the stream. */
+int fs_assign_sweep(fs_ctx *ctx, const float *A_hi, const float *A_lo, int64_t n, int32_t n_classes,
+                    const float *gammas, int32_t n_gamma, uint8_t *S, int64_t *counts);
+
+/* Stream compaction of the Gaussians: keeps, in their original order, the
+ * Gaussians g with (select[g] != 0) == (keep_selected != 0), i.e. an object's
+ * Gaussians (keep_selected = 1, extraction) or the rest of the scene
+ * (keep_selected = 0, removal), given select = one row S[t] of fs_assign.
+ * in: device arrays of in->n Gaussians. out: device arrays with room for
+ * out->n Gaussians (FS_ERR_CAPACITY, with *n_out set, if more are kept).
+ * select: device uint8 [in->n]. index_map: device int64 [out->n] receiving the
+ * source index of every kept Gaussian, or NULL. n_out: host; the call
+ * synchronises the stream to read it. */
+int fs_compact(fs_ctx *ctx, const fs_gaussians *in, const uint8_t *select, int32_t keep_selected,
+               const fs_gaussians *out, int64_t *index_map, int64_t *n_out);
+
 /* Batched solve ------------------------------------------------------------
  * Many scenes of uneven size, all their views, in one graph launch: the
  * splat-and-accumulate pass is a sum over views (Eq. (7)), so views of all

@@ -15,6 +15,8 @@ Pieces (paper sections in brackets):
   weights64              dense per-pixel weights (tiny scenes only)
   assign64               L1-normalised, background-biased argmax per object
                          [Sec. 3.2 "Regularized ILP", Eq. (8), Listing 1 of the supplement]
+  sweep64 / compact64    bias sweep and object extraction/removal
+                         [Sec. 3.2 "Regularized ILP", Sec. 4.4]
   objective_eq2 / brute_force_binary   exhaustive checks of Eq. (2)/(6)
 """
 from __future__ import annotations
@@ -241,6 +243,24 @@ def assign64(A: np.ndarray, gamma: float = 0.0):
     S = (a_n > o_n + gamma).T.astype(np.uint8)
     margin = np.abs(a_n - o_n - gamma).T
     return np.ascontiguousarray(S), np.ascontiguousarray(margin)
+
+
+def sweep64(A: np.ndarray, gammas: Sequence[float]):
+    """Labels and member counts for several background biases (the bias of
+    Sec. 3.2 "Regularized ILP for Noise Reduction", adjusted interactively once
+    A is known, Sec. 4.2): the closed-form assignment evaluated per bias.
+    Returns S uint8 [K][E][n] and counts int64 [K][E]."""
+    S = np.stack([assign64(A, g)[0] for g in gammas])
+    return S, S.sum(axis=2).astype(np.int64)
+
+
+def compact64(arrays: Sequence[np.ndarray], select: np.ndarray, keep_selected: bool):
+    """Object extraction (keep_selected) or removal (Sec. 4.4): the Gaussians
+    whose selection flag matches, in their original order, by boolean
+    indexing. Returns (kept arrays, source indices)."""
+    mask = (np.asarray(select) != 0) == bool(keep_selected)
+    idx = np.nonzero(mask)[0]
+    return [np.asarray(a)[mask] for a in arrays], idx
 
 
 def objective_eq2(weights: Sequence[np.ndarray], masks: Sequence[np.ndarray], P: np.ndarray) -> float:

@@ -98,7 +98,8 @@ class FsBatchInfo(ctypes.Structure):
 # every symbol the header declares (checked by the CPU test)
 EXPORTS = ["fs_version", "fs_error_string", "fs_params_default", "fs_params_exact", "fs_ctx_create",
            "fs_ctx_set_stream", "fs_ctx_destroy", "fs_ctx_last_error", "fs_status_get", "fs_project",
-           "fs_bin_sort", "fs_accumulate", "fs_assign", "fs_batch_opts_default", "fs_batch_create",
+           "fs_bin_sort", "fs_accumulate", "fs_assign", "fs_assign_sweep", "fs_compact",
+           "fs_batch_opts_default", "fs_batch_create",
            "fs_batch_run", "fs_batch_get_info", "fs_batch_destroy"]
 
 _lib = None
@@ -130,6 +131,9 @@ def load(path: str = LIB_PATH):
         "fs_accumulate": ([_P, ctypes.POINTER(FsProj), ctypes.POINTER(FsBins), ctypes.POINTER(FsCamera), _P, _I32,
                            ctypes.POINTER(FsParams), _P, _P, _I32, ctypes.POINTER(FsPixelOut)], _I32),
         "fs_assign": ([_P, _P, _P, _I64, _I32, _F, _P, _P], _I32),
+        "fs_assign_sweep": ([_P, _P, _P, _I64, _I32, ctypes.POINTER(_F), _I32, _P, ctypes.POINTER(_I64)], _I32),
+        "fs_compact": ([_P, ctypes.POINTER(FsGaussians), _P, _I32, ctypes.POINTER(FsGaussians), _P,
+                        ctypes.POINTER(_I64)], _I32),
         "fs_batch_opts_default": ([ctypes.POINTER(FsBatchOpts)], None),
         "fs_batch_create": ([_P, ctypes.POINTER(FsScene), _I32, ctypes.POINTER(FsParams),
                              ctypes.POINTER(FsBatchOpts), ctypes.POINTER(_P)], _I32),
@@ -254,6 +258,28 @@ class Context:
                   S: torch.Tensor, margin: Optional[torch.Tensor] = None):
         return self._check(self.L.fs_assign(self.h, _ptr(A_hi), _ptr(A_lo), n, n_classes, float(gamma), _ptr(S),
                                             _ptr(margin)))
+
+
+    def fs_assign_sweep(self, A_hi: torch.Tensor, A_lo: Optional[torch.Tensor], n: int, n_classes: int, gammas,
+                        S: Optional[torch.Tensor] = None, want_counts: bool = True):
+        g = (_F * len(gammas))(*[float(x) for x in gammas])
+        cnt = (_I64 * (len(gammas) * n_classes))() if want_counts else None
+        self._check(self.L.fs_assign_sweep(self.h, _ptr(A_hi), _ptr(A_lo), n, n_classes, g, len(gammas), _ptr(S),
+                                           cnt))
+        return np.frombuffer(cnt, dtype=np.int64).reshape(len(gammas), n_classes).copy() if want_counts else None
+
+    def fs_compact(self, scene: "DeviceScene", select: torch.Tensor, keep_selected: bool,
+                   capacity: Optional[int] = None, want_index: bool = True):
+        """Returns (arrays: list of 11 device tensors, index_map or None)."""
+        cap = scene.n if capacity is None else int(capacity)
+        out = [torch.empty(max(1, cap), dtype=torch.float32, device=select.device) for _ in range(11)]
+        idx = torch.empty(max(1, cap), dtype=torch.int64, device=select.device) if want_index else None
+        o = FsGaussians(*[_ptr(a) for a in out], cap)
+        n_out = _I64(0)
+        self._check(self.L.fs_compact(self.h, ctypes.byref(scene.struct()), _ptr(select), 1 if keep_selected else 0,
+                                      ctypes.byref(o), _ptr(idx), ctypes.byref(n_out)))
+        k = int(n_out.value)
+        return [a[:k] for a in out], (idx[:k] if idx is not None else None)
 
 
 class DeviceScene:

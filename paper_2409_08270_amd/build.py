@@ -24,6 +24,7 @@ SOURCES = {
     "fs_sort.hip": ["-ffp-contract=off"],
     "fs_accum.hip": ["-ffp-contract=fast"],
     "fs_assign.hip": [],
+    "fs_select.hip": [],
     "fs_api.hip": [],
 }
 

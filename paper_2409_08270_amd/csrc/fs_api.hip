@@ -662,6 +662,70 @@ int fs_assign(fs_ctx *ctx, const float *A_hi, const float *A_lo, int64_t n, int3
     return FS_OK;
 }
 
+int fs_assign_sweep(fs_ctx *ctx, const float *A_hi, const float *A_lo, int64_t n, int32_t n_classes,
+                    const float *gammas, int32_t n_gamma, uint8_t *S, int64_t *counts)
+{
+    if (!ctx) return FS_ERR_ARG;
+    if (n < 0) return set_err(ctx, FS_ERR_ARG, "n < 0");
+    if (n_classes < 2 || n_classes > 256) return set_err(ctx, FS_ERR_ARG, "n_classes %d not in [2, 256]", n_classes);
+    if (!gammas || n_gamma < 1 || n_gamma > sweep_max_gammas(n_classes))
+        return set_err(ctx, FS_ERR_ARG, "n_gamma must be in [1, %d]", sweep_max_gammas(n_classes));
+    for (int k = 0; k < n_gamma; ++k)
+        if (!finite_f(gammas[k]) || gammas[k] < -1.f || gammas[k] > 1.f)
+            return set_err(ctx, FS_ERR_ARG, "gamma %d must be finite in [-1, 1]", k);
+    if (n > 0 && !A_hi) return set_err(ctx, FS_ERR_ARG, "A_hi is NULL");
+    if (!S && !counts) return set_err(ctx, FS_ERR_ARG, "nothing to compute: S and counts are NULL");
+    const size_t ncnt = (size_t)n_gamma * n_classes;
+    RCHECK(upload(ctx, ctx->items_ws, gammas, sizeof(float) * n_gamma));
+    RCHECK(ensure(ctx, ctx->items_k, ncnt * 8));
+    HIPCHECK(ctx, launch_fill_u32(ctx->stream, (uint32_t *)ctx->items_k.p, 0u, (int64_t)ncnt * 2));
+    HIPCHECK(ctx, launch_assign_sweep(ctx->stream, A_hi, A_lo, n, n_classes, (const float *)ctx->items_ws.p, n_gamma,
+                                      S, (unsigned long long *)ctx->items_k.p));
+    if (counts) {
+        HIPCHECK(ctx, hipMemcpyAsync(counts, ctx->items_k.p, ncnt * 8, hipMemcpyDeviceToHost, ctx->stream));
+        HIPCHECK(ctx, hipStreamSynchronize(ctx->stream));
+    }
+    return FS_OK;
+}
+
+int fs_compact(fs_ctx *ctx, const fs_gaussians *in, const uint8_t *select, int32_t keep_selected,
+               const fs_gaussians *out, int64_t *index_map, int64_t *n_out)
+{
+    if (!ctx) return FS_ERR_ARG;
+    RCHECK(check_gauss(ctx, in));
+    if (!out || !n_out) return set_err(ctx, FS_ERR_ARG, "out or n_out is NULL");
+    if (out->n < 0) return set_err(ctx, FS_ERR_ARG, "out->n < 0");
+    if (in->n > 0 && !select) return set_err(ctx, FS_ERR_ARG, "select is NULL");
+    const int64_t n = in->n;
+    *n_out = 0;
+    if (n == 0) return FS_OK;
+    RCHECK(ensure(ctx, ctx->counts, (size_t)n * 4));
+    RCHECK(ensure(ctx, ctx->offsets, (size_t)n * 4));
+    RCHECK(ensure(ctx, ctx->scan_ws, scan_ws_bytes(n)));
+    HIPCHECK(ctx, launch_select_flags(ctx->stream, select, n, keep_selected, (uint32_t *)ctx->counts.p));
+    HIPCHECK(ctx, scan_exclusive(ctx->stream, (const uint32_t *)ctx->counts.p, (uint32_t *)ctx->offsets.p, n,
+                                 ctx->npairs_dev, ctx->scan_ws.p));
+    HIPCHECK(ctx, hipMemcpyAsync(ctx->npairs_host, ctx->npairs_dev, 4, hipMemcpyDeviceToHost, ctx->stream));
+    HIPCHECK(ctx, hipStreamSynchronize(ctx->stream));
+    const int64_t kept = (int64_t)ctx->npairs_host[0];
+    *n_out = kept;
+    if (kept > out->n) return set_err(ctx, FS_ERR_CAPACITY, "%lld Gaussians kept, room for %lld", (long long)kept,
+                                      (long long)out->n);
+    if (kept == 0) return FS_OK;
+    const float *src[11] = {in->mx, in->my, in->mz, in->qw, in->qx, in->qy, in->qz, in->sx, in->sy, in->sz,
+                            in->opacity};
+    // fs_gaussians holds read-only pointers; the output arrays are written here
+    float *dst[11] = {const_cast<float *>(out->mx), const_cast<float *>(out->my), const_cast<float *>(out->mz),
+                      const_cast<float *>(out->qw), const_cast<float *>(out->qx), const_cast<float *>(out->qy),
+                      const_cast<float *>(out->qz), const_cast<float *>(out->sx), const_cast<float *>(out->sy),
+                      const_cast<float *>(out->sz), const_cast<float *>(out->opacity)};
+    for (int k = 0; k < 11; ++k)
+        if (!dst[k]) return set_err(ctx, FS_ERR_ARG, "output Gaussian array %d is NULL", k);
+    HIPCHECK(ctx, launch_compact(ctx->stream, src, dst, (const uint32_t *)ctx->counts.p,
+                                 (const uint32_t *)ctx->offsets.p, n, index_map));
+    return FS_OK;
+}
+
 }  // extern "C"
 
 // ===========================================================================

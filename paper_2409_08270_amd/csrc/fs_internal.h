@@ -197,6 +197,14 @@ hipError_t launch_accumulate(hipStream_t s, const float *rec, const uint32_t *va
 hipError_t launch_assign(hipStream_t s, const float *A_hi, const float *A_lo, int64_t n, int32_t E, float gamma,
                          uint8_t *S, float *margin, unsigned long long *status);
 
+// gamma sweep and stream compaction (fs_select.hip)
+int sweep_max_gammas(int32_t E);
+hipError_t launch_assign_sweep(hipStream_t s, const float *A_hi, const float *A_lo, int64_t n, int32_t E,
+                               const float *gammas_dev, int32_t n_gamma, uint8_t *S, unsigned long long *counts);
+hipError_t launch_select_flags(hipStream_t s, const uint8_t *select, int64_t n, int32_t keep_selected, uint32_t *flags);
+hipError_t launch_compact(hipStream_t s, const float *const in[11], float *const out[11], const uint32_t *flags,
+                          const uint32_t *pos, int64_t n, int64_t *index_map);
+
 // ---- device helpers ------------------------------------------------------
 // View holding element i: the wave searches once (scalar) for its first
 // lane's element, then each lane steps forward while its element lies beyond
