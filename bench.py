@@ -200,8 +200,13 @@ def main():
                                                  want_counts=False))
     sel = batch.S[0][1].contiguous()
     compact_ms = timed(lambda: ctx.fs_compact(ds, sel, False))
+    labels = torch.empty(sc.pixels(), dtype=torch.uint8, device="cuda")
+    render_ms = timed(lambda: ctx.fs_render_masks(solver.proj, solver.bins, cams, batch.S[0], sc.E, prm, 0.1,
+                                                  L.FS_MASK_DEPTH, labels))
+    agree = float((labels.cpu().numpy() == ds.masks.cpu().numpy()).mean())
     followups = {"bias_sweep_64_gammas_ms": sweep_ms, "object_removal_compaction_ms": compact_ms,
-                 "gaussians": sc.n}
+                 "mask_render_all_views_ms": render_ms, "mask_render_views_per_sec": V / (render_ms * 1e-3),
+                 "rendered_masks_agree_with_inputs": agree, "gaussians": sc.n}
     print(f"[bench] follow-ups: {followups}", file=sys.stderr, flush=True)
 
     # ---- roofline of the compositing kernel (one launch over all views) -----

@@ -250,6 +250,27 @@ int fs_assign_sweep(fs_ctx *ctx, const float *A_hi, const float *A_lo, int64_t n
 int fs_compact(fs_ctx *ctx, const fs_gaussians *in, const uint8_t *select, int32_t keep_selected,
                const fs_gaussians *out, int64_t *index_map, int64_t *n_out);
 
+/* Novel-view masks (Sec. 3.4 "Depth-guided Novel View Mask Rendering"; the
+ * supplement's "Quantization in novel view mask"). For every object e the
+ * Gaussians with S[e][g] != 0 are composited on their own with the rules of
+ * fs_accumulate, giving its alpha mask rho_e = sum alpha*T and its depth
+ * D_e = sum alpha*T*z / rho_e (z: camera-space depth of the mean). The label
+ * of a pixel is
+ *   mode FS_MASK_DEPTH: the object e >= 1 with rho_e > tau and least D_e
+ *                       (0 if there is none; ties go to the smaller e);
+ *   mode FS_MASK_ARGMAX: argmax over every e >= 0 of rho_e (first maximum).
+ * proj, bins: fs_project / fs_bin_sort of the rendered views (256-pixel tiles
+ * as for fs_accumulate). S: device uint8 [n_classes][n], e.g. fs_assign's
+ * output. labels: device uint8, the views' pixels concatenated [H][W] each.
+ * rho, depth: device float32 [n_classes][pixels of all views], or NULL
+ * (entries for objects that are not rendered are left untouched; depth is
+ * 3e38 where rho_e = 0). tau: finite. */
+#define FS_MASK_DEPTH 0
+#define FS_MASK_ARGMAX 1
+int fs_render_masks(fs_ctx *ctx, const fs_proj *proj, const fs_bins *bins, const fs_camera *cams,
+                    const uint8_t *S, int32_t n_classes, const fs_params *p, float tau, int32_t mode,
+                    uint8_t *labels, float *rho, float *depth);
+
 /* Batched solve ------------------------------------------------------------
  * Many scenes of uneven size, all their views, in one graph launch: the
  * splat-and-accumulate pass is a sum over views (Eq. (7)), so views of all

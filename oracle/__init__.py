@@ -13,6 +13,8 @@ Pieces (paper sections in brackets):
                          Listing 1 of the supplement]
   render64               Eq. (1) with an arbitrary per-Gaussian property
   weights64              dense per-pixel weights (tiny scenes only)
+  render_masks64         novel-view masks: per-object alpha and depth,
+                         depth-guided or argmax label [Sec. 3.4, supplement]
   assign64               L1-normalised, background-biased argmax per object
                          [Sec. 3.2 "Regularized ILP", Eq. (8), Listing 1 of the supplement]
   sweep64 / compact64    bias sweep and object extraction/removal
@@ -78,6 +80,8 @@ def lib():
         L.or_render64.restype = None
         L.or_weights64.argtypes = [I64, P, P, P, P, P, P, P]
         L.or_weights64.restype = None
+        L.or_render_masks64.argtypes = [I64, P, P, P, P, P, P, P, P, I32, ctypes.c_double, I32, P, P, P]
+        L.or_render_masks64.restype = None
         _lib = L
     return _lib
 
@@ -197,9 +201,40 @@ def render64(scene, v: int, prm: np.ndarray, x: np.ndarray, bins: Optional[dict]
     out = np.zeros((H, W), np.float64)
     xx = np.ascontiguousarray(x, dtype=np.float64)
     lst = np.ascontiguousarray(b["g"]) if b["g"].size else np.zeros(1, np.uint32)
-    lib().or_render64(scene.n, _p(p), _p(np.ascontiguousarray(scene.op)), _p(cam), _p(prm),
+    op = np.ascontiguousarray(scene.op)  # kept alive for the call
+    lib().or_render64(scene.n, _p(p), _p(op), _p(cam), _p(prm),
                       _p(lst), _p(b["ranges"]), _p(xx), _p(out))
     return out
+
+
+def depth64(scene, v: int) -> np.ndarray:
+    """Camera-space depth z of every Gaussian mean in view v, binary64."""
+    R = scene.R[v].astype(np.float64).reshape(3, 3)
+    t = scene.t[v].astype(np.float64)
+    m = np.stack([scene.mx, scene.my, scene.mz]).astype(np.float64)
+    return np.ascontiguousarray(R[2] @ m + t[2])
+
+
+def render_masks64(scene, v: int, prm: np.ndarray, S: np.ndarray, tau: float = 0.1, mode: int = 0,
+                   bins: Optional[dict] = None, p64: Optional[np.ndarray] = None):
+    """Novel-view mask of view v from per-object membership S uint8 [E][n]
+    (Sec. 3.4): returns label uint8 [H][W], rho and depth float64 [E][H][W]."""
+    b = bin_view(scene, v, prm) if bins is None else bins
+    p = project64(scene, v, prm) if p64 is None else p64
+    cam = np.ascontiguousarray(scene.camera_rows()[v])
+    W, H = int(scene.W[v]), int(scene.H[v])
+    S = np.ascontiguousarray(S, dtype=np.uint8)
+    E = S.shape[0]
+    label = np.zeros((H, W), np.uint8)
+    rho = np.zeros((E, H, W), np.float64)
+    depth = np.full((E, H, W), np.inf)
+    lst = np.ascontiguousarray(b["g"]) if b["g"].size else np.zeros(1, np.uint32)
+    op = np.ascontiguousarray(scene.op)  # arrays passed by address are kept alive for the call
+    z = depth64(scene, v)
+    lib().or_render_masks64(scene.n, _p(p), _p(op), _p(z), _p(cam),
+                            _p(prm), _p(lst), _p(b["ranges"]), _p(S), E, float(tau), int(mode), _p(label), _p(rho),
+                            _p(depth))
+    return label, rho, depth
 
 
 def weights64(scene, v: int, prm: np.ndarray) -> np.ndarray:
@@ -211,7 +246,8 @@ def weights64(scene, v: int, prm: np.ndarray) -> np.ndarray:
     assert W * H * scene.n <= 50_000_000
     out = np.zeros((H * W, scene.n), np.float64)
     lst = np.ascontiguousarray(b["g"]) if b["g"].size else np.zeros(1, np.uint32)
-    lib().or_weights64(scene.n, _p(p), _p(np.ascontiguousarray(scene.op)), _p(cam), _p(prm),
+    op = np.ascontiguousarray(scene.op)  # kept alive for the call
+    lib().or_weights64(scene.n, _p(p), _p(op), _p(cam), _p(prm),
                        _p(lst), _p(b["ranges"]), _p(out))
     return out
 

@@ -562,3 +562,70 @@ void or_weights64(int64_t n, const double *p64, const float *opacity, const floa
             }
     }
 }
+
+/* ------------------------------------------------------------------------
+ * Novel-view masks (Sec. 3.4; the supplement's "Quantization in novel view
+ * mask"), binary64. For every object e, only its member Gaussians
+ * (S[e][g] != 0) are composited, front to back over the tile lists, with the
+ * same rules as or_composite64:
+ *   rho_e = sum alpha T          (the object's alpha mask)
+ *   D_e   = sum alpha T z / rho_e (its depth where visible; +inf if rho_e = 0)
+ * label = mode 0: the object e >= 1 with rho_e > tau and least D_e (ties to
+ *                 the smaller e), 0 if there is none (depth-guided);
+ *         mode 1: argmax over every e >= 0 of rho_e (first maximum).
+ * z: double [n] camera-space depth of each Gaussian. S: uint8 [E][n].
+ * Outputs: label uint8 [H][W]; rho, depth double [E][H][W] (may be NULL).
+ * ---------------------------------------------------------------------- */
+void or_render_masks64(int64_t n, const double *p64, const float *opacity, const double *z, const float *cam,
+                       const float *prm, const uint32_t *list, const uint32_t *ranges, const uint8_t *S, int32_t E,
+                       double tau, int32_t mode, uint8_t *label, double *rho_out, double *depth_out)
+{
+    int W = (int)cam[16], H = (int)cam[17];
+    int tw = (int)prm[P_TW], th = (int)prm[P_TH];
+    int tiles_x = (W + tw - 1) / tw, tiles_y = (H + th - 1) / th;
+    double k = prm[P_K], cut = -0.5 * k * k;
+    double amin = prm[P_AMIN], amax = prm[P_AMAX], tmin = prm[P_TMIN];
+    int64_t npix = (int64_t)W * H;
+#pragma omp parallel for schedule(dynamic, 1)
+    for (int tile = 0; tile < tiles_x * tiles_y; ++tile) {
+        int tx = tile % tiles_x, ty = tile / tiles_x;
+        uint32_t rs = ranges[2 * tile], re = ranges[2 * tile + 1];
+        for (int jj = 0; jj < th; ++jj)
+            for (int kk = 0; kk < tw; ++kk) {
+                int j = ty * th + jj, kx = tx * tw + kk;
+                if (j >= H || kx >= W) continue;
+                int64_t pix = (int64_t)j * W + kx;
+                int best = 0;
+                double best_d = INFINITY, best_rho = -1.0;
+                for (int e = (mode == 1 ? 0 : 1); e < E; ++e) {
+                    const uint8_t *mem = S + (int64_t)e * n;
+                    double T = 1.0, rho = 0.0, dz = 0.0;
+                    for (uint32_t i = rs; i < re; ++i) {
+                        uint32_t g = list[i];
+                        if (!mem[g]) continue;
+                        const double *q = p64 + 5 * (int64_t)g;
+                        double dx = (kx + 0.5) - q[0], dy = (j + 0.5) - q[1];
+                        double power = -0.5 * (q[2] * dx * dx + q[4] * dy * dy) - q[3] * dx * dy;
+                        if (power < cut) continue;
+                        double a = fmin(amax, (double)opacity[g] * exp(power));
+                        if (a < amin) continue;
+                        double Tn = T * (1.0 - a);
+                        if (Tn < tmin) break;
+                        rho += a * T;
+                        dz += a * T * z[g];
+                        T = Tn;
+                    }
+                    double d = rho > 0.0 ? dz / rho : INFINITY;
+                    if (rho_out) rho_out[(int64_t)e * npix + pix] = rho;
+                    if (depth_out) depth_out[(int64_t)e * npix + pix] = d;
+                    if (mode == 1) {
+                        if (rho > best_rho) { best_rho = rho; best = e; }
+                    } else if (rho > tau && d < best_d) {
+                        best_d = d;
+                        best = e;
+                    }
+                }
+                label[pix] = (uint8_t)best;
+            }
+    }
+}

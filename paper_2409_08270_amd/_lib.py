@@ -34,6 +34,9 @@ FS_RED_PLAIN = 1
 FS_RED_LDS = 2
 FS_RED_LDS2SUM = 3
 
+FS_MASK_DEPTH = 0
+FS_MASK_ARGMAX = 1
+
 _P = ctypes.c_void_p
 _F = ctypes.c_float
 _I32 = ctypes.c_int32
@@ -98,7 +101,7 @@ class FsBatchInfo(ctypes.Structure):
 # every symbol the header declares (checked by the CPU test)
 EXPORTS = ["fs_version", "fs_error_string", "fs_params_default", "fs_params_exact", "fs_ctx_create",
            "fs_ctx_set_stream", "fs_ctx_destroy", "fs_ctx_last_error", "fs_status_get", "fs_project",
-           "fs_bin_sort", "fs_accumulate", "fs_assign", "fs_assign_sweep", "fs_compact",
+           "fs_bin_sort", "fs_accumulate", "fs_assign", "fs_assign_sweep", "fs_compact", "fs_render_masks",
            "fs_batch_opts_default", "fs_batch_create",
            "fs_batch_run", "fs_batch_get_info", "fs_batch_destroy"]
 
@@ -134,6 +137,8 @@ def load(path: str = LIB_PATH):
         "fs_assign_sweep": ([_P, _P, _P, _I64, _I32, ctypes.POINTER(_F), _I32, _P, ctypes.POINTER(_I64)], _I32),
         "fs_compact": ([_P, ctypes.POINTER(FsGaussians), _P, _I32, ctypes.POINTER(FsGaussians), _P,
                         ctypes.POINTER(_I64)], _I32),
+        "fs_render_masks": ([_P, ctypes.POINTER(FsProj), ctypes.POINTER(FsBins), ctypes.POINTER(FsCamera), _P, _I32,
+                             ctypes.POINTER(FsParams), _F, _I32, _P, _P, _P], _I32),
         "fs_batch_opts_default": ([ctypes.POINTER(FsBatchOpts)], None),
         "fs_batch_create": ([_P, ctypes.POINTER(FsScene), _I32, ctypes.POINTER(FsParams),
                              ctypes.POINTER(FsBatchOpts), ctypes.POINTER(_P)], _I32),
@@ -267,6 +272,13 @@ class Context:
         self._check(self.L.fs_assign_sweep(self.h, _ptr(A_hi), _ptr(A_lo), n, n_classes, g, len(gammas), _ptr(S),
                                            cnt))
         return np.frombuffer(cnt, dtype=np.int64).reshape(len(gammas), n_classes).copy() if want_counts else None
+
+    def fs_render_masks(self, proj: "Proj", bins: "Bins", cams, S: torch.Tensor, n_classes: int, prm: FsParams,
+                        tau: float, mode: int, labels: torch.Tensor, rho: Optional[torch.Tensor] = None,
+                        depth: Optional[torch.Tensor] = None):
+        return self._check(self.L.fs_render_masks(self.h, ctypes.byref(proj.struct()), ctypes.byref(bins.struct()),
+                                                  cams, _ptr(S), n_classes, ctypes.byref(prm), float(tau), int(mode),
+                                                  _ptr(labels), _ptr(rho), _ptr(depth)))
 
     def fs_compact(self, scene: "DeviceScene", select: torch.Tensor, keep_selected: bool,
                    capacity: Optional[int] = None, want_index: bool = True):

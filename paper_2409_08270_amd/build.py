@@ -25,6 +25,7 @@ SOURCES = {
     "fs_accum.hip": ["-ffp-contract=fast"],
     "fs_assign.hip": [],
     "fs_select.hip": [],
+    "fs_render.hip": [],
     "fs_api.hip": [],
 }
 

@@ -662,6 +662,30 @@ int fs_assign(fs_ctx *ctx, const float *A_hi, const float *A_lo, int64_t n, int3
     return FS_OK;
 }
 
+int fs_render_masks(fs_ctx *ctx, const fs_proj *proj, const fs_bins *bins, const fs_camera *cams,
+                    const uint8_t *S, int32_t n_classes, const fs_params *p, float tau, int32_t mode,
+                    uint8_t *labels, float *rho, float *depth)
+{
+    if (!ctx) return FS_ERR_ARG;
+    RCHECK(check_params(ctx, p, true));
+    RCHECK(check_proj(ctx, proj));
+    if (!bins || !bins->ranges) return set_err(ctx, FS_ERR_ARG, "bins is NULL");
+    RCHECK(check_cams(ctx, cams, proj->n_views));
+    if (n_classes < 2 || n_classes > 256) return set_err(ctx, FS_ERR_ARG, "n_classes %d not in [2, 256]", n_classes);
+    if (mode != FS_MASK_DEPTH && mode != FS_MASK_ARGMAX) return set_err(ctx, FS_ERR_ARG, "unknown mask mode %d", mode);
+    if (!finite_f(tau)) return set_err(ctx, FS_ERR_ARG, "tau must be finite");
+    const int32_t V = proj->n_views;
+    if (proj->n == 0 || V == 0) return FS_OK;
+    if (!S || !labels) return set_err(ctx, FS_ERR_ARG, "S or labels is NULL");
+    Plan pl;
+    plan_add(pl, p, 0, proj->n, cams, 0, V, 0);
+    RCHECK(upload_vec(ctx, ctx->views, pl.views));
+    HIPCHECK(ctx, launch_render(ctx->stream, proj->rec, bins->vals, bins->ranges, (const ViewDev *)ctx->views.p, V,
+                                (uint32_t)pl.tiles, S, proj->n, n_classes, acc_params(p, FS_RED_LDS), tau, mode, labels,
+                                rho, depth, (int64_t)pl.pixels));
+    return FS_OK;
+}
+
 int fs_assign_sweep(fs_ctx *ctx, const float *A_hi, const float *A_lo, int64_t n, int32_t n_classes,
                     const float *gammas, int32_t n_gamma, uint8_t *S, int64_t *counts)
 {

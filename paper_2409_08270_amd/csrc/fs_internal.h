@@ -197,6 +197,12 @@ hipError_t launch_accumulate(hipStream_t s, const float *rec, const uint32_t *va
 hipError_t launch_assign(hipStream_t s, const float *A_hi, const float *A_lo, int64_t n, int32_t E, float gamma,
                          uint8_t *S, float *margin, unsigned long long *status);
 
+// novel-view masks (fs_render.hip)
+hipError_t launch_render(hipStream_t s, const float *rec, const uint32_t *vals, const uint32_t *ranges,
+                         const ViewDev *views, int32_t n_views, uint32_t n_tiles, const uint8_t *S, int64_t n,
+                         int32_t E, const AccParams &p, float tau, int32_t mode, uint8_t *labels, float *rho,
+                         float *depth, int64_t n_pixels);
+
 // gamma sweep and stream compaction (fs_select.hip)
 int sweep_max_gammas(int32_t E);
 hipError_t launch_assign_sweep(hipStream_t s, const float *A_hi, const float *A_lo, int64_t n, int32_t E,

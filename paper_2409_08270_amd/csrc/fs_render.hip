@@ -1,0 +1,138 @@
+// Novel-view mask rendering (paper Sec. 3.4 "Depth-guided Novel View Mask
+// Rendering" and the supplement's "Quantization in novel view mask").
+//
+// For every object e, the Gaussians labelled e (row e of S) are composited on
+// their own, front to back, with the compositing rules of the accumulation
+// pass: rho_e = sum of alpha*T (the object's alpha mask) and
+// D_e = sum of alpha*T*z / rho_e (its depth where it is visible). The mask
+// label is then either
+//   depth-guided: the object with rho_e > tau of least D_e (0 if none), or
+//   argmax:       argmax over all objects (background included) of rho_e.
+//
+// One workgroup renders one tile (one pixel per thread). For each object the
+// tile's depth-ordered list is staged through LDS in batches; the members of
+// the object are compacted with wave ballots and every thread walks them.
+#include "fs_internal.h"
+
+namespace fs {
+namespace {
+
+constexpr int kRBatch = 256;
+
+__global__ __launch_bounds__(256) void k_render(const float4 *__restrict__ rec, const uint32_t *__restrict__ vals,
+                                                const uint2 *__restrict__ ranges, const ViewDev *__restrict__ views,
+                                                int32_t n_views, const uint8_t *__restrict__ S, int64_t n, int32_t E,
+                                                AccParams P, float tau, int32_t mode, uint8_t *__restrict__ labels,
+                                                float *__restrict__ rho_out, float *__restrict__ depth_out,
+                                                int64_t n_pixels)
+{
+    __shared__ float4 s_q[kRBatch];   // u, v, a', b' (conic in log2 units)
+    __shared__ float4 s_q2[kRBatch];  // c', lo, thr, z
+    __shared__ uint16_t s_list[kRBatch];
+    __shared__ uint32_t s_wcnt[4];
+
+    const uint32_t tile = blockIdx.x;
+    const int view = find_view_of_tile(views, n_views, tile);
+    const ViewDev &C = views[view];
+    const uint32_t local = tile - C.tile_base;
+    const int tx = (int)(local % (uint32_t)C.tiles_x), ty = (int)(local / (uint32_t)C.tiles_x);
+    const int tid = threadIdx.x, w = tid >> 6, lane = tid & 63;
+    const int x = tx * P.tile_w + tid % P.tile_w;
+    const int y = ty * P.tile_h + tid / P.tile_w;
+    const bool inside = x < C.W && y < C.H;
+    const int64_t pix = (int64_t)C.mask_off + (int64_t)y * C.W + x;
+    const float pxc = (float)x + 0.5f, pyc = (float)y + 0.5f;
+    const float LOG2E = 1.4426950408889634f;
+    const uint2 rg = ranges[tile];
+    const int64_t rec_base = (int64_t)C.elem_off;
+
+    int best = 0;
+    float best_d = 3.0e38f, best_rho = -1.0f;
+    for (int e = (mode == 1 ? 0 : 1); e < E; ++e) {
+        const uint8_t *__restrict__ member = S + (int64_t)e * n;
+        float T = 1.0f, rho = 0.0f, dz = 0.0f;
+        bool live = inside;
+        for (uint32_t base = rg.x; base < rg.y; base += kRBatch) {
+            const uint32_t cnt = min((uint32_t)kRBatch, rg.y - base);
+            __syncthreads();  // previous batch consumed
+            bool mine = false;
+            if ((uint32_t)tid < cnt) {
+                const uint32_t g = vals[base + tid];
+                mine = member[g] != 0;
+                if (mine) {
+                    const float4 r0 = rec[(rec_base + g) * 2];
+                    const float4 r1 = rec[(rec_base + g) * 2 + 1];
+                    const float lo = fmaxf(__builtin_amdgcn_logf(r1.y), -200.0f);
+                    s_q[tid] = make_float4(r0.x, r0.y, -0.5f * LOG2E * r0.z, -LOG2E * r0.w);
+                    s_q2[tid] = make_float4(-0.5f * LOG2E * r1.x, lo, P.cut2 + lo, r1.z);
+                }
+            }
+            // members of the batch in list order: per-wave ballots, then wave offsets
+            const unsigned long long bm = __ballot(mine);
+            if (lane == 0) s_wcnt[w] = (uint32_t)__popcll(bm);
+            __syncthreads();
+            uint32_t before = 0, total = 0;
+            for (int i = 0; i < 4; ++i) {
+                const uint32_t c = s_wcnt[i];
+                if (i < w) before += c;
+                total += c;
+            }
+            if (mine) s_list[before + (uint32_t)__popcll(bm & ((1ull << lane) - 1ull))] = (uint16_t)tid;
+            __syncthreads();
+            if (live) {
+                for (uint32_t k = 0; k < total; ++k) {
+                    const uint32_t j = s_list[k];
+                    const float4 q = s_q[j];
+                    const float4 q2 = s_q2[j];
+                    const float dx = pxc - q.x, dy = pyc - q.y;
+                    const float pw = fmaf(fmaf(q.z, dx, q.w * dy), dx, fmaf(q2.x * dy, dy, q2.y));
+                    if (pw < q2.z) continue;
+                    const float alpha = fminf(P.alpha_max, __builtin_amdgcn_exp2f(pw));
+                    if (alpha < P.alpha_min) continue;
+                    const float Tn = fmaf(-T, alpha, T);
+                    if (Tn < P.t_min) {
+                        live = false;
+                        break;
+                    }
+                    const float wv = alpha * T;
+                    rho += wv;
+                    dz = fmaf(wv, q2.w, dz);
+                    T = Tn;
+                }
+            }
+            if (__syncthreads_or(live) == 0) break;
+        }
+        const float d = rho > 0.0f ? dz / rho : 3.0e38f;
+        if (inside) {
+            const int64_t o = (int64_t)e * n_pixels + pix;
+            if (rho_out) rho_out[o] = rho;
+            if (depth_out) depth_out[o] = d;
+        }
+        if (mode == 1) {
+            if (rho > best_rho) {
+                best_rho = rho;
+                best = e;
+            }
+        } else if (rho > tau && d < best_d) {
+            best_d = d;
+            best = e;
+        }
+    }
+    if (inside) labels[pix] = (uint8_t)best;
+}
+
+}  // namespace
+
+hipError_t launch_render(hipStream_t s, const float *rec, const uint32_t *vals, const uint32_t *ranges,
+                         const ViewDev *views, int32_t n_views, uint32_t n_tiles, const uint8_t *S, int64_t n,
+                         int32_t E, const AccParams &p, float tau, int32_t mode, uint8_t *labels, float *rho,
+                         float *depth, int64_t n_pixels)
+{
+    if (n_tiles == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_render, dim3(n_tiles), dim3(256), 0, s, reinterpret_cast<const float4 *>(rec), vals,
+                       reinterpret_cast<const uint2 *>(ranges), views, n_views, S, n, E, p, tau, mode, labels, rho,
+                       depth, n_pixels);
+    return hipGetLastError();
+}
+
+}  // namespace fs

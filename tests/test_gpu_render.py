@@ -1,0 +1,117 @@
+"""GPU novel-view mask rendering (Sec. 3.4) against the oracle: per-object
+alpha masks and depths, the depth-guided and argmax labels, on the training
+views and on novel views of an orbit the masks never saw."""
+import dataclasses
+
+import numpy as np
+import pytest
+import torch
+
+import oracle as O
+import scenegen as sg
+from paper_2409_08270_amd import _lib as L
+from paper_2409_08270_amd.solve import Solver, tiles_of
+from tests._parity import log
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    return L.Context()
+
+
+def _novel(sc, n=3, res=112):
+    R, t, fx, fy, cx, cy, W, H = sg.orbit_cameras(n, 3.6, 25.0, res, res + 16, phase=0.37)
+    return dataclasses.replace(sc, R=R, t=t, fx=fx, fy=fy, cx=cx, cy=cy, W=W, H=H,
+                               masks=[np.zeros((res + 16, res), np.uint8) for _ in range(n)])
+
+
+def _render_gpu(ctx, sc, S_dev, E, mode, tau=0.1):
+    ds = L.DeviceScene(sc)
+    prm = L.params()
+    cams, nv = ds.cams()
+    proj = L.Proj(sc.n, nv)
+    ctx.fs_project(ds, cams, nv, prm, proj)
+    tt = sum(tiles_of(int(sc.W[v]), int(sc.H[v]), prm) for v in range(nv))
+    bins = L.Bins(1, tt)
+    n = ctx.fs_bin_sort(proj, cams, prm, bins)
+    if n < 0:
+        bins = L.Bins(-n, tt)
+        ctx.fs_bin_sort(proj, cams, prm, bins)
+    px = sc.pixels()
+    labels = torch.zeros(px, dtype=torch.uint8, device="cuda")
+    rho = torch.zeros((E, px), dtype=torch.float32, device="cuda")
+    depth = torch.zeros((E, px), dtype=torch.float32, device="cuda")
+    ctx.fs_render_masks(proj, bins, cams, S_dev, E, prm, tau, mode, labels, rho, depth)
+    torch.cuda.synchronize()
+    return labels.cpu().numpy(), rho.cpu().numpy().astype(np.float64), depth.cpu().numpy().astype(np.float64)
+
+
+def _compare(sc, S_host, E, mode, got, tau=0.1, what=""):
+    lab_g, rho_g, dep_g = got
+    off = 0
+    bad_total, amb_total, px_total = 0, 0, 0
+    for v in range(sc.n_views):
+        H, W = int(sc.H[v]), int(sc.W[v])
+        lab, rho, dep = O.render_masks64(sc, v, O.params(), S_host, tau=tau, mode=mode)
+        sl = slice(off, off + H * W)
+        off += H * W
+        r_g = rho_g[:, sl].reshape(E, H, W)
+        e0 = 0 if mode == 1 else 1
+        d = np.abs(r_g[e0:] - rho[e0:])
+        assert np.quantile(d, 0.999) <= 1e-4 and d.max() <= 0.05, (what, v, float(d.max()))
+        # labels: identical except where the oracle's own decision is within a band of its threshold
+        if mode == 1:
+            srt = np.sort(rho, axis=0)
+            amb = (srt[-1] - srt[-2]) < 2e-3
+        else:
+            amb = np.any(np.abs(rho[1:] - tau) < 2e-3, axis=0)
+            cand = rho[1:] > tau
+            dd = np.where(cand, dep[1:], np.inf)
+            srt = np.sort(dd, axis=0)
+            if srt.shape[0] > 1:
+                amb |= np.isfinite(srt[1]) & (srt[1] - srt[0] <= 1e-3 * srt[0])
+        mism = lab_g[sl].reshape(H, W) != lab
+        assert not np.any(mism & ~amb), (what, v, int((mism & ~amb).sum()))
+        bad_total += int(mism.sum())
+        amb_total += int(amb.sum())
+        px_total += H * W
+        # depth where the object is seen and both sides composited the same Gaussians
+        same = (rho[e0:] > 0.05) & (np.abs(r_g[e0:] - rho[e0:]) <= 1e-5)
+        dg = dep_g[:, sl].reshape(E, H, W)[e0:]
+        rel = np.abs(dg[same] - dep[e0:][same]) / dep[e0:][same]
+        assert rel.size == 0 or np.quantile(rel, 0.999) <= 1e-4, (what, v, float(rel.max()), int((rel > 1e-4).sum()))
+    log(f"[render {what}] pixels {px_total}, label mismatches {bad_total} (all within {amb_total} ambiguous)")
+
+
+def test_binary_masks_training_and_novel_views(ctx):
+    sc = sg.make_config("C1")
+    ds = L.DeviceScene(sc)
+    out = Solver(ctx, ds).solve(chunk=sc.n_views)
+    S_dev = out["S"]
+    S_host = S_dev.cpu().numpy()
+    for scene, what in ((sc, "C1 training views"), (_novel(sc), "C1 novel views")):
+        got = _render_gpu(ctx, scene, S_dev, 2, L.FS_MASK_DEPTH)
+        _compare(scene, S_host, 2, L.FS_MASK_DEPTH, got, what=what)
+        got = _render_gpu(ctx, scene, S_dev, 2, L.FS_MASK_ARGMAX)
+        _compare(scene, S_host, 2, L.FS_MASK_ARGMAX, got, what=what + " argmax")
+    ctx.status()
+
+
+def test_multi_object_depth_guided_masks(ctx):
+    sc = sg.make_config("C3", views=4, W=128, H=96, per_obj=1500, n_shell=4000)
+    ds = L.DeviceScene(sc)
+    out = Solver(ctx, ds).solve(chunk=sc.n_views)
+    S_dev = out["S"]
+    S_host = S_dev.cpu().numpy()
+    got = _render_gpu(ctx, sc, S_dev, sc.E, L.FS_MASK_DEPTH)
+    _compare(sc, S_host, sc.E, L.FS_MASK_DEPTH, got, what="C3-small depth-guided")
+    # rendered masks agree with the input masks on most pixels
+    lab = got[0]
+    masks = np.concatenate([m.reshape(-1) for m in sc.masks])
+    log(f"[render] C3-small agreement with the input masks: {(lab == masks).mean():.3f}")
+    assert (lab == masks).mean() > 0.7
+    got = _render_gpu(ctx, sc, S_dev, sc.E, L.FS_MASK_ARGMAX)
+    _compare(sc, S_host, sc.E, L.FS_MASK_ARGMAX, got, what="C3-small argmax")
+    ctx.status()
