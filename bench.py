@@ -204,7 +204,17 @@ def main():
     render_ms = timed(lambda: ctx.fs_render_masks(solver.proj, solver.bins, cams, batch.S[0], sc.E, prm, 0.1,
                                                   L.FS_MASK_DEPTH, labels))
     agree = float((labels.cpu().numpy() == ds.masks.cpu().numpy()).mean())
-    followups = {"bias_sweep_64_gammas_ms": sweep_ms, "object_removal_compaction_ms": compact_ms,
+    # point-prompt propagation (synchronous call: wall clock, host copies included)
+    rng = np.random.default_rng(11)
+    prompts = np.stack([rng.uniform(0, sc.W[0], 16), rng.uniform(0, sc.H[0], 16),
+                        rng.uniform(2.0, 5.0, 16)], 1).astype(np.float32)
+    ctx.fs_prompt_propagate(ds, 0, prompts, k=10)
+    pts = []
+    for _ in range(5):
+        t = time.perf_counter()
+        ctx.fs_prompt_propagate(ds, 0, prompts, k=10)
+        pts.append((time.perf_counter() - t) * 1e3)
+    followups = {"prompt_propagation_16_prompts_ms": float(np.median(pts)), "bias_sweep_64_gammas_ms": sweep_ms, "object_removal_compaction_ms": compact_ms,
                  "mask_render_all_views_ms": render_ms, "mask_render_views_per_sec": V / (render_ms * 1e-3),
                  "rendered_masks_agree_with_inputs": agree, "gaussians": sc.n}
     print(f"[bench] follow-ups: {followups}", file=sys.stderr, flush=True)

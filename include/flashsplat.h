@@ -271,6 +271,31 @@ int fs_render_masks(fs_ctx *ctx, const fs_proj *proj, const fs_bins *bins, const
                     const uint8_t *S, int32_t n_classes, const fs_params *p, float tau, int32_t mode,
                     uint8_t *labels, float *rho, float *depth);
 
+/* Point-prompt propagation (Sec. 4.1 "2D mask generation and association";
+ * the supplement's "Binary Mask Association"). Each prompt (px, py, depth)
+ * is a pixel of view ref_view and a camera depth there (for instance the
+ * depth fs_render_masks renders at that pixel with every Gaussian in one
+ * object). It is back-projected to the world point
+ * R^T (depth * K^-1 [px, py, 1] - t); the k Gaussian centres nearest to that
+ * point are found (squared L2 distance in binary32, ties to the smaller
+ * index); among them the one of least positive depth in the reference view is
+ * chosen (ties to the smaller index; -1 if none lies in front of it), and its
+ * centre is projected into every view.
+ * g: device Gaussians (n < 2^32 - 1). cams: host [n_views], n_views >= 1.
+ * prompts: host float [n_prompts][3], finite, depth > 0; n_prompts in
+ * [0, 65535]. k in [1, 32] (the paper uses 10).
+ * Outputs, all host memory, written whole:
+ *   chosen  int64 [n_prompts]: the chosen Gaussian or -1;
+ *   nearest int64 [n_prompts][k] by increasing distance (-1 past n), or NULL;
+ *   uv      float [n_prompts][n_views][2], the prompt carried to each view
+ *           (0 where the chosen centre is not beyond p->znear in that view);
+ *   visible uint8 [n_prompts][n_views], 1 where that projection lies beyond
+ *           p->znear and inside the image ([0, W) x [0, H)).
+ * Synchronous: returns after the outputs are on the host. */
+int fs_prompt_propagate(fs_ctx *ctx, const fs_gaussians *g, const fs_camera *cams, int32_t n_views,
+                        int32_t ref_view, const float *prompts, int32_t n_prompts, int32_t k, const fs_params *p,
+                        int64_t *chosen, int64_t *nearest, float *uv, uint8_t *visible);
+
 /* Batched solve ------------------------------------------------------------
  * Many scenes of uneven size, all their views, in one graph launch: the
  * splat-and-accumulate pass is a sum over views (Eq. (7)), so views of all

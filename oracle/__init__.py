@@ -19,6 +19,11 @@ Pieces (paper sections in brackets):
                          [Sec. 3.2 "Regularized ILP", Eq. (8), Listing 1 of the supplement]
   sweep64 / compact64    bias sweep and object extraction/removal
                          [Sec. 3.2 "Regularized ILP", Sec. 4.4]
+  prompt32               point-prompt propagation: back-projection, the k
+                         nearest centres, least reference depth, projection
+                         into every view [Sec. 4.1, supplement "Binary Mask
+                         Association"]; binary32 because its floating point
+                         decides which Gaussian is chosen
   objective_eq2 / brute_force_binary   exhaustive checks of Eq. (2)/(6)
 """
 from __future__ import annotations
@@ -34,7 +39,7 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 _SRC = os.path.join(_HERE, "fs_oracle.c")
 _LIB = os.path.join(_HERE, "liboracle.so")
 
-# default rasterizer constants (inherited by the paper from 3DGS; see DESIGN)
+# default rasterizer constants (the paper inherits them from 3DGS)
 DEFAULT = dict(tile_w=16, tile_h=16, sigma_k=3.0, lowpass=0.3, znear=0.2, guard=1.3,
                alpha_min=1.0 / 255.0, alpha_max=0.99, t_min=1e-4, fp64_cond=64.0,
                band_eps=2.0 ** -10)
@@ -297,6 +302,66 @@ def compact64(arrays: Sequence[np.ndarray], select: np.ndarray, keep_selected: b
     mask = (np.asarray(select) != 0) == bool(keep_selected)
     idx = np.nonzero(mask)[0]
     return [np.asarray(a)[mask] for a in arrays], idx
+
+
+def prompt32(scene, ref_view: int, prompts, k: int = 10, znear: float = 0.2):
+    """Point-prompt propagation (Sec. 4.1 "2D mask generation and association",
+    supplement "Binary Mask Association"), in binary32 with every sum in a fixed
+    left-to-right order, since the distances and depths decide which Gaussian
+    is chosen.
+
+    For each prompt (px, py, d) on view ref_view (R world-to-camera, pinhole
+    fx, fy, cx, cy):
+      1. back-project: camera point d * ((px - cx) / fx, (py - cy) / fy, 1),
+         world point R^T (camera point - t);
+      2. the k centres of least squared L2 distance, ties to the smaller index
+         (a stable sort of the distances);
+      3. of those, the one of least positive depth in the reference view
+         (ties to the smaller index), or -1;
+      4. its centre projected into every view: x = R m + t, kept where
+         x_z > znear; (u, v) = (fx x_x / x_z + cx, fy x_y / x_z + cy); visible
+         where 0 <= u < W and 0 <= v < H.
+    Returns (chosen [P], nearest [P, k] (-1 past n), uv [P, V, 2], visible [P, V])."""
+    f = np.float32
+    pr = np.asarray(prompts, dtype=f).reshape(-1, 3)
+    P, V, n = pr.shape[0], scene.n_views, scene.n
+    m = np.stack([scene.mx, scene.my, scene.mz]).astype(f)      # [3, n]
+    R, t = scene.R.astype(f), scene.t.astype(f)
+    chosen = np.full(P, -1, np.int64)
+    nearest = np.full((P, k), -1, np.int64)
+    uv = np.zeros((P, V, 2), f)
+    vis = np.zeros((P, V), np.uint8)
+    Rr, tr = R[ref_view], t[ref_view]
+    for p in range(P):
+        px, py, d = pr[p]
+        # step 1
+        c = np.array([d * ((px - scene.cx[ref_view]) / scene.fx[ref_view]) - tr[0],
+                      d * ((py - scene.cy[ref_view]) / scene.fy[ref_view]) - tr[1],
+                      d - tr[2]], dtype=f)
+        X = [(Rr[0, i] * c[0] + Rr[1, i] * c[1]) + Rr[2, i] * c[2] for i in range(3)]
+        # step 2
+        dd = [m[i] - X[i] for i in range(3)]
+        d2 = (dd[0] * dd[0] + dd[1] * dd[1]) + dd[2] * dd[2]
+        order = np.argsort(d2, kind="stable")[:k]
+        nearest[p, :len(order)] = order
+        # step 3
+        z = ((Rr[2, 0] * m[0, order] + Rr[2, 1] * m[1, order]) + Rr[2, 2] * m[2, order]) + tr[2]
+        front = [(z[j], int(order[j])) for j in range(len(order)) if z[j] > 0]
+        if not front:
+            continue
+        best = min(front)[1]
+        chosen[p] = best
+        # step 4
+        mb = m[:, best]
+        for v in range(V):
+            x = [((R[v, i, 0] * mb[0] + R[v, i, 1] * mb[1]) + R[v, i, 2] * mb[2]) + t[v, i] for i in range(3)]
+            if not x[2] > f(znear):
+                continue
+            u = scene.fx[v] * (x[0] / x[2]) + scene.cx[v]
+            w = scene.fy[v] * (x[1] / x[2]) + scene.cy[v]
+            uv[p, v] = (u, w)
+            vis[p, v] = 1 if (u >= 0 and u < f(scene.W[v]) and w >= 0 and w < f(scene.H[v])) else 0
+    return chosen, nearest, uv, vis
 
 
 def objective_eq2(weights: Sequence[np.ndarray], masks: Sequence[np.ndarray], P: np.ndarray) -> float:

@@ -102,6 +102,7 @@ class FsBatchInfo(ctypes.Structure):
 EXPORTS = ["fs_version", "fs_error_string", "fs_params_default", "fs_params_exact", "fs_ctx_create",
            "fs_ctx_set_stream", "fs_ctx_destroy", "fs_ctx_last_error", "fs_status_get", "fs_project",
            "fs_bin_sort", "fs_accumulate", "fs_assign", "fs_assign_sweep", "fs_compact", "fs_render_masks",
+           "fs_prompt_propagate",
            "fs_batch_opts_default", "fs_batch_create",
            "fs_batch_run", "fs_batch_get_info", "fs_batch_destroy"]
 
@@ -139,6 +140,8 @@ def load(path: str = LIB_PATH):
                         ctypes.POINTER(_I64)], _I32),
         "fs_render_masks": ([_P, ctypes.POINTER(FsProj), ctypes.POINTER(FsBins), ctypes.POINTER(FsCamera), _P, _I32,
                              ctypes.POINTER(FsParams), _F, _I32, _P, _P, _P], _I32),
+        "fs_prompt_propagate": ([_P, ctypes.POINTER(FsGaussians), ctypes.POINTER(FsCamera), _I32, _I32, _P, _I32,
+                                 _I32, ctypes.POINTER(FsParams), _P, _P, _P, _P], _I32),
         "fs_batch_opts_default": ([ctypes.POINTER(FsBatchOpts)], None),
         "fs_batch_create": ([_P, ctypes.POINTER(FsScene), _I32, ctypes.POINTER(FsParams),
                              ctypes.POINTER(FsBatchOpts), ctypes.POINTER(_P)], _I32),
@@ -279,6 +282,23 @@ class Context:
         return self._check(self.L.fs_render_masks(self.h, ctypes.byref(proj.struct()), ctypes.byref(bins.struct()),
                                                   cams, _ptr(S), n_classes, ctypes.byref(prm), float(tau), int(mode),
                                                   _ptr(labels), _ptr(rho), _ptr(depth)))
+
+    def fs_prompt_propagate(self, scene: "DeviceScene", ref_view: int, prompts, k: int = 10,
+                            prm: Optional[FsParams] = None):
+        """prompts: [P][3] (px, py, depth) on view ref_view. Returns (chosen int64 [P],
+        nearest int64 [P, k], uv float32 [P, V, 2], visible uint8 [P, V])."""
+        cams, nv = scene.cams()
+        prm = prm or params()
+        pr = np.ascontiguousarray(np.asarray(prompts, dtype=np.float32).reshape(-1, 3))
+        P = pr.shape[0]
+        chosen = np.zeros(P, np.int64)
+        nearest = np.zeros((P, k), np.int64)
+        uv = np.zeros((P, nv, 2), np.float32)
+        vis = np.zeros((P, nv), np.uint8)
+        self._check(self.L.fs_prompt_propagate(self.h, ctypes.byref(scene.struct()), cams, nv, ref_view,
+                                               pr.ctypes.data, P, k, ctypes.byref(prm), chosen.ctypes.data,
+                                               nearest.ctypes.data, uv.ctypes.data, vis.ctypes.data))
+        return chosen, nearest, uv, vis
 
     def fs_compact(self, scene: "DeviceScene", select: torch.Tensor, keep_selected: bool,
                    capacity: Optional[int] = None, want_index: bool = True):

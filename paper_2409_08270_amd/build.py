@@ -26,6 +26,7 @@ SOURCES = {
     "fs_assign.hip": [],
     "fs_select.hip": [],
     "fs_render.hip": [],
+    "fs_prompt.hip": ["-ffp-contract=off"],
     "fs_api.hip": [],
 }
 

@@ -686,6 +686,63 @@ int fs_render_masks(fs_ctx *ctx, const fs_proj *proj, const fs_bins *bins, const
     return FS_OK;
 }
 
+int fs_prompt_propagate(fs_ctx *ctx, const fs_gaussians *g, const fs_camera *cams, int32_t n_views,
+                        int32_t ref_view, const float *prompts, int32_t n_prompts, int32_t k, const fs_params *p,
+                        int64_t *chosen, int64_t *nearest, float *uv, uint8_t *visible)
+{
+    if (!ctx) return FS_ERR_ARG;
+    RCHECK(check_gauss(ctx, g));
+    RCHECK(check_params(ctx, p, false));
+    RCHECK(check_cams(ctx, cams, n_views));
+    if (n_views < 1 || ref_view < 0 || ref_view >= n_views) return set_err(ctx, FS_ERR_ARG, "bad ref_view");
+    if (k < 1 || k > prompt_max_k()) return set_err(ctx, FS_ERR_ARG, "k must be in [1, %d]", prompt_max_k());
+    if (n_prompts < 0 || n_prompts > 65535) return set_err(ctx, FS_ERR_ARG, "n_prompts must be in [0, 65535]");
+    if (n_prompts == 0) return FS_OK;
+    if (!prompts || !chosen || !uv || !visible) return set_err(ctx, FS_ERR_ARG, "NULL prompt or output");
+    for (int i = 0; i < n_prompts; ++i)
+        if (!finite_f(prompts[3 * i]) || !finite_f(prompts[3 * i + 1]) || !finite_f(prompts[3 * i + 2]) ||
+            !(prompts[3 * i + 2] > 0.f))
+            return set_err(ctx, FS_ERR_ARG, "prompt %d: need a finite pixel and a finite depth > 0", i);
+    const size_t P = (size_t)n_prompts, V = (size_t)n_views;
+    if (g->n == 0) {
+        for (size_t i = 0; i < P; ++i) chosen[i] = -1;
+        for (size_t i = 0; nearest && i < P * k; ++i) nearest[i] = -1;
+        memset(uv, 0, P * V * 2 * sizeof(float));
+        memset(visible, 0, P * V);
+        return FS_OK;
+    }
+    Plan pl;
+    plan_add(pl, p, 0, g->n, cams, 0, n_views, 0);
+    RCHECK(upload_vec(ctx, ctx->views, pl.views));
+    int64_t blocks = (g->n + 255) / 256;
+    if (blocks > 512) blocks = 512;
+    // device layout: prompts | ids [P][1+k] | uv [P][V][2] | visible [P][V]
+    const size_t in_bytes = P * 3 * sizeof(float);
+    const size_t ids_off = (in_bytes + 255) & ~(size_t)255;
+    const size_t uv_off = ids_off + P * (1 + k) * 8;
+    const size_t vis_off = uv_off + P * V * 8;
+    const size_t total = vis_off + P * V;
+    RCHECK(ensure(ctx, ctx->items_k, P * (size_t)blocks * k * 8));
+    RCHECK(ensure(ctx, ctx->items_k2, total));
+    char *o = (char *)ctx->items_k2.p;
+    HIPCHECK(ctx, hipMemcpyAsync(o, prompts, in_bytes, hipMemcpyHostToDevice, ctx->stream));
+    HIPCHECK(ctx, launch_prompt(ctx->stream, gauss_ptrs(g), g->n, (const ViewDev *)ctx->views.p, n_views,
+                                pl.views[ref_view], (const float *)o, n_prompts, k, p->znear,
+                                (unsigned long long *)ctx->items_k.p, (int32_t)blocks, (long long *)(o + ids_off),
+                                (float *)(o + uv_off), (uint8_t *)(o + vis_off)));
+    std::vector<char> h(total - ids_off);
+    HIPCHECK(ctx, hipMemcpyAsync(h.data(), o + ids_off, total - ids_off, hipMemcpyDeviceToHost, ctx->stream));
+    HIPCHECK(ctx, hipStreamSynchronize(ctx->stream));
+    const long long *hid = (const long long *)h.data();
+    for (size_t i = 0; i < P; ++i) {
+        chosen[i] = (int64_t)hid[i * (1 + k)];
+        for (int j = 0; nearest && j < k; ++j) nearest[i * k + j] = (int64_t)hid[i * (1 + k) + 1 + j];
+    }
+    memcpy(uv, h.data() + (uv_off - ids_off), P * V * 8);
+    memcpy(visible, h.data() + (vis_off - ids_off), P * V);
+    return FS_OK;
+}
+
 int fs_assign_sweep(fs_ctx *ctx, const float *A_hi, const float *A_lo, int64_t n, int32_t n_classes,
                     const float *gammas, int32_t n_gamma, uint8_t *S, int64_t *counts)
 {

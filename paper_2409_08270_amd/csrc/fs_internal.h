@@ -203,6 +203,15 @@ hipError_t launch_render(hipStream_t s, const float *rec, const uint32_t *vals, 
                          int32_t E, const AccParams &p, float tau, int32_t mode, uint8_t *labels, float *rho,
                          float *depth, int64_t n_pixels);
 
+// point-prompt propagation (fs_prompt.hip). prompts: device [n_prompts][3]
+// (px, py, depth); part: n_prompts * n_part_blocks * k keys; per prompt
+// out_ids = [chosen, k nearest], out_uv [n_views][2], out_vis [n_views]
+int prompt_max_k();
+hipError_t launch_prompt(hipStream_t s, const GaussPtrs &g, int64_t n, const ViewDev *views, int32_t n_views,
+                         const ViewDev &ref_host, const float *prompts, int32_t n_prompts, int32_t k, float znear,
+                         unsigned long long *part, int32_t n_part_blocks, long long *out_ids, float *out_uv,
+                         uint8_t *out_vis);
+
 // gamma sweep and stream compaction (fs_select.hip)
 int sweep_max_gammas(int32_t E);
 hipError_t launch_assign_sweep(hipStream_t s, const float *A_hi, const float *A_lo, int64_t n, int32_t E,
