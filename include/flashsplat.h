@@ -271,6 +271,32 @@ int fs_render_masks(fs_ctx *ctx, const fs_proj *proj, const fs_bins *bins, const
                     const uint8_t *S, int32_t n_classes, const fs_params *p, float tau, int32_t mode,
                     uint8_t *labels, float *rho, float *depth);
 
+/* Per-Gaussian diagnostics of a solved scene: the number of objects each
+ * Gaussian contributes to (the supplement's "Scene segmentation extension"
+ * counts it to show that Gaussians are shared between objects), how many
+ * objects' subsets each Gaussian falls in (more than one only for a negative
+ * bias, Sec. 3.3), and the overlap of every subset with given per-Gaussian
+ * labels (the fewer-masks ablation of Sec. 4.6 reads it as an IoU).
+ * A_hi, A_lo: device float [n][n_classes] as fs_accumulate leaves them
+ *   (A_lo may be NULL); A_hi NULL skips contrib_hist.
+ * S: device uint8 [n_classes][n] (fs_assign's layout); NULL skips
+ *   member_hist and overlap.
+ * gt: device int32 [n], a label per Gaussian (values outside
+ *   [0, n_classes) belong to no object); NULL skips overlap.
+ * rel_eps: finite, in [0, 1). Object e counts for Gaussian g when
+ *   a > rel_eps * t, a = (double)A_hi + (double)A_lo and t the row's sum of
+ *   those values taken in order e = 0, 1, ... in binary64 (0: A > 0).
+ * Outputs (host, overwritten; each may be NULL):
+ *   contrib_hist uint64 [n_classes + 1]: Gaussians per count of such objects
+ *     (unseen Gaussians count 0);
+ *   member_hist  uint64 [n_classes + 1]: Gaussians per number of rows of S
+ *     that hold them;
+ *   overlap      uint64 [n_classes][3]: |S_e and gt = e|, |S_e|, |gt = e|.
+ * Synchronous. n_classes in [2, 256]. */
+int fs_diagnose(fs_ctx *ctx, const float *A_hi, const float *A_lo, const uint8_t *S, const int32_t *gt, int64_t n,
+                int32_t n_classes, float rel_eps, uint64_t *contrib_hist, uint64_t *member_hist,
+                uint64_t *overlap);
+
 /* Point-prompt propagation (Sec. 4.1 "2D mask generation and association";
  * the supplement's "Binary Mask Association"). Each prompt (px, py, depth)
  * is a pixel of view ref_view and a camera depth there (for instance the

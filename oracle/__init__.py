@@ -24,6 +24,10 @@ Pieces (paper sections in brackets):
                          into every view [Sec. 4.1, supplement "Binary Mask
                          Association"]; binary32 because its floating point
                          decides which Gaussian is chosen
+  diagnose64             per-Gaussian diagnostics: objects each Gaussian
+                         contributes to, subsets it falls in, overlap of each
+                         subset with given labels [supplement "Scene
+                         segmentation extension", Sec. 4.6 fewer masks]
   objective_eq2 / brute_force_binary   exhaustive checks of Eq. (2)/(6)
 """
 from __future__ import annotations
@@ -302,6 +306,49 @@ def compact64(arrays: Sequence[np.ndarray], select: np.ndarray, keep_selected: b
     mask = (np.asarray(select) != 0) == bool(keep_selected)
     idx = np.nonzero(mask)[0]
     return [np.asarray(a)[mask] for a in arrays], idx
+
+
+def diagnose64(A: Optional[np.ndarray], S: Optional[np.ndarray] = None, gt: Optional[np.ndarray] = None,
+               rel_eps: float = 0.0, E: Optional[int] = None):
+    """Per-Gaussian diagnostics of a solved scene.
+
+    contrib[c]: Gaussians with exactly c objects e where A[g][e] > rel_eps * t_g,
+      t_g = sum over e of A[g][e] taken in order e = 0, 1, ... (binary64), the
+      number of objects a Gaussian is shared by (supplement "Scene segmentation
+      extension");
+    member[m]: Gaussians held by exactly m rows of S (Sec. 3.3: more than one
+      only for a negative bias);
+    overlap[e] = (|S_e and gt = e|, |S_e|, |gt = e|), read as an IoU in the
+      fewer-masks ablation (Sec. 4.6).
+    A: float64 [n][E] or None; S: [E][n] or None; gt: int [n] or None."""
+    out = [None, None, None]
+    if A is not None:
+        A = np.asarray(A, np.float64)
+        n, E = A.shape
+        t = np.zeros(n)
+        for e in range(E):
+            t = t + A[:, e]
+        c = (A > np.float64(rel_eps) * t[:, None]).sum(axis=1)
+        out[0] = np.bincount(c, minlength=E + 1).astype(np.uint64)
+    if S is not None:
+        S = np.asarray(S) != 0
+        E = S.shape[0]
+        out[1] = np.bincount(S.sum(axis=0), minlength=E + 1).astype(np.uint64)
+        if gt is not None:
+            gt = np.asarray(gt)
+            ov = np.zeros((E, 3), np.uint64)
+            for e in range(E):
+                ov[e] = (np.sum(S[e] & (gt == e)), np.sum(S[e]), np.sum(gt == e))
+            out[2] = ov
+    return tuple(out)
+
+
+def iou_of(overlap: np.ndarray) -> np.ndarray:
+    """Per-object IoU from diagnose64's overlap counts (NaN where both sets are empty)."""
+    ov = np.asarray(overlap, np.float64)
+    union = ov[:, 1] + ov[:, 2] - ov[:, 0]
+    with np.errstate(invalid="ignore", divide="ignore"):
+        return np.where(union > 0, ov[:, 0] / union, np.nan)
 
 
 def prompt32(scene, ref_view: int, prompts, k: int = 10, znear: float = 0.2):

@@ -102,7 +102,7 @@ class FsBatchInfo(ctypes.Structure):
 EXPORTS = ["fs_version", "fs_error_string", "fs_params_default", "fs_params_exact", "fs_ctx_create",
            "fs_ctx_set_stream", "fs_ctx_destroy", "fs_ctx_last_error", "fs_status_get", "fs_project",
            "fs_bin_sort", "fs_accumulate", "fs_assign", "fs_assign_sweep", "fs_compact", "fs_render_masks",
-           "fs_prompt_propagate",
+           "fs_prompt_propagate", "fs_diagnose",
            "fs_batch_opts_default", "fs_batch_create",
            "fs_batch_run", "fs_batch_get_info", "fs_batch_destroy"]
 
@@ -140,6 +140,7 @@ def load(path: str = LIB_PATH):
                         ctypes.POINTER(_I64)], _I32),
         "fs_render_masks": ([_P, ctypes.POINTER(FsProj), ctypes.POINTER(FsBins), ctypes.POINTER(FsCamera), _P, _I32,
                              ctypes.POINTER(FsParams), _F, _I32, _P, _P, _P], _I32),
+        "fs_diagnose": ([_P, _P, _P, _P, _P, _I64, _I32, _F, _P, _P, _P], _I32),
         "fs_prompt_propagate": ([_P, ctypes.POINTER(FsGaussians), ctypes.POINTER(FsCamera), _I32, _I32, _P, _I32,
                                  _I32, ctypes.POINTER(FsParams), _P, _P, _P, _P], _I32),
         "fs_batch_opts_default": ([ctypes.POINTER(FsBatchOpts)], None),
@@ -283,6 +284,17 @@ class Context:
                                                   cams, _ptr(S), n_classes, ctypes.byref(prm), float(tau), int(mode),
                                                   _ptr(labels), _ptr(rho), _ptr(depth)))
 
+    def fs_diagnose(self, A_hi, A_lo, S, gt, n: int, E: int, rel_eps: float = 0.0):
+        """Returns (contrib_hist [E+1], member_hist [E+1], overlap [E, 3]) as uint64
+        arrays; an entry whose inputs are None comes back as None."""
+        c = np.zeros(E + 1, np.uint64) if A_hi is not None else None
+        m = np.zeros(E + 1, np.uint64) if S is not None else None
+        o = np.zeros((E, 3), np.uint64) if (S is not None and gt is not None) else None
+        self._check(self.L.fs_diagnose(self.h, _ptr(A_hi), _ptr(A_lo), _ptr(S), _ptr(gt), n, E, float(rel_eps),
+                                       None if c is None else c.ctypes.data, None if m is None else m.ctypes.data,
+                                       None if o is None else o.ctypes.data))
+        return c, m, o
+
     def fs_prompt_propagate(self, scene: "DeviceScene", ref_view: int, prompts, k: int = 10,
                             prm: Optional[FsParams] = None):
         """prompts: [P][3] (px, py, depth) on view ref_view. Returns (chosen int64 [P],
@@ -338,6 +350,19 @@ class DeviceScene:
 
     def masks_of(self, v0: int, v1: int) -> torch.Tensor:
         return self.masks[int(self.mask_off[v0]):int(self.mask_off[v1])]
+
+    def view_subset(self, views: Sequence[int]) -> "DeviceScene":
+        """The same Gaussians (shared, not copied) seen from a subset of the
+        views; the subset's masks are gathered into one buffer."""
+        views = [int(v) for v in views]
+        sub = DeviceScene.__new__(DeviceScene)
+        sub.n, sub.E, sub.arrays = self.n, self.E, self.arrays
+        sub.cam_rows = self.cam_rows[views]
+        sub.n_views = len(views)
+        sub.W, sub.H = self.W[views], self.H[views]
+        sub.mask_off = np.concatenate([[0], np.cumsum(sub.W.astype(np.int64) * sub.H.astype(np.int64))])
+        sub.masks = torch.cat([self.masks_of(v, v + 1) for v in views]) if views else self.masks[:0]
+        return sub
 
 
 class Proj:

@@ -27,6 +27,7 @@ SOURCES = {
     "fs_select.hip": [],
     "fs_render.hip": [],
     "fs_prompt.hip": ["-ffp-contract=off"],
+    "fs_diag.hip": [],
     "fs_api.hip": [],
 }
 

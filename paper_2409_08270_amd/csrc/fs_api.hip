@@ -686,6 +686,32 @@ int fs_render_masks(fs_ctx *ctx, const fs_proj *proj, const fs_bins *bins, const
     return FS_OK;
 }
 
+int fs_diagnose(fs_ctx *ctx, const float *A_hi, const float *A_lo, const uint8_t *S, const int32_t *gt, int64_t n,
+                int32_t n_classes, float rel_eps, uint64_t *contrib_hist, uint64_t *member_hist, uint64_t *overlap)
+{
+    if (!ctx) return FS_ERR_ARG;
+    if (n < 0 || n >= 0xFFFFFFFFll) return set_err(ctx, FS_ERR_ARG, "n out of range");
+    if (n_classes < 2 || n_classes > kMaxDiagE)
+        return set_err(ctx, FS_ERR_ARG, "n_classes %d not in [2, %d]", n_classes, kMaxDiagE);
+    if (!finite_f(rel_eps) || rel_eps < 0.f || rel_eps >= 1.f) return set_err(ctx, FS_ERR_ARG, "need 0 <= rel_eps < 1");
+    const bool want_c = A_hi && contrib_hist, want_m = S && member_hist, want_o = S && gt && overlap;
+    if (!want_c && !want_m && !want_o) return set_err(ctx, FS_ERR_ARG, "nothing to compute");
+    const size_t E1 = (size_t)n_classes + 1, nw = 2 * E1 + 3 * (size_t)n_classes;
+    RCHECK(ensure(ctx, ctx->items_k, nw * 8));
+    unsigned long long *d = (unsigned long long *)ctx->items_k.p;
+    HIPCHECK(ctx, launch_fill_u32(ctx->stream, (uint32_t *)d, 0u, (int64_t)nw * 2));
+    HIPCHECK(ctx, launch_diag_rows(ctx->stream, want_c ? A_hi : nullptr, want_c ? A_lo : nullptr,
+                                   (want_m || want_o) ? S : nullptr, want_o ? gt : nullptr, n, n_classes,
+                                   (double)rel_eps, d, d + E1, d + 2 * E1));
+    std::vector<uint64_t> h(nw);
+    HIPCHECK(ctx, hipMemcpyAsync(h.data(), d, nw * 8, hipMemcpyDeviceToHost, ctx->stream));
+    HIPCHECK(ctx, hipStreamSynchronize(ctx->stream));
+    if (want_c) memcpy(contrib_hist, h.data(), E1 * 8);
+    if (want_m) memcpy(member_hist, h.data() + E1, E1 * 8);
+    if (want_o) memcpy(overlap, h.data() + 2 * E1, 3 * (size_t)n_classes * 8);
+    return FS_OK;
+}
+
 int fs_prompt_propagate(fs_ctx *ctx, const fs_gaussians *g, const fs_camera *cams, int32_t n_views,
                         int32_t ref_view, const float *prompts, int32_t n_prompts, int32_t k, const fs_params *p,
                         int64_t *chosen, int64_t *nearest, float *uv, uint8_t *visible)

@@ -203,6 +203,13 @@ hipError_t launch_render(hipStream_t s, const float *rec, const uint32_t *vals, 
                          int32_t E, const AccParams &p, float tau, int32_t mode, uint8_t *labels, float *rho,
                          float *depth, int64_t n_pixels);
 
+// per-Gaussian diagnostics (fs_diag.hip): histograms [E+1] and overlap [E][3],
+// zeroed by the caller
+constexpr int kMaxDiagE = 256;
+hipError_t launch_diag_rows(hipStream_t s, const float *A_hi, const float *A_lo, const uint8_t *S, const int32_t *gt,
+                            int64_t n, int32_t E, double rel_eps, unsigned long long *contrib,
+                            unsigned long long *member, unsigned long long *overlap);
+
 // point-prompt propagation (fs_prompt.hip). prompts: device [n_prompts][3]
 // (px, py, depth); part: n_prompts * n_part_blocks * k keys; per prompt
 // out_ids = [chosen, k nearest], out_uv [n_views][2], out_vis [n_views]
