@@ -356,7 +356,7 @@ int enqueue_lpt(fs_ctx *ctx, hipStream_t s, const uint32_t *ranges, uint64_t n_t
 {
     HIPCHECK(ctx, launch_tile_keys(s, ranges, (int64_t)n_tiles, k, items));
     const uint32_t blocks = (uint32_t)((n_tiles + kSortTile - 1) / kSortTile);
-    HIPCHECK(ctx, radix_sort(s, k, items, k2, v2, lseg, 1, blocks, 16, ws, nullptr));
+    HIPCHECK(ctx, radix_sort(s, k, items, k2, v2, lseg, 1, blocks, 16, ws, nullptr, 1));
     return FS_OK;
 }
 
@@ -561,7 +561,7 @@ int fs_bin_sort(fs_ctx *ctx, const fs_proj *proj, const fs_camera *cams, const f
     // depth order of each view's emitting Gaussians (4 passes: result back in dk/dv)
     HIPCHECK(ctx, launch_depth_keys(s, proj->rec, proj->ntiles, proj->flags, views, V, total, dk, dv));
     HIPCHECK(ctx, radix_sort(s, dk, dv, (uint32_t *)ctx->dkeys2.p, (uint32_t *)ctx->dvals2.p,
-                             (const SegDev *)ctx->dsegs.p, V, pl.dblocks, 32, ctx->sort_ws.p, nullptr));
+                             (const SegDev *)ctx->dsegs.p, V, pl.dblocks, 32, ctx->sort_ws.p, nullptr, 1));
     HIPCHECK(ctx, launch_gather_counts(s, dk, dv, proj->ntiles, views, V, total, (uint32_t *)ctx->counts.p));
     HIPCHECK(ctx, scan_exclusive(s, (const uint32_t *)ctx->counts.p, (uint32_t *)ctx->offsets.p, total, ctx->npairs_dev,
                                  ctx->scan_ws.p));
@@ -582,7 +582,8 @@ int fs_bin_sort(fs_ctx *ctx, const fs_proj *proj, const fs_camera *cams, const f
     const int passes = (bits_for(pl.tiles) + 7) / 8;
     RCHECK(ensure(ctx, ctx->pk_alt, (size_t)sort_len * 4));
     RCHECK(ensure(ctx, ctx->pv_alt, (size_t)sort_len * 4));
-    const uint32_t pblocks = (uint32_t)((sort_len + kSortTile - 1) / kSortTile);
+    const int32_t ptpb = radix_tiles_per_block((uint64_t)sort_len);
+    const uint32_t pblocks = (uint32_t)((sort_len + (int64_t)kSortTile * ptpb - 1) / ((int64_t)kSortTile * ptpb));
     RCHECK(ensure(ctx, ctx->sort_ws, radix_ws_bytes(pblocks)));
     std::vector<SegDev> ps{SegDev{0, (uint32_t)sort_len, 0}};
     RCHECK(upload_vec(ctx, ctx->psegs, ps));
@@ -593,11 +594,12 @@ int fs_bin_sort(fs_ctx *ctx, const fs_proj *proj, const fs_camera *cams, const f
         k0 = (uint32_t *)ctx->pk_alt.p; v0 = (uint32_t *)ctx->pv_alt.p; k1 = out->tiles; v1 = out->vals;
     }
     HIPCHECK(ctx, launch_emit(s, dk, dv, (const uint32_t *)ctx->offsets.p, (const uint32_t *)ctx->counts.p, proj->rec,
-                              proj->rect, proj->flags, views, V, total, (uint32_t)out->capacity, p->tile_w, p->tile_h,
+                              proj->rect, p->fp64_conic ? nullptr : proj->flags, views, V, total,
+                              (uint32_t)out->capacity, p->tile_w, p->tile_h,
                               p->sigma_k, nullptr, k0, v0, ctx->status_dev));
     // without a host count, the device count caps the sort (entries past it are never read)
     HIPCHECK(ctx, radix_sort(s, k0, v0, k1, v1, (const SegDev *)ctx->psegs.p, 1, pblocks, passes * 8, ctx->sort_ws.p,
-                             n_pairs ? nullptr : ctx->npairs_dev));
+                             n_pairs ? nullptr : ctx->npairs_dev, ptpb));
     HIPCHECK(ctx, launch_ranges(s, out->tiles, ctx->npairs_dev, (uint32_t)out->capacity, sort_len, out->ranges));
     return FS_OK;
 }
@@ -864,6 +866,7 @@ struct Chunk {
     uint64_t slab_max = 0;    // largest pair count of one depth slab (before culling finished tiles)
     uint32_t pair_cap = 0;    // slots used by this chunk
     uint32_t pblocks = 0;
+    int32_t ptpb = 1;         // block tiles per block of the pair sort
     uint32_t lblocks = 0;
     int passes = 0;
     DevBuf views, tasks, dsegs, psegs, lsegs;
@@ -881,7 +884,7 @@ struct fs_batch {
     // workspace shared by the chunks
     DevBuf rec, rect, ntiles, flags, dkeys, dvals, dkeys2, dvals2, counts, offsets;
     DevBuf ptiles, pvals, pk_alt, pv_alt, ranges, items, items_k, items_k2, items_v2;
-    DevBuf sort_ws, scan_ws, npairs, view_offs, tstate, tile_done;
+    DevBuf sort_ws, scan_ws, tscan_ws, npairs, view_offs, tstate, tile_done;
     uint64_t max_elems = 0, max_tiles = 0, max_pairs = 0, max_pixels = 0;
     int n_slabs = 1;
     uint32_t slab_num[9] = {0, 1024};  // depth-slab boundaries, numerators over 1024
@@ -899,7 +902,8 @@ std::vector<DevBuf *> batch_bufs(fs_batch *b)
     std::vector<DevBuf *> v = {&b->scenes_d, &b->rec, &b->rect, &b->ntiles, &b->flags, &b->dkeys, &b->dvals,
                                &b->dkeys2, &b->dvals2, &b->counts, &b->offsets, &b->ptiles, &b->pvals, &b->pk_alt,
                                &b->pv_alt, &b->ranges, &b->items, &b->items_k, &b->items_k2, &b->items_v2,
-                               &b->sort_ws, &b->scan_ws, &b->npairs, &b->view_offs, &b->tstate, &b->tile_done};
+                               &b->sort_ws, &b->scan_ws, &b->tscan_ws, &b->npairs, &b->view_offs, &b->tstate,
+                               &b->tile_done};
     for (Chunk &c : b->chunks) {
         v.push_back(&c.views);
         v.push_back(&c.tasks);
@@ -937,7 +941,7 @@ int enqueue_front(fs_batch *b, Chunk &c, hipStream_t s)
                                  (float *)b->rec.p, (int16_t *)b->rect.p, (int32_t *)b->ntiles.p, (uint8_t *)b->flags.p,
                                  dk, dv, ctx->status_dev));
     HIPCHECK(ctx, radix_sort(s, dk, dv, (uint32_t *)b->dkeys2.p, (uint32_t *)b->dvals2.p, (const SegDev *)c.dsegs.p,
-                             (int32_t)pl.views.size(), pl.dblocks, 32, b->sort_ws.p, nullptr));
+                             (int32_t)pl.views.size(), pl.dblocks, 32, b->sort_ws.p, nullptr, 1));
     return FS_OK;
 }
 
@@ -987,19 +991,26 @@ int enqueue_slabs(fs_batch *b, Chunk &c, int chunk_idx, hipStream_t s)
         uint32_t *np = (uint32_t *)b->npairs.p + (size_t)chunk_idx * S + k;
         const Slab sl{b->slab_num[k], b->slab_num[k + 1]};
         HIPCHECK(ctx, launch_slab_counts(s, dk, dv, (const float *)b->rec.p, (const int16_t *)b->rect.p,
-                                         (const uint8_t *)b->flags.p, (const int32_t *)b->ntiles.p,
+                                         b->p.fp64_conic ? nullptr : (const uint8_t *)b->flags.p,
+                                         (const int32_t *)b->ntiles.p,
                                          (const ViewDev *)c.views.p, V, total, sl, k > 0 ? done : nullptr,
                                          b->p.tile_w, b->p.tile_h, b->p.sigma_k, (uint32_t *)b->counts.p));
         HIPCHECK(ctx, scan_exclusive(s, (const uint32_t *)b->counts.p, (uint32_t *)b->offsets.p, total, np,
                                      b->scan_ws.p));
         HIPCHECK(ctx, launch_emit(s, dk, dv, (const uint32_t *)b->offsets.p, (const uint32_t *)b->counts.p,
-                                  (const float *)b->rec.p, (const int16_t *)b->rect.p, (const uint8_t *)b->flags.p,
+                                  (const float *)b->rec.p, (const int16_t *)b->rect.p,
+                                  b->p.fp64_conic ? nullptr : (const uint8_t *)b->flags.p,
                                   (const ViewDev *)c.views.p, V, total, c.pair_cap, b->p.tile_w, b->p.tile_h,
                                   b->p.sigma_k, k > 0 ? done : nullptr, k0, v0, ctx->status_dev));
+        // tile lists: the sort's last pass counts the pairs of every tile (and
+        // skips writing the sorted tile ids, which nothing reads), then the
+        // ranges are the exclusive scan of those counts
+        uint32_t *tcount = (uint32_t *)b->items_k.p, *tstart = (uint32_t *)b->items_k2.p;
+        HIPCHECK(ctx, launch_fill_u32(s, tcount, 0u, (int64_t)pl.tiles));
         HIPCHECK(ctx, radix_sort(s, k0, v0, k1, v1, (const SegDev *)c.psegs.p, 1, c.pblocks, c.passes * 8,
-                                 b->sort_ws.p, np));
-        HIPCHECK(ctx, launch_fill_u32(s, (uint32_t *)b->ranges.p, 0u, (int64_t)pl.tiles * 2));
-        HIPCHECK(ctx, launch_ranges(s, pt, np, c.pair_cap, c.pair_cap, (uint32_t *)b->ranges.p));
+                                 b->sort_ws.p, np, c.ptpb, tcount, false));
+        HIPCHECK(ctx, scan_exclusive(s, tcount, tstart, (int64_t)pl.tiles, nullptr, b->tscan_ws.p));
+        HIPCHECK(ctx, launch_count_ranges(s, tcount, tstart, (int64_t)pl.tiles, (uint32_t *)b->ranges.p));
         const uint32_t *items = nullptr;
         if (b->p.tile_order == 0) {
             RCHECK(enqueue_lpt(ctx, s, (const uint32_t *)b->ranges.p, pl.tiles, (const SegDev *)c.lsegs.p,
@@ -1211,7 +1222,8 @@ int batch_build(fs_batch *b, const fs_scene *scenes, int32_t n_scenes)
     const uint64_t cap = std::min<uint64_t>(0xFFFFF000ull, b->max_pairs + b->max_pairs / 64 + 4096);
     for (Chunk &c : b->chunks) {
         c.pair_cap = (uint32_t)std::min<uint64_t>(cap, c.slab_max + c.slab_max / 64 + 4096);
-        c.pblocks = (c.pair_cap + kSortTile - 1) / kSortTile;
+        c.ptpb = radix_tiles_per_block(c.pair_cap);
+        c.pblocks = (uint32_t)(((uint64_t)c.pair_cap + (uint64_t)kSortTile * c.ptpb - 1) / ((uint64_t)kSortTile * c.ptpb));
         c.lblocks = (uint32_t)((c.plan.tiles + kSortTile - 1) / kSortTile);
         c.passes = (bits_for(std::max<uint64_t>(c.plan.tiles, 2)) + 7) / 8;
         b->max_pblocks = std::max(b->max_pblocks, c.pblocks);
@@ -1236,6 +1248,7 @@ int batch_build(fs_batch *b, const fs_scene *scenes, int32_t n_scenes)
     RCHECK(batch_alloc(b, b->items_k, T4));
     RCHECK(batch_alloc(b, b->items_k2, T4));
     RCHECK(batch_alloc(b, b->items_v2, T4));
+    RCHECK(batch_alloc(b, b->tscan_ws, scan_ws_bytes((int64_t)std::max<uint64_t>(b->max_tiles, 1))));
     const uint32_t sb = std::max(std::max(b->max_dblocks, b->max_pblocks), std::max<uint32_t>(b->max_lblocks, 1));
     RCHECK(batch_alloc(b, b->sort_ws, radix_ws_bytes(sb)));
     if (S > 1) {

@@ -120,12 +120,18 @@ hipError_t launch_depth_keys(hipStream_t s, const float *rec, const int32_t *nti
 
 // Stable LSD radix sort of (key, val) u32 pairs over segments, on bits
 // [0, bits) in 8-bit passes; len_dev (optional, single-segment sorts only)
-// caps the length on the device. After an even number of passes the result
-// is in (keys, vals), after an odd number in (keys_alt, vals_alt).
+// caps the length on the device. A block sorts `tpb` block tiles of
+// kSortTile items; n_blocks and the segments' blk0 count such blocks. After
+// an even number of passes the result is in (keys, vals), after an odd number
+// in (keys_alt, vals_alt). key_count (optional, zeroed by the caller, one u32
+// per key value) receives the number of items of each key; with
+// last_keys = false the last pass writes the values only.
 size_t radix_ws_bytes(uint32_t n_blocks);
 hipError_t radix_sort(hipStream_t s, uint32_t *keys, uint32_t *vals, uint32_t *keys_alt, uint32_t *vals_alt,
                       const SegDev *segs, int32_t n_segs, uint32_t n_blocks, int32_t bits, void *ws,
-                      const uint32_t *len_dev);
+                      const uint32_t *len_dev, int32_t tpb, uint32_t *key_count = nullptr, bool last_keys = true);
+// block tiles per block for a single-segment sort of n_items
+int32_t radix_tiles_per_block(uint64_t n_items);
 
 // Exclusive scan of u32 -> u32 (device-wide), total written to *total_out.
 size_t scan_ws_bytes(int64_t n);
@@ -143,7 +149,9 @@ struct Slab {
 };
 
 // counts[i] = listed tiles of depth-sorted element i that lie in the slab and
-// whose tile is not marked in `done` (NULL: no tile is done); 0 outside the slab
+// whose tile is not marked in `done` (NULL: no tile is done); 0 outside the slab.
+// `flags` may be NULL when float64 conics are on: rec's float64 mark then
+// gives the degenerate flag, and one gather per element is saved.
 hipError_t launch_slab_counts(hipStream_t s, const uint32_t *sorted_keys, const uint32_t *sorted_vals,
                               const float *rec, const int16_t *rect, const uint8_t *flags, const int32_t *ntiles,
                               const ViewDev *views, int32_t n_views, int64_t total, Slab slab, const uint8_t *done,
@@ -152,12 +160,17 @@ hipError_t launch_slab_counts(hipStream_t s, const uint32_t *sorted_keys, const 
 // emits, for every depth-sorted element, one (tile, id) pair per listed tile
 // (the row_span rule) at offsets[i]; pairs at or beyond `capacity` are
 // dropped and latched
-// (tiles marked in `done`, if not NULL, are skipped, as in launch_slab_counts)
+// (tiles marked in `done`, if not NULL, are skipped, as in launch_slab_counts;
+// `flags` may be NULL as there)
 hipError_t launch_emit(hipStream_t s, const uint32_t *sorted_keys, const uint32_t *sorted_vals,
                        const uint32_t *offsets, const uint32_t *counts, const float *rec, const int16_t *rect,
                        const uint8_t *flags, const ViewDev *views, int32_t n_views, int64_t total,
                        uint32_t capacity, int32_t tile_w, int32_t tile_h, float sigma_k, const uint8_t *done,
                        uint32_t *tiles_out, uint32_t *vals_out, unsigned long long *status);
+
+// ranges[t] = [starts[t], starts[t] + counts[t]), or [0, 0) if counts[t] == 0
+hipError_t launch_count_ranges(hipStream_t s, const uint32_t *counts, const uint32_t *starts, int64_t n_tiles,
+                               uint32_t *ranges);
 
 hipError_t launch_ranges(hipStream_t s, const uint32_t *tiles, const uint32_t *n_pairs_dev, uint32_t capacity,
                          int64_t n_pairs_max, uint32_t *ranges);

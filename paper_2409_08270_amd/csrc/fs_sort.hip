@@ -104,17 +104,20 @@ __global__ __launch_bounds__(kThreads) void k_scan_down(const uint32_t *__restri
 // adds runs of equal digits with one LDS atomic per run: keys emitted per
 // Gaussian in tile order repeat their high digit, which would otherwise
 // serialise the atomics.
-// Segment of block b: the last segment whose first block tile is <= b.
+// A block handles `tpb` consecutive block tiles of kTile items (a super-tile),
+// so that large sorts keep their digit tables small: one histogram row per
+// super-tile. Segment of block b: the last segment whose first block is <= b
+// (segments' blk0 count super-tiles).
 struct SegInfo {
-    int64_t base;     // first element of this block tile
-    int nvalid;       // valid items in the tile
-    uint32_t bps;     // block tiles of the segment
-    uint32_t lb;      // tile index inside the segment
+    int64_t base;     // first element of this super-tile
+    int nvalid;       // valid items in the super-tile
+    uint32_t bps;     // super-tiles of the segment
+    uint32_t lb;      // super-tile index inside the segment
     uint32_t blk0;
 };
 
 __device__ __forceinline__ SegInfo seg_of_block(const SegDev *__restrict__ segs, int32_t n_segs, uint32_t b,
-                                                const uint32_t *__restrict__ len_dev)
+                                                const uint32_t *__restrict__ len_dev, int32_t tpb)
 {
     int lo = 0, hi = n_segs - 1;
     while (lo < hi) {
@@ -122,48 +125,65 @@ __device__ __forceinline__ SegInfo seg_of_block(const SegDev *__restrict__ segs,
         if (segs[mid].blk0 <= b) lo = mid; else hi = mid - 1;
     }
     const SegDev sg = segs[lo];
+    const int64_t span = (int64_t)kTile * tpb;
     SegInfo r;
     r.blk0 = sg.blk0;
     r.lb = b - sg.blk0;
-    r.bps = (sg.len + kTile - 1) / kTile;
+    r.bps = (uint32_t)(((int64_t)sg.len + span - 1) / span);
     uint32_t len = sg.len;
     if (len_dev) len = min(len, *len_dev);
-    const int64_t rem = (int64_t)len - (int64_t)r.lb * kTile;
-    r.nvalid = rem <= 0 ? 0 : (rem < kTile ? (int)rem : kTile);
-    r.base = (int64_t)sg.off + (int64_t)r.lb * kTile;
+    const int64_t rem = (int64_t)len - (int64_t)r.lb * span;
+    r.nvalid = rem <= 0 ? 0 : (rem < span ? (int)rem : (int)span);
+    r.base = (int64_t)sg.off + (int64_t)r.lb * span;
     return r;
 }
 
-// Digit histogram of one block tile. Each thread reads 16 consecutive keys and
-// adds runs of equal digits with one LDS atomic per run: keys emitted per
-// Gaussian in tile order repeat their high digit, which would otherwise
-// serialise the atomics. Counts are stored [segment][digit][tile] so that one
-// exclusive scan over the whole table gives every tile's output positions.
+// Digit histogram of one super-tile. Each thread reads 16 consecutive keys per
+// block tile and adds runs of equal digits with one LDS atomic per run: keys
+// emitted per Gaussian in tile order repeat their high digit, which would
+// otherwise serialise the atomics. Counts are stored [segment][digit][block]
+// so that one exclusive scan over the whole table gives every block's output
+// positions.
 __global__ __launch_bounds__(kThreads) void k_radix_hist(const uint32_t *__restrict__ keys,
                                                          const SegDev *__restrict__ segs, int32_t n_segs,
                                                          int32_t shift, uint32_t *__restrict__ hist,
-                                                         const uint32_t *__restrict__ len_dev)
+                                                         const uint32_t *__restrict__ len_dev, int32_t tpb)
 {
     __shared__ uint32_t s_h[kWaves][256];
-    const SegInfo si = seg_of_block(segs, n_segs, blockIdx.x, len_dev);
+    const SegInfo si = seg_of_block(segs, n_segs, blockIdx.x, len_dev, tpb);
     const int w = threadIdx.x >> 6;
     for (int i = threadIdx.x; i < kWaves * 256; i += kThreads) (&s_h[0][0])[i] = 0;
     __syncthreads();
-    const int t0 = threadIdx.x * kItems;
-    const uint32_t *k = keys + si.base;
     uint32_t run_d = 0xFFFFFFFFu, run_n = 0;
-    if (t0 + kItems <= si.nvalid) {
-        const uint4 *k4 = reinterpret_cast<const uint4 *>(k + t0);
-        const bool aligned = ((reinterpret_cast<uintptr_t>(k + t0) & 15u) == 0);
+    for (int tb = 0; tb * kTile < si.nvalid; ++tb) {
+        const int nvalid = min(kTile, si.nvalid - tb * kTile);
+        const int t0 = threadIdx.x * kItems;
+        const uint32_t *k = keys + si.base + (int64_t)tb * kTile;
+        if (t0 + kItems <= nvalid) {
+            const uint4 *k4 = reinterpret_cast<const uint4 *>(k + t0);
+            const bool aligned = ((reinterpret_cast<uintptr_t>(k + t0) & 15u) == 0);
 #pragma unroll
-        for (int q = 0; q < kItems / 4; ++q) {
-            uint4 x;
-            if (aligned) x = k4[q];
-            else x = make_uint4(k[t0 + 4 * q], k[t0 + 4 * q + 1], k[t0 + 4 * q + 2], k[t0 + 4 * q + 3]);
-            const uint32_t xs[4] = {x.x, x.y, x.z, x.w};
+            for (int q = 0; q < kItems / 4; ++q) {
+                uint4 x;
+                if (aligned) x = k4[q];
+                else x = make_uint4(k[t0 + 4 * q], k[t0 + 4 * q + 1], k[t0 + 4 * q + 2], k[t0 + 4 * q + 3]);
+                const uint32_t xs[4] = {x.x, x.y, x.z, x.w};
 #pragma unroll
-            for (int e = 0; e < 4; ++e) {
-                const uint32_t d = (xs[e] >> shift) & 255u;
+                for (int e = 0; e < 4; ++e) {
+                    const uint32_t d = (xs[e] >> shift) & 255u;
+                    if (d != run_d) {
+                        if (run_n) atomicAdd(&s_h[w][run_d], run_n);
+                        run_d = d;
+                        run_n = 0;
+                    }
+                    run_n++;
+                }
+            }
+        } else {
+            for (int it = 0; it < kItems; ++it) {
+                const int i = t0 + it;
+                if (i >= nvalid) break;
+                const uint32_t d = (k[i] >> shift) & 255u;
                 if (d != run_d) {
                     if (run_n) atomicAdd(&s_h[w][run_d], run_n);
                     run_d = d;
@@ -171,18 +191,6 @@ __global__ __launch_bounds__(kThreads) void k_radix_hist(const uint32_t *__restr
                 }
                 run_n++;
             }
-        }
-    } else {
-        for (int it = 0; it < kItems; ++it) {
-            const int i = t0 + it;
-            if (i >= si.nvalid) break;
-            const uint32_t d = (k[i] >> shift) & 255u;
-            if (d != run_d) {
-                if (run_n) atomicAdd(&s_h[w][run_d], run_n);
-                run_d = d;
-                run_n = 0;
-            }
-            run_n++;
         }
     }
     if (run_n) atomicAdd(&s_h[w][run_d], run_n);
@@ -194,13 +202,20 @@ __global__ __launch_bounds__(kThreads) void k_radix_hist(const uint32_t *__restr
     hist[(int64_t)si.blk0 * 256 + (int64_t)d * si.bps + si.lb] = c;
 }
 
-// Stable scatter: wave w ranks the contiguous items [w*1024, (w+1)*1024) of
-// the block tile in 16 rounds of 64; equal digits are matched with 8 ballots.
+// Stable scatter of one super-tile, block tile after block tile: wave w ranks
+// the contiguous items [w*1024, (w+1)*1024) of the block tile in 16 rounds of
+// 64, equal digits matched with 8 ballots; each digit's output cursor then
+// advances by the block tile's count of that digit.
+// On the last pass the staged block tile is ordered by the whole key, so runs
+// of equal keys are contiguous in LDS: with key_count, each run adds its
+// length to its key's count (+end at its last item, -start at its first, which
+// sums to the length whatever the order of the atomics); kout may be NULL.
 __global__ __launch_bounds__(kThreads) void k_radix_scatter(const uint32_t *__restrict__ kin, const uint32_t *__restrict__ vin,
                                                             uint32_t *__restrict__ kout, uint32_t *__restrict__ vout,
                                                             const SegDev *__restrict__ segs, int32_t n_segs,
                                                             int32_t shift, const uint32_t *__restrict__ offs,
-                                                            const uint32_t *__restrict__ len_dev)
+                                                            const uint32_t *__restrict__ len_dev, int32_t tpb,
+                                                            uint32_t *__restrict__ key_count)
 {
     __shared__ uint32_t s_cnt[kWaves][256];
     __shared__ uint32_t s_dstart[256];
@@ -209,73 +224,83 @@ __global__ __launch_bounds__(kThreads) void k_radix_scatter(const uint32_t *__re
     __shared__ uint32_t s_k[kTile];
     __shared__ uint32_t s_v[kTile];
 
-    const SegInfo si = seg_of_block(segs, n_segs, blockIdx.x, len_dev);
+    const SegInfo si = seg_of_block(segs, n_segs, blockIdx.x, len_dev, tpb);
     const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
-    for (int i = threadIdx.x; i < kWaves * 256; i += kThreads) (&s_cnt[0][0])[i] = 0;
-    s_gofs[threadIdx.x] = offs[(int64_t)si.blk0 * 256 + (int64_t)threadIdx.x * si.bps + si.lb];
-    __syncthreads();
-
-    const int nvalid = si.nvalid;
-    const uint32_t *kbase = kin + si.base;
-    const uint32_t *vbase = vin + si.base;
-    const unsigned long long lt = (1ull << lane) - 1ull;
-
-    uint32_t key[kItems], val[kItems], rnk[kItems];
-#pragma unroll
-    for (int r = 0; r < kItems; ++r) {
-        const int li = w * (kItems * 64) + r * 64 + lane;
-        const bool ok = li < nvalid;
-        key[r] = ok ? kbase[li] : 0xFFFFFFFFu;
-        val[r] = ok ? vbase[li] : 0u;
-    }
-#pragma unroll
-    for (int r = 0; r < kItems; ++r) {
-        const uint32_t d = (key[r] >> shift) & 255u;
-        unsigned long long peers = ~0ull;
-#pragma unroll
-        for (int bit = 0; bit < 8; ++bit) {
-            const bool on = (d >> bit) & 1u;
-            const unsigned long long bb = __ballot(on);
-            peers &= on ? bb : ~bb;
-        }
-        const uint32_t before = s_cnt[w][d];
-        rnk[r] = before + (uint32_t)__popcll(peers & lt);
-        __builtin_amdgcn_wave_barrier();
-        if ((peers & lt) == 0ull) s_cnt[w][d] = before + (uint32_t)__popcll(peers);
-        __builtin_amdgcn_wave_barrier();
-    }
-    __syncthreads();
-    // per-digit totals, wave prefixes and the digit starts inside the tile
-    {
-        const int d = threadIdx.x;
-        uint32_t run = 0;
-#pragma unroll
-        for (int i = 0; i < kWaves; ++i) {
-            const uint32_t c = s_cnt[i][d];
-            s_cnt[i][d] = run;
-            run += c;
-        }
-        uint32_t tot;
-        const uint32_t ex = block_excl_scan(run, s_wsum, tot);
-        s_dstart[d] = ex;
-    }
-    __syncthreads();
-#pragma unroll
-    for (int r = 0; r < kItems; ++r) {
-        const uint32_t d = (key[r] >> shift) & 255u;
-        const uint32_t pos = s_dstart[d] + s_cnt[w][d] + rnk[r];
-        s_k[pos] = key[r];
-        s_v[pos] = val[r];
-    }
-    __syncthreads();
     // s_gofs comes from one exclusive scan over the [segment][digit][block]
     // counts of all segments, so it is already a position in the whole array
-    for (int i = threadIdx.x; i < nvalid; i += kThreads) {
-        const uint32_t k = s_k[i];
-        const uint32_t d = (k >> shift) & 255u;
-        const int64_t p = (int64_t)s_gofs[d] + (i - (int64_t)s_dstart[d]);
-        kout[p] = k;
-        vout[p] = s_v[i];
+    s_gofs[threadIdx.x] = offs[(int64_t)si.blk0 * 256 + (int64_t)threadIdx.x * si.bps + si.lb];
+    const unsigned long long lt = (1ull << lane) - 1ull;
+
+    for (int tb = 0; tb * kTile < si.nvalid; ++tb) {
+        const int nvalid = min(kTile, si.nvalid - tb * kTile);
+        const uint32_t *kbase = kin + si.base + (int64_t)tb * kTile;
+        const uint32_t *vbase = vin + si.base + (int64_t)tb * kTile;
+        for (int i = threadIdx.x; i < kWaves * 256; i += kThreads) (&s_cnt[0][0])[i] = 0;
+        __syncthreads();
+
+        uint32_t key[kItems], val[kItems], rnk[kItems];
+#pragma unroll
+        for (int r = 0; r < kItems; ++r) {
+            const int li = w * (kItems * 64) + r * 64 + lane;
+            const bool ok = li < nvalid;
+            key[r] = ok ? kbase[li] : 0xFFFFFFFFu;
+            val[r] = ok ? vbase[li] : 0u;
+        }
+#pragma unroll
+        for (int r = 0; r < kItems; ++r) {
+            const uint32_t d = (key[r] >> shift) & 255u;
+            unsigned long long peers = ~0ull;
+#pragma unroll
+            for (int bit = 0; bit < 8; ++bit) {
+                const bool on = (d >> bit) & 1u;
+                const unsigned long long bb = __ballot(on);
+                peers &= on ? bb : ~bb;
+            }
+            const uint32_t before = s_cnt[w][d];
+            rnk[r] = before + (uint32_t)__popcll(peers & lt);
+            __builtin_amdgcn_wave_barrier();
+            if ((peers & lt) == 0ull) s_cnt[w][d] = before + (uint32_t)__popcll(peers);
+            __builtin_amdgcn_wave_barrier();
+        }
+        __syncthreads();
+        // per-digit totals, wave prefixes and the digit starts inside the block tile
+        uint32_t tile_count;
+        {
+            const int d = threadIdx.x;
+            uint32_t run = 0;
+#pragma unroll
+            for (int i = 0; i < kWaves; ++i) {
+                const uint32_t c = s_cnt[i][d];
+                s_cnt[i][d] = run;
+                run += c;
+            }
+            uint32_t tot;
+            const uint32_t ex = block_excl_scan(run, s_wsum, tot);
+            s_dstart[d] = ex;
+            tile_count = run;
+        }
+        __syncthreads();
+#pragma unroll
+        for (int r = 0; r < kItems; ++r) {
+            const uint32_t d = (key[r] >> shift) & 255u;
+            const uint32_t pos = s_dstart[d] + s_cnt[w][d] + rnk[r];
+            s_k[pos] = key[r];
+            s_v[pos] = val[r];
+        }
+        __syncthreads();
+        for (int i = threadIdx.x; i < nvalid; i += kThreads) {
+            const uint32_t k = s_k[i];
+            const uint32_t d = (k >> shift) & 255u;
+            const int64_t p = (int64_t)s_gofs[d] + (i - (int64_t)s_dstart[d]);
+            if (kout) kout[p] = k;
+            vout[p] = s_v[i];
+            if (key_count) {
+                if (i + 1 == nvalid || s_k[i + 1] != k) atomicAdd(&key_count[k], (uint32_t)(i + 1));
+                if (i > 0 && s_k[i - 1] != k) atomicSub(&key_count[k], (uint32_t)i);
+            }
+        }
+        __syncthreads();
+        s_gofs[threadIdx.x] += tile_count;
     }
 }
 
@@ -336,8 +361,8 @@ __global__ void k_slab_counts(const uint32_t *__restrict__ skeys, const uint32_t
                 const short4 rc = rect[idx];
                 const float4 r0 = rec[2 * idx];
                 const float4 r1 = rec[2 * idx + 1];
-                const Span32 sp = make_span32(r0.x, r0.y, r0.z, r0.w, r1.x, (flags[idx] & 2u) != 0,
-                                              support_limit(sigma_k));
+                const bool deg = flags ? (flags[idx] & 2u) != 0 : r1.w != 0.0f;
+                const Span32 sp = make_span32(r0.x, r0.y, r0.z, r0.w, r1.x, deg, support_limit(sigma_k));
                 for (int ty = rc.y; ty <= rc.w; ++ty) {
                     int l, r;
                     if (!row_span(sp, ty, rc.x, rc.z, tw, th, C.W, C.H, l, r)) continue;
@@ -355,7 +380,7 @@ __global__ void k_slab_counts(const uint32_t *__restrict__ skeys, const uint32_t
 // thread enumerates its Gaussian's tiles (the row_span rule, as in the count)
 // into an LDS window of kEmitWin pairs, and the block writes the window out
 // with consecutive threads on consecutive addresses.
-constexpr int kEmitWin = 4096;
+constexpr int kEmitWin = 2048;
 
 __global__ __launch_bounds__(kThreads) void k_emit(const uint32_t *__restrict__ skeys, const uint32_t *__restrict__ svals,
                                                    const uint32_t *__restrict__ offsets, const uint32_t *__restrict__ counts,
@@ -392,7 +417,10 @@ __global__ __launch_bounds__(kThreads) void k_emit(const uint32_t *__restrict__ 
         rc = rect[idx];
         const float4 r0 = rec[2 * idx];
         const float4 r1 = rec[2 * idx + 1];
-        sp = make_span32(r0.x, r0.y, r0.z, r0.w, r1.x, (flags[idx] & 2u) != 0, support_limit(sigma_k));
+        // without the flag plane, rec's float64-conic mark stands for the
+        // degenerate flag (the two agree whenever float64 conics are on)
+        const bool deg = flags ? (flags[idx] & 2u) != 0 : r1.w != 0.0f;
+        sp = make_span32(r0.x, r0.y, r0.z, r0.w, r1.x, deg, support_limit(sigma_k));
         tbase = C.tile_base;
         tiles_x = (uint32_t)C.tiles_x;
         W = C.W;
@@ -482,6 +510,16 @@ __global__ __launch_bounds__(256) void k_ranges(const uint32_t *__restrict__ til
     }
 }
 
+// Ranges from per-tile counts and their exclusive scan; [0, 0) for empty tiles.
+__global__ void k_count_ranges(const uint32_t *__restrict__ counts, const uint32_t *__restrict__ starts,
+                               int64_t n_tiles, uint2 *__restrict__ ranges)
+{
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= n_tiles) return;
+    const uint32_t c = counts[t], s0 = starts[t];
+    ranges[t] = c ? make_uint2(s0, s0 + c) : make_uint2(0u, 0u);
+}
+
 // Work-order keys: tiles with longer lists get smaller keys (lengths clamp
 // at 65535), so an ascending stable sort puts the longest lists first.
 __global__ void k_tile_keys(const uint2 *__restrict__ ranges, int64_t n_tiles, uint32_t *__restrict__ keys,
@@ -563,26 +601,39 @@ size_t radix_ws_bytes(uint32_t n_blocks)
 
 hipError_t radix_sort(hipStream_t s, uint32_t *keys, uint32_t *vals, uint32_t *keys_alt, uint32_t *vals_alt,
                       const SegDev *segs, int32_t n_segs, uint32_t n_blocks, int32_t bits, void *ws,
-                      const uint32_t *len_dev)
+                      const uint32_t *len_dev, int32_t tpb, uint32_t *key_count, bool last_keys)
 {
     if (n_blocks == 0 || n_segs == 0) return hipSuccess;
+    if (tpb < 1) return hipErrorInvalidValue;
     const int64_t hist_n = (int64_t)n_blocks * 256;
     uint32_t *hist = (uint32_t *)ws;
     uint32_t *offs = hist + hist_n;
     void *scan_ws = offs + hist_n;
     uint32_t *ki = keys, *vi = vals, *ko = keys_alt, *vo = vals_alt;
     for (int shift = 0; shift < bits; shift += 8) {
-        hipLaunchKernelGGL(k_radix_hist, dim3(n_blocks), dim3(kThreads), 0, s, ki, segs, n_segs, shift, hist, len_dev);
+        hipLaunchKernelGGL(k_radix_hist, dim3(n_blocks), dim3(kThreads), 0, s, ki, segs, n_segs, shift, hist, len_dev,
+                           tpb);
         hipError_t e = scan_exclusive(s, hist, offs, hist_n, nullptr, scan_ws);
         if (e != hipSuccess) return e;
-        hipLaunchKernelGGL(k_radix_scatter, dim3(n_blocks), dim3(kThreads), 0, s, ki, vi, ko, vo, segs, n_segs, shift,
-                           (const uint32_t *)offs, len_dev);
+        const bool last = shift + 8 >= bits;
+        hipLaunchKernelGGL(k_radix_scatter, dim3(n_blocks), dim3(kThreads), 0, s, ki, vi,
+                           (last && !last_keys) ? nullptr : ko, vo, segs, n_segs, shift, (const uint32_t *)offs,
+                           len_dev, tpb, last ? key_count : nullptr);
         e = hipGetLastError();
         if (e != hipSuccess) return e;
         uint32_t *tk = ki, *tv = vi;
         ki = ko; vi = vo; ko = tk; vo = tv;
     }
     return hipSuccess;
+}
+
+int32_t radix_tiles_per_block(uint64_t n_items)
+{
+    // about 4096 blocks (16 per CU) once the sort is large enough; tables of
+    // 256 counts per block stay a few MB
+    const uint64_t tiles = (n_items + kTile - 1) / kTile;
+    const uint64_t t = tiles / 4096;
+    return (int32_t)(t < 1 ? 1 : (t > 64 ? 64 : t));
 }
 
 hipError_t launch_depth_keys(hipStream_t s, const float *rec, const int32_t *ntiles, const uint8_t *flags,
@@ -639,6 +690,15 @@ hipError_t launch_slab_counts(hipStream_t s, const uint32_t *sorted_keys, const 
     return hipGetLastError();
 }
 
+
+hipError_t launch_count_ranges(hipStream_t s, const uint32_t *counts, const uint32_t *starts, int64_t n_tiles,
+                               uint32_t *ranges)
+{
+    if (n_tiles <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_count_ranges, dim3(grid_for(n_tiles, 256)), dim3(256), 0, s, counts, starts, n_tiles,
+                       reinterpret_cast<uint2 *>(ranges));
+    return hipGetLastError();
+}
 
 hipError_t launch_tile_keys(hipStream_t s, const uint32_t *ranges, int64_t n_tiles, uint32_t *keys, uint32_t *vals)
 {
