@@ -105,6 +105,10 @@ typedef struct {
     int32_t tile_order;      /* fs_accumulate work order: 0 (default) longest tile list first;
                                 1 = image order; 2 = each of the chip's 8 XCDs (each with its
                                 own L2) gets a contiguous run of tiles */
+    int32_t count_ops;       /* 1 (default): compositing counts its in-support evaluations and
+                                blends into the status (fs_status_get); 0 leaves those two
+                                counters alone and saves two instructions per pixel step
+                                (A, S and every other output are the same either way) */
 } fs_params;
 
 /* Projected Gaussians, caller-owned device buffers, one plane per view:

@@ -55,7 +55,7 @@ class FsCamera(ctypes.Structure):
 class FsParams(ctypes.Structure):
     _fields_ = [("tile_w", _I32), ("tile_h", _I32), ("sigma_k", _F), ("lowpass", _F), ("znear", _F),
                 ("guard", _F), ("alpha_min", _F), ("alpha_max", _F), ("t_min", _F), ("fp64_cond", _F),
-                ("fp64_conic", _I32), ("tile_order", _I32)]
+                ("fp64_conic", _I32), ("tile_order", _I32), ("count_ops", _I32)]
 
 
 class FsProj(ctypes.Structure):

@@ -126,7 +126,7 @@ __device__ __forceinline__ bool block_hit(float u, float v, float A, float B, fl
     return qmin <= lim;
 }
 
-template <bool PIX>
+template <bool PIX, bool COUNT>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(7, 7))) void k_accum(const float4 *__restrict__ rec, const uint32_t *__restrict__ vals,
                                                const uint2 *__restrict__ ranges, const ViewDev *__restrict__ views,
                                                int32_t n_views, const SceneDev *__restrict__ scenes,
@@ -278,8 +278,10 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(7, 7))) voi
             const float Tn = fmaf(-T, alpha, T);
             const bool stop = ok && Tn < P.t_min;
             const bool take = ok && !stop;
-            ne_l += insup ? 1u : 0u;
-            nb_l += take ? 1u : 0u;
+            if (COUNT) {
+                ne_l += insup ? 1u : 0u;
+                nb_l += take ? 1u : 0u;
+            }
             const float wv = take ? alpha * T : 0.0f;
             T = take ? Tn : T;
             live = live && !stop;
@@ -396,7 +398,10 @@ hipError_t launch_accumulate(hipStream_t s, const float *rec, const uint32_t *va
                              float *tstate, uint8_t *tile_done, int32_t first, unsigned long long *status)
 {
     if (n_items == 0) return hipSuccess;
-    auto kern = (t_final || n_blend) ? k_accum<true> : k_accum<false>;
+    const bool pix = t_final || n_blend;
+    const bool count = p.count || n_blend;  // per-pixel blend counts need the counters
+    auto kern = pix ? (count ? k_accum<true, true> : k_accum<true, false>)
+                    : (count ? k_accum<false, true> : k_accum<false, false>);
     hipLaunchKernelGGL(kern, dim3(n_items), dim3(256), 0, s, reinterpret_cast<const float4 *>(rec), vals,
                        reinterpret_cast<const uint2 *>(ranges), views, n_views, scenes, items, p, t_final, n_blend,
                        tstate, tile_done, first, status);

@@ -168,6 +168,7 @@ int check_params(fs_ctx *ctx, const fs_params *p, bool for_accum)
     if (!finite_f(p->t_min) || p->t_min < 0.f || p->t_min >= 1.f) return set_err(ctx, FS_ERR_ARG, "need 0 <= t_min < 1");
     if (!finite_f(p->fp64_cond) || p->fp64_cond < 1.f) return set_err(ctx, FS_ERR_ARG, "fp64_cond must be >= 1");
     if (p->tile_order < 0 || p->tile_order > 2) return set_err(ctx, FS_ERR_ARG, "tile_order must be 0, 1 or 2");
+    if (p->count_ops != 0 && p->count_ops != 1) return set_err(ctx, FS_ERR_ARG, "count_ops must be 0 or 1");
     return FS_OK;
 }
 
@@ -242,7 +243,7 @@ AccParams acc_params(const fs_params *p, int32_t reduction)
     ap.tile_w = p->tile_w;
     ap.tile_h = p->tile_h;
     ap.reduction = reduction;
-    ap.pad = 0;
+    ap.count = p->count_ops ? 1 : 0;
     return ap;
 }
 
@@ -395,6 +396,7 @@ void fs_params_default(fs_params *p)
     p->fp64_cond = 64.0f;
     p->fp64_conic = 1;
     p->tile_order = 0;
+    p->count_ops = 1;
 }
 
 void fs_params_exact(fs_params *p)

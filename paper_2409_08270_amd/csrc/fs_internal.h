@@ -194,7 +194,7 @@ struct AccParams {
     float alpha_min, alpha_max, t_min;
     int32_t tile_w, tile_h;
     int32_t reduction;
-    int32_t pad;
+    int32_t count;    // 1: count in-support evaluations and blends
 };
 
 // Resumable compositing (depth slabs): with `tstate` set, each pixel's

@@ -194,3 +194,28 @@ def test_depth_slabs_give_the_single_pass_result(ctx):
             a, c = _A(one, i), _A(b, i)
             d = np.abs(a - c).sum(1)
             assert np.all(d <= 1e-5 * np.abs(a).sum(1) + 1e-9), f"S={S} scene {i}"
+
+
+def test_uncounted_batch_gives_the_same_result(ctx):
+    # count_ops = 0 drops only the evaluation/blend counters of the compositing
+    scenes = _uneven_scenes()
+    dss = [L.DeviceScene(s) for s in scenes]
+    out = {}
+    for count in (1, 0):
+        b = L.Batch(ctx, dss, L.params(count_ops=count), gammas=[0.0, 0.3, -0.2], want_margin=True)
+        ctx.status()
+        b.run()
+        torch.cuda.synchronize()
+        st = ctx.status()
+        out[count] = ([_A(b, i) for i in range(3)], [b.S[i].cpu().numpy() for i in range(3)], st)
+        b.close()
+    (A1, S1, st1), (A0, S0, st0) = out[1], out[0]
+    assert st1["blends"] > 0 and st1["evaluated"] >= st1["blends"]
+    assert st0["blends"] == 0 and st0["evaluated"] == 0
+    assert st0["pairs_emitted"] == st1["pairs_emitted"] and st0["wave_steps"] == st1["wave_steps"]
+    for i in range(3):
+        # the atomics' order may differ between runs; A_hi + A_lo agrees to about one rounding
+        assert np.allclose(A0[i], A1[i], rtol=1e-6, atol=1e-9)
+        assert np.array_equal(S0[i], S1[i])
+    with pytest.raises(RuntimeError):
+        L.Batch(ctx, dss, L.params(count_ops=2))
