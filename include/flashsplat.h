@@ -176,6 +176,13 @@ const char *fs_ctx_last_error(fs_ctx *ctx);
  * any error bit (not FS_DEV_MANY_LABELS) was set. */
 int fs_status_get(fs_ctx *ctx, fs_status *out, int32_t clear);
 
+/* Duration in ms of the last compositing kernel that fs_accumulate launched on
+ * this context, from HIP events recorded on the context's stream right before
+ * and after that launch (the work-order sort and the host's checks are
+ * outside). Waits for the launch to finish. FS_ERR_ARG if no fs_accumulate
+ * call has been timed (calls made under stream capture are not). */
+int fs_last_accumulate_ms(fs_ctx *ctx, float *ms);
+
 /* a1: projection (Sec. 3.1; EWA splatting of 3DGS, which the paper's renderer
  * inherits). For every view v in cams[0..n_views) and Gaussian g: camera-space
  * mean, 2D covariance J W Sigma3 W^T J^T + lowpass*I, its inverse (conic),

@@ -102,7 +102,7 @@ class FsBatchInfo(ctypes.Structure):
 EXPORTS = ["fs_version", "fs_error_string", "fs_params_default", "fs_params_exact", "fs_ctx_create",
            "fs_ctx_set_stream", "fs_ctx_destroy", "fs_ctx_last_error", "fs_status_get", "fs_project",
            "fs_bin_sort", "fs_accumulate", "fs_assign", "fs_assign_sweep", "fs_compact", "fs_render_masks",
-           "fs_prompt_propagate", "fs_diagnose",
+           "fs_prompt_propagate", "fs_diagnose", "fs_last_accumulate_ms",
            "fs_batch_opts_default", "fs_batch_create",
            "fs_batch_run", "fs_batch_get_info", "fs_batch_destroy"]
 
@@ -141,6 +141,7 @@ def load(path: str = LIB_PATH):
         "fs_render_masks": ([_P, ctypes.POINTER(FsProj), ctypes.POINTER(FsBins), ctypes.POINTER(FsCamera), _P, _I32,
                              ctypes.POINTER(FsParams), _F, _I32, _P, _P, _P], _I32),
         "fs_diagnose": ([_P, _P, _P, _P, _P, _I64, _I32, _F, _P, _P, _P], _I32),
+        "fs_last_accumulate_ms": ([_P, ctypes.POINTER(_F)], _I32),
         "fs_prompt_propagate": ([_P, ctypes.POINTER(FsGaussians), ctypes.POINTER(FsCamera), _I32, _I32, _P, _I32,
                                  _I32, ctypes.POINTER(FsParams), _P, _P, _P, _P], _I32),
         "fs_batch_opts_default": ([ctypes.POINTER(FsBatchOpts)], None),
@@ -283,6 +284,12 @@ class Context:
         return self._check(self.L.fs_render_masks(self.h, ctypes.byref(proj.struct()), ctypes.byref(bins.struct()),
                                                   cams, _ptr(S), n_classes, ctypes.byref(prm), float(tau), int(mode),
                                                   _ptr(labels), _ptr(rho), _ptr(depth)))
+
+    def fs_last_accumulate_ms(self) -> float:
+        """Duration of the last fs_accumulate's compositing kernel (HIP events on the stream)."""
+        ms = _F(0.0)
+        self._check(self.L.fs_last_accumulate_ms(self.h, ctypes.byref(ms)))
+        return float(ms.value)
 
     def fs_diagnose(self, A_hi, A_lo, S, gt, n: int, E: int, rel_eps: float = 0.0):
         """Returns (contrib_hist [E+1], member_hist [E+1], overlap [E, 3]) as uint64

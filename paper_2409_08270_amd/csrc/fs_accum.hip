@@ -102,15 +102,17 @@ __device__ __forceinline__ void add_global(float *hi, float *lo, int64_t idx, fl
     if (err != 0.0f) unsafeAtomicAdd(lo + idx, err);
 }
 
-// Can any pixel centre of the 8x8 block with corner (bx, by) lie inside the
-// ellipse A dx^2 + 2B dx dy + C dy^2 <= lim around (u, v)? Minimum of the
-// quadratic over the block's pixel-centre box: zero if the mean is inside,
-// else the least edge minimum (clamped parabola vertex). Conservative through
-// the margin folded into lim; used only to skip work, never to decide a weight.
-__device__ __forceinline__ bool block_hit(float u, float v, float A, float B, float C, float bx, float by, float lim)
+// Can any pixel centre of columns [x0, x1] and rows [y0, y1] of the 8x8 block
+// with corner (bx, by) lie inside the ellipse A dx^2 + 2B dx dy + C dy^2 <= lim
+// around (u, v)? Minimum of the quadratic over that box of pixel centres: zero
+// if the mean is inside, else the least edge minimum (clamped parabola vertex).
+// Conservative through the margin folded into lim; used only to skip work,
+// never to decide a weight.
+__device__ __forceinline__ bool block_hit(float u, float v, float A, float B, float C, float bx, float by, float lim,
+                                          float x0, float x1, float y0, float y1)
 {
-    const float xl = bx + 0.5f - u, xh = bx + 7.5f - u;
-    const float yl = by + 0.5f - v, yh = by + 7.5f - v;
+    const float xl = bx + x0 + 0.5f - u, xh = bx + x1 + 0.5f - u;
+    const float yl = by + y0 + 0.5f - v, yh = by + y1 + 0.5f - v;
     if (xl <= 0.0f && xh >= 0.0f && yl <= 0.0f && yh >= 0.0f) return true;
     const float iA = 1.0f / A, iC = 1.0f / C;
     float qmin = 3.4e38f;
@@ -147,6 +149,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(7, 7))) voi
     __shared__ int32_t s_slot_label[kSlots];
     __shared__ uint32_t s_wslots[4];
     __shared__ uint32_t s_misc[5];      // bad labels, longest wave walk, blends, evaluations, walked entries
+    __shared__ int4 s_wbox[4];          // per wave: columns x0..x1, rows y0..y1 of its live pixels
 
     const uint32_t tile = items ? items[blockIdx.x] : blockIdx.x;
     if (tile_done && tile_done[tile]) return;  // every pixel of this tile has finished (whole block)
@@ -232,6 +235,24 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(7, 7))) voi
 
     for (uint32_t base = any_live ? rg.x : rg.y; base < rg.y; base += kBatch) {
         const uint32_t cnt = min((uint32_t)kBatch, rg.y - base);
+        // the box of this wave's live pixels (lane = 8 * row + column): pixels only
+        // ever finish, so entries that cannot reach the box cannot add a weight
+        {
+            const unsigned long long lm = __ballot(live);
+            if (lane == 0) {
+                uint32_t cols = 0;
+                int r0 = 8, r1 = -1;
+                for (int r = 0; r < 8; ++r) {
+                    const uint32_t row = (uint32_t)(lm >> (8 * r)) & 0xFFu;
+                    if (row) {
+                        cols |= row;
+                        r0 = min(r0, r);
+                        r1 = r;
+                    }
+                }
+                s_wbox[w] = cols ? make_int4(__ffs(cols) - 1, 31 - __clz(cols), r0, r1) : make_int4(1, 0, 1, 0);
+            }
+        }
         __syncthreads();  // previous batch fully consumed
         if ((uint32_t)tid < cnt) {
             const uint32_t g = vals[base + tid];
@@ -242,13 +263,20 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(7, 7))) voi
             s_rec[2 * tid + 1] = make_float4(-0.5f * LOG2E * r1.x, lo, P.cut2 + lo, 0.0f);
             s_g[tid] = g;
             uint32_t m = 0xFu;
-            if (r1.w == 0.0f) {  // float32 conic: cull the 8x8 blocks the support cannot reach
+            if (r1.w == 0.0f) {  // float32 conic: cull the waves whose live pixels the support cannot reach
                 m = 0;
 #pragma unroll
                 for (int b = 0; b < 4; ++b) {
                     const float bx = tx0 + (float)((b % bpr) * 8), by = ty0 + (float)((b / bpr) * 8);
-                    if (block_hit(r0.x, r0.y, r0.z, r0.w, r1.x, bx, by, lim)) m |= 1u << b;
+                    const int4 bb = s_wbox[b];
+                    if (bb.x <= bb.y && block_hit(r0.x, r0.y, r0.z, r0.w, r1.x, bx, by, lim, (float)bb.x,
+                                                  (float)bb.y, (float)bb.z, (float)bb.w))
+                        m |= 1u << b;
                 }
+            } else {
+#pragma unroll
+                for (int b = 0; b < 4; ++b)
+                    if (s_wbox[b].x > s_wbox[b].y) m &= ~(1u << b);  // no live pixel left in that wave
             }
             s_wmask[tid] = (uint8_t)m;
         }

@@ -54,6 +54,8 @@ struct fs_ctx {
     uint64_t items_tiles = 0;  // tile count the XCD-run table in `items` was built for
     Staging stage[kStaging];
     int stage_next = 0;
+    hipEvent_t acc_ev[2] = {nullptr, nullptr};  // around the last compositing launch
+    bool acc_timed = false;
     std::string last_error;
 };
 
@@ -424,6 +426,8 @@ int fs_ctx_create(fs_ctx **out, void *stream)
     if (!rc && hipHostMalloc((void **)&ctx->npairs_host, 64, hipHostMallocDefault) != hipSuccess) rc = FS_ERR_ALLOC;
     for (int i = 0; !rc && i < kStaging; ++i)
         if (hipEventCreateWithFlags(&ctx->stage[i].ev, hipEventDisableTiming) != hipSuccess) rc = FS_ERR_HIP;
+    for (int i = 0; !rc && i < 2; ++i)
+        if (hipEventCreate(&ctx->acc_ev[i]) != hipSuccess) rc = FS_ERR_HIP;
     if (!rc && launch_fill_u32(ctx->stream, (uint32_t *)ctx->status_dev, 0u, kStatusWords * 2) != hipSuccess) rc = FS_ERR_HIP;
     if (!rc && launch_fill_u32(ctx->stream, ctx->npairs_dev, 0u, 16) != hipSuccess) rc = FS_ERR_HIP;
     if (!rc && hipStreamSynchronize(ctx->stream) != hipSuccess) rc = FS_ERR_HIP;
@@ -456,6 +460,8 @@ int fs_ctx_destroy(fs_ctx *ctx)
         if (ctx->stage[i].host) (void)hipHostFree(ctx->stage[i].host);
         if (ctx->stage[i].ev) (void)hipEventDestroy(ctx->stage[i].ev);
     }
+    for (int i = 0; i < 2; ++i)
+        if (ctx->acc_ev[i]) (void)hipEventDestroy(ctx->acc_ev[i]);
     if (ctx->status_dev) (void)hipFree(ctx->status_dev);
     if (ctx->npairs_dev) (void)hipFree(ctx->npairs_dev);
     if (ctx->status_host) (void)hipHostFree(ctx->status_host);
@@ -647,10 +653,26 @@ int fs_accumulate(fs_ctx *ctx, const fs_proj *proj, const fs_bins *bins, const f
         RCHECK(build_xcd_items(ctx, pl.tiles));
         items = (const uint32_t *)ctx->items.p;
     }
+    // events around the compositing launch alone (not under stream capture)
+    hipStreamCaptureStatus cap = hipStreamCaptureStatusNone;
+    HIPCHECK(ctx, hipStreamIsCapturing(ctx->stream, &cap));
+    const bool timed = cap == hipStreamCaptureStatusNone;
+    if (timed) HIPCHECK(ctx, hipEventRecord(ctx->acc_ev[0], ctx->stream));
     HIPCHECK(ctx, launch_accumulate(ctx->stream, proj->rec, bins->vals, bins->ranges, (const ViewDev *)ctx->views.p, V,
                                     (const SceneDev *)ctx->scenes.p, items, (uint32_t)pl.tiles, acc_params(p, reduction),
                                     pix ? pix->t_final : nullptr, pix ? pix->n_blend : nullptr, nullptr, nullptr, 1,
                                     ctx->status_dev));
+    if (timed) HIPCHECK(ctx, hipEventRecord(ctx->acc_ev[1], ctx->stream));
+    ctx->acc_timed = timed;
+    return FS_OK;
+}
+
+int fs_last_accumulate_ms(fs_ctx *ctx, float *ms)
+{
+    if (!ctx || !ms) return FS_ERR_ARG;
+    if (!ctx->acc_timed) return set_err(ctx, FS_ERR_ARG, "no timed compositing launch on this context");
+    HIPCHECK(ctx, hipEventSynchronize(ctx->acc_ev[1]));
+    HIPCHECK(ctx, hipEventElapsedTime(ms, ctx->acc_ev[0], ctx->acc_ev[1]));
     return FS_OK;
 }
 

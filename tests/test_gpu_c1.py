@@ -136,3 +136,14 @@ def test_chunked_equals_per_view(c1):
     a8 = (s8["A_hi"].double() + s8["A_lo"].double()).cpu().numpy()
     assert np.allclose(a1, a8, rtol=1e-6, atol=1e-9)
     assert torch.equal(s1["S"], s8["S"]) or (s1["S"] != s8["S"]).sum().item() <= 2
+
+
+def test_last_accumulate_ms_times_the_compositing_launch():
+    ctx = L.Context()
+    with pytest.raises(RuntimeError):
+        ctx.fs_last_accumulate_ms()          # nothing timed yet
+    sc = sg.make_config("C1")
+    ds = L.DeviceScene(sc)
+    Solver(ctx, ds).solve(chunk=sc.n_views)
+    ms = ctx.fs_last_accumulate_ms()
+    assert 0.0 < ms < 1000.0
