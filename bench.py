@@ -78,7 +78,7 @@ def main():
         copy_probe(args.copy_probe)
         return
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
-        print(json.dumps({"error": "this build runs on exactly one GPU; multi-GPU runs are not supported "
+        print(json.dumps({"error": "this program runs on exactly one GPU; multi-GPU runs are not supported "
                                    "(views would shard across GPUs with one reduce-scatter of A)"}))
         sys.exit(2)
     import numpy as np

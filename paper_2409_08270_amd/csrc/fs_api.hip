@@ -297,6 +297,8 @@ void plan_add(Plan &pl, const fs_params *p, uint32_t scene, int64_t n, const fs_
         sg.off = pl.elems;
         sg.len = (uint32_t)n;
         sg.blk0 = pl.dblocks;
+        sg.alen = (uint32_t)n;
+        sg.kbase = 0;
         pl.dsegs.push_back(sg);
         pl.dblocks += (uint32_t)((n + kSortTile - 1) / kSortTile);
         pl.elems += (uint64_t)n;
@@ -593,7 +595,7 @@ int fs_bin_sort(fs_ctx *ctx, const fs_proj *proj, const fs_camera *cams, const f
     const int32_t ptpb = radix_tiles_per_block((uint64_t)sort_len);
     const uint32_t pblocks = (uint32_t)((sort_len + (int64_t)kSortTile * ptpb - 1) / ((int64_t)kSortTile * ptpb));
     RCHECK(ensure(ctx, ctx->sort_ws, radix_ws_bytes(pblocks)));
-    std::vector<SegDev> ps{SegDev{0, (uint32_t)sort_len, 0}};
+    std::vector<SegDev> ps{SegDev{0, (uint32_t)sort_len, 0, (uint32_t)sort_len, 0}};
     RCHECK(upload_vec(ctx, ctx->psegs, ps));
     uint32_t *k0, *v0, *k1, *v1;
     if (passes % 2 == 0) {
@@ -642,7 +644,7 @@ int fs_accumulate(fs_ctx *ctx, const fs_proj *proj, const fs_bins *bins, const f
         RCHECK(ensure(ctx, ctx->items_k2, tb));
         RCHECK(ensure(ctx, ctx->items_v2, tb));
         RCHECK(ensure(ctx, ctx->items_ws, radix_ws_bytes(lblocks)));
-        std::vector<SegDev> ls{SegDev{0, (uint32_t)pl.tiles, 0}};
+        std::vector<SegDev> ls{SegDev{0, (uint32_t)pl.tiles, 0, (uint32_t)pl.tiles, 0}};
         RCHECK(upload_vec(ctx, ctx->lsegs, ls));
         ctx->items_tiles = 0;  // the XCD-run table (tile_order 2) shares the buffer
         RCHECK(enqueue_lpt(ctx, ctx->stream, bins->ranges, pl.tiles, (const SegDev *)ctx->lsegs.p,
@@ -891,6 +893,11 @@ struct Chunk {
     uint32_t pair_cap = 0;    // slots used by this chunk
     uint32_t pblocks = 0;
     int32_t ptpb = 1;         // block tiles per block of the pair sort
+    std::vector<uint64_t> vpairs;  // planned pairs of each view
+    // packed pair sort: one u32 item (tile in view << gbits | Gaussian) per pair,
+    // one sort segment per view; used when both fit in 32 bits (single pass)
+    bool packed = false;
+    int32_t gbits = 0, tbits = 0;
     uint32_t lblocks = 0;
     int passes = 0;
     DevBuf views, tasks, dsegs, psegs, lsegs;
@@ -1021,18 +1028,30 @@ int enqueue_slabs(fs_batch *b, Chunk &c, int chunk_idx, hipStream_t s)
                                          b->p.tile_w, b->p.tile_h, b->p.sigma_k, (uint32_t *)b->counts.p));
         HIPCHECK(ctx, scan_exclusive(s, (const uint32_t *)b->counts.p, (uint32_t *)b->offsets.p, total, np,
                                      b->scan_ws.p));
-        HIPCHECK(ctx, launch_emit(s, dk, dv, (const uint32_t *)b->offsets.p, (const uint32_t *)b->counts.p,
-                                  (const float *)b->rec.p, (const int16_t *)b->rect.p,
-                                  b->p.fp64_conic ? nullptr : (const uint8_t *)b->flags.p,
-                                  (const ViewDev *)c.views.p, V, total, c.pair_cap, b->p.tile_w, b->p.tile_h,
-                                  b->p.sigma_k, k > 0 ? done : nullptr, k0, v0, ctx->status_dev));
+        const uint8_t *fl = b->p.fp64_conic ? nullptr : (const uint8_t *)b->flags.p;
         // tile lists: the sort's last pass counts the pairs of every tile (and
         // skips writing the sorted tile ids, which nothing reads), then the
         // ranges are the exclusive scan of those counts
         uint32_t *tcount = (uint32_t *)b->items_k.p, *tstart = (uint32_t *)b->items_k2.p;
         HIPCHECK(ctx, launch_fill_u32(s, tcount, 0u, (int64_t)pl.tiles));
-        HIPCHECK(ctx, radix_sort(s, k0, v0, k1, v1, (const SegDev *)c.psegs.p, 1, c.pblocks, c.passes * 8,
-                                 b->sort_ws.p, np, c.ptpb, tcount, false));
+        if (c.packed) {
+            // one u32 item per pair, sorted per view by its tile bits only
+            HIPCHECK(ctx, launch_emit(s, dk, dv, (const uint32_t *)b->offsets.p, (const uint32_t *)b->counts.p,
+                                      (const float *)b->rec.p, (const int16_t *)b->rect.p, fl,
+                                      (const ViewDev *)c.views.p, V, total, c.pair_cap, b->p.tile_w, b->p.tile_h,
+                                      b->p.sigma_k, nullptr, pt, nullptr, ctx->status_dev, c.gbits));
+            HIPCHECK(ctx, launch_pair_segs(s, (const uint32_t *)b->offsets.p, (const ViewDev *)c.views.p, V, total, np,
+                                           c.pair_cap, (SegDev *)c.psegs.p, ctx->status_dev));
+            HIPCHECK(ctx, radix_sort_packed(s, pt, pta, pv, (const SegDev *)c.psegs.p, V, c.pblocks, c.gbits, c.tbits,
+                                            b->sort_ws.p, c.ptpb, tcount));
+        } else {
+            HIPCHECK(ctx, launch_emit(s, dk, dv, (const uint32_t *)b->offsets.p, (const uint32_t *)b->counts.p,
+                                      (const float *)b->rec.p, (const int16_t *)b->rect.p, fl,
+                                      (const ViewDev *)c.views.p, V, total, c.pair_cap, b->p.tile_w, b->p.tile_h,
+                                      b->p.sigma_k, k > 0 ? done : nullptr, k0, v0, ctx->status_dev));
+            HIPCHECK(ctx, radix_sort(s, k0, v0, k1, v1, (const SegDev *)c.psegs.p, 1, c.pblocks, c.passes * 8,
+                                     b->sort_ws.p, np, c.ptpb, tcount, false));
+        }
         HIPCHECK(ctx, scan_exclusive(s, tcount, tstart, (int64_t)pl.tiles, nullptr, b->tscan_ws.p));
         HIPCHECK(ctx, launch_count_ranges(s, tcount, tstart, (int64_t)pl.tiles, (uint32_t *)b->ranges.p));
         const uint32_t *items = nullptr;
@@ -1226,7 +1245,10 @@ int batch_build(fs_batch *b, const fs_scene *scenes, int32_t n_scenes)
     size_t k = 0;
     for (Chunk &c : b->chunks) {
         chunk_plan(b, c);
-        for (size_t j = 0; j < c.refs.size(); ++j) c.pairs += (uint64_t)vpairs[k + j];
+        for (size_t j = 0; j < c.refs.size(); ++j) {
+            c.pairs += (uint64_t)vpairs[k + j];
+            c.vpairs.push_back((uint64_t)vpairs[k + j]);
+        }
         for (int q = 0; q < S; ++q) {
             uint64_t sum = 0;
             for (size_t j = 0; j < c.refs.size(); ++j) sum += (uint64_t)vslab[(k + j) * S + q];
@@ -1248,6 +1270,32 @@ int batch_build(fs_batch *b, const fs_scene *scenes, int32_t n_scenes)
         c.pair_cap = (uint32_t)std::min<uint64_t>(cap, c.slab_max + c.slab_max / 64 + 4096);
         c.ptpb = radix_tiles_per_block(c.pair_cap);
         c.pblocks = (uint32_t)(((uint64_t)c.pair_cap + (uint64_t)kSortTile * c.ptpb - 1) / ((uint64_t)kSortTile * c.ptpb));
+        std::vector<SegDev> ps{SegDev{0, c.pair_cap, 0, c.pair_cap, 0}};
+        {
+            uint64_t max_n = 1, max_tv = 1;
+            for (const ViewDev &vd : c.plan.views) {
+                max_n = std::max<uint64_t>(max_n, vd.n);
+                max_tv = std::max<uint64_t>(max_tv, (uint64_t)vd.tiles_x * (uint64_t)vd.tiles_y);
+            }
+            c.gbits = bits_for(max_n);
+            c.tbits = bits_for(max_tv);
+            c.packed = S == 1 && c.tbits <= 16 && c.gbits + c.tbits <= 32 && c.vpairs.size() == c.plan.views.size();
+            if (c.packed) {
+                // per-view capacities (planned count plus slack) and blocks
+                uint64_t sum = 0;
+                for (uint64_t vp : c.vpairs) sum += vp + vp / 64 + 256;
+                c.ptpb = radix_tiles_per_block(sum);
+                const uint64_t span = (uint64_t)kSortTile * c.ptpb;
+                ps.clear();
+                uint32_t blk = 0;
+                for (size_t j = 0; j < c.vpairs.size(); ++j) {
+                    const uint64_t capj = std::min<uint64_t>(c.vpairs[j] + c.vpairs[j] / 64 + 256, c.pair_cap);
+                    ps.push_back(SegDev{0, (uint32_t)capj, blk, 0, c.plan.views[j].tile_base});
+                    blk += (uint32_t)std::max<uint64_t>(1, (capj + span - 1) / span);
+                }
+                c.pblocks = blk;
+            }
+        }
         c.lblocks = (uint32_t)((c.plan.tiles + kSortTile - 1) / kSortTile);
         c.passes = (bits_for(std::max<uint64_t>(c.plan.tiles, 2)) + 7) / 8;
         b->max_pblocks = std::max(b->max_pblocks, c.pblocks);
@@ -1255,9 +1303,8 @@ int batch_build(fs_batch *b, const fs_scene *scenes, int32_t n_scenes)
         RCHECK(upload_vec(ctx, c.views, c.plan.views));
         RCHECK(upload_vec(ctx, c.tasks, c.plan.tasks));
         RCHECK(upload_vec(ctx, c.dsegs, c.plan.dsegs));
-        std::vector<SegDev> ps{SegDev{0, c.pair_cap, 0}};
         RCHECK(upload_vec(ctx, c.psegs, ps));
-        std::vector<SegDev> ls{SegDev{0, (uint32_t)c.plan.tiles, 0}};
+        std::vector<SegDev> ls{SegDev{0, (uint32_t)c.plan.tiles, 0, (uint32_t)c.plan.tiles, 0}};
         RCHECK(upload_vec(ctx, c.lsegs, ls));
         for (DevBuf *d : {&c.views, &c.tasks, &c.dsegs, &c.psegs, &c.lsegs}) b->ws_bytes += (int64_t)d->cap;
     }

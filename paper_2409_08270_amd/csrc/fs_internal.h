@@ -54,10 +54,15 @@ struct ProjTask {
 };
 
 // radix-sort segment: elements [off, off + len), block tiles from blk0
+// A segment of a radix sort: items [off, off + min(len, alen)); `len` (the
+// planned capacity) fixes the segment's blocks, `alen` the items present.
+// kbase is added to the key's count index (packed pair sort).
 struct SegDev {
     uint64_t off;
     uint32_t len;
     uint32_t blk0;
+    uint32_t alen;
+    uint32_t kbase;
 };
 
 struct ProjParams {
@@ -133,6 +138,23 @@ hipError_t radix_sort(hipStream_t s, uint32_t *keys, uint32_t *vals, uint32_t *k
 // block tiles per block for a single-segment sort of n_items
 int32_t radix_tiles_per_block(uint64_t n_items);
 
+// Packed pair sort: items = (local tile << gbits) | Gaussian id, one segment
+// per view (segs[j].kbase = the view's first tile id). Stable sort by the
+// tbits tile bits (one or two passes); the last pass writes the Gaussian ids
+// to ids_out and adds every tile's item count to key_count[kbase + tile]
+// (zeroed by the caller). items_alt: scratch of the same size; ws as in
+// radix_sort.
+hipError_t radix_sort_packed(hipStream_t s, uint32_t *items, uint32_t *items_alt, uint32_t *ids_out,
+                             const SegDev *segs, int32_t n_segs, uint32_t n_blocks, int32_t gbits, int32_t tbits,
+                             void *ws, int32_t tpb, uint32_t *key_count);
+
+// Per-view segments of the pairs emitted this run: segs[j].off/alen from the
+// device offsets (pairs beyond the planned capacity segs[j].len, or beyond
+// `capacity`, are dropped and latched); len, blk0 and kbase stay as planned.
+hipError_t launch_pair_segs(hipStream_t s, const uint32_t *offsets, const ViewDev *views, int32_t n_views,
+                            int64_t total_elems, const uint32_t *total_pairs, uint32_t capacity, SegDev *segs,
+                            unsigned long long *status);
+
 // Exclusive scan of u32 -> u32 (device-wide), total written to *total_out.
 size_t scan_ws_bytes(int64_t n);
 hipError_t scan_exclusive(hipStream_t s, const uint32_t *in, uint32_t *out, int64_t n, uint32_t *total_out, void *ws);
@@ -161,12 +183,14 @@ hipError_t launch_slab_counts(hipStream_t s, const uint32_t *sorted_keys, const 
 // (the row_span rule) at offsets[i]; pairs at or beyond `capacity` are
 // dropped and latched
 // (tiles marked in `done`, if not NULL, are skipped, as in launch_slab_counts;
-// `flags` may be NULL as there)
+// `flags` may be NULL as there). With gbits > 0 each pair is one packed item
+// (tile index within its view << gbits) | Gaussian id in tiles_out, and
+// vals_out is not used.
 hipError_t launch_emit(hipStream_t s, const uint32_t *sorted_keys, const uint32_t *sorted_vals,
                        const uint32_t *offsets, const uint32_t *counts, const float *rec, const int16_t *rect,
                        const uint8_t *flags, const ViewDev *views, int32_t n_views, int64_t total,
                        uint32_t capacity, int32_t tile_w, int32_t tile_h, float sigma_k, const uint8_t *done,
-                       uint32_t *tiles_out, uint32_t *vals_out, unsigned long long *status);
+                       uint32_t *tiles_out, uint32_t *vals_out, unsigned long long *status, int32_t gbits = 0);
 
 // ranges[t] = [starts[t], starts[t] + counts[t]), or [0, 0) if counts[t] == 0
 hipError_t launch_count_ranges(hipStream_t s, const uint32_t *counts, const uint32_t *starts, int64_t n_tiles,

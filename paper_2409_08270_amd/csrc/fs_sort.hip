@@ -114,6 +114,7 @@ struct SegInfo {
     uint32_t bps;     // super-tiles of the segment
     uint32_t lb;      // super-tile index inside the segment
     uint32_t blk0;
+    uint32_t kbase;   // added to count indexes
 };
 
 __device__ __forceinline__ SegInfo seg_of_block(const SegDev *__restrict__ segs, int32_t n_segs, uint32_t b,
@@ -130,24 +131,27 @@ __device__ __forceinline__ SegInfo seg_of_block(const SegDev *__restrict__ segs,
     r.blk0 = sg.blk0;
     r.lb = b - sg.blk0;
     r.bps = (uint32_t)(((int64_t)sg.len + span - 1) / span);
-    uint32_t len = sg.len;
+    uint32_t len = min(sg.len, sg.alen);
     if (len_dev) len = min(len, *len_dev);
+    r.kbase = sg.kbase;
     const int64_t rem = (int64_t)len - (int64_t)r.lb * span;
     r.nvalid = rem <= 0 ? 0 : (rem < span ? (int)rem : (int)span);
     r.base = (int64_t)sg.off + (int64_t)r.lb * span;
     return r;
 }
 
-// Digit histogram of one super-tile. Each thread reads 16 consecutive keys per
-// block tile and adds runs of equal digits with one LDS atomic per run: keys
-// emitted per Gaussian in tile order repeat their high digit, which would
-// otherwise serialise the atomics. Counts are stored [segment][digit][block]
-// so that one exclusive scan over the whole table gives every block's output
-// positions.
+// Digit histogram of one super-tile. Each thread reads 4 groups of 4
+// consecutive keys per block tile (16-byte loads, consecutive lanes on
+// consecutive addresses) and adds runs of equal digits with one LDS atomic per
+// run: keys emitted per Gaussian in tile order repeat their high digit, which
+// would otherwise serialise the atomics. Counts are stored
+// [segment][digit][block] so that one exclusive scan over the whole table
+// gives every block's output positions.
 __global__ __launch_bounds__(kThreads) void k_radix_hist(const uint32_t *__restrict__ keys,
                                                          const SegDev *__restrict__ segs, int32_t n_segs,
                                                          int32_t shift, uint32_t *__restrict__ hist,
-                                                         const uint32_t *__restrict__ len_dev, int32_t tpb)
+                                                         const uint32_t *__restrict__ len_dev, int32_t tpb,
+                                                         uint32_t dmask)
 {
     __shared__ uint32_t s_h[kWaves][256];
     const SegInfo si = seg_of_block(segs, n_segs, blockIdx.x, len_dev, tpb);
@@ -157,20 +161,19 @@ __global__ __launch_bounds__(kThreads) void k_radix_hist(const uint32_t *__restr
     uint32_t run_d = 0xFFFFFFFFu, run_n = 0;
     for (int tb = 0; tb * kTile < si.nvalid; ++tb) {
         const int nvalid = min(kTile, si.nvalid - tb * kTile);
-        const int t0 = threadIdx.x * kItems;
         const uint32_t *k = keys + si.base + (int64_t)tb * kTile;
-        if (t0 + kItems <= nvalid) {
-            const uint4 *k4 = reinterpret_cast<const uint4 *>(k + t0);
-            const bool aligned = ((reinterpret_cast<uintptr_t>(k + t0) & 15u) == 0);
+        if (nvalid == kTile) {
+            const bool aligned = ((reinterpret_cast<uintptr_t>(k) & 15u) == 0);
 #pragma unroll
             for (int q = 0; q < kItems / 4; ++q) {
+                const int i0 = 4 * (q * kThreads + threadIdx.x);
                 uint4 x;
-                if (aligned) x = k4[q];
-                else x = make_uint4(k[t0 + 4 * q], k[t0 + 4 * q + 1], k[t0 + 4 * q + 2], k[t0 + 4 * q + 3]);
+                if (aligned) x = *reinterpret_cast<const uint4 *>(k + i0);
+                else x = make_uint4(k[i0], k[i0 + 1], k[i0 + 2], k[i0 + 3]);
                 const uint32_t xs[4] = {x.x, x.y, x.z, x.w};
 #pragma unroll
                 for (int e = 0; e < 4; ++e) {
-                    const uint32_t d = (xs[e] >> shift) & 255u;
+                    const uint32_t d = (xs[e] >> shift) & dmask;
                     if (d != run_d) {
                         if (run_n) atomicAdd(&s_h[w][run_d], run_n);
                         run_d = d;
@@ -181,9 +184,9 @@ __global__ __launch_bounds__(kThreads) void k_radix_hist(const uint32_t *__restr
             }
         } else {
             for (int it = 0; it < kItems; ++it) {
-                const int i = t0 + it;
+                const int i = it * kThreads + threadIdx.x;
                 if (i >= nvalid) break;
-                const uint32_t d = (k[i] >> shift) & 255u;
+                const uint32_t d = (k[i] >> shift) & dmask;
                 if (d != run_d) {
                     if (run_n) atomicAdd(&s_h[w][run_d], run_n);
                     run_d = d;
@@ -206,16 +209,19 @@ __global__ __launch_bounds__(kThreads) void k_radix_hist(const uint32_t *__restr
 // the contiguous items [w*1024, (w+1)*1024) of the block tile in 16 rounds of
 // 64, equal digits matched with 8 ballots; each digit's output cursor then
 // advances by the block tile's count of that digit.
-// On the last pass the staged block tile is ordered by the whole key, so runs
-// of equal keys are contiguous in LDS: with key_count, each run adds its
-// length to its key's count (+end at its last item, -start at its first, which
-// sums to the length whatever the order of the atomics); kout may be NULL.
+// On the last pass the staged block tile is ordered by the sorted key bits,
+// so runs of equal keys (k >> kshift) are contiguous in LDS: with key_count,
+// each run adds its length to count[kbase + (k >> kshift)] (+end at its last
+// item, -start at its first, which sums to the length whatever the order of
+// the atomics). kout and vout may be NULL; without vin (keys only), vout
+// receives k & vmask.
 __global__ __launch_bounds__(kThreads) void k_radix_scatter(const uint32_t *__restrict__ kin, const uint32_t *__restrict__ vin,
                                                             uint32_t *__restrict__ kout, uint32_t *__restrict__ vout,
                                                             const SegDev *__restrict__ segs, int32_t n_segs,
                                                             int32_t shift, const uint32_t *__restrict__ offs,
                                                             const uint32_t *__restrict__ len_dev, int32_t tpb,
-                                                            uint32_t *__restrict__ key_count)
+                                                            uint32_t *__restrict__ key_count, uint32_t dmask,
+                                                            int32_t kshift, uint32_t vmask)
 {
     __shared__ uint32_t s_cnt[kWaves][256];
     __shared__ uint32_t s_dstart[256];
@@ -234,7 +240,7 @@ __global__ __launch_bounds__(kThreads) void k_radix_scatter(const uint32_t *__re
     for (int tb = 0; tb * kTile < si.nvalid; ++tb) {
         const int nvalid = min(kTile, si.nvalid - tb * kTile);
         const uint32_t *kbase = kin + si.base + (int64_t)tb * kTile;
-        const uint32_t *vbase = vin + si.base + (int64_t)tb * kTile;
+        const uint32_t *vbase = vin ? vin + si.base + (int64_t)tb * kTile : nullptr;
         for (int i = threadIdx.x; i < kWaves * 256; i += kThreads) (&s_cnt[0][0])[i] = 0;
         __syncthreads();
 
@@ -244,11 +250,11 @@ __global__ __launch_bounds__(kThreads) void k_radix_scatter(const uint32_t *__re
             const int li = w * (kItems * 64) + r * 64 + lane;
             const bool ok = li < nvalid;
             key[r] = ok ? kbase[li] : 0xFFFFFFFFu;
-            val[r] = ok ? vbase[li] : 0u;
+            val[r] = (ok && vbase) ? vbase[li] : 0u;
         }
 #pragma unroll
         for (int r = 0; r < kItems; ++r) {
-            const uint32_t d = (key[r] >> shift) & 255u;
+            const uint32_t d = (key[r] >> shift) & dmask;
             unsigned long long peers = ~0ull;
 #pragma unroll
             for (int bit = 0; bit < 8; ++bit) {
@@ -282,7 +288,7 @@ __global__ __launch_bounds__(kThreads) void k_radix_scatter(const uint32_t *__re
         __syncthreads();
 #pragma unroll
         for (int r = 0; r < kItems; ++r) {
-            const uint32_t d = (key[r] >> shift) & 255u;
+            const uint32_t d = (key[r] >> shift) & dmask;
             const uint32_t pos = s_dstart[d] + s_cnt[w][d] + rnk[r];
             s_k[pos] = key[r];
             s_v[pos] = val[r];
@@ -290,13 +296,15 @@ __global__ __launch_bounds__(kThreads) void k_radix_scatter(const uint32_t *__re
         __syncthreads();
         for (int i = threadIdx.x; i < nvalid; i += kThreads) {
             const uint32_t k = s_k[i];
-            const uint32_t d = (k >> shift) & 255u;
+            const uint32_t d = (k >> shift) & dmask;
             const int64_t p = (int64_t)s_gofs[d] + (i - (int64_t)s_dstart[d]);
             if (kout) kout[p] = k;
-            vout[p] = s_v[i];
+            if (vout) vout[p] = vin ? s_v[i] : (k & vmask);
             if (key_count) {
-                if (i + 1 == nvalid || s_k[i + 1] != k) atomicAdd(&key_count[k], (uint32_t)(i + 1));
-                if (i > 0 && s_k[i - 1] != k) atomicSub(&key_count[k], (uint32_t)i);
+                const uint32_t kk = k >> kshift;
+                uint32_t *cnt = key_count + si.kbase + kk;
+                if (i + 1 == nvalid || (s_k[i + 1] >> kshift) != kk) atomicAdd(cnt, (uint32_t)(i + 1));
+                if (i > 0 && (s_k[i - 1] >> kshift) != kk) atomicSub(cnt, (uint32_t)i);
             }
         }
         __syncthreads();
@@ -389,7 +397,8 @@ __global__ __launch_bounds__(kThreads) void k_emit(const uint32_t *__restrict__ 
                                                    int32_t n_views, int64_t total, uint32_t capacity, int32_t tw, int32_t th,
                                                    float sigma_k, const uint8_t *__restrict__ done,
                                                    uint32_t *__restrict__ tiles_out,
-                                                   uint32_t *__restrict__ vals_out, unsigned long long *__restrict__ status)
+                                                   uint32_t *__restrict__ vals_out, unsigned long long *__restrict__ status,
+                                                   int32_t gbits)
 {
     __shared__ uint32_t s_t[kEmitWin];
     __shared__ uint32_t s_g[kEmitWin];
@@ -435,13 +444,14 @@ __global__ __launch_bounds__(kThreads) void k_emit(const uint32_t *__restrict__ 
                 int l, r;
                 if (!row_span(sp, ty, rc.x, rc.z, tw, th, W, H, l, r)) continue;
                 const uint32_t rowbase = tbase + (uint32_t)ty * tiles_x;
+                const uint32_t outbase = gbits ? rowbase - tbase : rowbase;  // packed: the view's local tile
                 if (done == nullptr) {
                     const uint32_t n_row = (uint32_t)(r - l + 1);
                     if (p + n_row > w0) {
                         const uint32_t a = p < w0 ? w0 - p : 0u;
                         const uint32_t b = min(n_row, wend - p);
                         for (uint32_t e = a; e < b; ++e) {
-                            s_t[p + e - w0] = rowbase + (uint32_t)l + e;
+                            s_t[p + e - w0] = outbase + (uint32_t)l + e;
                             s_g[p + e - w0] = g;
                         }
                     }
@@ -450,7 +460,7 @@ __global__ __launch_bounds__(kThreads) void k_emit(const uint32_t *__restrict__ 
                     for (int t = l; t <= r && p < wend; ++t) {
                         if (done[rowbase + (uint32_t)t]) continue;
                         if (p >= w0) {
-                            s_t[p - w0] = rowbase + (uint32_t)t;
+                            s_t[p - w0] = outbase + (uint32_t)t;
                             s_g[p - w0] = g;
                         }
                         ++p;
@@ -462,8 +472,12 @@ __global__ __launch_bounds__(kThreads) void k_emit(const uint32_t *__restrict__ 
         for (uint32_t q = threadIdx.x; q < wend - w0; q += kThreads) {
             const uint32_t p = w0 + q;
             if (p < capacity) {
-                tiles_out[p] = s_t[q];
-                vals_out[p] = s_g[q];
+                if (gbits) {
+                    tiles_out[p] = (s_t[q] << gbits) | s_g[q];
+                } else {
+                    tiles_out[p] = s_t[q];
+                    vals_out[p] = s_g[q];
+                }
             } else {
                 dropped++;
             }
@@ -546,6 +560,29 @@ __global__ void k_slab_offsets(const uint32_t *__restrict__ offsets, const ViewD
     out[i] = e < total_elems ? offsets[e] : *total_pairs;
 }
 
+// Segments of the packed pair sort, one per view (see launch_pair_segs).
+__global__ void k_pair_segs(const uint32_t *__restrict__ offsets, const ViewDev *__restrict__ views, int32_t n_views,
+                            int64_t total_elems, const uint32_t *__restrict__ total_pairs, uint32_t capacity,
+                            SegDev *__restrict__ segs, unsigned long long *__restrict__ status)
+{
+    const int j = blockIdx.x * blockDim.x + threadIdx.x;
+    if (j >= n_views) return;
+    const uint32_t np = min(*total_pairs, capacity);
+    const int64_t e0 = (int64_t)views[j].elem_off;
+    const int64_t e1 = j + 1 < n_views ? (int64_t)views[j + 1].elem_off : total_elems;
+    const uint32_t a = min(e0 < total_elems ? offsets[e0] : *total_pairs, np);
+    const uint32_t b = min(e1 < total_elems ? offsets[e1] : *total_pairs, np);
+    const uint32_t have = b > a ? b - a : 0u;
+    SegDev sg = segs[j];
+    sg.off = a;
+    sg.alen = min(have, sg.len);
+    if (have > sg.len) {
+        status_add(status, ST_DROPPED, (unsigned long long)(have - sg.len));
+        status_flag(status, (unsigned long long)FS_DEV_PAIR_OVERFLOW);
+    }
+    segs[j] = sg;
+}
+
 inline unsigned grid_for(int64_t n, int threads) { return (unsigned)((n + threads - 1) / threads); }
 
 }  // namespace
@@ -612,17 +649,53 @@ hipError_t radix_sort(hipStream_t s, uint32_t *keys, uint32_t *vals, uint32_t *k
     uint32_t *ki = keys, *vi = vals, *ko = keys_alt, *vo = vals_alt;
     for (int shift = 0; shift < bits; shift += 8) {
         hipLaunchKernelGGL(k_radix_hist, dim3(n_blocks), dim3(kThreads), 0, s, ki, segs, n_segs, shift, hist, len_dev,
-                           tpb);
+                           tpb, 255u);
         hipError_t e = scan_exclusive(s, hist, offs, hist_n, nullptr, scan_ws);
         if (e != hipSuccess) return e;
         const bool last = shift + 8 >= bits;
         hipLaunchKernelGGL(k_radix_scatter, dim3(n_blocks), dim3(kThreads), 0, s, ki, vi,
                            (last && !last_keys) ? nullptr : ko, vo, segs, n_segs, shift, (const uint32_t *)offs,
-                           len_dev, tpb, last ? key_count : nullptr);
+                           len_dev, tpb, last ? key_count : nullptr, 255u, 0, 0u);
         e = hipGetLastError();
         if (e != hipSuccess) return e;
         uint32_t *tk = ki, *tv = vi;
         ki = ko; vi = vo; ko = tk; vo = tv;
+    }
+    return hipSuccess;
+}
+
+hipError_t radix_sort_packed(hipStream_t s, uint32_t *items, uint32_t *items_alt, uint32_t *ids_out,
+                             const SegDev *segs, int32_t n_segs, uint32_t n_blocks, int32_t gbits, int32_t tbits,
+                             void *ws, int32_t tpb, uint32_t *key_count)
+{
+    if (n_blocks == 0 || n_segs == 0) return hipSuccess;
+    if (tpb < 1 || gbits < 1 || tbits < 1 || tbits > 16 || gbits + tbits > 32) return hipErrorInvalidValue;
+    const int64_t hist_n = (int64_t)n_blocks * 256;
+    uint32_t *hist = (uint32_t *)ws;
+    uint32_t *offs = hist + hist_n;
+    void *scan_ws = offs + hist_n;
+    // one pass up to 8 tile bits, else two passes of (nearly) equal width:
+    // fewer buckets per pass keep the scattered runs long
+    const int passes = tbits <= 8 ? 1 : 2;
+    const int d0 = passes == 1 ? tbits : (tbits + 1) / 2;
+    const uint32_t vmask = gbits == 32 ? 0xFFFFFFFFu : ((1u << gbits) - 1u);
+    const uint32_t *ki = items;
+    for (int p = 0; p < passes; ++p) {
+        const int shift = gbits + (p == 0 ? 0 : d0);
+        const int bits = p == 0 ? d0 : tbits - d0;
+        const uint32_t dmask = (1u << bits) - 1u;
+        const bool last = p + 1 == passes;
+        hipLaunchKernelGGL(k_radix_hist, dim3(n_blocks), dim3(kThreads), 0, s, ki, segs, n_segs, shift, hist,
+                           (const uint32_t *)nullptr, tpb, dmask);
+        hipError_t e = scan_exclusive(s, hist, offs, hist_n, nullptr, scan_ws);
+        if (e != hipSuccess) return e;
+        hipLaunchKernelGGL(k_radix_scatter, dim3(n_blocks), dim3(kThreads), 0, s, ki, (const uint32_t *)nullptr,
+                           last ? nullptr : items_alt, last ? ids_out : nullptr, segs, n_segs, shift,
+                           (const uint32_t *)offs, (const uint32_t *)nullptr, tpb, last ? key_count : nullptr, dmask,
+                           gbits, vmask);
+        e = hipGetLastError();
+        if (e != hipSuccess) return e;
+        ki = items_alt;
     }
     return hipSuccess;
 }
@@ -660,12 +733,23 @@ hipError_t launch_emit(hipStream_t s, const uint32_t *sorted_keys, const uint32_
                        const uint8_t *flags, const ViewDev *views, int32_t n_views, int64_t total,
                        uint32_t capacity, int32_t tile_w, int32_t tile_h, float sigma_k, const uint8_t *done,
                        uint32_t *tiles_out,
-                       uint32_t *vals_out, unsigned long long *status)
+                       uint32_t *vals_out, unsigned long long *status, int32_t gbits)
 {
     if (total == 0) return hipSuccess;
     hipLaunchKernelGGL(k_emit, dim3(grid_for(total, kThreads)), dim3(kThreads), 0, s, sorted_keys, sorted_vals, offsets,
                        counts, reinterpret_cast<const float4 *>(rec), reinterpret_cast<const short4 *>(rect), flags,
-                       views, n_views, total, capacity, tile_w, tile_h, sigma_k, done, tiles_out, vals_out, status);
+                       views, n_views, total, capacity, tile_w, tile_h, sigma_k, done, tiles_out, vals_out, status,
+                       gbits);
+    return hipGetLastError();
+}
+
+hipError_t launch_pair_segs(hipStream_t s, const uint32_t *offsets, const ViewDev *views, int32_t n_views,
+                            int64_t total_elems, const uint32_t *total_pairs, uint32_t capacity, SegDev *segs,
+                            unsigned long long *status)
+{
+    if (n_views <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_pair_segs, dim3(grid_for(n_views, 256)), dim3(256), 0, s, offsets, views, n_views,
+                       total_elems, total_pairs, capacity, segs, status);
     return hipGetLastError();
 }
 
