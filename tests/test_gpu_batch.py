@@ -219,3 +219,37 @@ def test_uncounted_batch_gives_the_same_result(ctx):
         assert np.array_equal(S0[i], S1[i])
     with pytest.raises(RuntimeError):
         L.Batch(ctx, dss, L.params(count_ops=2))
+
+
+@pytest.mark.parametrize("slabs", [1, 2])
+def test_grown_inputs_overflow_is_latched(ctx, slabs):
+    # The plan (pair capacities, per-view sort segments) is exact for the inputs
+    # at creation. Scaling the Gaussians up afterwards makes every view need more
+    # pairs: the excess must be dropped and latched, never written out of bounds,
+    # and restoring the inputs restores the result. One slab takes the packed
+    # per-view pair sort, two slabs the global (tile, id) sort.
+    sc = sg.make_config("C1", n=5000, views=3, res=96)
+    ds = L.DeviceScene(sc)
+    b = L.Batch(ctx, [ds], L.params(), depth_slabs=slabs)
+    ctx.status()
+    b.run()
+    torch.cuda.synchronize()
+    st = ctx.status()
+    assert st["flags"] & L.FS_DEV_PAIR_OVERFLOW == 0 and st["pairs_dropped"] == 0
+    A0, S0 = _A(b, 0), b.S[0].cpu().numpy()
+    scales = [ds.arrays[k].clone() for k in (7, 8, 9)]
+    for k in (7, 8, 9):
+        ds.arrays[k].mul_(6.0)
+    b.run()
+    torch.cuda.synchronize()
+    st = ctx.status()
+    log(f"[batch overflow slabs={slabs}] dropped {st['pairs_dropped']} flags {st['flags']}")
+    assert st["flags"] & L.FS_DEV_PAIR_OVERFLOW and st["pairs_dropped"] > 0
+    for k, s0 in zip((7, 8, 9), scales):
+        ds.arrays[k].copy_(s0)
+    b.run()
+    torch.cuda.synchronize()
+    st = ctx.status()
+    assert st["flags"] & L.FS_DEV_PAIR_OVERFLOW == 0
+    assert np.allclose(_A(b, 0), A0, rtol=1e-6, atol=1e-9) and np.array_equal(b.S[0].cpu().numpy(), S0)
+    b.close()
