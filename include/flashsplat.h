@@ -370,6 +370,10 @@ typedef struct {
                                   many depth slabs, front to back, and tiles whose pixels have all
                                   finished get no pairs from later slabs; 0 (default): 1, one pass
                                   over the full lists */
+    int32_t lanes;             /* 1..4 workspaces, each with its own stream: the views are split into
+                                  at least this many chunks, which take the lanes in turn, so that
+                                  one chunk's binning overlaps another's compositing (each lane
+                                  holds its own workspace); 0 (default): 2 */
 } fs_batch_opts;
 
 typedef struct {

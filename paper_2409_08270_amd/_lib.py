@@ -87,7 +87,7 @@ class FsScene(ctypes.Structure):
 
 class FsBatchOpts(ctypes.Structure):
     _fields_ = [("pair_budget", _I64), ("elem_budget", _I64), ("zero_accumulators", _I32), ("use_graph", _I32),
-                ("reduction", _I32), ("depth_slabs", _I32)]
+                ("reduction", _I32), ("depth_slabs", _I32), ("lanes", _I32)]
 
 
 class FsBatchInfo(ctypes.Structure):

@@ -905,6 +905,16 @@ struct Chunk {
 
 }  // namespace
 
+// Workspace of one lane. Chunks go to the lanes in turn; each lane has its own
+// stream, so one chunk's sort can run while another's compositing does.
+struct Work {
+    DevBuf rec, rect, ntiles, flags, dkeys, dvals, dkeys2, dvals2, counts, offsets;
+    DevBuf ptiles, pvals, pk_alt, pv_alt, ranges, items, items_k, items_k2, items_v2;
+    DevBuf sort_ws, scan_ws, tscan_ws, view_offs, tstate, tile_done;
+    hipStream_t stream = nullptr;  // default priority, created with the batch (lanes > 1)
+    hipEvent_t done = nullptr;
+};
+
 struct fs_batch {
     fs_ctx *ctx = nullptr;
     fs_params p;
@@ -912,10 +922,9 @@ struct fs_batch {
     std::vector<SceneIn> scenes;
     std::vector<Chunk> chunks;
     DevBuf scenes_d;
-    // workspace shared by the chunks
-    DevBuf rec, rect, ntiles, flags, dkeys, dvals, dkeys2, dvals2, counts, offsets;
-    DevBuf ptiles, pvals, pk_alt, pv_alt, ranges, items, items_k, items_k2, items_v2;
-    DevBuf sort_ws, scan_ws, tscan_ws, npairs, view_offs, tstate, tile_done;
+    std::vector<Work> work;  // one per lane
+    hipEvent_t fork = nullptr;
+    DevBuf npairs;
     uint64_t max_elems = 0, max_tiles = 0, max_pairs = 0, max_pixels = 0;
     int n_slabs = 1;
     uint32_t slab_num[9] = {0, 1024};  // depth-slab boundaries, numerators over 1024
@@ -930,11 +939,13 @@ namespace {
 
 std::vector<DevBuf *> batch_bufs(fs_batch *b)
 {
-    std::vector<DevBuf *> v = {&b->scenes_d, &b->rec, &b->rect, &b->ntiles, &b->flags, &b->dkeys, &b->dvals,
-                               &b->dkeys2, &b->dvals2, &b->counts, &b->offsets, &b->ptiles, &b->pvals, &b->pk_alt,
-                               &b->pv_alt, &b->ranges, &b->items, &b->items_k, &b->items_k2, &b->items_v2,
-                               &b->sort_ws, &b->scan_ws, &b->tscan_ws, &b->npairs, &b->view_offs, &b->tstate,
-                               &b->tile_done};
+    std::vector<DevBuf *> v = {&b->scenes_d, &b->npairs};
+    for (Work &w : b->work)
+        for (DevBuf *d : {&w.rec, &w.rect, &w.ntiles, &w.flags, &w.dkeys, &w.dvals, &w.dkeys2, &w.dvals2, &w.counts,
+                          &w.offsets, &w.ptiles, &w.pvals, &w.pk_alt, &w.pv_alt, &w.ranges, &w.items, &w.items_k,
+                          &w.items_k2, &w.items_v2, &w.sort_ws, &w.scan_ws, &w.tscan_ws, &w.view_offs, &w.tstate,
+                          &w.tile_done})
+            v.push_back(d);
     for (Chunk &c : b->chunks) {
         v.push_back(&c.views);
         v.push_back(&c.tasks);
@@ -961,23 +972,23 @@ void chunk_plan(fs_batch *b, Chunk &c)
 }
 
 // projection and per-view depth sort of one chunk
-int enqueue_front(fs_batch *b, Chunk &c, hipStream_t s)
+int enqueue_front(fs_batch *b, Work &w, Chunk &c, hipStream_t s)
 {
     fs_ctx *ctx = b->ctx;
     const Plan &pl = c.plan;
     if (pl.elems == 0) return FS_OK;
-    uint32_t *dk = (uint32_t *)b->dkeys.p, *dv = (uint32_t *)b->dvals.p;
+    uint32_t *dk = (uint32_t *)w.dkeys.p, *dv = (uint32_t *)w.dvals.p;
     HIPCHECK(ctx, launch_project(s, (const ProjTask *)c.tasks.p, (int32_t)pl.tasks.size(), pl.proj_blocks,
                                  (const SceneDev *)b->scenes_d.p, (const ViewDev *)c.views.p, proj_params(&b->p),
-                                 (float *)b->rec.p, (int16_t *)b->rect.p, (int32_t *)b->ntiles.p, (uint8_t *)b->flags.p,
+                                 (float *)w.rec.p, (int16_t *)w.rect.p, (int32_t *)w.ntiles.p, (uint8_t *)w.flags.p,
                                  dk, dv, ctx->status_dev));
-    HIPCHECK(ctx, radix_sort(s, dk, dv, (uint32_t *)b->dkeys2.p, (uint32_t *)b->dvals2.p, (const SegDev *)c.dsegs.p,
-                             (int32_t)pl.views.size(), pl.dblocks, 32, b->sort_ws.p, nullptr, 1));
+    HIPCHECK(ctx, radix_sort(s, dk, dv, (uint32_t *)w.dkeys2.p, (uint32_t *)w.dvals2.p, (const SegDev *)c.dsegs.p,
+                             (int32_t)pl.views.size(), pl.dblocks, 32, w.sort_ws.p, nullptr, 1));
     return FS_OK;
 }
 
 // pair counts of every element (no slab, no culling) and their exclusive scan; total into *np
-int enqueue_full_count(fs_batch *b, Chunk &c, uint32_t *np, hipStream_t s)
+int enqueue_full_count(fs_batch *b, Work &w, Chunk &c, uint32_t *np, hipStream_t s)
 {
     fs_ctx *ctx = b->ctx;
     const Plan &pl = c.plan;
@@ -986,10 +997,10 @@ int enqueue_full_count(fs_batch *b, Chunk &c, uint32_t *np, hipStream_t s)
         HIPCHECK(ctx, launch_fill_u32(s, np, 0u, 1));
         return FS_OK;
     }
-    HIPCHECK(ctx, launch_gather_counts(s, (const uint32_t *)b->dkeys.p, (const uint32_t *)b->dvals.p,
-                                       (const int32_t *)b->ntiles.p, (const ViewDev *)c.views.p,
-                                       (int32_t)pl.views.size(), total, (uint32_t *)b->counts.p));
-    HIPCHECK(ctx, scan_exclusive(s, (const uint32_t *)b->counts.p, (uint32_t *)b->offsets.p, total, np, b->scan_ws.p));
+    HIPCHECK(ctx, launch_gather_counts(s, (const uint32_t *)w.dkeys.p, (const uint32_t *)w.dvals.p,
+                                       (const int32_t *)w.ntiles.p, (const ViewDev *)c.views.p,
+                                       (int32_t)pl.views.size(), total, (uint32_t *)w.counts.p));
+    HIPCHECK(ctx, scan_exclusive(s, (const uint32_t *)w.counts.p, (uint32_t *)w.offsets.p, total, np, w.scan_ws.p));
     return FS_OK;
 }
 
@@ -998,7 +1009,7 @@ int enqueue_full_count(fs_batch *b, Chunk &c, uint32_t *np, hipStream_t s)
 // resuming every pixel's transmittance from the previous slab. Tiles whose
 // pixels have all finished are marked by the compositing and get no pairs in
 // later slabs, so the long tails of dense tiles are never sorted.
-int enqueue_slabs(fs_batch *b, Chunk &c, int chunk_idx, hipStream_t s)
+int enqueue_slabs(fs_batch *b, Work &w, Chunk &c, int chunk_idx, hipStream_t s)
 {
     fs_ctx *ctx = b->ctx;
     const Plan &pl = c.plan;
@@ -1006,62 +1017,62 @@ int enqueue_slabs(fs_batch *b, Chunk &c, int chunk_idx, hipStream_t s)
     const int32_t V = (int32_t)pl.views.size();
     if (total == 0 || c.pair_cap == 0 || pl.tiles == 0) return FS_OK;
     const int S = b->n_slabs;
-    uint32_t *dk = (uint32_t *)b->dkeys.p, *dv = (uint32_t *)b->dvals.p;
+    uint32_t *dk = (uint32_t *)w.dkeys.p, *dv = (uint32_t *)w.dvals.p;
     uint32_t *k0, *v0, *k1, *v1;
-    uint32_t *pt = (uint32_t *)b->ptiles.p, *pv = (uint32_t *)b->pvals.p;
-    uint32_t *pta = (uint32_t *)b->pk_alt.p, *pva = (uint32_t *)b->pv_alt.p;
+    uint32_t *pt = (uint32_t *)w.ptiles.p, *pv = (uint32_t *)w.pvals.p;
+    uint32_t *pta = (uint32_t *)w.pk_alt.p, *pva = (uint32_t *)w.pv_alt.p;
     if (c.passes % 2 == 0) {
         k0 = pt; v0 = pv; k1 = pta; v1 = pva;
     } else {
         k0 = pta; v0 = pva; k1 = pt; v1 = pv;
     }
-    uint8_t *done = S > 1 ? (uint8_t *)b->tile_done.p : nullptr;
-    float *tstate = S > 1 ? (float *)b->tstate.p : nullptr;
+    uint8_t *done = S > 1 ? (uint8_t *)w.tile_done.p : nullptr;
+    float *tstate = S > 1 ? (float *)w.tstate.p : nullptr;
     if (done) HIPCHECK(ctx, launch_fill_u32(s, (uint32_t *)done, 0u, (int64_t)((pl.tiles + 3) / 4)));
     for (int k = 0; k < S; ++k) {
         uint32_t *np = (uint32_t *)b->npairs.p + (size_t)chunk_idx * S + k;
         const Slab sl{b->slab_num[k], b->slab_num[k + 1]};
-        HIPCHECK(ctx, launch_slab_counts(s, dk, dv, (const float *)b->rec.p, (const int16_t *)b->rect.p,
-                                         b->p.fp64_conic ? nullptr : (const uint8_t *)b->flags.p,
-                                         (const int32_t *)b->ntiles.p,
+        HIPCHECK(ctx, launch_slab_counts(s, dk, dv, (const float *)w.rec.p, (const int16_t *)w.rect.p,
+                                         b->p.fp64_conic ? nullptr : (const uint8_t *)w.flags.p,
+                                         (const int32_t *)w.ntiles.p,
                                          (const ViewDev *)c.views.p, V, total, sl, k > 0 ? done : nullptr,
-                                         b->p.tile_w, b->p.tile_h, b->p.sigma_k, (uint32_t *)b->counts.p));
-        HIPCHECK(ctx, scan_exclusive(s, (const uint32_t *)b->counts.p, (uint32_t *)b->offsets.p, total, np,
-                                     b->scan_ws.p));
-        const uint8_t *fl = b->p.fp64_conic ? nullptr : (const uint8_t *)b->flags.p;
+                                         b->p.tile_w, b->p.tile_h, b->p.sigma_k, (uint32_t *)w.counts.p));
+        HIPCHECK(ctx, scan_exclusive(s, (const uint32_t *)w.counts.p, (uint32_t *)w.offsets.p, total, np,
+                                     w.scan_ws.p));
+        const uint8_t *fl = b->p.fp64_conic ? nullptr : (const uint8_t *)w.flags.p;
         // tile lists: the sort's last pass counts the pairs of every tile (and
         // skips writing the sorted tile ids, which nothing reads), then the
         // ranges are the exclusive scan of those counts
-        uint32_t *tcount = (uint32_t *)b->items_k.p, *tstart = (uint32_t *)b->items_k2.p;
+        uint32_t *tcount = (uint32_t *)w.items_k.p, *tstart = (uint32_t *)w.items_k2.p;
         HIPCHECK(ctx, launch_fill_u32(s, tcount, 0u, (int64_t)pl.tiles));
         if (c.packed) {
             // one u32 item per pair, sorted per view by its tile bits only
-            HIPCHECK(ctx, launch_emit(s, dk, dv, (const uint32_t *)b->offsets.p, (const uint32_t *)b->counts.p,
-                                      (const float *)b->rec.p, (const int16_t *)b->rect.p, fl,
+            HIPCHECK(ctx, launch_emit(s, dk, dv, (const uint32_t *)w.offsets.p, (const uint32_t *)w.counts.p,
+                                      (const float *)w.rec.p, (const int16_t *)w.rect.p, fl,
                                       (const ViewDev *)c.views.p, V, total, c.pair_cap, b->p.tile_w, b->p.tile_h,
                                       b->p.sigma_k, nullptr, pt, nullptr, ctx->status_dev, c.gbits));
-            HIPCHECK(ctx, launch_pair_segs(s, (const uint32_t *)b->offsets.p, (const ViewDev *)c.views.p, V, total, np,
+            HIPCHECK(ctx, launch_pair_segs(s, (const uint32_t *)w.offsets.p, (const ViewDev *)c.views.p, V, total, np,
                                            c.pair_cap, (SegDev *)c.psegs.p, ctx->status_dev));
             HIPCHECK(ctx, radix_sort_packed(s, pt, pta, pv, (const SegDev *)c.psegs.p, V, c.pblocks, c.gbits, c.tbits,
-                                            b->sort_ws.p, c.ptpb, tcount));
+                                            w.sort_ws.p, c.ptpb, tcount));
         } else {
-            HIPCHECK(ctx, launch_emit(s, dk, dv, (const uint32_t *)b->offsets.p, (const uint32_t *)b->counts.p,
-                                      (const float *)b->rec.p, (const int16_t *)b->rect.p, fl,
+            HIPCHECK(ctx, launch_emit(s, dk, dv, (const uint32_t *)w.offsets.p, (const uint32_t *)w.counts.p,
+                                      (const float *)w.rec.p, (const int16_t *)w.rect.p, fl,
                                       (const ViewDev *)c.views.p, V, total, c.pair_cap, b->p.tile_w, b->p.tile_h,
                                       b->p.sigma_k, k > 0 ? done : nullptr, k0, v0, ctx->status_dev));
             HIPCHECK(ctx, radix_sort(s, k0, v0, k1, v1, (const SegDev *)c.psegs.p, 1, c.pblocks, c.passes * 8,
-                                     b->sort_ws.p, np, c.ptpb, tcount, false));
+                                     w.sort_ws.p, np, c.ptpb, tcount, false));
         }
-        HIPCHECK(ctx, scan_exclusive(s, tcount, tstart, (int64_t)pl.tiles, nullptr, b->tscan_ws.p));
-        HIPCHECK(ctx, launch_count_ranges(s, tcount, tstart, (int64_t)pl.tiles, (uint32_t *)b->ranges.p));
+        HIPCHECK(ctx, scan_exclusive(s, tcount, tstart, (int64_t)pl.tiles, nullptr, w.tscan_ws.p));
+        HIPCHECK(ctx, launch_count_ranges(s, tcount, tstart, (int64_t)pl.tiles, (uint32_t *)w.ranges.p));
         const uint32_t *items = nullptr;
         if (b->p.tile_order == 0) {
-            RCHECK(enqueue_lpt(ctx, s, (const uint32_t *)b->ranges.p, pl.tiles, (const SegDev *)c.lsegs.p,
-                               (uint32_t *)b->items.p, (uint32_t *)b->items_k.p, (uint32_t *)b->items_k2.p,
-                               (uint32_t *)b->items_v2.p, b->sort_ws.p));
-            items = (const uint32_t *)b->items.p;
+            RCHECK(enqueue_lpt(ctx, s, (const uint32_t *)w.ranges.p, pl.tiles, (const SegDev *)c.lsegs.p,
+                               (uint32_t *)w.items.p, (uint32_t *)w.items_k.p, (uint32_t *)w.items_k2.p,
+                               (uint32_t *)w.items_v2.p, w.sort_ws.p));
+            items = (const uint32_t *)w.items.p;
         }
-        HIPCHECK(ctx, launch_accumulate(s, (const float *)b->rec.p, pv, (const uint32_t *)b->ranges.p,
+        HIPCHECK(ctx, launch_accumulate(s, (const float *)w.rec.p, pv, (const uint32_t *)w.ranges.p,
                                         (const ViewDev *)c.views.p, V, (const SceneDev *)b->scenes_d.p, items,
                                         (uint32_t)pl.tiles, acc_params(&b->p, b->o.reduction), nullptr, nullptr,
                                         tstate, done, k == 0 ? 1 : 0,
@@ -1081,9 +1092,24 @@ int enqueue_run(fs_batch *b, hipStream_t s)
             if (sc.A_lo) HIPCHECK(ctx, launch_fill_u32(s, (uint32_t *)sc.A_lo, 0u, cnt));
         }
     }
+    const size_t L = b->work.size();
+    if (L > 1) {
+        // fork: every lane starts after the zeroing; chunk i runs on lane i % L
+        HIPCHECK(ctx, hipEventRecord(b->fork, s));
+        for (Work &w : b->work) HIPCHECK(ctx, hipStreamWaitEvent(w.stream, b->fork, 0));
+    }
     for (size_t i = 0; i < b->chunks.size(); ++i) {
-        RCHECK(enqueue_front(b, b->chunks[i], s));
-        RCHECK(enqueue_slabs(b, b->chunks[i], (int)i, s));
+        Work &w = b->work[i % L];
+        hipStream_t ls = L > 1 ? w.stream : s;
+        RCHECK(enqueue_front(b, w, b->chunks[i], ls));
+        RCHECK(enqueue_slabs(b, w, b->chunks[i], (int)i, ls));
+    }
+    if (L > 1) {
+        // join: the assignment waits for every lane
+        for (Work &w : b->work) {
+            HIPCHECK(ctx, hipEventRecord(w.done, w.stream));
+            HIPCHECK(ctx, hipStreamWaitEvent(s, w.done, 0));
+        }
     }
     for (const SceneIn &sc : b->scenes)
         if (sc.S)
@@ -1133,6 +1159,7 @@ int batch_build(fs_batch *b, const fs_scene *scenes, int32_t n_scenes)
     std::vector<ViewRef> all;
     for (int i = 0; i < n_scenes; ++i)
         for (int v = 0; v < scenes[i].n_views; ++v) all.push_back(ViewRef{(uint32_t)i, v});
+    int64_t pb = pair_budget, eb = elem_budget;  // lowered below to give every lane a chunk
     auto chunk_by = [&](const std::vector<int64_t> *pairs) {
         std::vector<Chunk> out;
         Chunk cur;
@@ -1145,7 +1172,7 @@ int batch_build(fs_batch *b, const fs_scene *scenes, int32_t n_scenes)
             const fs_camera &c = s.cams[all[k].v];
             const uint64_t t = (uint64_t)((c.width + b->p.tile_w - 1) / b->p.tile_w) *
                                (uint64_t)((c.height + b->p.tile_h - 1) / b->p.tile_h);
-            if (!cur.refs.empty() && (ce + e > elem_budget || cp + p > pair_budget || ct + t > 0x7FFFFFFFull)) {
+            if (!cur.refs.empty() && (ce + e > eb || cp + p > pb || ct + t > 0x7FFFFFFFull)) {
                 out.push_back(std::move(cur));
                 cur = Chunk();
                 ce = cp = 0;
@@ -1172,20 +1199,25 @@ int batch_build(fs_batch *b, const fs_scene *scenes, int32_t n_scenes)
     if (max_e >= 0xFFFFFFFFull) return set_err(ctx, FS_ERR_ARG, "a single view holds too many Gaussians");
     // projection and depth-sort workspace (sized for the element budget)
     const size_t E4 = (size_t)std::max<uint64_t>(max_e, 1) * 4;
-    RCHECK(batch_alloc(b, b->rec, E4 * 8));
-    RCHECK(batch_alloc(b, b->rect, E4 * 2));
-    RCHECK(batch_alloc(b, b->ntiles, E4));
-    RCHECK(batch_alloc(b, b->flags, E4 / 4 + 256));
-    RCHECK(batch_alloc(b, b->dkeys, E4));
-    RCHECK(batch_alloc(b, b->dvals, E4));
-    RCHECK(batch_alloc(b, b->dkeys2, E4));
-    RCHECK(batch_alloc(b, b->dvals2, E4));
-    RCHECK(batch_alloc(b, b->counts, E4));
-    RCHECK(batch_alloc(b, b->offsets, E4));
-    RCHECK(batch_alloc(b, b->scan_ws, scan_ws_bytes((int64_t)max_e)));
+    b->work.resize(1);
+    auto alloc_elem_ws = [&](Work &w) -> int {
+        RCHECK(batch_alloc(b, w.rec, E4 * 8));
+        RCHECK(batch_alloc(b, w.rect, E4 * 2));
+        RCHECK(batch_alloc(b, w.ntiles, E4));
+        RCHECK(batch_alloc(b, w.flags, E4 / 4 + 256));
+        RCHECK(batch_alloc(b, w.dkeys, E4));
+        RCHECK(batch_alloc(b, w.dvals, E4));
+        RCHECK(batch_alloc(b, w.dkeys2, E4));
+        RCHECK(batch_alloc(b, w.dvals2, E4));
+        RCHECK(batch_alloc(b, w.counts, E4));
+        RCHECK(batch_alloc(b, w.offsets, E4));
+        RCHECK(batch_alloc(b, w.scan_ws, scan_ws_bytes((int64_t)max_e)));
+        return FS_OK;
+    };
+    RCHECK(alloc_elem_ws(b->work[0]));
     const int S = b->n_slabs, NB = S + 1;
     RCHECK(batch_alloc(b, b->npairs, 4 * (all.size() * S + 64)));
-    RCHECK(batch_alloc(b, b->view_offs, 4 * (max_v * NB + 64)));
+    RCHECK(batch_alloc(b, b->work[0].view_offs, 4 * (max_v * NB + 64)));
     SlabBounds nb;
     nb.n = (uint32_t)NB;
     for (int i = 0; i < 9; ++i) nb.num[i] = i < NB ? b->slab_num[i] : 1024u;
@@ -1204,19 +1236,19 @@ int batch_build(fs_batch *b, const fs_scene *scenes, int32_t n_scenes)
         if ((rc = upload_vec(ctx, c.views, c.plan.views)) || (rc = upload_vec(ctx, c.tasks, c.plan.tasks)) ||
             (rc = upload_vec(ctx, c.dsegs, c.plan.dsegs)))
             break;
-        std::swap(b->sort_ws, tmp_sort);
-        rc = enqueue_front(b, c, ctx->stream);
-        if (!rc) rc = enqueue_full_count(b, c, (uint32_t *)b->npairs.p, ctx->stream);
-        std::swap(b->sort_ws, tmp_sort);
+        std::swap(b->work[0].sort_ws, tmp_sort);
+        rc = enqueue_front(b, b->work[0], c, ctx->stream);
+        if (!rc) rc = enqueue_full_count(b, b->work[0], c, (uint32_t *)b->npairs.p, ctx->stream);
+        std::swap(b->work[0].sort_ws, tmp_sort);
         if (rc) break;
         hipError_t e = c.plan.elems > 0
-                           ? launch_slab_offsets(ctx->stream, (const uint32_t *)b->offsets.p, (const ViewDev *)c.views.p,
+                           ? launch_slab_offsets(ctx->stream, (const uint32_t *)b->work[0].offsets.p, (const ViewDev *)c.views.p,
                                                  V, (int64_t)c.plan.elems, (const uint32_t *)b->npairs.p, nb,
-                                                 (uint32_t *)b->view_offs.p)
-                           : launch_fill_u32(ctx->stream, (uint32_t *)b->view_offs.p, 0u, (int64_t)V * NB);
+                                                 (uint32_t *)b->work[0].view_offs.p)
+                           : launch_fill_u32(ctx->stream, (uint32_t *)b->work[0].view_offs.p, 0u, (int64_t)V * NB);
         hoff.assign((size_t)V * NB, 0);
         if (e == hipSuccess)
-            e = hipMemcpyAsync(hoff.data(), b->view_offs.p, 4 * hoff.size(), hipMemcpyDeviceToHost, ctx->stream);
+            e = hipMemcpyAsync(hoff.data(), b->work[0].view_offs.p, 4 * hoff.size(), hipMemcpyDeviceToHost, ctx->stream);
         if (e == hipSuccess) e = hipStreamSynchronize(ctx->stream);
         if (e != hipSuccess) {
             rc = set_err(ctx, FS_ERR_HIP, "batch count failed: %s", hipGetErrorString(e));
@@ -1241,6 +1273,20 @@ int batch_build(fs_batch *b, const fs_scene *scenes, int32_t n_scenes)
     if (rc) return rc;
 
     // 3. final chunks by elements and pairs; per-chunk tables
+    const int lanes_req = b->o.lanes == 0 ? 2 : b->o.lanes;
+    if (lanes_req > 1) {
+        // a lane's share plus one view, so that the greedy split gives `lanes`
+        // chunks of nearly equal work rather than one more small chunk
+        int64_t tp = 0, te = 0, mp = 0, me = 0;
+        for (size_t q = 0; q < all.size(); ++q) {
+            tp += vpairs[q];
+            te += b->scenes[all[q].scene].g.n;
+            mp = std::max<int64_t>(mp, vpairs[q]);
+            me = std::max<int64_t>(me, b->scenes[all[q].scene].g.n);
+        }
+        pb = std::min<int64_t>(pb, std::max<int64_t>(1, (tp + lanes_req - 1) / lanes_req + mp));
+        eb = std::min<int64_t>(eb, std::max<int64_t>(1, (te + lanes_req - 1) / lanes_req + me));
+    }
     b->chunks = chunk_by(&vpairs);
     size_t k = 0;
     for (Chunk &c : b->chunks) {
@@ -1308,23 +1354,35 @@ int batch_build(fs_batch *b, const fs_scene *scenes, int32_t n_scenes)
         RCHECK(upload_vec(ctx, c.lsegs, ls));
         for (DevBuf *d : {&c.views, &c.tasks, &c.dsegs, &c.psegs, &c.lsegs}) b->ws_bytes += (int64_t)d->cap;
     }
+    const size_t n_lanes = std::max<size_t>(1, std::min<size_t>((size_t)lanes_req, b->chunks.size()));
+    b->work.resize(n_lanes);
+    for (size_t l = 1; l < n_lanes; ++l) RCHECK(alloc_elem_ws(b->work[l]));
     const size_t P4 = (size_t)std::max<uint64_t>(cap, 1) * 4;
-    RCHECK(batch_alloc(b, b->ptiles, P4));
-    RCHECK(batch_alloc(b, b->pvals, P4));
-    RCHECK(batch_alloc(b, b->pk_alt, P4));
-    RCHECK(batch_alloc(b, b->pv_alt, P4));
     const size_t T4 = (size_t)std::max<uint64_t>(b->max_tiles, 1) * 4;
-    RCHECK(batch_alloc(b, b->ranges, T4 * 2));
-    RCHECK(batch_alloc(b, b->items, T4));
-    RCHECK(batch_alloc(b, b->items_k, T4));
-    RCHECK(batch_alloc(b, b->items_k2, T4));
-    RCHECK(batch_alloc(b, b->items_v2, T4));
-    RCHECK(batch_alloc(b, b->tscan_ws, scan_ws_bytes((int64_t)std::max<uint64_t>(b->max_tiles, 1))));
     const uint32_t sb = std::max(std::max(b->max_dblocks, b->max_pblocks), std::max<uint32_t>(b->max_lblocks, 1));
-    RCHECK(batch_alloc(b, b->sort_ws, radix_ws_bytes(sb)));
-    if (S > 1) {
-        RCHECK(batch_alloc(b, b->tstate, (size_t)std::max<uint64_t>(b->max_pixels, 1) * 4));
-        RCHECK(batch_alloc(b, b->tile_done, ((size_t)b->max_tiles + 3) / 4 * 4 + 4));
+    for (Work &w : b->work) {
+        RCHECK(batch_alloc(b, w.ptiles, P4));
+        RCHECK(batch_alloc(b, w.pvals, P4));
+        RCHECK(batch_alloc(b, w.pk_alt, P4));
+        RCHECK(batch_alloc(b, w.pv_alt, P4));
+        RCHECK(batch_alloc(b, w.ranges, T4 * 2));
+        RCHECK(batch_alloc(b, w.items, T4));
+        RCHECK(batch_alloc(b, w.items_k, T4));
+        RCHECK(batch_alloc(b, w.items_k2, T4));
+        RCHECK(batch_alloc(b, w.items_v2, T4));
+        RCHECK(batch_alloc(b, w.tscan_ws, scan_ws_bytes((int64_t)std::max<uint64_t>(b->max_tiles, 1))));
+        RCHECK(batch_alloc(b, w.sort_ws, radix_ws_bytes(sb)));
+        if (S > 1) {
+            RCHECK(batch_alloc(b, w.tstate, (size_t)std::max<uint64_t>(b->max_pixels, 1) * 4));
+            RCHECK(batch_alloc(b, w.tile_done, ((size_t)b->max_tiles + 3) / 4 * 4 + 4));
+        }
+    }
+    if (n_lanes > 1) {
+        HIPCHECK(ctx, hipEventCreateWithFlags(&b->fork, hipEventDisableTiming));
+        for (Work &w : b->work) {
+            HIPCHECK(ctx, hipStreamCreateWithFlags(&w.stream, hipStreamNonBlocking));
+            HIPCHECK(ctx, hipEventCreateWithFlags(&w.done, hipEventDisableTiming));
+        }
     }
     HIPCHECK(ctx, hipStreamSynchronize(ctx->stream));
 
@@ -1369,6 +1427,7 @@ void fs_batch_opts_default(fs_batch_opts *o)
     o->use_graph = 1;
     o->reduction = FS_RED_AUTO;
     o->depth_slabs = 0;
+    o->lanes = 0;
 }
 
 int fs_batch_create(fs_ctx *ctx, const fs_scene *scenes, int32_t n_scenes, const fs_params *p,
@@ -1385,6 +1444,7 @@ int fs_batch_create(fs_ctx *ctx, const fs_scene *scenes, int32_t n_scenes, const
     if (opts) o = *opts;
     if (o.reduction < FS_RED_AUTO || o.reduction > FS_RED_LDS2SUM) return set_err(ctx, FS_ERR_ARG, "unknown reduction");
     if (o.depth_slabs < 0 || o.depth_slabs > 4) return set_err(ctx, FS_ERR_ARG, "depth_slabs must be in [0, 4]");
+    if (o.lanes < 0 || o.lanes > 4) return set_err(ctx, FS_ERR_ARG, "lanes must be in [0, 4]");
     bool all_lo = true;
     for (int i = 0; i < n_scenes; ++i) {
         const fs_scene &s = scenes[i];
@@ -1439,7 +1499,7 @@ int fs_batch_get_info(fs_batch *b, fs_batch_info *out)
     for (const SceneIn &s : b->scenes) nv += (int32_t)s.cams.size();
     out->n_views = nv;
     out->pairs = b->total_pairs;
-    out->pair_capacity = (int64_t)(b->ptiles.cap / 4);
+    out->pair_capacity = b->work.empty() ? 0 : (int64_t)(b->work[0].ptiles.cap / 4);
     out->elements = b->total_elems;
     out->tiles = b->total_tiles;
     out->workspace_bytes = b->ws_bytes;
@@ -1452,6 +1512,14 @@ int fs_batch_destroy(fs_batch *b)
     if (b->ctx) (void)hipStreamSynchronize(b->ctx->stream);
     if (b->exec) (void)hipGraphExecDestroy(b->exec);
     if (b->graph) (void)hipGraphDestroy(b->graph);
+    for (Work &w : b->work) {
+        if (w.stream) {
+            (void)hipStreamSynchronize(w.stream);
+            (void)hipStreamDestroy(w.stream);
+        }
+        if (w.done) (void)hipEventDestroy(w.done);
+    }
+    if (b->fork) (void)hipEventDestroy(b->fork);
     for (DevBuf *d : batch_bufs(b)) free_buf(*d);
     delete b;
     return FS_OK;

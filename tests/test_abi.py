@@ -53,6 +53,7 @@ def test_batch_defaults_and_null_handling(lib):
     from paper_2409_08270_amd import _lib as L
     o = L.batch_opts()
     assert (o.pair_budget, o.elem_budget, o.zero_accumulators, o.use_graph, o.reduction) == (0, 0, 1, 1, L.FS_RED_AUTO)
+    assert (o.depth_slabs, o.lanes) == (0, 0)
     out = ctypes.c_void_p()
     assert lib.fs_batch_create(None, None, 0, None, None, ctypes.byref(out)) == L.FS_ERR_ARG
     assert lib.fs_batch_run(None) == L.FS_ERR_ARG

@@ -48,7 +48,7 @@ def test_multi_scene_batch_matches_the_oracle(ctx):
     gammas = [0.0, 0.3, -0.2]
     dss = [L.DeviceScene(s) for s in scenes]
     log("[batch] 3 scenes, one graph")
-    b = L.Batch(ctx, dss, L.params(), gammas=gammas, want_margin=True)
+    b = L.Batch(ctx, dss, L.params(), gammas=gammas, want_margin=True, lanes=1)
     b.run()
     torch.cuda.synchronize()
     st = ctx.status()
@@ -71,7 +71,7 @@ def test_multi_scene_batch_matches_the_oracle(ctx):
 def test_chunked_batch_equals_one_chunk(ctx):
     scenes = _uneven_scenes()
     dss = [L.DeviceScene(s) for s in scenes]
-    one = L.Batch(ctx, dss, L.params())
+    one = L.Batch(ctx, dss, L.params(), lanes=1)
     one.run()
     # budgets that force a chunk boundary inside scenes
     many = L.Batch(ctx, dss, L.params(), elem_budget=5000, pair_budget=20000)
@@ -253,3 +253,34 @@ def test_grown_inputs_overflow_is_latched(ctx, slabs):
     assert st["flags"] & L.FS_DEV_PAIR_OVERFLOW == 0
     assert np.allclose(_A(b, 0), A0, rtol=1e-6, atol=1e-9) and np.array_equal(b.S[0].cpu().numpy(), S0)
     b.close()
+
+
+@pytest.mark.parametrize("use_graph", [1, 0])
+def test_lanes_give_the_one_lane_result(ctx, use_graph):
+    # chunks on two to four lanes (streams) add into the same accumulators
+    scenes = _uneven_scenes()
+    dss = [L.DeviceScene(s) for s in scenes]
+    one = L.Batch(ctx, dss, L.params(), gammas=[0.0, 0.3, -0.2], lanes=1, use_graph=use_graph)
+    one.run()
+    torch.cuda.synchronize()
+    ctx.status()
+    assert one.info()["n_chunks"] == 1
+    for lanes in (0, 2, 3, 4):
+        b = L.Batch(ctx, dss, L.params(), gammas=[0.0, 0.3, -0.2], lanes=lanes, use_graph=use_graph)
+        for _ in range(2):  # replays start from zero again
+            b.run()
+        torch.cuda.synchronize()
+        st = ctx.status()
+        assert st["flags"] == 0
+        assert b.info()["n_chunks"] >= (lanes if lanes else 2)
+        assert b.info()["pairs"] == one.info()["pairs"]
+        for i in range(len(scenes)):
+            a, c = _A(one, i), _A(b, i)
+            d = np.abs(a - c).sum(1)
+            s = np.abs(a).sum(1)
+            assert np.all(d <= 1e-5 * s + 1e-9), f"lanes {lanes} scene {i}"
+            diff = one.S[i].cpu().numpy() != b.S[i].cpu().numpy()
+            assert diff.sum() <= 2, f"lanes {lanes} scene {i}: {int(diff.sum())} label flips"
+        b.close()
+    with pytest.raises(RuntimeError):
+        L.Batch(ctx, dss, L.params(), lanes=5)
