@@ -215,7 +215,10 @@ __global__ __launch_bounds__(kThreads) void k_radix_hist(const uint32_t *__restr
 // item, -start at its first, which sums to the length whatever the order of
 // the atomics). kout and vout may be NULL; without vin (keys only), vout
 // receives k & vmask.
-__global__ __launch_bounds__(kThreads) void k_radix_scatter(const uint32_t *__restrict__ kin, const uint32_t *__restrict__ vin,
+// VALS = false: keys only (vin is not read). At most 128 VGPRs, so that as many
+// blocks fit a CU as its LDS allows (four).
+template <bool VALS>
+__global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(4))) void k_radix_scatter(const uint32_t *__restrict__ kin, const uint32_t *__restrict__ vin,
                                                             uint32_t *__restrict__ kout, uint32_t *__restrict__ vout,
                                                             const SegDev *__restrict__ segs, int32_t n_segs,
                                                             int32_t shift, const uint32_t *__restrict__ offs,
@@ -240,17 +243,17 @@ __global__ __launch_bounds__(kThreads) void k_radix_scatter(const uint32_t *__re
     for (int tb = 0; tb * kTile < si.nvalid; ++tb) {
         const int nvalid = min(kTile, si.nvalid - tb * kTile);
         const uint32_t *kbase = kin + si.base + (int64_t)tb * kTile;
-        const uint32_t *vbase = vin ? vin + si.base + (int64_t)tb * kTile : nullptr;
+        const uint32_t *vbase = VALS ? vin + si.base + (int64_t)tb * kTile : nullptr;
         for (int i = threadIdx.x; i < kWaves * 256; i += kThreads) (&s_cnt[0][0])[i] = 0;
         __syncthreads();
 
-        uint32_t key[kItems], val[kItems], rnk[kItems];
+        uint32_t key[kItems], val[VALS ? kItems : 1], rnk[kItems];
 #pragma unroll
         for (int r = 0; r < kItems; ++r) {
             const int li = w * (kItems * 64) + r * 64 + lane;
             const bool ok = li < nvalid;
             key[r] = ok ? kbase[li] : 0xFFFFFFFFu;
-            val[r] = (ok && vbase) ? vbase[li] : 0u;
+            if constexpr (VALS) val[r] = ok ? vbase[li] : 0u;
         }
 #pragma unroll
         for (int r = 0; r < kItems; ++r) {
@@ -291,7 +294,7 @@ __global__ __launch_bounds__(kThreads) void k_radix_scatter(const uint32_t *__re
             const uint32_t d = (key[r] >> shift) & dmask;
             const uint32_t pos = s_dstart[d] + s_cnt[w][d] + rnk[r];
             s_k[pos] = key[r];
-            s_v[pos] = val[r];
+            if constexpr (VALS) s_v[pos] = val[r];
         }
         __syncthreads();
         for (int i = threadIdx.x; i < nvalid; i += kThreads) {
@@ -299,7 +302,10 @@ __global__ __launch_bounds__(kThreads) void k_radix_scatter(const uint32_t *__re
             const uint32_t d = (k >> shift) & dmask;
             const int64_t p = (int64_t)s_gofs[d] + (i - (int64_t)s_dstart[d]);
             if (kout) kout[p] = k;
-            if (vout) vout[p] = vin ? s_v[i] : (k & vmask);
+            if (vout) {
+                if constexpr (VALS) vout[p] = s_v[i];
+                else vout[p] = k & vmask;
+            }
             if (key_count) {
                 const uint32_t kk = k >> kshift;
                 uint32_t *cnt = key_count + si.kbase + kk;
@@ -653,7 +659,7 @@ hipError_t radix_sort(hipStream_t s, uint32_t *keys, uint32_t *vals, uint32_t *k
         hipError_t e = scan_exclusive(s, hist, offs, hist_n, nullptr, scan_ws);
         if (e != hipSuccess) return e;
         const bool last = shift + 8 >= bits;
-        hipLaunchKernelGGL(k_radix_scatter, dim3(n_blocks), dim3(kThreads), 0, s, ki, vi,
+        hipLaunchKernelGGL(k_radix_scatter<true>, dim3(n_blocks), dim3(kThreads), 0, s, ki, vi,
                            (last && !last_keys) ? nullptr : ko, vo, segs, n_segs, shift, (const uint32_t *)offs,
                            len_dev, tpb, last ? key_count : nullptr, 255u, 0, 0u);
         e = hipGetLastError();
@@ -689,7 +695,7 @@ hipError_t radix_sort_packed(hipStream_t s, uint32_t *items, uint32_t *items_alt
                            (const uint32_t *)nullptr, tpb, dmask);
         hipError_t e = scan_exclusive(s, hist, offs, hist_n, nullptr, scan_ws);
         if (e != hipSuccess) return e;
-        hipLaunchKernelGGL(k_radix_scatter, dim3(n_blocks), dim3(kThreads), 0, s, ki, (const uint32_t *)nullptr,
+        hipLaunchKernelGGL(k_radix_scatter<false>, dim3(n_blocks), dim3(kThreads), 0, s, ki, (const uint32_t *)nullptr,
                            last ? nullptr : items_alt, last ? ids_out : nullptr, segs, n_segs, shift,
                            (const uint32_t *)offs, (const uint32_t *)nullptr, tpb, last ? key_count : nullptr, dmask,
                            gbits, vmask);
