@@ -215,8 +215,8 @@ __global__ __launch_bounds__(kThreads) void k_radix_hist(const uint32_t *__restr
 // item, -start at its first, which sums to the length whatever the order of
 // the atomics). kout and vout may be NULL; without vin (keys only), vout
 // receives k & vmask.
-// VALS = false: keys only (vin is not read). At most 128 VGPRs, so that as many
-// blocks fit a CU as its LDS allows (four).
+// VALS = false: keys only (vin is not read, no value staging in LDS). The
+// 128-VGPR budget keeps four blocks on a CU (a tighter one spills and is slower).
 template <bool VALS>
 __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(4))) void k_radix_scatter(const uint32_t *__restrict__ kin, const uint32_t *__restrict__ vin,
                                                             uint32_t *__restrict__ kout, uint32_t *__restrict__ vout,
@@ -231,7 +231,7 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(4))) v
     __shared__ uint32_t s_gofs[256];
     __shared__ uint32_t s_wsum[kWaves];
     __shared__ uint32_t s_k[kTile];
-    __shared__ uint32_t s_v[kTile];
+    __shared__ uint32_t s_v[VALS ? kTile : 1];
 
     const SegInfo si = seg_of_block(segs, n_segs, blockIdx.x, len_dev, tpb);
     const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
