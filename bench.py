@@ -33,6 +33,7 @@ def parse():
     ap.add_argument("--config", default="C2")
     ap.add_argument("--cpu-views", type=int, default=24, help="views of the CPU oracle sample (0: skip)")
     ap.add_argument("--no-plain", action="store_true")
+    ap.add_argument("--lanes", type=int, default=0, help="batch lanes (0: the library's default, 2)")
     ap.add_argument("--no-strategies", action="store_true",
                     help="skip the per-strategy compositing comparison (keeps one launch shape per kernel)")
     ap.add_argument("--copy-probe", type=int, default=0, metavar="MIB",
@@ -103,7 +104,7 @@ def main():
     # one replay of an instrumented graph of the same workload.
     prm = L.params(count_ops=0)
     prm_count = L.params(count_ops=1)
-    counted = L.Batch(ctx, [ds], prm_count, gammas=[0.0])
+    counted = L.Batch(ctx, [ds], prm_count, gammas=[0.0], lanes=args.lanes)
     ctx.status()
     counted.run()
     torch.cuda.synchronize()
@@ -114,7 +115,7 @@ def main():
     blends = float(st["blends"])
     evals = float(st["evaluated"])
     wsteps, wsteps_max = float(st["wave_steps"]), float(st["wave_steps_max"])
-    batch = L.Batch(ctx, [ds], prm, gammas=[0.0])
+    batch = L.Batch(ctx, [ds], prm, gammas=[0.0], lanes=args.lanes)
     binfo = batch.info()
     print(f"[bench] batch planned: {binfo}", file=sys.stderr, flush=True)
     for _ in range(args.warmup):
@@ -286,7 +287,8 @@ def main():
         "data": "synthetic",
         "config": {"workload": f"{args.config}: {sc.n} Gaussians (4 clusters + shell), {V} views "
                                f"{int(sc.W[0])}x{int(sc.H[0])}, E={sc.E}, gamma=0", "mode": "batched, one hipGraph",
-                   "reduction": "lds+two-sum", "chunks": binfo["n_chunks"]},
+                   "reduction": "lds+two-sum", "chunks": binfo["n_chunks"],
+                   "lanes": args.lanes or 2},
         "blends_per_sec": blends / dt_b,
         "op_counts": "timed graph and compositing launches run with count_ops=0; evaluations and blends "
                      "come from one instrumented replay of the same workload",
