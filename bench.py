@@ -114,6 +114,7 @@ def main():
     del counted
     blends = float(st["blends"])
     evals = float(st["evaluated"])
+    staged = float(st["entries_staged"])
     wsteps, wsteps_max = float(st["wave_steps"]), float(st["wave_steps_max"])
     batch = L.Batch(ctx, [ds], prm, gammas=[0.0], lanes=args.lanes)
     binfo = batch.info()
@@ -202,6 +203,9 @@ def main():
             ts.append(e0.elapsed_time(e1))
         return float(np.median(ts))
 
+    S_one = torch.empty((sc.E, sc.n), dtype=torch.uint8, device="cuda")
+    m_one = torch.empty((sc.E, sc.n), dtype=torch.float32, device="cuda")
+    assign_ms = timed(lambda: ctx.fs_assign(batch.A_hi[0], batch.A_lo[0], sc.n, sc.E, 0.0, S_one, m_one))
     gam = [float(x) for x in np.linspace(-0.5, 0.5, 64)]
     S_sw = torch.empty((64, sc.E, sc.n), dtype=torch.uint8, device="cuda")
     sweep_ms = timed(lambda: ctx.fs_assign_sweep(batch.A_hi[0], batch.A_lo[0], sc.n, sc.E, gam, S_sw,
@@ -222,7 +226,7 @@ def main():
         t = time.perf_counter()
         ctx.fs_prompt_propagate(ds, 0, prompts, k=10)
         pts.append((time.perf_counter() - t) * 1e3)
-    followups = {"prompt_propagation_16_prompts_ms": float(np.median(pts)), "bias_sweep_64_gammas_ms": sweep_ms, "object_removal_compaction_ms": compact_ms,
+    followups = {"assign_ms": assign_ms, "prompt_propagation_16_prompts_ms": float(np.median(pts)), "bias_sweep_64_gammas_ms": sweep_ms, "object_removal_compaction_ms": compact_ms,
                  "mask_render_all_views_ms": render_ms, "mask_render_views_per_sec": V / (render_ms * 1e-3),
                  "rendered_masks_agree_with_inputs": agree, "gaussians": sc.n}
     print(f"[bench] follow-ups: {followups}", file=sys.stderr, flush=True)
@@ -238,6 +242,23 @@ def main():
             "kernel": "k_accum",
             "ops_per_launch": ops, "launch_ms": acc_s * 1e3,
             "wave_steps": wsteps, "wave_balance": wsteps / max(1.0, 4 * wsteps_max)}
+
+    # ---- the whole path against the HBM roof --------------------------------
+    # algorithmic bytes of one step (what the method must move, from counted quantities):
+    # Gaussians read once per chunk, 44 B per (Gaussian, view) for the projected record and its
+    # count, 36 B per pair (emit + one sort read and write), 8 B per tile range, 28 B per staged
+    # list entry (id + gathered record), the masks, and A written, read and S written once
+    n_chunks = binfo["n_chunks"]
+    terms = {"gaussians": 44.0 * sc.n * n_chunks, "projected": 44.0 * sc.n * V, "pairs": 36.0 * pairs,
+             "ranges": 8.0 * binfo["tiles"], "staged": 28.0 * staged, "masks": float(sc.pixels()),
+             "assign": 17.0 * sc.n * sc.E}
+    path_bytes = sum(terms.values())
+    hbm_frac = path_bytes / dt_b / PEAK_HBM
+    path = {"hbm": {"algorithmic_bytes_per_step": path_bytes, "achieved": path_bytes / dt_b / 1e9,
+                    "peak": PEAK_HBM / 1e9, "unit": "GB/s", "frac": hbm_frac, "terms": terms,
+                    "entries_staged": staged},
+            "alu_compositing_frac": roof["frac"],
+            "binding": "alu (compositing)" if roof["frac"] >= hbm_frac else "hbm"}
 
     # ---- CPU oracle on a bounded sample of views -----------------------------
     cpu = None
@@ -301,6 +322,7 @@ def main():
         "accumulate_ms_by_strategy": strat,
         "followups": followups,
         "roofline": roof,
+        "path_roofline": path,
         "cpu_baseline": cpu,
         "parity_sample": parity,
     }

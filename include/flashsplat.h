@@ -156,6 +156,8 @@ typedef struct {
     int64_t multi_member;    /* fs_assign: Gaussians assigned to more than one object */
     int64_t low_margin;      /* fs_assign: (object, Gaussian) entries with margin < 1e-4 */
     int64_t pairs_emitted;   /* tile pairs written by fs_bin_sort and the batched solve */
+    int64_t entries_staged;  /* tile-list entries the compositing read, each tile's list up to the
+                                batch in which its last pixel finished */
 } fs_status;
 
 /* Library and context ---------------------------------------------------- */

@@ -74,7 +74,7 @@ class FsStatus(ctypes.Structure):
     _fields_ = [("flags", ctypes.c_uint32), ("bad_labels", _I64), ("invalid_gauss", _I64),
                 ("fp64_splats", _I64), ("pairs_dropped", _I64), ("blends", _I64), ("evaluated", _I64), ("wave_steps", _I64),
                 ("wave_steps_max", _I64), ("unseen", _I64),
-                ("multi_member", _I64), ("low_margin", _I64), ("pairs_emitted", _I64)]
+                ("multi_member", _I64), ("low_margin", _I64), ("pairs_emitted", _I64), ("entries_staged", _I64)]
 
     def as_dict(self):
         return {k: int(getattr(self, k)) for k, _ in self._fields_}

@@ -229,12 +229,14 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(7, 7))) voi
     }
     uint32_t nb_l = 0, ne_l = 0;      // this pixel's blends and in-support evaluations
     uint32_t steps_w = 0;             // list entries this wave walked
+    uint32_t staged = 0;              // list entries this block read (thread 0)
     bool live = active;
     const bool any_live = __syncthreads_or(live) != 0;
     const int64_t rec_base = (int64_t)C.elem_off;
 
     for (uint32_t base = any_live ? rg.x : rg.y; base < rg.y; base += kBatch) {
         const uint32_t cnt = min((uint32_t)kBatch, rg.y - base);
+        staged += cnt;
         // the box of this wave's live pixels (lane = 8 * row + column): pixels only
         // ever finish, so entries that cannot reach the box cannot add a weight
         {
@@ -415,6 +417,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(7, 7))) voi
         if (s_misc[3]) status_add(status, ST_EVALS, (unsigned long long)s_misc[3]);
         if (s_misc[4]) status_add(status, ST_WSTEPS, (unsigned long long)s_misc[4]);
         if (s_misc[1]) status_add(status, ST_WSTEPS_MAX, (unsigned long long)s_misc[1]);
+        if (staged) status_add(status, ST_STAGED, (unsigned long long)staged);
     }
 }
 

@@ -500,6 +500,7 @@ int fs_status_get(fs_ctx *ctx, fs_status *out, int32_t clear)
     out->multi_member = (int64_t)h[ST_MULTI];
     out->low_margin = (int64_t)h[ST_LOWMARGIN];
     out->pairs_emitted = (int64_t)h[ST_PAIRS];
+    out->entries_staged = (int64_t)h[ST_STAGED];
     if (clear) HIPCHECK(ctx, launch_fill_u32(ctx->stream, (uint32_t *)ctx->status_dev, 0u, kStatusWords * 2));
     const uint32_t errbits = FS_DEV_BAD_LABEL | FS_DEV_PAIR_OVERFLOW | FS_DEV_INVALID_GAUSS;
     if (out->flags & errbits) return set_err(ctx, FS_ERR_DEVICE, "device status flags 0x%x", out->flags);

@@ -89,6 +89,7 @@ enum StatusIdx {
     ST_EVALS,
     ST_WSTEPS,      // list entries walked, summed over waves (diagnostic)
     ST_WSTEPS_MAX,  // per tile, the longest walk of its waves, summed over tiles (diagnostic)
+    ST_STAGED,      // tile-list entries the compositing read (up to each tile's termination)
     ST_COUNT = 16
 };
 
