@@ -528,7 +528,8 @@ int fs_project(fs_ctx *ctx, const fs_gaussians *g, const fs_camera *cams, int32_
     RCHECK(upload_vec(ctx, ctx->tasks, pl.tasks));
     HIPCHECK(ctx, launch_project(ctx->stream, (const ProjTask *)ctx->tasks.p, (int32_t)pl.tasks.size(), pl.proj_blocks,
                                  (const SceneDev *)ctx->scenes.p, (const ViewDev *)ctx->views.p, proj_params(p),
-                                 out->rec, out->rect, out->ntiles, out->flags, nullptr, nullptr, ctx->status_dev));
+                                 out->rec, out->rect, out->ntiles, out->flags, nullptr, nullptr, nullptr,
+                                 ctx->status_dev));
     return FS_OK;
 }
 
@@ -909,7 +910,7 @@ struct Chunk {
 // Workspace of one lane. Chunks go to the lanes in turn; each lane has its own
 // stream, so one chunk's sort can run while another's compositing does.
 struct Work {
-    DevBuf rec, rect, ntiles, flags, dkeys, dvals, dkeys2, dvals2, counts, offsets;
+    DevBuf rec, rect, ntiles, flags, codes, dkeys, dvals, dkeys2, dvals2, counts, offsets;
     DevBuf ptiles, pvals, pk_alt, pv_alt, ranges, items, items_k, items_k2, items_v2;
     DevBuf sort_ws, scan_ws, tscan_ws, view_offs, tstate, tile_done;
     hipStream_t stream = nullptr;  // default priority, created with the batch (lanes > 1)
@@ -942,8 +943,8 @@ std::vector<DevBuf *> batch_bufs(fs_batch *b)
 {
     std::vector<DevBuf *> v = {&b->scenes_d, &b->npairs};
     for (Work &w : b->work)
-        for (DevBuf *d : {&w.rec, &w.rect, &w.ntiles, &w.flags, &w.dkeys, &w.dvals, &w.dkeys2, &w.dvals2, &w.counts,
-                          &w.offsets, &w.ptiles, &w.pvals, &w.pk_alt, &w.pv_alt, &w.ranges, &w.items, &w.items_k,
+        for (DevBuf *d : {&w.rec, &w.rect, &w.ntiles, &w.flags, &w.codes, &w.dkeys, &w.dvals, &w.dkeys2, &w.dvals2,
+                          &w.counts, &w.offsets, &w.ptiles, &w.pvals, &w.pk_alt, &w.pv_alt, &w.ranges, &w.items, &w.items_k,
                           &w.items_k2, &w.items_v2, &w.sort_ws, &w.scan_ws, &w.tscan_ws, &w.view_offs, &w.tstate,
                           &w.tile_done})
             v.push_back(d);
@@ -982,7 +983,7 @@ int enqueue_front(fs_batch *b, Work &w, Chunk &c, hipStream_t s)
     HIPCHECK(ctx, launch_project(s, (const ProjTask *)c.tasks.p, (int32_t)pl.tasks.size(), pl.proj_blocks,
                                  (const SceneDev *)b->scenes_d.p, (const ViewDev *)c.views.p, proj_params(&b->p),
                                  (float *)w.rec.p, (int16_t *)w.rect.p, (int32_t *)w.ntiles.p, (uint8_t *)w.flags.p,
-                                 dk, dv, ctx->status_dev));
+                                 dk, dv, (uint64_t *)w.codes.p, ctx->status_dev));
     HIPCHECK(ctx, radix_sort(s, dk, dv, (uint32_t *)w.dkeys2.p, (uint32_t *)w.dvals2.p, (const SegDev *)c.dsegs.p,
                              (int32_t)pl.views.size(), pl.dblocks, 32, w.sort_ws.p, nullptr, 1));
     return FS_OK;
@@ -1037,7 +1038,8 @@ int enqueue_slabs(fs_batch *b, Work &w, Chunk &c, int chunk_idx, hipStream_t s)
                                          b->p.fp64_conic ? nullptr : (const uint8_t *)w.flags.p,
                                          (const int32_t *)w.ntiles.p,
                                          (const ViewDev *)c.views.p, V, total, sl, k > 0 ? done : nullptr,
-                                         b->p.tile_w, b->p.tile_h, b->p.sigma_k, (uint32_t *)w.counts.p));
+                                         b->p.tile_w, b->p.tile_h, b->p.sigma_k, (const uint64_t *)w.codes.p,
+                                         (uint32_t *)w.counts.p));
         HIPCHECK(ctx, scan_exclusive(s, (const uint32_t *)w.counts.p, (uint32_t *)w.offsets.p, total, np,
                                      w.scan_ws.p));
         const uint8_t *fl = b->p.fp64_conic ? nullptr : (const uint8_t *)w.flags.p;
@@ -1051,7 +1053,8 @@ int enqueue_slabs(fs_batch *b, Work &w, Chunk &c, int chunk_idx, hipStream_t s)
             HIPCHECK(ctx, launch_emit(s, dk, dv, (const uint32_t *)w.offsets.p, (const uint32_t *)w.counts.p,
                                       (const float *)w.rec.p, (const int16_t *)w.rect.p, fl,
                                       (const ViewDev *)c.views.p, V, total, c.pair_cap, b->p.tile_w, b->p.tile_h,
-                                      b->p.sigma_k, nullptr, pt, nullptr, ctx->status_dev, c.gbits));
+                                      b->p.sigma_k, nullptr, pt, nullptr, ctx->status_dev, c.gbits,
+                                      (const uint64_t *)w.codes.p));
             HIPCHECK(ctx, launch_pair_segs(s, (const uint32_t *)w.offsets.p, (const ViewDev *)c.views.p, V, total, np,
                                            c.pair_cap, (SegDev *)c.psegs.p, ctx->status_dev));
             HIPCHECK(ctx, radix_sort_packed(s, pt, pta, pv, (const SegDev *)c.psegs.p, V, c.pblocks, c.gbits, c.tbits,
@@ -1060,7 +1063,8 @@ int enqueue_slabs(fs_batch *b, Work &w, Chunk &c, int chunk_idx, hipStream_t s)
             HIPCHECK(ctx, launch_emit(s, dk, dv, (const uint32_t *)w.offsets.p, (const uint32_t *)w.counts.p,
                                       (const float *)w.rec.p, (const int16_t *)w.rect.p, fl,
                                       (const ViewDev *)c.views.p, V, total, c.pair_cap, b->p.tile_w, b->p.tile_h,
-                                      b->p.sigma_k, k > 0 ? done : nullptr, k0, v0, ctx->status_dev));
+                                      b->p.sigma_k, k > 0 ? done : nullptr, k0, v0, ctx->status_dev, 0,
+                                      (const uint64_t *)w.codes.p));
             HIPCHECK(ctx, radix_sort(s, k0, v0, k1, v1, (const SegDev *)c.psegs.p, 1, c.pblocks, c.passes * 8,
                                      w.sort_ws.p, np, c.ptpb, tcount, false));
         }
@@ -1206,6 +1210,7 @@ int batch_build(fs_batch *b, const fs_scene *scenes, int32_t n_scenes)
         RCHECK(batch_alloc(b, w.rect, E4 * 2));
         RCHECK(batch_alloc(b, w.ntiles, E4));
         RCHECK(batch_alloc(b, w.flags, E4 / 4 + 256));
+        RCHECK(batch_alloc(b, w.codes, E4 * 4));
         RCHECK(batch_alloc(b, w.dkeys, E4));
         RCHECK(batch_alloc(b, w.dvals, E4));
         RCHECK(batch_alloc(b, w.dkeys2, E4));

@@ -114,11 +114,12 @@ hipError_t launch_fill_u32(hipStream_t s, uint32_t *p, uint32_t v, int64_t count
 
 // a1: projection of every task; optionally also writes the depth-sort keys
 // (float bits of depth for elements that emit pairs, 0xFFFFFFFF otherwise) and
-// values (Gaussian id within its scene) of every element.
+// values (Gaussian id within its scene) of every element, and (if `codes` is
+// not NULL) every element's 16-byte span code (fs_tiles.h), two u64 per element.
 hipError_t launch_project(hipStream_t s, const ProjTask *tasks, int32_t n_tasks, uint32_t n_blocks,
                           const SceneDev *scenes, const ViewDev *views, const ProjParams &p, float *rec,
                           int16_t *rect, int32_t *ntiles, uint8_t *flags, uint32_t *dkeys, uint32_t *dvals,
-                          unsigned long long *status);
+                          uint64_t *codes, unsigned long long *status);
 
 // depth-sort keys from existing projection planes (same rule as above)
 hipError_t launch_depth_keys(hipStream_t s, const float *rec, const int32_t *ntiles, const uint8_t *flags,
@@ -174,11 +175,13 @@ struct Slab {
 // counts[i] = listed tiles of depth-sorted element i that lie in the slab and
 // whose tile is not marked in `done` (NULL: no tile is done); 0 outside the slab.
 // `flags` may be NULL when float64 conics are on: rec's float64 mark then
-// gives the degenerate flag, and one gather per element is saved.
+// gives the degenerate flag, and one gather per element is saved. `codes` as
+// for launch_emit.
 hipError_t launch_slab_counts(hipStream_t s, const uint32_t *sorted_keys, const uint32_t *sorted_vals,
                               const float *rec, const int16_t *rect, const uint8_t *flags, const int32_t *ntiles,
                               const ViewDev *views, int32_t n_views, int64_t total, Slab slab, const uint8_t *done,
-                              int32_t tile_w, int32_t tile_h, float sigma_k, uint32_t *counts);
+                              int32_t tile_w, int32_t tile_h, float sigma_k, const uint64_t *codes,
+                              uint32_t *counts);
 
 // emits, for every depth-sorted element, one (tile, id) pair per listed tile
 // (the row_span rule) at offsets[i]; pairs at or beyond `capacity` are
@@ -186,12 +189,14 @@ hipError_t launch_slab_counts(hipStream_t s, const uint32_t *sorted_keys, const 
 // (tiles marked in `done`, if not NULL, are skipped, as in launch_slab_counts;
 // `flags` may be NULL as there). With gbits > 0 each pair is one packed item
 // (tile index within its view << gbits) | Gaussian id in tiles_out, and
-// vals_out is not used.
+// vals_out is not used. `codes` (may be NULL) are the projection's span
+// codes; elements with one skip the row_span recomputation.
 hipError_t launch_emit(hipStream_t s, const uint32_t *sorted_keys, const uint32_t *sorted_vals,
                        const uint32_t *offsets, const uint32_t *counts, const float *rec, const int16_t *rect,
                        const uint8_t *flags, const ViewDev *views, int32_t n_views, int64_t total,
                        uint32_t capacity, int32_t tile_w, int32_t tile_h, float sigma_k, const uint8_t *done,
-                       uint32_t *tiles_out, uint32_t *vals_out, unsigned long long *status, int32_t gbits = 0);
+                       uint32_t *tiles_out, uint32_t *vals_out, unsigned long long *status, int32_t gbits = 0,
+                       const uint64_t *codes = nullptr);
 
 // ranges[t] = [starts[t], starts[t] + counts[t]), or [0, 0) if counts[t] == 0
 hipError_t launch_count_ranges(hipStream_t s, const uint32_t *counts, const uint32_t *starts, int64_t n_tiles,

@@ -21,7 +21,7 @@ __global__ __launch_bounds__(256) void k_project(const ProjTask *__restrict__ ta
                                                  ProjParams P, float4 *__restrict__ rec, short4 *__restrict__ rect,
                                                  int32_t *__restrict__ ntiles, uint8_t *__restrict__ flags,
                                                  uint32_t *__restrict__ dkeys, uint32_t *__restrict__ dvals,
-                                                 unsigned long long *__restrict__ status)
+                                                 ulonglong2 *__restrict__ codes, unsigned long long *__restrict__ status)
 {
     int lo = 0, hi = n_tasks - 1;
     while (lo < hi) {
@@ -79,6 +79,7 @@ __global__ __launch_bounds__(256) void k_project(const ProjTask *__restrict__ ta
         const int64_t idx = (int64_t)C.elem_off + g;
         uint8_t f = 0;
         int nt = 0;
+        SpanCode code = no_code();
         short4 rc = make_short4(0, 0, 0, 0);
         float4 r0 = make_float4(0.f, 0.f, 0.f, 0.f), r1 = make_float4(0.f, 0.f, 0.f, 0.f);
         if (live && !valid) {
@@ -162,9 +163,13 @@ __global__ __launch_bounds__(256) void k_project(const ProjTask *__restrict__ ta
                         // tiles of the rectangle that the support ellipse reaches, row by row,
                         // from the float32 conic computed above (c/det, -b/det, a/det)
                         const Span32 sp = make_span32(u, vv, ca, cb, cc, deg, support_limit(P.sigma_k));
+                        const bool small = y1 - y0 < kSpanCodeRows && x1 - x0 < 16;
                         for (int ty = y0; ty <= y1; ++ty) {
                             int l, r;
-                            if (row_span(sp, ty, x0, x1, P.tile_w, P.tile_h, C.W, C.H, l, r)) nt += r - l + 1;
+                            if (row_span(sp, ty, x0, x1, P.tile_w, P.tile_h, C.W, C.H, l, r)) {
+                                nt += r - l + 1;
+                                if (small) code_set(code, ty - y0, l, r, x0);
+                            }
                         }
                     }
                 }
@@ -176,6 +181,7 @@ __global__ __launch_bounds__(256) void k_project(const ProjTask *__restrict__ ta
             rect[idx] = rc;
             ntiles[idx] = nt;
             flags[idx] = f;
+            if (codes) codes[idx] = make_ulonglong2(code.lo, code.hi);
             if (dkeys) {
                 // depth-sort key: positive float bits order like the depths; the
                 // sentinel puts elements without pairs last
@@ -208,12 +214,12 @@ __global__ __launch_bounds__(256) void k_project(const ProjTask *__restrict__ ta
 hipError_t launch_project(hipStream_t s, const ProjTask *tasks, int32_t n_tasks, uint32_t n_blocks,
                           const SceneDev *scenes, const ViewDev *views, const ProjParams &p, float *rec,
                           int16_t *rect, int32_t *ntiles, uint8_t *flags, uint32_t *dkeys, uint32_t *dvals,
-                          unsigned long long *status)
+                          uint64_t *codes, unsigned long long *status)
 {
     if (n_blocks == 0 || n_tasks == 0) return hipSuccess;
     hipLaunchKernelGGL(k_project, dim3(n_blocks), dim3(256), 0, s, tasks, n_tasks, scenes, views, p,
                        reinterpret_cast<float4 *>(rec), reinterpret_cast<short4 *>(rect), ntiles, flags, dkeys, dvals,
-                       status);
+                       reinterpret_cast<ulonglong2 *>(codes), status);
     return hipGetLastError();
 }
 

@@ -359,7 +359,7 @@ __global__ void k_slab_counts(const uint32_t *__restrict__ skeys, const uint32_t
                               const uint8_t *__restrict__ flags, const int32_t *__restrict__ ntiles,
                               const ViewDev *__restrict__ views, int32_t n_views, int64_t total, Slab sl,
                               const uint8_t *__restrict__ done, int32_t tw, int32_t th, float sigma_k,
-                              uint32_t *__restrict__ counts)
+                              const ulonglong2 *__restrict__ codes, uint32_t *__restrict__ counts)
 {
     int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= total) return;
@@ -373,13 +373,19 @@ __global__ void k_slab_counts(const uint32_t *__restrict__ skeys, const uint32_t
                 c = (uint32_t)ntiles[idx];
             } else {
                 const short4 rc = rect[idx];
-                const float4 r0 = rec[2 * idx];
-                const float4 r1 = rec[2 * idx + 1];
-                const bool deg = flags ? (flags[idx] & 2u) != 0 : r1.w != 0.0f;
-                const Span32 sp = make_span32(r0.x, r0.y, r0.z, r0.w, r1.x, deg, support_limit(sigma_k));
+                const SpanCode code = load_code(codes, idx);
+                Span32 sp = make_span32(0.f, 0.f, 1.f, 0.f, 1.f, true, 1.0f);
+                if (!has_code(code)) {
+                    const float4 r0 = rec[2 * idx];
+                    const float4 r1 = rec[2 * idx + 1];
+                    const bool deg = flags ? (flags[idx] & 2u) != 0 : r1.w != 0.0f;
+                    sp = make_span32(r0.x, r0.y, r0.z, r0.w, r1.x, deg, support_limit(sigma_k));
+                }
                 for (int ty = rc.y; ty <= rc.w; ++ty) {
                     int l, r;
-                    if (!row_span(sp, ty, rc.x, rc.z, tw, th, C.W, C.H, l, r)) continue;
+                    const bool any = has_code(code) ? code_span(code, ty - rc.y, rc.x, l, r)
+                                                    : row_span(sp, ty, rc.x, rc.z, tw, th, C.W, C.H, l, r);
+                    if (!any) continue;
                     const uint8_t *d = done + C.tile_base + (uint32_t)ty * (uint32_t)C.tiles_x;
                     for (int t = l; t <= r; ++t) c += d[t] ? 0u : 1u;
                 }
@@ -404,7 +410,7 @@ __global__ __launch_bounds__(kThreads) void k_emit(const uint32_t *__restrict__ 
                                                    float sigma_k, const uint8_t *__restrict__ done,
                                                    uint32_t *__restrict__ tiles_out,
                                                    uint32_t *__restrict__ vals_out, unsigned long long *__restrict__ status,
-                                                   int32_t gbits)
+                                                   int32_t gbits, const ulonglong2 *__restrict__ codes)
 {
     __shared__ uint32_t s_t[kEmitWin];
     __shared__ uint32_t s_g[kEmitWin];
@@ -423,6 +429,7 @@ __global__ __launch_bounds__(kThreads) void k_emit(const uint32_t *__restrict__ 
     uint32_t g = 0, tbase = 0, tiles_x = 0;
     short4 rc = make_short4(0, 0, -1, -1);
     Span32 sp = make_span32(0.f, 0.f, 1.f, 0.f, 1.f, true, 1.0f);
+    SpanCode code = no_code();
     int W = 0, H = 0;
     if (cnt > 0) {
         const int vw = find_view_of_elem(views, n_views, i);
@@ -430,12 +437,15 @@ __global__ __launch_bounds__(kThreads) void k_emit(const uint32_t *__restrict__ 
         const ViewDev &C = views[vw];
         const int64_t idx = (int64_t)C.elem_off + g;
         rc = rect[idx];
-        const float4 r0 = rec[2 * idx];
-        const float4 r1 = rec[2 * idx + 1];
-        // without the flag plane, rec's float64-conic mark stands for the
-        // degenerate flag (the two agree whenever float64 conics are on)
-        const bool deg = flags ? (flags[idx] & 2u) != 0 : r1.w != 0.0f;
-        sp = make_span32(r0.x, r0.y, r0.z, r0.w, r1.x, deg, support_limit(sigma_k));
+        code = load_code(codes, idx);
+        if (!has_code(code)) {
+            const float4 r0 = rec[2 * idx];
+            const float4 r1 = rec[2 * idx + 1];
+            // without the flag plane, rec's float64-conic mark stands for the
+            // degenerate flag (the two agree whenever float64 conics are on)
+            const bool deg = flags ? (flags[idx] & 2u) != 0 : r1.w != 0.0f;
+            sp = make_span32(r0.x, r0.y, r0.z, r0.w, r1.x, deg, support_limit(sigma_k));
+        }
         tbase = C.tile_base;
         tiles_x = (uint32_t)C.tiles_x;
         W = C.W;
@@ -448,7 +458,9 @@ __global__ __launch_bounds__(kThreads) void k_emit(const uint32_t *__restrict__ 
             uint32_t p = off;
             for (int ty = rc.y; ty <= rc.w && p < wend; ++ty) {
                 int l, r;
-                if (!row_span(sp, ty, rc.x, rc.z, tw, th, W, H, l, r)) continue;
+                const bool any = has_code(code) ? code_span(code, ty - rc.y, rc.x, l, r)
+                                                : row_span(sp, ty, rc.x, rc.z, tw, th, W, H, l, r);
+                if (!any) continue;
                 const uint32_t rowbase = tbase + (uint32_t)ty * tiles_x;
                 const uint32_t outbase = gbits ? rowbase - tbase : rowbase;  // packed: the view's local tile
                 if (done == nullptr) {
@@ -739,13 +751,13 @@ hipError_t launch_emit(hipStream_t s, const uint32_t *sorted_keys, const uint32_
                        const uint8_t *flags, const ViewDev *views, int32_t n_views, int64_t total,
                        uint32_t capacity, int32_t tile_w, int32_t tile_h, float sigma_k, const uint8_t *done,
                        uint32_t *tiles_out,
-                       uint32_t *vals_out, unsigned long long *status, int32_t gbits)
+                       uint32_t *vals_out, unsigned long long *status, int32_t gbits, const uint64_t *codes)
 {
     if (total == 0) return hipSuccess;
     hipLaunchKernelGGL(k_emit, dim3(grid_for(total, kThreads)), dim3(kThreads), 0, s, sorted_keys, sorted_vals, offsets,
                        counts, reinterpret_cast<const float4 *>(rec), reinterpret_cast<const short4 *>(rect), flags,
                        views, n_views, total, capacity, tile_w, tile_h, sigma_k, done, tiles_out, vals_out, status,
-                       gbits);
+                       gbits, reinterpret_cast<const ulonglong2 *>(codes));
     return hipGetLastError();
 }
 
@@ -771,12 +783,14 @@ hipError_t launch_slab_offsets(hipStream_t s, const uint32_t *offsets, const Vie
 hipError_t launch_slab_counts(hipStream_t s, const uint32_t *sorted_keys, const uint32_t *sorted_vals,
                               const float *rec, const int16_t *rect, const uint8_t *flags, const int32_t *ntiles,
                               const ViewDev *views, int32_t n_views, int64_t total, Slab slab, const uint8_t *done,
-                              int32_t tile_w, int32_t tile_h, float sigma_k, uint32_t *counts)
+                              int32_t tile_w, int32_t tile_h, float sigma_k, const uint64_t *codes,
+                              uint32_t *counts)
 {
     if (total == 0) return hipSuccess;
     hipLaunchKernelGGL(k_slab_counts, dim3(grid_for(total, 256)), dim3(256), 0, s, sorted_keys, sorted_vals,
                        reinterpret_cast<const float4 *>(rec), reinterpret_cast<const short4 *>(rect), flags, ntiles,
-                       views, n_views, total, slab, done, tile_w, tile_h, sigma_k, counts);
+                       views, n_views, total, slab, done, tile_w, tile_h, sigma_k,
+                       reinterpret_cast<const ulonglong2 *>(codes), counts);
     return hipGetLastError();
 }
 

@@ -17,7 +17,8 @@
 // column inside [Xmin, Xmax], within the image and the splat's tile
 // rectangle. Splats whose conic was inverted in float64 list their whole
 // rectangle. Per row this is O(1) work; the count (fs_project) and the
-// emission (fs_bin_sort) share this code, so they agree exactly.
+// emission (fs_bin_sort) share this code, so they agree exactly. Small splats
+// hand their spans from the count to the emission as a span code (below).
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -88,6 +89,47 @@ __device__ __forceinline__ bool row_span(const Span32 &s, int ty, int x0, int x1
     l = a;
     r = b;
     return true;
+}
+
+// Span codes. A splat whose tile rectangle has at most kSpanCodeRows rows and
+// 16 columns keeps the spans the count found in 16 bytes: byte k describes row
+// y0 + k as (l - x0) | (r - l) << 4, and 0xFF marks an empty (or absent) row;
+// 0xFF is never a valid span there, since l - x0 = 15 forces r = l. Any other
+// splat gets the code with every byte 0xFF (no_code) and its spans are
+// recomputed with row_span; a splat whose rows are all empty has that code
+// too, but it lists no tile.
+constexpr int kSpanCodeRows = 16;
+
+struct SpanCode {
+    uint64_t lo, hi;  // rows 0-7, rows 8-15
+};
+
+__device__ __forceinline__ SpanCode no_code() { return SpanCode{~0ull, ~0ull}; }
+
+__device__ __forceinline__ bool has_code(const SpanCode &c) { return (c.lo & c.hi) != ~0ull; }
+
+__device__ __forceinline__ void code_set(SpanCode &c, int row, int l, int r, int x0)
+{
+    const uint64_t byte = (uint64_t)(uint32_t)(l - x0) | ((uint64_t)(uint32_t)(r - l) << 4);
+    const uint32_t sh = 8u * (uint32_t)(row & 7);
+    if (row < 8) c.lo = (c.lo & ~(0xFFull << sh)) | (byte << sh);
+    else c.hi = (c.hi & ~(0xFFull << sh)) | (byte << sh);
+}
+
+__device__ __forceinline__ bool code_span(const SpanCode &c, int row, int x0, int &l, int &r)
+{
+    const uint32_t byte = (uint32_t)(((row < 8 ? c.lo : c.hi) >> (8u * (uint32_t)(row & 7))) & 0xFFull);
+    if (byte == 0xFFu) return false;
+    l = x0 + (int)(byte & 15u);
+    r = l + (int)(byte >> 4);
+    return true;
+}
+
+__device__ __forceinline__ SpanCode load_code(const ulonglong2 *codes, int64_t idx)
+{
+    if (codes == nullptr) return no_code();
+    const ulonglong2 q = codes[idx];
+    return SpanCode{q.x, q.y};
 }
 
 }  // namespace fs
