@@ -137,8 +137,10 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(7, 7))) voi
                                                float *__restrict__ tstate, uint8_t *__restrict__ tile_done,
                                                int32_t first, unsigned long long *__restrict__ status)
 {
-    // staged entry e: s_rec[e] = (u, v, a', b'), (c', lo, thr, 0), with the conic scaled to log2
-    // units, lo = log2(opacity) and thr = cut2 + lo; entry kBatch is a null record
+    // staged entry e: s_rec[e] = (u, v, a', b'), (c', lo, thr, sup), with the conic scaled to
+    // log2 units, lo = log2(opacity), sup = cut2 + lo (the support bound on the power) and
+    // thr = max(sup, log2(alpha_min)): a weight is taken only if the power reaches thr, which
+    // is the support test and the alpha_min test in one comparison; entry kBatch is a null record
     __shared__ float4 s_rec[2 * (kBatch + 1)];
     __shared__ uint32_t s_g[kBatch];
     __shared__ float s_part[kBatch][kSlots];
@@ -212,7 +214,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(7, 7))) voi
     for (int i = tid; i < kBatch * kSlots; i += 256) (&s_part[0][0])[i] = 0.0f;
     if (tid == 0) {  // null record: far away, never inside its support, zero opacity
         s_rec[2 * kBatch] = make_float4(-1.0e6f, -1.0e6f, 0.0f, 0.0f);
-        s_rec[2 * kBatch + 1] = make_float4(0.0f, kLoFloor, 3.0e38f, 0.0f);
+        s_rec[2 * kBatch + 1] = make_float4(0.0f, kLoFloor, 3.0e38f, 3.0e38f);
     }
 
     const uint2 rg = ranges[tile];
@@ -262,7 +264,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(7, 7))) voi
             const float4 r1 = rec[(rec_base + g) * 2 + 1];
             const float lo = fmaxf(__builtin_amdgcn_logf(r1.y), kLoFloor);
             s_rec[2 * tid] = make_float4(r0.x, r0.y, -0.5f * LOG2E * r0.z, -LOG2E * r0.w);
-            s_rec[2 * tid + 1] = make_float4(-0.5f * LOG2E * r1.x, lo, P.cut2 + lo, 0.0f);
+            s_rec[2 * tid + 1] = make_float4(-0.5f * LOG2E * r1.x, lo, fmaxf(P.cut2 + lo, P.lmin), P.cut2 + lo);
             s_g[tid] = g;
             uint32_t m = 0xFu;
             if (r1.w == 0.0f) {  // float32 conic: cull the waves whose live pixels the support cannot reach
@@ -298,18 +300,17 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(7, 7))) voi
 
         // one front-to-back step of this lane's pixel over a staged entry (branch-free):
         // power in log2 units via Horner with log2(opacity) folded in, so that
-        // alpha = min(alpha_max, 2^(power + lo)); the support test compares against thr
+        // alpha = min(alpha_max, 2^(power + lo)); support and alpha_min tests against thr
         auto step = [&](const float4 q, const float4 q2) -> float {
             const float dx = pxc - q.x, dy = pyc - q.y;
             const float pw = fmaf(fmaf(q.z, dx, q.w * dy), dx, fmaf(q2.x * dy, dy, q2.y));
-            const bool insup = live && pw >= q2.z;
             const float alpha = fminf(P.alpha_max, __builtin_amdgcn_exp2f(pw));
-            const bool ok = insup && alpha >= P.alpha_min;
+            const bool ok = live && pw >= q2.z;
             const float Tn = fmaf(-T, alpha, T);
             const bool stop = ok && Tn < P.t_min;
             const bool take = ok && !stop;
             if (COUNT) {
-                ne_l += insup ? 1u : 0u;
+                ne_l += (live && pw >= q2.w) ? 1u : 0u;
                 nb_l += take ? 1u : 0u;
             }
             const float wv = take ? alpha * T : 0.0f;

@@ -242,6 +242,7 @@ AccParams acc_params(const fs_params *p, int32_t reduction)
     ap.alpha_min = p->alpha_min;
     ap.alpha_max = p->alpha_max;
     ap.t_min = p->t_min;
+    ap.lmin = p->alpha_min > 0.0f ? (float)std::log2((double)p->alpha_min) : -INFINITY;
     ap.tile_w = p->tile_w;
     ap.tile_h = p->tile_h;
     ap.reduction = reduction;

@@ -222,6 +222,7 @@ hipError_t launch_tile_keys(hipStream_t s, const uint32_t *ranges, int64_t n_til
 struct AccParams {
     float cut2;       // -0.5*k^2*log2(e): support bound on the log2-scaled power
     float alpha_min, alpha_max, t_min;
+    float lmin;       // log2(alpha_min) (-inf for 0): alpha >= alpha_min as a bound on the power
     int32_t tile_w, tile_h;
     int32_t reduction;
     int32_t count;    // 1: count in-support evaluations and blends

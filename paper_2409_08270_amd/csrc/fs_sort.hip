@@ -239,6 +239,7 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(4))) v
     // counts of all segments, so it is already a position in the whole array
     s_gofs[threadIdx.x] = offs[(int64_t)si.blk0 * 256 + (int64_t)threadIdx.x * si.bps + si.lb];
     const unsigned long long lt = (1ull << lane) - 1ull;
+    const int dbits = 32 - __clz(dmask);  // digit width (dmask is 2^dbits - 1)
 
     for (int tb = 0; tb * kTile < si.nvalid; ++tb) {
         const int nvalid = min(kTile, si.nvalid - tb * kTile);
@@ -261,6 +262,7 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(4))) v
             unsigned long long peers = ~0ull;
 #pragma unroll
             for (int bit = 0; bit < 8; ++bit) {
+                if (bit >= dbits) break;
                 const bool on = (d >> bit) & 1u;
                 const unsigned long long bb = __ballot(on);
                 peers &= on ? bb : ~bb;
