@@ -298,24 +298,33 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(7, 7))) voi
         if (lane < 16) s_list[w][nlist + lane] = (uint32_t)kBatch * 32u;  // pad the last group with the null record
         __builtin_amdgcn_wave_barrier();
 
-        // one front-to-back step of this lane's pixel over a staged entry (branch-free):
-        // power in log2 units via Horner with log2(opacity) folded in, so that
-        // alpha = min(alpha_max, 2^(power + lo)); support and alpha_min tests against thr
+        // one front-to-back step of this lane's pixel over a staged entry: power in
+        // log2 units via Horner with log2(opacity) folded in, so that
+        // alpha = min(alpha_max, 2^(power + lo)); support and alpha_min tests against
+        // thr. A lane that fails them gets alpha = 0, which leaves T exactly as it is
+        // and adds nothing. A pixel stops (Eq. (1)'s transmittance cut) at most once,
+        // so the step where some lane does is fixed up under a wave-uniform branch:
+        // that lane adds no weight and keeps its T.
         auto step = [&](const float4 q, const float4 q2) -> float {
             const float dx = pxc - q.x, dy = pyc - q.y;
             const float pw = fmaf(fmaf(q.z, dx, q.w * dy), dx, fmaf(q2.x * dy, dy, q2.y));
-            const float alpha = fminf(P.alpha_max, __builtin_amdgcn_exp2f(pw));
             const bool ok = live && pw >= q2.z;
-            const float Tn = fmaf(-T, alpha, T);
-            const bool stop = ok && Tn < P.t_min;
-            const bool take = ok && !stop;
+            const float alpha = ok ? fminf(P.alpha_max, __builtin_amdgcn_exp2f(pw)) : 0.0f;
+            float wv = alpha * T;
+            float Tn = fmaf(-T, alpha, T);
+            // only a lane that takes a weight can stop: every other lane keeps a T
+            // that is at least t_min (or 1 for pixels outside the image)
+            const bool stop = Tn < P.t_min;
+            if (__builtin_expect(__ballot(stop) != 0ull, 0)) {
+                wv = stop ? 0.0f : wv;
+                Tn = stop ? T : Tn;
+            }
             if (COUNT) {
                 ne_l += (live && pw >= q2.w) ? 1u : 0u;
-                nb_l += take ? 1u : 0u;
+                nb_l += (ok && !stop) ? 1u : 0u;
             }
-            const float wv = take ? alpha * T : 0.0f;
-            T = take ? Tn : T;
             live = live && !stop;
+            T = Tn;
             return wv;
         };
         auto rec_at = [&](uint32_t off) -> const float4 * {
