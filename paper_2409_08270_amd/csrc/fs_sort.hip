@@ -80,21 +80,52 @@ __global__ __launch_bounds__(kThreads) void k_scan_down(const uint32_t *__restri
 {
     __shared__ uint32_t s_wsum[kWaves];
     const int64_t base = (int64_t)blockIdx.x * kTile + (int64_t)threadIdx.x * kItems;
+    // 16-byte accesses where the thread's 16 elements are whole and aligned
+    const bool vec = base + kItems <= n &&
+                     ((reinterpret_cast<uintptr_t>(in + base) | reinterpret_cast<uintptr_t>(out + base)) & 15u) == 0;
     uint32_t v[kItems];
     uint32_t acc = 0;
+    if (vec) {
 #pragma unroll
-    for (int k = 0; k < kItems; ++k) {
-        int64_t i = base + k;
-        v[k] = i < n ? in[i] : 0u;
-        acc += v[k];
+        for (int q = 0; q < kItems / 4; ++q) {
+            const uint4 x = *reinterpret_cast<const uint4 *>(in + base + 4 * q);
+            v[4 * q] = x.x;
+            v[4 * q + 1] = x.y;
+            v[4 * q + 2] = x.z;
+            v[4 * q + 3] = x.w;
+        }
+    } else {
+#pragma unroll
+        for (int k = 0; k < kItems; ++k) {
+            int64_t i = base + k;
+            v[k] = i < n ? in[i] : 0u;
+        }
     }
+#pragma unroll
+    for (int k = 0; k < kItems; ++k) acc += v[k];
     uint32_t tot;
     uint32_t ex = block_excl_scan(acc, s_wsum, tot) + (offs ? offs[blockIdx.x] : 0u);
+    if (vec) {
 #pragma unroll
-    for (int k = 0; k < kItems; ++k) {
-        int64_t i = base + k;
-        if (i < n) out[i] = ex;
-        ex += v[k];
+        for (int q = 0; q < kItems / 4; ++q) {
+            uint4 y;
+            y.x = ex;
+            ex += v[4 * q];
+            y.y = ex;
+            ex += v[4 * q + 1];
+            y.z = ex;
+            ex += v[4 * q + 2];
+            y.w = ex;
+            ex += v[4 * q + 3];
+            *reinterpret_cast<uint4 *>(out + base + 4 * q) = y;
+        }
+    } else {
+#pragma unroll
+        for (int k = 0; k < kItems; ++k) {
+            int64_t i = base + k;
+            if (i < n) out[i] = ex;
+            ex += v[k];
+        }
     }
     if (total_out && blockIdx.x == gridDim.x - 1 && threadIdx.x == kThreads - 1) *total_out = ex;
 }
@@ -164,12 +195,18 @@ __global__ __launch_bounds__(kThreads) void k_radix_hist(const uint32_t *__restr
         const uint32_t *k = keys + si.base + (int64_t)tb * kTile;
         if (nvalid == kTile) {
             const bool aligned = ((reinterpret_cast<uintptr_t>(k) & 15u) == 0);
+            // all four loads are issued before any is used, so that each thread
+            // keeps 64 bytes in flight
+            uint4 xq[kItems / 4];
 #pragma unroll
             for (int q = 0; q < kItems / 4; ++q) {
                 const int i0 = 4 * (q * kThreads + threadIdx.x);
-                uint4 x;
-                if (aligned) x = *reinterpret_cast<const uint4 *>(k + i0);
-                else x = make_uint4(k[i0], k[i0 + 1], k[i0 + 2], k[i0 + 3]);
+                if (aligned) xq[q] = *reinterpret_cast<const uint4 *>(k + i0);
+                else xq[q] = make_uint4(k[i0], k[i0 + 1], k[i0 + 2], k[i0 + 3]);
+            }
+#pragma unroll
+            for (int q = 0; q < kItems / 4; ++q) {
+                const uint4 x = xq[q];
                 const uint32_t xs[4] = {x.x, x.y, x.z, x.w};
 #pragma unroll
                 for (int e = 0; e < 4; ++e) {
