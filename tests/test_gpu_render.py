@@ -71,7 +71,8 @@ def _compare(sc, S_host, E, mode, got, tau=0.1, what=""):
             dd = np.where(cand, dep[1:], np.inf)
             srt = np.sort(dd, axis=0)
             if srt.shape[0] > 1:
-                amb |= np.isfinite(srt[1]) & (srt[1] - srt[0] <= 1e-3 * srt[0])
+                with np.errstate(invalid="ignore"):  # inf - inf where no object passes tau
+                    amb |= np.isfinite(srt[1]) & (srt[1] - srt[0] <= 1e-3 * srt[0])
         mism = lab_g[sl].reshape(H, W) != lab
         assert not np.any(mism & ~amb), (what, v, int((mism & ~amb).sum()))
         bad_total += int(mism.sum())
