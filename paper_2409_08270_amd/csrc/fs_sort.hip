@@ -296,14 +296,19 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(4))) v
 #pragma unroll
         for (int r = 0; r < kItems; ++r) {
             const uint32_t d = (key[r] >> shift) & dmask;
-            unsigned long long peers = ~0ull;
+            // lanes whose digit equals this lane's: for every bit, the lanes that
+            // agree with it are ~(ballot ^ m), m = all ones if the bit is set
+            // (one three-input bit operation per half of the 64-bit mask)
+            uint32_t plo = ~0u, phi = ~0u;
 #pragma unroll
             for (int bit = 0; bit < 8; ++bit) {
                 if (bit >= dbits) break;
-                const bool on = (d >> bit) & 1u;
-                const unsigned long long bb = __ballot(on);
-                peers &= on ? bb : ~bb;
+                const uint32_t m = (uint32_t)__builtin_amdgcn_sbfe((int)d, (unsigned)bit, 1u);
+                const unsigned long long bb = __ballot(m != 0u);
+                plo &= ~((uint32_t)bb ^ m);
+                phi &= ~((uint32_t)(bb >> 32) ^ m);
             }
+            const unsigned long long peers = ((unsigned long long)phi << 32) | plo;
             const uint32_t before = s_cnt[w][d];
             rnk[r] = before + (uint32_t)__popcll(peers & lt);
             __builtin_amdgcn_wave_barrier();
