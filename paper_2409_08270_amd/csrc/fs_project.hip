@@ -158,7 +158,8 @@ __global__ __launch_bounds__(256) void k_project(const ProjTask *__restrict__ ta
                           fk0 > fk1 || fj0 > fj1)) {
                         int kmin = (int)fmaxf(fk0, 0.0f), kmax = (int)fminf(fk1, (float)(C.W - 1));
                         int jmin = (int)fmaxf(fj0, 0.0f), jmax = (int)fminf(fj1, (float)(C.H - 1));
-                        int x0 = kmin / P.tile_w, y0 = jmin / P.tile_h, x1 = kmax / P.tile_w, y1 = jmax / P.tile_h;
+                        int x0 = tile_of(kmin, P.tile_w), y0 = tile_of(jmin, P.tile_h);
+                        int x1 = tile_of(kmax, P.tile_w), y1 = tile_of(jmax, P.tile_h);
                         rc = make_short4((short)x0, (short)y0, (short)x1, (short)y1);
                         // tiles of the rectangle that the support ellipse reaches, row by row,
                         // from the float32 conic computed above (c/det, -b/det, a/det)

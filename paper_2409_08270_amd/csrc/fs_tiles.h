@@ -59,6 +59,13 @@ __device__ __forceinline__ float edge_x(const Span32 &s, float y, float sgn)
     return (-(s.B * y) + sgn * r) / s.A;
 }
 
+// n / t for n >= 0: a shift when the tile size t is a power of two (t is the
+// same for every lane, so the choice costs one uniform branch)
+__device__ __forceinline__ int tile_of(int n, int t)
+{
+    return (t & (t - 1)) == 0 ? (n >> (__ffs(t) - 1)) : n / t;
+}
+
 // listed span [l, r] of tile row ty within tile columns [x0, x1]; false if empty
 __device__ __forceinline__ bool row_span(const Span32 &s, int ty, int x0, int x1, int tw, int th, int W, int H,
                                          int &l, int &r)
@@ -82,7 +89,7 @@ __device__ __forceinline__ bool row_span(const Span32 &s, int ty, int x0, int x1
     const float kl = fmaxf(ceilf((s.u + xmin) - 0.5f), 0.0f);
     const float kr = fminf(floorf((s.u + xmax) - 0.5f), (float)(W - 1));
     if (!(kl <= kr)) return false;
-    int a = (int)kl / tw, b = (int)kr / tw;
+    int a = tile_of((int)kl, tw), b = tile_of((int)kr, tw);
     if (a < x0) a = x0;
     if (b > x1) b = x1;
     if (a > b) return false;
