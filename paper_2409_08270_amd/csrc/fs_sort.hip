@@ -74,9 +74,12 @@ __global__ __launch_bounds__(kThreads) void k_scan_reduce(const uint32_t *__rest
     if (threadIdx.x == 0) sums[blockIdx.x] = tot;
 }
 
+// Exclusive scan of block tile blockIdx.x. The tile's offset is offs[b] or,
+// with `raw`, the sum of the block totals offs[0 .. b), added up here (this
+// saves scanning the totals in a launch of their own).
 __global__ __launch_bounds__(kThreads) void k_scan_down(const uint32_t *__restrict__ in, uint32_t *__restrict__ out,
                                                         int64_t n, const uint32_t *__restrict__ offs,
-                                                        uint32_t *__restrict__ total_out)
+                                                        uint32_t *__restrict__ total_out, int32_t raw)
 {
     __shared__ uint32_t s_wsum[kWaves];
     const int64_t base = (int64_t)blockIdx.x * kTile + (int64_t)threadIdx.x * kItems;
@@ -103,8 +106,18 @@ __global__ __launch_bounds__(kThreads) void k_scan_down(const uint32_t *__restri
     }
 #pragma unroll
     for (int k = 0; k < kItems; ++k) acc += v[k];
+    uint32_t pre = 0;
+    if (offs && raw) {
+        uint32_t part = 0;
+        for (int i = threadIdx.x; i < (int)blockIdx.x; i += kThreads) part += offs[i];
+        uint32_t all;
+        block_excl_scan(part, s_wsum, all);
+        pre = all;
+    } else if (offs) {
+        pre = offs[blockIdx.x];
+    }
     uint32_t tot;
-    uint32_t ex = block_excl_scan(acc, s_wsum, tot) + (offs ? offs[blockIdx.x] : 0u);
+    uint32_t ex = block_excl_scan(acc, s_wsum, tot) + pre;
     if (vec) {
 #pragma unroll
         for (int q = 0; q < kItems / 4; ++q) {
@@ -679,15 +692,21 @@ hipError_t scan_exclusive(hipStream_t s, const uint32_t *in, uint32_t *out, int6
     }
     const int64_t blocks = (n + kTile - 1) / kTile;
     if (blocks == 1) {
-        hipLaunchKernelGGL(k_scan_down, dim3(1), dim3(kThreads), 0, s, in, out, n, (const uint32_t *)nullptr, total_out);
+        hipLaunchKernelGGL(k_scan_down, dim3(1), dim3(kThreads), 0, s, in, out, n, (const uint32_t *)nullptr, total_out,
+                           0);
         return hipGetLastError();
     }
     uint32_t *sums = (uint32_t *)ws;
     uint32_t *rest = sums + ((blocks + 64) & ~int64_t(63));
     hipLaunchKernelGGL(k_scan_reduce, dim3((unsigned)blocks), dim3(kThreads), 0, s, in, n, sums);
-    hipError_t e = scan_exclusive(s, sums, sums, blocks, nullptr, rest);
-    if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(k_scan_down, dim3((unsigned)blocks), dim3(kThreads), 0, s, in, out, n, (const uint32_t *)sums, total_out);
+    // up to one tile of block totals: each block adds up the totals before it
+    const bool raw = blocks <= kTile;
+    if (!raw) {
+        hipError_t e = scan_exclusive(s, sums, sums, blocks, nullptr, rest);
+        if (e != hipSuccess) return e;
+    }
+    hipLaunchKernelGGL(k_scan_down, dim3((unsigned)blocks), dim3(kThreads), 0, s, in, out, n, (const uint32_t *)sums,
+                       total_out, raw ? 1 : 0);
     return hipGetLastError();
 }
 
