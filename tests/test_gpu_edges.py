@@ -40,12 +40,24 @@ def _check_bins(ctx, sc, prm, views):
         bins = L.Bins(-n, tt)
         n = ctx.fs_bin_sort(proj, cams, prm, bins)
     vals = bins.vals[:n].cpu().numpy().view(np.uint32)
+    tiles = bins.tiles[:n].cpu().numpy()
+    ranges = bins.ranges[:tt].cpu().numpy().astype(np.int64)
     off = 0
+    tbase = 0
     for v in views:
         b = O.bin_view(sc, v, _oparams(prm))
         cnt = b["g"].size
+        nt = b["ranges"].shape[0]
         assert np.array_equal(vals[off:off + cnt], b["g"])
+        # tile ids (global numbering on the GPU) and every tile's list length
+        assert np.array_equal(tiles[off:off + cnt].astype(np.int64), b["tile"].astype(np.int64) + tbase)
+        r = ranges[tbase:tbase + nt]
+        ro = b["ranges"].astype(np.int64)
+        assert np.array_equal(r[:, 1] - r[:, 0], ro[:, 1] - ro[:, 0])
+        nz = ro[:, 1] > ro[:, 0]
+        assert np.array_equal(r[nz, 0] - off, ro[nz, 0])
         off += cnt
+        tbase += nt
     assert off == n
 
 
@@ -81,6 +93,14 @@ def test_other_tile_shapes(ctx, tw, th):
     prm = L.params(tile_w=tw, tile_h=th)
     _check_bins(ctx, sc, prm, [0, 1, 2])
     _solve_and_compare(ctx, sc, prm, f"tiles {tw}x{th}")
+
+
+@pytest.mark.parametrize("tw,th", [(12, 20), (24, 10), (5, 7)])
+def test_binning_with_tile_sizes_that_are_not_powers_of_two(ctx, tw, th):
+    # projection and binning take any tile size (compositing needs 256-pixel
+    # tiles): tile indices then come from a division rather than a shift
+    sc = sg.make_config("C1", n=1500, views=3, res=100)
+    _check_bins(ctx, sc, L.params(tile_w=tw, tile_h=th), [0, 1, 2])
 
 
 def test_tile_shape_does_not_change_A(ctx):
