@@ -8,10 +8,10 @@
 // and every thread walks the batch for its pixel.
 //
 // Scatter-add. The paper adds alpha*T with one atomic per (pixel, Gaussian).
-// Here the distinct labels of the tile are compacted into a few slots; for
-// each Gaussian, each wave sums its lanes' weights per slot with DPP
-// (cross-lane) adds, the four waves combine in an LDS partial, and one
-// global atomic per (tile, Gaussian, label) remains. With A_lo, the exact
+// Here the distinct labels of the tile are compacted into a few slots; each
+// wave sums its lanes' weights of 8 Gaussians at once per slot with a
+// cross-lane reduce-scatter, the four waves combine in an LDS partial, and
+// one global atomic per (tile, Gaussian, label) remains. With A_lo, the exact
 // rounding error of that atomic (two-sum on the returned old value) goes to
 // A_lo, so that A_hi + A_lo carries the sum to about one rounding.
 #include "fs_internal.h"
@@ -40,20 +40,6 @@ __device__ __forceinline__ float dpp_xor4(float x)
     int r = __builtin_amdgcn_update_dpp(xi, xi, 0x104, 0xF, 0x5, false);
     r = __builtin_amdgcn_update_dpp(r, xi, 0x114, 0xF, 0xA, false);
     return __int_as_float(r);
-}
-
-// sum over the 64 lanes; the result is returned in every lane
-__device__ __forceinline__ float wave_sum(float x)
-{
-    x += dpp_mov<0xB1>(x);   // quad_perm [1,0,3,2]
-    x += dpp_mov<0x4E>(x);   // quad_perm [2,3,0,1]
-    x += dpp_mov<0x124>(x);  // row_ror:4
-    x += dpp_mov<0x128>(x);  // row_ror:8  -> every lane holds its row's sum
-    const float r0 = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(x), 0));
-    const float r1 = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(x), 16));
-    const float r2 = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(x), 32));
-    const float r3 = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(x), 48));
-    return (r0 + r1) + (r2 + r3);
 }
 
 // Butterfly reduce-scatter of 8 per-lane values over the 64 lanes: on return,
@@ -332,8 +318,9 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(7, 7))) voi
         };
 
         if (__ballot(live) != 0ull) {
-            if (!plain && __popc(wslots) == 1) {
-                // single label in this wave: the weights of 8 entries are summed at once
+            if (!plain) {
+                // the weights of 8 entries are summed at once, per label of the wave
+                const bool one = __popc(wslots) == 1;
                 const int slot0 = __ffs(wslots) - 1;
                 for (int g0 = 0; g0 < nlist; g0 += 8) {
                     steps_w += 8;
@@ -356,31 +343,34 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(7, 7))) voi
                         q = qn;
                         q2 = qn2;
                     }
-                    const float tot = reduce_scatter8(wr);
                     const int e = lane >> 3;
-                    if ((lane & 7) == 0 && g0 + e < nlist && tot != 0.0f)
-                        atomicAdd(&s_part[s_list[w][g0 + e] >> 5][slot0], tot);
+                    const bool head = (lane & 7) == 0 && g0 + e < nlist;
+                    if (one) {
+                        const float tot = reduce_scatter8(wr);
+                        if (head && tot != 0.0f) atomicAdd(&s_part[s_list[w][g0 + e] >> 5][slot0], tot);
+                    } else {
+                        // several labels in this wave's block: one reduce-scatter per label
+                        uint32_t sl = wslots;
+                        while (sl) {
+                            const int sidx = __ffs(sl) - 1;
+                            sl &= sl - 1u;
+                            float v[8];
+#pragma unroll
+                            for (int k = 0; k < 8; ++k) v[k] = slot == sidx ? wr[k] : 0.0f;
+                            const float tot = reduce_scatter8(v);
+                            if (head && tot != 0.0f) atomicAdd(&s_part[s_list[w][g0 + e] >> 5][sidx], tot);
+                        }
+                    }
                     if (__ballot(live) == 0ull) break;
                 }
             } else {
+                // the paper's scheme: one global atomic per (pixel, Gaussian)
                 for (int it = 0; it < nlist; ++it) {
                     steps_w += 1;
                     const uint32_t off = s_list[w][it];
                     const uint32_t j = off >> 5;
                     const float wgt = step(rec_at(off)[0], rec_at(off)[1]);
-                    if (__ballot(wgt != 0.0f)) {
-                        if (plain) {
-                            if (wgt != 0.0f) add_global(A_hi, A_lo, (int64_t)s_g[j] * E + lab, wgt);
-                        } else {
-                            uint32_t sl = wslots;
-                            while (sl) {
-                                const int sidx = __ffs(sl) - 1;
-                                sl &= sl - 1u;
-                                const float part = wave_sum(slot == sidx ? wgt : 0.0f);
-                                if (lane == 0 && part != 0.0f) atomicAdd(&s_part[j][sidx], part);
-                            }
-                        }
-                    }
+                    if (wgt != 0.0f) add_global(A_hi, A_lo, (int64_t)s_g[j] * E + lab, wgt);
                     if ((it & 15) == 15 && __ballot(live) == 0ull) break;
                 }
             }
