@@ -188,8 +188,10 @@ int fs_last_accumulate_ms(fs_ctx *ctx, float *ms);
 /* a1: projection (Sec. 3.1; EWA splatting of 3DGS, which the paper's renderer
  * inherits). For every view v in cams[0..n_views) and Gaussian g: camera-space
  * mean, 2D covariance J W Sigma3 W^T J^T + lowpass*I, its inverse (conic),
- * pixel mean, depth, bounding radius ceil(sigma_k*sqrt(lambda_max)) and the
- * tile rectangle of the pixel square mean +- radius. Visibility, rectangle and
+ * pixel mean, depth, the per-axis half extents rx = ceil(sigma_k*sqrt(cov_xx)),
+ * ry = ceil(sigma_k*sqrt(cov_yy)) of the support ellipse (its exact bounding
+ * box, rounded up to whole pixels) and the tile rectangle of the pixel box
+ * mean +- (rx, ry). Visibility, rectangle and
  * ntiles are computed in strict binary32 in a fixed operation order (the
  * bit-exact contract); the conic is float32 except for splats selected by
  * fp64_cond, which are inverted in float64. cams: host [n_views];
@@ -226,8 +228,10 @@ int fs_accumulate(fs_ctx *ctx, const fs_proj *proj, const fs_bins *bins, const f
 
 /* a7: assignment (Sec. 3.2 Eq. (7) and "Regularized ILP"; Sec. 3.3 Eq. (8);
  * Listing 1 of the supplement). For every Gaussian g and object t:
- * a = A[g][t], o = sum_{e != t} A[g][e] (prefix + suffix sums, no
- * subtraction), (o_n, a_n) = (o, a) / max(o + a, 1e-12);
+ * a = A[g][t], o = sum_{e != t} A[g][e], formed as the row total minus a
+ * (as Listing 1 does; the row total is summed once per Gaussian in float64
+ * from A_hi + A_lo, so o is exact to about 1e-16 of the row sum and is
+ * clamped at 0), (o_n, a_n) = (o, a) / max(o + a, 1e-12);
  * S[t][g] = a_n > o_n + gamma (ties go to "others"); margin[t][g] =
  * |a_n - o_n - gamma|. Sums are formed in float64 from A_hi + A_lo.
  * A_hi, A_lo (A_lo may be NULL): device float32 [n][n_classes].
@@ -289,7 +293,7 @@ int fs_render_masks(fs_ctx *ctx, const fs_proj *proj, const fs_bins *bins, const
  * counts it to show that Gaussians are shared between objects), how many
  * objects' subsets each Gaussian falls in (more than one only for a negative
  * bias, Sec. 3.3), and the overlap of every subset with given per-Gaussian
- * labels (the fewer-masks ablation of Sec. 4.6 reads it as an IoU).
+ * labels (the fewer-masks ablation of Sec. 4.8 reads it as an IoU).
  * A_hi, A_lo: device float [n][n_classes] as fs_accumulate leaves them
  *   (A_lo may be NULL); A_hi NULL skips contrib_hist.
  * S: device uint8 [n_classes][n] (fs_assign's layout); NULL skips

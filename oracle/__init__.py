@@ -27,7 +27,7 @@ Pieces (paper sections in brackets):
   diagnose64             per-Gaussian diagnostics: objects each Gaussian
                          contributes to, subsets it falls in, overlap of each
                          subset with given labels [supplement "Scene
-                         segmentation extension", Sec. 4.6 fewer masks]
+                         segmentation extension", Sec. 4.8 fewer masks]
   objective_eq2 / brute_force_binary   exhaustive checks of Eq. (2)/(6)
 """
 from __future__ import annotations
@@ -319,7 +319,7 @@ def diagnose64(A: Optional[np.ndarray], S: Optional[np.ndarray] = None, gt: Opti
     member[m]: Gaussians held by exactly m rows of S (Sec. 3.3: more than one
       only for a negative bias);
     overlap[e] = (|S_e and gt = e|, |S_e|, |gt = e|), read as an IoU in the
-      fewer-masks ablation (Sec. 4.6).
+      fewer-masks ablation (Sec. 4.8).
     A: float64 [n][E] or None; S: [E][n] or None; gt: int [n] or None."""
     out = [None, None, None]
     if A is not None:

@@ -1,6 +1,6 @@
 // Per-Gaussian diagnostics of a solved scene (the supplement's "Scene
 // segmentation extension", its count of the objects each Gaussian contributes
-// to, and the fewer-masks ablation of Sec. 4.6):
+// to, and the fewer-masks ablation of Sec. 4.8):
 //   contrib[c]  Gaussians with exactly c objects e whose A[g][e] exceeds
 //               rel_eps times the row's total (c = 0 also holds unseen rows);
 //   member[m]   Gaussians that belong to exactly m rows of S (m > 1 happens

@@ -1,4 +1,4 @@
-"""The fewer-masks study (Sec. 4.6 and the supplement's ablation on the number
+"""The fewer-masks study (Sec. 4.8 "Ablation study" and the supplement's ablation on the number
 of masks, with its count of the objects each Gaussian contributes to).
 
 Every 1/f-th view of a scene is kept, for several f; all the subsets are

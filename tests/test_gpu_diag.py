@@ -1,5 +1,5 @@
 """GPU per-Gaussian diagnostics and the fewer-masks study against the oracle
-(supplement "Scene segmentation extension"; Sec. 4.6 fewer masks)."""
+(supplement "Scene segmentation extension"; Sec. 4.8 fewer masks)."""
 import numpy as np
 import pytest
 import torch

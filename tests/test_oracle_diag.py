@@ -1,5 +1,5 @@
 """Pins of the oracle's per-Gaussian diagnostics (supplement "Scene
-segmentation extension"; Sec. 4.6 fewer masks), CPU only: hand-counted rows,
+segmentation extension"; Sec. 4.8 fewer masks), CPU only: hand-counted rows,
 the generator's ground-truth labels, and invariants of the assignment."""
 import numpy as np
 
