@@ -7,6 +7,8 @@ path; both sides read the same inputs from `scenegen`.
 Pieces (paper sections in brackets):
   project32 / bin_view   strict binary32 projection and tile binning
                          [Sec. 3.1]; the reference of the bit-exact contract
+  listed_rows32          the tile-listing definition applied to arbitrary
+                         splats (mean, covariance, rectangle)
   project64              binary64 mean2D / conic [Sec. 3.1]
   composite64 / solve64  binary64 alpha compositing, A = sum of alpha*T per
                          (Gaussian, pixel label) [Eq. (1), Eq. (7), Eq. (8),
@@ -91,6 +93,8 @@ def lib():
         L.or_weights64.restype = None
         L.or_render_masks64.argtypes = [I64, P, P, P, P, P, P, P, P, I32, ctypes.c_double, I32, P, P, P]
         L.or_render_masks64.restype = None
+        L.or_listed_rows32.argtypes = [I64, P, P, P, P, I32, I32, I32, I32, ctypes.c_float, I32, P]
+        L.or_listed_rows32.restype = None
         _lib = L
     return _lib
 
@@ -129,6 +133,25 @@ def project32(scene, v: int, prm: np.ndarray, gauss: Optional[np.ndarray] = None
                cov=np.zeros((n, 3), np.float32), mean2d=np.zeros((n, 2), np.float32))
     lib().or_project32(n, _p(g), _p(cam), _p(prm), _p(out["flags"]), _p(out["rect"]),
                        _p(out["ntiles"]), _p(out["depth"]), _p(out["cov"]), _p(out["mean2d"]))
+    return out
+
+
+def listed_rows32(mean2d, cov, flags, rect, tile_w, tile_h, W, H, k=3.0, max_rows=8) -> np.ndarray:
+    """Listed tiles of arbitrary splats, row by row of their tile rectangles.
+
+    mean2d float32 [n][2], cov float32 [n][3] (a, b, c), flags uint8 [n]
+    (bit 1: list the whole rectangle), rect int32 [n][4] (x0, y0, x1, y1).
+    Returns int32 [n][max_rows][2]: (l, r) per tile row from y0, (-1, -1) where
+    the row lists nothing or lies past y1.
+    """
+    mean2d = np.ascontiguousarray(mean2d, np.float32)
+    cov = np.ascontiguousarray(cov, np.float32)
+    flags = np.ascontiguousarray(flags, np.uint8)
+    rect = np.ascontiguousarray(rect, np.int32)
+    n = len(flags)
+    out = np.zeros((n, max_rows, 2), np.int32)
+    lib().or_listed_rows32(n, _p(mean2d), _p(cov), _p(flags), _p(rect), int(tile_w), int(tile_h),
+                           int(W), int(H), float(k), int(max_rows), _p(out))
     return out
 
 

@@ -40,72 +40,88 @@ enum { P_TW, P_TH, P_K, P_LP, P_ZN, P_GUARD, P_AMIN, P_AMAX, P_TMIN, P_COND, P_E
 /* camera row, float32 [18]: R (row-major 9), t (3), fx, fy, cx, cy, W, H */
 
 /* ------------------------------------------------------------------------
- * Which tiles of a Gaussian's rectangle are listed (strict binary32, fixed
- * order). The support is the ellipse q(d) = A dx^2 + 2B dx dy + C dy^2 <= L,
- * with (A, B, C) the float32 conic (c/det, -b/det, a/det) and
- * L = k^2 (1 + 2^-7), a margin far above the rounding of a float32 conic that
- * passed the conditioning predicate.
+ * Which tiles of a Gaussian's rectangle are listed: the plain definition,
+ * evaluated pixel by pixel.
  *
- * Tile row ty covers pixel-centre offsets y in [y0, y1] from the mean. The
- * ellipse reaches |y| <= ye = sqrt(L A / dt) (dt = AC - B^2); its left-most
- * point is (-xe, yx) with xe = sqrt(L C / dt), yx = B xe / C, its right-most
- * point (xe, -yx). At height y it spans x = (-B y -/+ sqrt(A L - dt y^2)) / A.
- * The left edge is convex in y and the right edge concave, so over the band
- * (clipped to |y| <= ye) the least x is -xe if yx lies in the band, else the
- * left edge at the band end nearer to yx; the greatest x likewise. The row
- * lists the tiles holding a pixel-centre column k with k + 0.5 - u in
- * [Xmin, Xmax], inside the image and the tile rectangle. Splats that fail the
- * conditioning predicate (flag bit 1) list their whole rectangle.
+ * The inverse 2D covariance is taken in its LDL^T form: with the float32
+ * covariance (a, b, c) and det = ac - b^2 (Kahan's two-product form, fused
+ * multiply-adds), p = c/det, r = -b/c, s = 1/c, and
+ *   q(dx, dy) = p (dx + r dy)^2 + s dy^2 = (c dx^2 - 2b dx dy + a dy^2)/det.
+ * A pixel centre (row j, column k) is in the listing support when, in strict
+ * binary32 with each operation as written,
+ *   dx = (k + 0.5) - u,  dy = (j + 0.5) - v,  e = dx + (r dy),
+ *   q  = (p e) e + (s dy) dy  <=  L = k^2 (1 + 2^-7).
+ * The margin 2^-7 keeps every centre of the compositing support (q <= k^2) in.
+ * In each tile row of the rectangle, the listed tiles run from the first to
+ * the last tile holding a passing centre inside the image. Splats that fail
+ * the conditioning predicate (flag bit 1) list their whole rectangle.
+ * Each pixel row of the tile row is walked from its left end to its first
+ * passing centre and from its right end to its last one.
  * ---------------------------------------------------------------------- */
-typedef struct { float u, v, A, B, dt, lim, xe, ye, yx; int full; } span32_t;
+typedef struct { float u, v, p, r, s, L; int full; } supp32_t;
 
-static span32_t span32(float u, float v, float a, float b, float c, uint8_t f, float k)
+static supp32_t supp32(float u, float v, float a, float b, float c, uint8_t f, float k)
 {
-    span32_t s;
-    s.u = u; s.v = v;
-    s.full = (f & 2) != 0;
-    float det = a * c - b * b;
-    float A = c / det, B = -b / det, C = a / det;
-    s.A = A; s.B = B;
-    s.lim = (k * k) * 1.0078125f;
-    s.dt = A * C - B * B;
-    s.xe = sqrtf((s.lim * C) / s.dt);
-    s.ye = sqrtf((s.lim * A) / s.dt);
-    s.yx = (B * s.xe) / C;
-    return s;
+    supp32_t sp;
+    sp.u = u; sp.v = v;
+    sp.full = (f & 2) != 0;
+    float w = b * b;
+    float det = fmaf(a, c, -w) + fmaf(-b, b, w);
+    if (!(det > 0.0f)) det = 1e-30f;
+    sp.p = c / det; sp.r = -b / c; sp.s = 1.0f / c;
+    sp.L = (k * k) * 1.0078125f;
+    return sp;
 }
 
-/* x of the ellipse boundary at offset y: left edge (sgn -1) or right (+1) */
-static float edge_x32(const span32_t *s, float y, float sgn)
+static int supp_pass32(const supp32_t *sp, int k, int j)
 {
-    float r = sqrtf(fmaxf((s->A * s->lim) - (s->dt * y) * y, 0.0f));
-    return (-(s->B * y) + sgn * r) / s->A;
+    float dx = ((float)k + 0.5f) - sp->u;
+    float dy = ((float)j + 0.5f) - sp->v;
+    float e = dx + sp->r * dy;
+    float q = (sp->p * e) * e + (sp->s * dy) * dy;
+    return q <= sp->L;
 }
 
-/* listed span [*l, *r] of tile row ty within tile columns [x0, x1]; returns 0 if empty */
-static int row_span32(const span32_t *s, int ty, int x0, int x1, int tw, int th, int W, int H, int *l, int *r)
+/* listed tiles [*l, *r] of tile row ty within tile columns [x0, x1]; 0 if none */
+static int row_listed32(const supp32_t *sp, int ty, int x0, int x1, int tw, int th, int W, int H, int *l, int *r)
 {
-    if (s->full) { *l = x0; *r = x1; return 1; }
-    int j1 = ty * th + th - 1;
+    if (sp->full) { *l = x0; *r = x1; return 1; }
+    int j0 = ty * th, j1 = ty * th + th - 1;
+    int k0 = x0 * tw, k1 = x1 * tw + tw - 1;
     if (j1 > H - 1) j1 = H - 1;
-    float y0 = ((float)(ty * th) + 0.5f) - s->v;
-    float y1 = ((float)j1 + 0.5f) - s->v;
-    float lo = fmaxf(y0, -s->ye), hi = fminf(y1, s->ye);
-    if (!(lo <= hi)) return 0;
-    float yl = s->yx, yr = -s->yx, xmin, xmax;
-    if (yl >= lo && yl <= hi) xmin = -s->xe;
-    else xmin = edge_x32(s, yl < lo ? lo : hi, -1.0f);
-    if (yr >= lo && yr <= hi) xmax = s->xe;
-    else xmax = edge_x32(s, yr < lo ? lo : hi, 1.0f);
-    float kl = fmaxf(ceilf((s->u + xmin) - 0.5f), 0.0f);
-    float kr = fminf(floorf((s->u + xmax) - 0.5f), (float)(W - 1));
-    if (!(kl <= kr)) return 0;
-    int a = (int)kl / tw, b = (int)kr / tw;
-    if (a < x0) a = x0;
-    if (b > x1) b = x1;
-    if (a > b) return 0;
-    *l = a; *r = b;
+    if (k1 > W - 1) k1 = W - 1;
+    int kl = k1 + 1, kr = k0 - 1; /* first and last passing column so far */
+    for (int j = j0; j <= j1; ++j) {
+        for (int k = k0; k < kl; ++k)
+            if (supp_pass32(sp, k, j)) { kl = k; break; }
+        for (int k = k1; k > kr; --k)
+            if (supp_pass32(sp, k, j)) { kr = k; break; }
+    }
+    if (kl > kr) return 0;
+    *l = kl / tw; *r = kr / tw;
     return 1;
+}
+
+/* The listing of arbitrary splats given by mean, 2D covariance, flag and
+ * tile rectangle (used to check the rule on shapes a scene rarely produces).
+ * Per splat, up to max_rows tile rows from rect[1]: out [n][max_rows][2] =
+ * (l, r), or (-1, -1) for a row that lists nothing. */
+void or_listed_rows32(int64_t n, const float *mean2d, const float *cov, const uint8_t *flags, const int32_t *rect,
+                      int32_t tw, int32_t th, int32_t W, int32_t H, float k, int32_t max_rows, int32_t *out)
+{
+#pragma omp parallel for schedule(dynamic, 64)
+    for (int64_t g = 0; g < n; ++g) {
+        supp32_t sp = supp32(mean2d[2 * g], mean2d[2 * g + 1], cov[3 * g], cov[3 * g + 1], cov[3 * g + 2], flags[g], k);
+        for (int i = 0; i < max_rows; ++i) {
+            int ty = rect[4 * g + 1] + i, l = -1, r = -1;
+            if (ty > rect[4 * g + 3] || !row_listed32(&sp, ty, rect[4 * g + 0], rect[4 * g + 2], tw, th, W, H, &l, &r)) {
+                l = -1;
+                r = -1;
+            }
+            out[(g * max_rows + i) * 2] = l;
+            out[(g * max_rows + i) * 2 + 1] = r;
+        }
+    }
 }
 
 /* ------------------------------------------------------------------------
@@ -116,7 +132,7 @@ static int row_span32(const span32_t *s, int ty, int x0, int x1, int tw, int th,
  * Outputs: flags bit0 visible, bit1 fp64-conic predicate, bit2 culled for
  * invalid input; rect = tile rectangle [x0,y0,x1,y1] (inclusive) of the
  * support ellipse's pixel bounding box; ntiles = tiles of the rectangle that
- * row_span32 lists; depth; cov = (a, b, c) of the 2D covariance incl. low-pass.
+ * row_listed32 lists; depth; cov = (a, b, c) of the 2D covariance incl. low-pass.
  * ---------------------------------------------------------------------- */
 static void proj32_one(const float *gin /*11*/, const float *cam, const float *prm,
                        uint8_t *flags, int32_t *rect, int32_t *ntiles, float *depth,
@@ -215,11 +231,11 @@ static void proj32_one(const float *gin /*11*/, const float *cam, const float *p
     int jmin = (int)fmaxf(fj0, 0.0f), jmax = (int)fminf(fj1, (float)(H - 1));
     int tw = (int)prm[P_TW], th = (int)prm[P_TH];
     rect[0] = kmin / tw; rect[1] = jmin / th; rect[2] = kmax / tw; rect[3] = jmax / th;
-    span32_t sp = span32(u, v, a, b, c, f, prm[P_K]);
+    supp32_t sp = supp32(u, v, a, b, c, f, prm[P_K]);
     int nt = 0;
     for (int ty = rect[1]; ty <= rect[3]; ++ty) {
         int l, r;
-        if (row_span32(&sp, ty, rect[0], rect[2], tw, th, W, H, &l, &r)) nt += r - l + 1;
+        if (row_listed32(&sp, ty, rect[0], rect[2], tw, th, W, H, &l, &r)) nt += r - l + 1;
     }
     *ntiles = nt;
 }
@@ -228,6 +244,7 @@ static void proj32_one(const float *gin /*11*/, const float *cam, const float *p
 void or_project32(int64_t n, const float *gauss, const float *cam, const float *prm,
                   uint8_t *flags, int32_t *rect, int32_t *ntiles, float *depth, float *cov, float *mean2d)
 {
+#pragma omp parallel for schedule(dynamic, 256)
     for (int64_t g = 0; g < n; ++g) {
         float gin[11];
         for (int i = 0; i < 11; ++i) gin[i] = gauss[(int64_t)i * n + g];
@@ -268,10 +285,10 @@ int64_t or_bin(int64_t n, const uint8_t *flags, const int32_t *rect, const int32
     int64_t k = 0;
     for (int64_t g = 0; g < n; ++g) {
         if (!(flags[g] & 1) || ntiles[g] == 0) continue;
-        span32_t sp = span32(mean2d[2 * g], mean2d[2 * g + 1], cov[3 * g], cov[3 * g + 1], cov[3 * g + 2], flags[g], prm[P_K]);
+        supp32_t sp = supp32(mean2d[2 * g], mean2d[2 * g + 1], cov[3 * g], cov[3 * g + 1], cov[3 * g + 2], flags[g], prm[P_K]);
         for (int ty = rect[4 * g + 1]; ty <= rect[4 * g + 3]; ++ty) {
             int l, r;
-            if (!row_span32(&sp, ty, rect[4 * g + 0], rect[4 * g + 2], tw, th, W, H, &l, &r)) continue;
+            if (!row_listed32(&sp, ty, rect[4 * g + 0], rect[4 * g + 2], tw, th, W, H, &l, &r)) continue;
             for (int tx = l; tx <= r; ++tx) {
                 p[k].tile = ty * tiles_x + tx;
                 p[k].depth = depth[g];
@@ -418,15 +435,19 @@ void or_composite64(int64_t n, const double *p64, const float *opacity, const fl
                     if (power >= cut) s_eval++;
                     int f_sup = fabs(power - cut) <= eps * (-cut);
                     int f_amin = amin > 0.0 && fabs(alpha - amin) <= eps * amin;
-                    int flip = f_sup || f_amin;
                     int take = (power >= cut) && (alpha >= amin);
+                    /* could a float32 evaluation decide this Gaussian the other way? A taken
+                     * one if either test lies in its band; a skipped one only if every test
+                     * it fails lies in its band */
+                    int flip = take ? (f_sup || f_amin)
+                                    : ((power >= cut || f_sup) && (alpha >= amin || f_amin));
                     double rel = alpha < 1.0 ? alpha / (1.0 - alpha) : 1.0;
                     if (!take) {
                         if (flip) {
                             s_flag++;
 #pragma omp atomic
-                            slack[g] += alpha * T;
-                            pert += rel;
+                            slack[g] += alpha * T * (1.0 + pert);
+                            pert += rel + pert * rel;
                         }
                         continue;
                     }
@@ -434,9 +455,24 @@ void or_composite64(int64_t n, const double *p64, const float *opacity, const fl
                     int f_tmin = tmin > 0.0 && fabs(Tn - tmin) <= (eps + pert) * tmin;
                     if (Tn < tmin) {
                         if (f_tmin) {
+                            /* the alternative does not stop here: this Gaussian and the
+                             * next ones it could still add, at most at the raised T */
                             s_flag++;
 #pragma omp atomic
-                            slack[g] += alpha * T;
+                            slack[g] += alpha * T * (1.0 + pert);
+                            double Ts = Tn * (1.0 + pert);
+                            double Tlow = tmin * (1.0 - (eps + pert));
+                            for (uint32_t i2 = i + 1; i2 < re && Ts >= Tlow; ++i2) {
+                                uint32_t g2 = list[i2];
+                                const double *q2 = p64 + 5 * (int64_t)g2;
+                                double dx2 = pxc - q2[0], dy2 = pyc - q2[1];
+                                double pw2 = -0.5 * (q2[2] * dx2 * dx2 + q2[4] * dy2 * dy2) - q2[3] * dx2 * dy2;
+                                double a2 = fmin(amax, (double)opacity[g2] * exp(pw2));
+                                if (pw2 < cut * (1.0 + eps) || a2 < amin * (1.0 - eps)) continue;
+#pragma omp atomic
+                                slack[g2] += a2 * Ts;
+                                Ts *= 1.0 - a2;
+                            }
                         }
                         break;
                     }
@@ -450,7 +486,7 @@ void or_composite64(int64_t n, const double *p64, const float *opacity, const fl
 #pragma omp atomic
                         slack[g] += sl;
                     }
-                    if (flip) { s_flag++; pert += rel; }
+                    if (flip) { s_flag++; pert += rel + pert * rel; }
                     if (f_tmin) { s_flag++; tail = 1; }
                     T = Tn;
                     nb++;

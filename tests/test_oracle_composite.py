@@ -146,3 +146,72 @@ def test_slack_is_zero_without_thresholds_near_decisions():
     prm = O.params(alpha_min=0.0, alpha_max=1.0, t_min=0.0, sigma_k=7.0)
     r = O.solve64(sc, prm)
     assert r["flagged"] == 0 and r["slack"][0] == 0.0
+
+
+def _inside(base, rel, sign):
+    """The float32 value farthest from `base` on one side, within `rel` of it."""
+    b = float(np.float32(base))
+    x = np.float32(b * (1 + sign * rel))
+    while abs(float(x) - b) > rel * abs(b):
+        x = np.nextafter(x, np.float32(b))
+    return float(x)
+
+
+def _inside_k(k, rel, sign):
+    """The float32 sigma_k farthest from k on one side whose k^2/2 stays within rel of k's."""
+    k = float(np.float32(k))
+    c = 0.5 * k * k
+    x = np.float32(k * math.sqrt(1 + sign * rel))
+    while abs(0.5 * float(x) * float(x) - c) > rel * c:
+        x = np.nextafter(x, np.float32(k))
+    return float(x)
+
+
+@pytest.mark.parametrize("cfg", ["C1", "C3-small"])
+def test_slack_bounds_every_threshold_flip_within_the_band(cfg):
+    """The slack budget against the decisions it stands for.
+
+    The GPU takes the three compositing decisions (support, alpha_min, t_min)
+    in float32; the oracle's slack[g] bounds what deciding any of them the
+    other way can change in row g, for decisions within the relative band
+    band_eps of the threshold. Here the float64 oracle itself is re-run with
+    each threshold moved to the edge of that band, in each direction, which
+    flips exactly the decisions on that side of the band: the change of every
+    row must stay within its slack. The budget must not be loose either: in
+    total it stays within twice the sum of those changes, and for nearly
+    every row within four times its own."""
+    if cfg == "C1":
+        sc, views = sg.make_config("C1"), range(8)
+    else:
+        sc, views = sg.make_config("C3", views=4, W=320, H=240, per_obj=6000, n_shell=20000), range(4)
+    eps = float(PRM[10])
+    g = O._gauss(sc)
+    bins = {v: O.bin_view(sc, v, PRM, O.project32(sc, v, PRM, g)) for v in views}
+    p64 = {v: O.project64(sc, v, PRM, g) for v in views}
+
+    def solve(prm):
+        A = np.zeros((sc.n, sc.E))
+        sl = np.zeros(sc.n)
+        for v in views:
+            O.composite64(sc, v, prm, bins[v], A, sl, p64=p64[v])
+        return A, sl
+
+    A0, slack = solve(PRM)
+    s = np.abs(A0).sum(axis=1)
+    amin, tmin, k = float(PRM[6]), float(PRM[8]), float(PRM[2])
+    moved = dict(amin_up=O.params(alpha_min=_inside(amin, eps, 1)), amin_down=O.params(alpha_min=_inside(amin, eps, -1)),
+                 tmin_up=O.params(t_min=_inside(tmin, eps, 1)), tmin_down=O.params(t_min=_inside(tmin, eps, -1)),
+                 support_wider=O.params(sigma_k=_inside_k(k, eps, 1)),
+                 support_narrower=O.params(sigma_k=_inside_k(k, eps, -1)))
+    total = np.zeros(sc.n)
+    for name, prm in moved.items():
+        A1, _ = solve(prm)
+        d = np.abs(A1 - A0).sum(axis=1)
+        assert (d > 0).sum() > 100, name  # the move does flip decisions
+        over = d > slack + 1e-12 * s + 1e-15
+        assert not over.any(), (name, int(over.sum()), float(np.max(d - slack)))
+        total += d
+    has = slack > 0
+    assert slack.sum() <= 2.0 * total.sum(), (slack.sum(), total.sum())
+    loose = slack > 4.0 * total + 1e-12 * s
+    assert loose.sum() <= 0.03 * has.sum(), (int(loose.sum()), int(has.sum()))

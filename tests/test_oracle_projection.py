@@ -159,6 +159,16 @@ def test_tile_lists_lose_no_support_pixel_and_are_tight(cfg):
                 X, Y = np.meshgrid(xs, ys)
                 qmin = (A * X * X + 2 * B * X * Y + C * Y * Y).min()
                 assert qmin <= 9.0 * 1.01, (v, g, t, qmin)
+            # each tile row's listed span is contiguous and its end tiles hold a pixel centre
+            # inside 9 (1 + 2^-7), up to float32 rounding (the listing definition)
+            qpix = q <= 9.0 * 1.0078125 * (1 + 1e-4)
+            rows = {}
+            for t in have:
+                rows.setdefault(t // tx, []).append(t % tx)
+            for ty_, cols in rows.items():
+                assert sorted(cols) == list(range(min(cols), max(cols) + 1)), (v, g, ty_)
+                for tx_ in (min(cols), max(cols)):
+                    assert qpix[ty_ * 16:ty_ * 16 + 16, tx_ * 16:tx_ * 16 + 16].any(), (v, g, ty_, tx_)
             assert pr["ntiles"][g] == len(have)
 
 
