@@ -114,9 +114,13 @@ typedef struct {
 /* Projected Gaussians, caller-owned device buffers, one plane per view:
  * element (v, g) lives at index v*n + g. */
 typedef struct {
-    float *rec;       /* float32 [n_views][n][8]: u, v (pixel), conic_xx, conic_xy, conic_yy
-                         (inverse 2D covariance), opacity, depth (camera z), and 1 if the
-                         conic was inverted in float64 else 0 */
+    float *rec;       /* float32 [n_views][n][8]: u, v (pixel), p, r, s, opacity, depth
+                         (camera z), mark. (p, r, s) are the LDL^T factors of the inverse
+                         2D covariance (a, b, c): p = c/det, r = -b/c, s = 1/c, so that
+                         d^T Sigma^-1 d = p (dx + r dy)^2 + s dy^2. mark: 0 = float32
+                         factors, tiles listed by the support test; 1 = factors from the
+                         float64 inversion, whole rectangle listed; 2 = float32 factors,
+                         whole rectangle listed (fp64_conic = 0) */
     int16_t *rect;    /* int16 [n_views][n][4]: tile rectangle x0, y0, x1, y1, inclusive */
     int32_t *ntiles;  /* int32 [n_views][n]: tiles in the rectangle, 0 if not visible */
     uint8_t *flags;   /* uint8 [n_views][n]: bit0 visible, bit1 float64 conic, bit2 invalid input */
@@ -191,10 +195,15 @@ int fs_last_accumulate_ms(fs_ctx *ctx, float *ms);
  * pixel mean, depth, the per-axis half extents rx = ceil(sigma_k*sqrt(cov_xx)),
  * ry = ceil(sigma_k*sqrt(cov_yy)) of the support ellipse (its exact bounding
  * box, rounded up to whole pixels) and the tile rectangle of the pixel box
- * mean +- (rx, ry). Visibility, rectangle and
- * ntiles are computed in strict binary32 in a fixed operation order (the
- * bit-exact contract); the conic is float32 except for splats selected by
- * fp64_cond, which are inverted in float64. cams: host [n_views];
+ * mean +- (rx, ry). ntiles counts the listed tiles: in each tile row of the
+ * rectangle, the tiles from the first to the last that hold a pixel centre
+ * (inside the image) with p (dx + r dy)^2 + s dy^2 <= sigma_k^2 (1 + 2^-7),
+ * evaluated in binary32 in the order written; splats selected by fp64_cond
+ * list their whole rectangle. Visibility, rectangle and ntiles are computed in
+ * strict binary32 in a fixed operation order (the bit-exact contract); the
+ * conic factors are float32 (det by Kahan's fused two-product form) except for
+ * splats selected by fp64_cond, which are inverted in float64 (Cauchy-Binet
+ * determinant) and then rounded. cams: host [n_views];
  * out: caller-owned planes for n_views x g->n elements. */
 int fs_project(fs_ctx *ctx, const fs_gaussians *g, const fs_camera *cams, int32_t n_views,
                const fs_params *p, const fs_proj *out);

@@ -89,27 +89,31 @@ __device__ __forceinline__ void add_global(float *hi, float *lo, int64_t idx, fl
 }
 
 // Can any pixel centre of columns [x0, x1] and rows [y0, y1] of the 8x8 block
-// with corner (bx, by) lie inside the ellipse A dx^2 + 2B dx dy + C dy^2 <= lim
+// with corner (bx, by) lie inside the ellipse p (dx + r dy)^2 + s dy^2 <= lim
 // around (u, v)? Minimum of the quadratic over that box of pixel centres: zero
-// if the mean is inside, else the least edge minimum (clamped parabola vertex).
-// Conservative through the margin folded into lim; used only to skip work,
-// never to decide a weight.
-__device__ __forceinline__ bool block_hit(float u, float v, float A, float B, float C, float bx, float by, float lim,
+// if the mean is inside, else the least edge minimum (clamped parabola
+// vertex; on a column x the vertex is at y = -p r x / (s + p r^2), on a row y
+// at x = -r y). Conservative through the margin folded into lim; used only to
+// skip work, never to decide a weight.
+__device__ __forceinline__ bool block_hit(float u, float v, float p, float r, float s, float bx, float by, float lim,
                                           float x0, float x1, float y0, float y1)
 {
     const float xl = bx + x0 + 0.5f - u, xh = bx + x1 + 0.5f - u;
     const float yl = by + y0 + 0.5f - v, yh = by + y1 + 0.5f - v;
     if (xl <= 0.0f && xh >= 0.0f && yl <= 0.0f && yh >= 0.0f) return true;
-    const float iA = 1.0f / A, iC = 1.0f / C;
+    const float pr = p * r;
+    const float iC = __builtin_amdgcn_rcpf(fmaf(pr, r, s));
+    auto q = [&](float x, float y) {
+        const float e = fmaf(r, y, x);
+        return fmaf(p * e, e, s * y * y);
+    };
     float qmin = 3.4e38f;
 #pragma unroll
     for (int i = 0; i < 2; ++i) {
         const float x = i ? xh : xl;
-        const float y = fminf(fmaxf(-(B * x) * iC, yl), yh);
-        qmin = fminf(qmin, A * x * x + 2.0f * B * x * y + C * y * y);
-        const float y2 = i ? yh : yl;
-        const float x2 = fminf(fmaxf(-(B * y2) * iA, xl), xh);
-        qmin = fminf(qmin, A * x2 * x2 + 2.0f * B * x2 * y2 + C * y2 * y2);
+        qmin = fminf(qmin, q(x, fminf(fmaxf(-(pr * x) * iC, yl), yh)));
+        const float y = i ? yh : yl;
+        qmin = fminf(qmin, q(fminf(fmaxf(-(r * y), xl), xh), y));
     }
     return qmin <= lim;
 }
@@ -123,8 +127,8 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(7, 7))) voi
                                                float *__restrict__ tstate, uint8_t *__restrict__ tile_done,
                                                int32_t first, unsigned long long *__restrict__ status)
 {
-    // staged entry e: s_rec[e] = (u, v, a', b'), (c', lo, thr, sup), with the conic scaled to
-    // log2 units, lo = log2(opacity), sup = cut2 + lo (the support bound on the power) and
+    // staged entry e: s_rec[e] = (u, v, p', r), (s', lo, thr, sup), with the LDL^T factors
+    // p, s scaled to log2 units, lo = log2(opacity), sup = cut2 + lo (the support bound on the power) and
     // thr = max(sup, log2(alpha_min)): a weight is taken only if the power reaches thr, which
     // is the support test and the alpha_min test in one comparison; entry kBatch is a null record
     __shared__ float4 s_rec[2 * (kBatch + 1)];
@@ -249,24 +253,18 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(7, 7))) voi
             const float4 r0 = rec[(rec_base + g) * 2];
             const float4 r1 = rec[(rec_base + g) * 2 + 1];
             const float lo = fmaxf(__builtin_amdgcn_logf(r1.y), kLoFloor);
-            s_rec[2 * tid] = make_float4(r0.x, r0.y, -0.5f * LOG2E * r0.z, -LOG2E * r0.w);
+            s_rec[2 * tid] = make_float4(r0.x, r0.y, -0.5f * LOG2E * r0.z, r0.w);
             s_rec[2 * tid + 1] = make_float4(-0.5f * LOG2E * r1.x, lo, fmaxf(P.cut2 + lo, P.lmin), P.cut2 + lo);
             s_g[tid] = g;
-            uint32_t m = 0xFu;
-            if (r1.w == 0.0f) {  // float32 conic: cull the waves whose live pixels the support cannot reach
-                m = 0;
+            // cull the waves whose live pixels the support cannot reach
+            uint32_t m = 0;
 #pragma unroll
-                for (int b = 0; b < 4; ++b) {
-                    const float bx = tx0 + (float)((b % bpr) * 8), by = ty0 + (float)((b / bpr) * 8);
-                    const int4 bb = s_wbox[b];
-                    if (bb.x <= bb.y && block_hit(r0.x, r0.y, r0.z, r0.w, r1.x, bx, by, lim, (float)bb.x,
-                                                  (float)bb.y, (float)bb.z, (float)bb.w))
-                        m |= 1u << b;
-                }
-            } else {
-#pragma unroll
-                for (int b = 0; b < 4; ++b)
-                    if (s_wbox[b].x > s_wbox[b].y) m &= ~(1u << b);  // no live pixel left in that wave
+            for (int b = 0; b < 4; ++b) {
+                const float bx = tx0 + (float)((b % bpr) * 8), by = ty0 + (float)((b / bpr) * 8);
+                const int4 bb = s_wbox[b];
+                if (bb.x <= bb.y && block_hit(r0.x, r0.y, r0.z, r0.w, r1.x, bx, by, lim, (float)bb.x,
+                                              (float)bb.y, (float)bb.z, (float)bb.w))
+                    m |= 1u << b;
             }
             s_wmask[tid] = (uint8_t)m;
         }
@@ -285,15 +283,16 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(7, 7))) voi
         __builtin_amdgcn_wave_barrier();
 
         // one front-to-back step of this lane's pixel over a staged entry: power in
-        // log2 units via Horner with log2(opacity) folded in, so that
-        // alpha = min(alpha_max, 2^(power + lo)); support and alpha_min tests against
-        // thr. A lane that fails them gets alpha = 0, which leaves T exactly as it is
+        // log2 units from the LDL^T factors, -(1/2) log2(e) (p (dx + r dy)^2 + s dy^2),
+        // with log2(opacity) folded in, so that alpha = min(alpha_max, 2^(power + lo));
+        // support and alpha_min tests against thr. A lane that fails them gets alpha = 0, which leaves T exactly as it is
         // and adds nothing. A pixel stops (Eq. (1)'s transmittance cut) at most once,
         // so the step where some lane does is fixed up under a wave-uniform branch:
         // that lane adds no weight and keeps its T.
         auto step = [&](const float4 q, const float4 q2) -> float {
             const float dx = pxc - q.x, dy = pyc - q.y;
-            const float pw = fmaf(fmaf(q.z, dx, q.w * dy), dx, fmaf(q2.x * dy, dy, q2.y));
+            const float e = fmaf(q.w, dy, dx);
+            const float pw = fmaf(q.z * e, e, fmaf(q2.x * dy, dy, q2.y));
             const bool ok = live && pw >= q2.z;
             const float alpha = ok ? fminf(P.alpha_max, __builtin_amdgcn_exp2f(pw)) : 0.0f;
             float wv = alpha * T;

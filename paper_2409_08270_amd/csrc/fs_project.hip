@@ -124,8 +124,8 @@ __global__ __launch_bounds__(256) void k_project(const ProjTask *__restrict__ ta
                     float det = a * c - b * b;
                     bool deg = !(det > 0.0f) || (a * c >= P.fp64_cond * det);
                     f = deg ? 3 : 1;
-                    // conic (inverse 2D covariance)
-                    float ca, cb, cc;
+                    // inverse 2D covariance as LDL^T factors: q = p (dx + r dy)^2 + s dy^2
+                    float cp, cr, cs;
                     if (deg && P.fp64_conic) {
                         n_fp64++;
                         const double d00 = (double)m0[0], d01 = (double)m0[1], d02 = (double)m0[2];
@@ -139,19 +139,19 @@ __global__ __launch_bounds__(256) void k_project(const ProjTask *__restrict__ ta
                         const double lpd = (double)lp;
                         // Cauchy-Binet: det(M M^T + lp I), every term non-negative
                         const double det64 = mn01 * mn01 + mn02 * mn02 + mn12 * mn12 + lpd * (s00 + s11) + lpd * lpd;
-                        ca = (float)((s11 + lpd) / det64);
-                        cb = (float)(-s01 / det64);
-                        cc = (float)((s00 + lpd) / det64);
+                        const double c64 = s11 + lpd;
+                        cp = (float)(c64 / det64);
+                        cr = (float)(-s01 / c64);
+                        cs = (float)(1.0 / c64);
                     } else {
-                        float dd = det > 0.0f ? det : 1e-30f;
-                        ca = c / dd;
-                        cb = -b / dd;
-                        cc = a / dd;
+                        ldl32(a, b, c, cp, cr, cs);
                     }
-                    r0 = make_float4(u, vv, ca, cb);
-                    r1.x = cc;
+                    r0 = make_float4(u, vv, cp, cr);
+                    r1.x = cs;
                     r1.y = op;
-                    r1.w = (deg && P.fp64_conic) ? 1.0f : 0.0f;
+                    // 0: float32 factors, listed by the support test; 1: float64 factors,
+                    // whole rectangle listed; 2: float32 factors, whole rectangle listed
+                    r1.w = deg ? (P.fp64_conic ? 1.0f : 2.0f) : 0.0f;
                     float fk0 = ceilf((u - rx) - 0.5f), fk1 = floorf((u + rx) - 0.5f);
                     float fj0 = ceilf((vv - ry) - 0.5f), fj1 = floorf((vv + ry) - 0.5f);
                     if (!(fk1 < 0.0f || fk0 > (float)(C.W - 1) || fj1 < 0.0f || fj0 > (float)(C.H - 1) ||
@@ -161,9 +161,8 @@ __global__ __launch_bounds__(256) void k_project(const ProjTask *__restrict__ ta
                         int x0 = tile_of(kmin, P.tile_w), y0 = tile_of(jmin, P.tile_h);
                         int x1 = tile_of(kmax, P.tile_w), y1 = tile_of(jmax, P.tile_h);
                         rc = make_short4((short)x0, (short)y0, (short)x1, (short)y1);
-                        // tiles of the rectangle that the support ellipse reaches, row by row,
-                        // from the float32 conic computed above (c/det, -b/det, a/det)
-                        const Span32 sp = make_span32(u, vv, ca, cb, cc, deg, support_limit(P.sigma_k));
+                        // tiles of the rectangle that the support reaches, row by row
+                        const Span32 sp = make_span32(u, vv, cp, cr, cs, deg, support_limit(P.sigma_k));
                         const bool small = y1 - y0 < kSpanCodeRows && x1 - x0 < 16;
                         for (int ty = y0; ty <= y1; ++ty) {
                             int l, r;

@@ -26,7 +26,7 @@ __global__ __launch_bounds__(256) void k_render(const float4 *__restrict__ rec, 
                                                 float *__restrict__ rho_out, float *__restrict__ depth_out,
                                                 int64_t n_pixels)
 {
-    __shared__ float4 s_q[kRBatch];   // u, v, a', b' (conic in log2 units)
+    __shared__ float4 s_q[kRBatch];   // u, v, p', r (LDL^T factors, p in log2 units)
     __shared__ float4 s_q2[kRBatch];  // c', lo, thr, z
     __shared__ uint16_t s_list[kRBatch];
     __shared__ uint32_t s_wcnt[4];
@@ -63,7 +63,7 @@ __global__ __launch_bounds__(256) void k_render(const float4 *__restrict__ rec, 
                     const float4 r0 = rec[(rec_base + g) * 2];
                     const float4 r1 = rec[(rec_base + g) * 2 + 1];
                     const float lo = fmaxf(__builtin_amdgcn_logf(r1.y), -200.0f);
-                    s_q[tid] = make_float4(r0.x, r0.y, -0.5f * LOG2E * r0.z, -LOG2E * r0.w);
+                    s_q[tid] = make_float4(r0.x, r0.y, -0.5f * LOG2E * r0.z, r0.w);
                     s_q2[tid] = make_float4(-0.5f * LOG2E * r1.x, lo, P.cut2 + lo, r1.z);
                 }
             }
@@ -85,7 +85,8 @@ __global__ __launch_bounds__(256) void k_render(const float4 *__restrict__ rec, 
                     const float4 q = s_q[j];
                     const float4 q2 = s_q2[j];
                     const float dx = pxc - q.x, dy = pyc - q.y;
-                    const float pw = fmaf(fmaf(q.z, dx, q.w * dy), dx, fmaf(q2.x * dy, dy, q2.y));
+                    const float e = fmaf(q.w, dy, dx);
+                    const float pw = fmaf(q.z * e, e, fmaf(q2.x * dy, dy, q2.y));
                     if (pw < q2.z) continue;
                     const float alpha = fminf(P.alpha_max, __builtin_amdgcn_exp2f(pw));
                     if (alpha < P.alpha_min) continue;

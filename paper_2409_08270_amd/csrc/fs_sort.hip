@@ -435,8 +435,7 @@ __global__ void k_slab_counts(const uint32_t *__restrict__ skeys, const uint32_t
                 if (!has_code(code)) {
                     const float4 r0 = rec[2 * idx];
                     const float4 r1 = rec[2 * idx + 1];
-                    const bool deg = flags ? (flags[idx] & 2u) != 0 : r1.w != 0.0f;
-                    sp = make_span32(r0.x, r0.y, r0.z, r0.w, r1.x, deg, support_limit(sigma_k));
+                    sp = make_span32(r0.x, r0.y, r0.z, r0.w, r1.x, r1.w != 0.0f, support_limit(sigma_k));
                 }
                 for (int ty = rc.y; ty <= rc.w; ++ty) {
                     int l, r;
@@ -498,10 +497,8 @@ __global__ __launch_bounds__(kThreads) void k_emit(const uint32_t *__restrict__ 
         if (!has_code(code)) {
             const float4 r0 = rec[2 * idx];
             const float4 r1 = rec[2 * idx + 1];
-            // without the flag plane, rec's float64-conic mark stands for the
-            // degenerate flag (the two agree whenever float64 conics are on)
-            const bool deg = flags ? (flags[idx] & 2u) != 0 : r1.w != 0.0f;
-            sp = make_span32(r0.x, r0.y, r0.z, r0.w, r1.x, deg, support_limit(sigma_k));
+            // rec's mark: non-zero for splats that list their whole rectangle
+            sp = make_span32(r0.x, r0.y, r0.z, r0.w, r1.x, r1.w != 0.0f, support_limit(sigma_k));
         }
         tbase = C.tile_base;
         tiles_x = (uint32_t)C.tiles_x;

@@ -1,100 +1,223 @@
-// Tile-listing rule of the binning (strict binary32, no contraction).
+// Tile-listing rule of the binning.
 //
-// The support of a splat is the ellipse q(d) = A dx^2 + 2B dx dy + C dy^2 <= L
-// (A, B, C = the float32 conic c/det, -b/det, a/det; L = k^2 (1 + 2^-7), a
-// margin far above the rounding of a float32 conic that passed the
-// conditioning predicate, so no pixel inside the support k^2 is lost).
+// Conic form. A splat's inverse 2D covariance is kept as its LDL^T factors:
+// with the covariance (a, b, c) and det = ac - b^2,
+//     q(dx, dy) = p (dx + r dy)^2 + s dy^2,  p = c/det, r = -b/c, s = 1/c,
+// which equals (c dx^2 - 2b dx dy + a dy^2)/det. Both terms are non-negative,
+// so evaluating q does not cancel, even for needle-like splats. On the float32
+// path det comes from Kahan's two-product form (fused multiply-adds), and
+// p, r, s are correctly rounded quotients.
 //
-// A tile row covers the pixel-centre rows y in [y0, y1] (offsets from the
-// mean). The ellipse meets that band in a convex set whose x-extent is found
-// in closed form: with dt = AC - B^2, the ellipse spans |y| <= ye = sqrt(LA/dt),
-// its left-most point (-xe, yx) has xe = sqrt(LC/dt), yx = B xe / C, and its
-// right-most point is (xe, -yx). At height y the ellipse spans
-// x = (-By -/+ sqrt(AL - dt y^2)) / A; the left edge is convex in y, the right
-// edge concave, so over the band the minimum of x is -xe when yx lies in the
-// band and the left edge at the band end nearest yx otherwise (likewise for
-// the maximum). The listed tiles of the row are those holding a pixel-centre
-// column inside [Xmin, Xmax], within the image and the splat's tile
-// rectangle. Splats whose conic was inverted in float64 list their whole
-// rectangle. Per row this is O(1) work; the count (fs_project) and the
-// emission (fs_bin_sort) share this code, so they agree exactly. Small splats
-// hand their spans from the count to the emission as a span code (below).
+// Definition (strict binary32, every operation as written). A pixel centre
+// (row j, column k) is in the listing support of a splat with mean (u, v) iff
+//     dx = (k + 0.5) - u,  dy = (j + 0.5) - v,  e = dx + (r dy),
+//     q  = (p e) e + (s dy) dy  <=  L = k^2 (1 + 2^-7).
+// The margin 2^-7 lies far above the rounding of q, so no pixel of the
+// compositing support (q <= k^2) is missed. Each tile row of the splat's tile
+// rectangle lists the tiles from the first to the last one holding a pixel
+// centre (inside the image) that passes. Splats that fail the conditioning
+// predicate list their whole rectangle.
+//
+// How it is found in O(boundary) work rather than by testing every pixel.
+// The ellipse q <= Lo with Lo slightly above L bounds, in real arithmetic,
+// every centre that can pass in binary32 (the relative rounding of q is at
+// most about 8 u (1 + sqrt(AC/dt)), u = 2^-24). With A = p, B = pr,
+// C = s + pr^2 and dt = AC - B^2 = ps, the ellipse spans |y| <= ye =
+// sqrt(Lo A/dt), its left-most point (-xe, yx) has xe = sqrt(Lo C/dt),
+// yx = B xe / C, its right-most point is (xe, -yx), and at height y it spans
+// x = -ry -/+ sqrt((Lo - s y^2)/p); the left edge is convex in y, the right
+// edge concave, so over the band of the tile row's centre rows the least x is
+// -xe when yx lies in the band and the left edge at the band end nearer yx
+// otherwise (likewise for the greatest x). Those bounds, widened by a pixel
+// and by the rounding of this approximate arithmetic, give the candidate
+// columns. Columns are then walked inward from each end; in a column only the
+// rows of the chord of the Lo ellipse (widened the same way) can pass, and
+// each of those centres is decided by the definition's own test. So the
+// listed set is the definition's exactly; the approximations only choose
+// which centres to test. The count (fs_project) and the emission
+// (fs_bin_sort) call the same code on the same record, so they agree. Small
+// splats hand their spans from the count to the emission as a span code.
+//
+// The functions are host-callable too, so that the rule can be checked
+// against a brute-force listing on the CPU.
 #pragma once
 
 #include <hip/hip_runtime.h>
+#include <stdint.h>
 
 namespace fs {
 
+// approximate square root and reciprocal (about 1 ulp on the device); they
+// only bound which centres are tested, never decide one
+__host__ __device__ __forceinline__ float approx_sqrt(float x)
+{
+#if defined(__HIP_DEVICE_COMPILE__)
+    return __builtin_amdgcn_sqrtf(x);
+#else
+    return sqrtf(x);
+#endif
+}
+
+__host__ __device__ __forceinline__ float approx_rcp(float x)
+{
+#if defined(__HIP_DEVICE_COMPILE__)
+    return __builtin_amdgcn_rcpf(x);
+#else
+    return 1.0f / x;
+#endif
+}
+
 struct Span32 {
-    float u, v, A, B, dt, lim, xe, ye, yx;
-    bool full;
+    float u, v, p, r, s, lim;  // the definition's inputs
+    float lo, A, B, C, dt, iC, xe, ye, yx, mx, my;  // candidate bounds (approximate, widened)
+    bool full, ok;
 };
 
-// k2lim = (k * k) * (1 + 2^-7)
-__device__ __forceinline__ float support_limit(float k)
+// LDL^T factors (p, r, s) of the inverse of the 2D covariance (a, b, c), float32
+// path: det by Kahan's two-product form, then correctly rounded quotients
+__host__ __device__ __forceinline__ void ldl32(float a, float b, float c, float &p, float &r, float &s)
+{
+#pragma clang fp contract(off)
+    const float w = b * b;
+    const float err = fmaf(-b, b, w);  // w - b^2, exactly
+    float det = fmaf(a, c, -w) + err;
+    if (!(det > 0.0f)) det = 1e-30f;
+    p = c / det;
+    r = -b / c;
+    s = 1.0f / c;
+}
+
+// L = (k * k) * (1 + 2^-7)
+__host__ __device__ __forceinline__ float support_limit(float k)
 {
 #pragma clang fp contract(off)
     return (k * k) * 1.0078125f;
 }
 
-__device__ __forceinline__ Span32 make_span32(float u, float v, float A, float B, float C, bool full, float lim)
+// the definition's test of pixel centre (row j, column k)
+__host__ __device__ __forceinline__ bool support_pass(const Span32 &sp, int k, int j)
 {
 #pragma clang fp contract(off)
-    Span32 s;
-    s.u = u; s.v = v; s.A = A; s.B = B;
-    s.full = full;
-    s.lim = lim;
-    s.dt = full ? 1.0f : A * C - B * B;
-    s.xe = full ? 0.0f : sqrtf((lim * C) / s.dt);
-    s.ye = full ? 0.0f : sqrtf((lim * A) / s.dt);
-    s.yx = full ? 0.0f : (B * s.xe) / C;
-    return s;
+    const float dx = ((float)k + 0.5f) - sp.u;
+    const float dy = ((float)j + 0.5f) - sp.v;
+    const float e = dx + (sp.r * dy);
+    const float q = ((sp.p * e) * e) + ((sp.s * dy) * dy);
+    return q <= sp.lim;
 }
 
-// x of the ellipse boundary at height y: left (sgn = -1) or right (sgn = +1)
-__device__ __forceinline__ float edge_x(const Span32 &s, float y, float sgn)
+__host__ __device__ __forceinline__ Span32 make_span32(float u, float v, float p, float r, float s, bool full,
+                                                       float lim)
 {
-#pragma clang fp contract(off)
-    const float r = sqrtf(fmaxf((s.A * s.lim) - (s.dt * y) * y, 0.0f));
-    return (-(s.B * y) + sgn * r) / s.A;
+    Span32 sp;
+    sp.u = u; sp.v = v; sp.p = p; sp.r = r; sp.s = s; sp.lim = lim;
+    sp.full = full;
+    sp.ok = false;
+    sp.lo = sp.A = sp.B = sp.C = sp.dt = sp.iC = sp.xe = sp.ye = sp.yx = sp.mx = sp.my = 0.0f;
+    if (full) return sp;
+    sp.A = p;
+    sp.B = p * r;
+    sp.C = s + sp.B * r;
+    sp.dt = p * s;
+    // conditioning AC / dt = 1 + p r^2 / s >= 1: scales the rounding of q and of
+    // the cancellations in the chord and edge formulas
+    const float kap = fmaxf(sp.C * approx_rcp(s), 1.0f);
+    const float rq = 0x1p-8f + 0x1p-17f * kap;              // bound on the relative rounding of q, widened
+    const float rc = approx_sqrt(0x1p-15f * (kap + 2.0f));  // relative error of the chord and edge half-widths
+    sp.lo = lim * (1.0f + rq);
+    sp.iC = approx_rcp(sp.C);
+    const float iD = approx_rcp(sp.dt);
+    sp.xe = approx_sqrt((sp.lo * sp.C) * iD);
+    sp.ye = approx_sqrt((sp.lo * p) * iD);
+    sp.yx = (sp.B * sp.xe) * sp.iC;
+    sp.mx = 1.0f + sp.xe * rc;
+    sp.my = 1.0f + sp.ye * rc;
+    sp.ok = p > 0.0f && s > 0.0f && rc < 0.25f && __builtin_isfinite(sp.xe) && __builtin_isfinite(sp.ye) &&
+            __builtin_isfinite(sp.yx) && __builtin_isfinite(sp.iC) && __builtin_isfinite(sp.B);
+    return sp;
+}
+
+// x of the widened ellipse's boundary at offset y: left (sgn = -1) or right (+1)
+__host__ __device__ __forceinline__ float edge_x(const Span32 &sp, float y, float sgn)
+{
+    const float h = approx_sqrt(fmaxf((sp.lo - (sp.s * y) * y) * approx_rcp(sp.p), 0.0f));
+    return -(sp.r * y) + sgn * h;
+}
+
+// float bound -> integer index, clamped to [lo, hi] (NaN -> lo)
+__host__ __device__ __forceinline__ int clamp_index(float x, int lo, int hi)
+{
+    if (!(x >= (float)lo)) return lo;
+    if (!(x <= (float)hi)) return hi;
+    return (int)x;
+}
+
+// Does column k hold a passing centre in pixel rows [j0, j1]?
+__host__ __device__ __forceinline__ bool column_hit(const Span32 &sp, int k, int j0, int j1)
+{
+    int a = j0, b = j1;
+    if (sp.ok) {
+        const float dx = ((float)k + 0.5f) - sp.u;
+        const float clo = sp.C * sp.lo;
+        const float hh = clo - (sp.dt * dx) * dx;
+        // least q over the column is dt dx^2 / C: clearly above Lo, no row can
+        // pass (dt = ps has no cancellation, so dt dx^2 is within a few ulp)
+        if (hh < -0x1p-9f * clo) return false;
+        const float yc = -(sp.B * dx) * sp.iC;
+        const float hy = approx_sqrt(fmaxf(hh, 0.0f)) * sp.iC;
+        // rows j whose offset j + 0.5 - v lies in [yc - hy - my, yc + hy + my]
+        const float ylo = ((sp.v + yc) - hy) - 0.5f - sp.my;
+        const float yhi = ((sp.v + yc) + hy) - 0.5f + sp.my;
+        a = clamp_index(ceilf(ylo), j0, j1 + 1);
+        b = clamp_index(floorf(yhi), j0 - 1, j1);
+    }
+    for (int j = a; j <= b; ++j)
+        if (support_pass(sp, k, j)) return true;
+    return false;
 }
 
 // n / t for n >= 0: a shift when the tile size t is a power of two (t is the
 // same for every lane, so the choice costs one uniform branch)
-__device__ __forceinline__ int tile_of(int n, int t)
+__host__ __device__ __forceinline__ int tile_of(int n, int t)
 {
-    return (t & (t - 1)) == 0 ? (n >> (__ffs(t) - 1)) : n / t;
+    return (t & (t - 1)) == 0 ? (n >> __builtin_ctz((unsigned)t)) : n / t;
 }
 
 // listed span [l, r] of tile row ty within tile columns [x0, x1]; false if empty
-__device__ __forceinline__ bool row_span(const Span32 &s, int ty, int x0, int x1, int tw, int th, int W, int H,
-                                         int &l, int &r)
+__host__ __device__ __forceinline__ bool row_span(const Span32 &sp, int ty, int x0, int x1, int tw, int th, int W,
+                                                  int H, int &l, int &r)
 {
-#pragma clang fp contract(off)
-    if (s.full) {
+    if (sp.full) {
         l = x0;
         r = x1;
         return true;
     }
-    int j1 = ty * th + th - 1;
-    if (j1 > H - 1) j1 = H - 1;
-    const float y0 = ((float)(ty * th) + 0.5f) - s.v;
-    const float y1 = ((float)j1 + 0.5f) - s.v;
-    const float lo = fmaxf(y0, -s.ye), hi = fminf(y1, s.ye);
-    if (!(lo <= hi)) return false;
-    const float yl = s.yx, yr = -s.yx;
-    const float xmin = (yl >= lo && yl <= hi) ? -s.xe : edge_x(s, yl < lo ? lo : hi, -1.0f);
-    const float xmax = (yr >= lo && yr <= hi) ? s.xe : edge_x(s, yr < lo ? lo : hi, 1.0f);
-    // pixel-centre columns k with k + 0.5 - u in [xmin, xmax], clamped to the image
-    const float kl = fmaxf(ceilf((s.u + xmin) - 0.5f), 0.0f);
-    const float kr = fminf(floorf((s.u + xmax) - 0.5f), (float)(W - 1));
-    if (!(kl <= kr)) return false;
-    int a = tile_of((int)kl, tw), b = tile_of((int)kr, tw);
-    if (a < x0) a = x0;
-    if (b > x1) b = x1;
-    if (a > b) return false;
-    l = a;
-    r = b;
+    const int j0 = ty * th;
+    const int j1 = min(j0 + th, H) - 1;
+    const int k0 = x0 * tw;
+    const int k1 = min((x1 + 1) * tw, W) - 1;
+    if (j0 > j1 || k0 > k1) return false;
+    int cl = k0, cr = k1;
+    if (sp.ok) {
+        // offsets of the band's centre rows, clipped to the ellipse's y-extent
+        const float y0 = ((float)j0 + 0.5f) - sp.v;
+        const float y1 = ((float)j1 + 0.5f) - sp.v;
+        if (y0 > sp.ye + sp.my || y1 < -sp.ye - sp.my) return false;
+        float lo = fmaxf(y0, -sp.ye), hi = fminf(y1, sp.ye);
+        if (lo > hi) lo = hi = y0 > 0.0f ? sp.ye : -sp.ye;  // band beyond the extent, within the margin
+        const float yl = sp.yx, yr = -sp.yx;
+        const float xmin = (yl >= lo && yl <= hi) ? -sp.xe : edge_x(sp, yl < lo ? lo : hi, -1.0f);
+        const float xmax = (yr >= lo && yr <= hi) ? sp.xe : edge_x(sp, yr < lo ? lo : hi, 1.0f);
+        // centre columns k with k + 0.5 - u in [xmin - mx, xmax + mx]
+        cl = clamp_index(floorf(((sp.u + xmin) - 0.5f) - sp.mx), k0, k1 + 1);
+        cr = clamp_index(ceilf(((sp.u + xmax) - 0.5f) + sp.mx), k0 - 1, k1);
+    }
+    int kl = cl;
+    while (kl <= cr && !column_hit(sp, kl, j0, j1)) ++kl;
+    if (kl > cr) return false;
+    int kr = cr;
+    while (kr > kl && !column_hit(sp, kr, j0, j1)) --kr;
+    l = tile_of(kl, tw);
+    r = tile_of(kr, tw);
     return true;
 }
 

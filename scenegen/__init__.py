@@ -24,6 +24,8 @@ from __future__ import annotations
 
 import dataclasses
 import math
+import os
+import multiprocessing
 from typing import List, Optional
 
 import numpy as np
@@ -267,14 +269,29 @@ def _raycast_view(objs: _Objects, R, t, fx, fy, cx, cy, W, H):
     return label
 
 
+def _raycast_one(args):
+    objs, R, t, fx, fy, cx, cy, W, H = args
+    return _raycast_view(objs, R, t, fx, fy, cx, cy, W, H).astype(np.uint8)
+
+
 def _raycast_masks(objs, cams, fg_map=None):
+    """Ray-cast label masks of every view. Large jobs run on a pool of fresh
+    worker processes (at most 16); each view is computed the same way wherever
+    it runs, so the masks do not depend on the pool."""
     R, t, fx, fy, cx, cy, W, H = cams
-    out = []
-    for v in range(R.shape[0]):
-        lab = _raycast_view(objs, R[v], t[v], float(fx[v]), float(fy[v]), float(cx[v]), float(cy[v]), int(W[v]), int(H[v]))
-        if fg_map is not None:
-            lab = fg_map[lab]
-        out.append(lab.astype(np.uint8))
+    n = R.shape[0]
+    jobs = [(objs, R[v], t[v], float(fx[v]), float(fy[v]), float(cx[v]), float(cy[v]), int(W[v]), int(H[v]))
+            for v in range(n)]
+    work = float(np.sum(W.astype(np.float64) * H)) * max(1, len(objs))
+    workers = max(1, min(16, os.cpu_count() or 1, n))
+    if workers > 1 and work > 2e8:
+        ctx = multiprocessing.get_context("spawn")
+        with ctx.Pool(workers) as pool:
+            out = pool.map(_raycast_one, jobs, chunksize=max(1, n // (4 * workers)))
+    else:
+        out = [_raycast_one(j) for j in jobs]
+    if fg_map is not None:
+        out = [fg_map[m].astype(np.uint8) for m in out]
     return out
 
 
@@ -296,11 +313,14 @@ def _noise_erode(rng, masks, p, dist=2):
 
 
 def _noise_relabel(rng, masks, p, E):
+    """Each pixel, with probability p, takes one of the other E - 1 labels uniformly."""
     out = []
     for m in masks:
-        sel = rng.random(m.shape) < p
-        shift = rng.integers(1, E, size=m.shape)
-        mm = np.where(sel, (m.astype(np.int64) + shift) % E, m).astype(np.uint8)
+        sel = np.flatnonzero(rng.random(m.shape) < p)
+        shift = rng.integers(1, E, size=sel.size)
+        mm = m.copy()
+        flat = mm.reshape(-1)
+        flat[sel] = ((flat[sel].astype(np.int64) + shift) % E).astype(np.uint8)
         out.append(mm)
     return out
 

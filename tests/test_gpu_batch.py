@@ -60,7 +60,7 @@ def test_multi_scene_batch_matches_the_oracle(ctx):
         blends += ref["blends"]
         assert_A(_A(b, i), ref["A"], ref["slack"], what=f"batch scene {i}")
         S64, m64 = O.assign64(ref["A"], gammas[i])
-        assert_labels(b.S[i].cpu().numpy(), S64, m64, ref["A"], ref["slack"], what=f"batch scene {i}")
+        assert_labels(b.S[i].cpu().numpy(), S64, m64, ref["A"], _A(b, i), what=f"batch scene {i}")
         # margins are |a_n - o_n - gamma| of the normalised sums (Eq. (8)), within the A tolerance
         mg = b.margin[i].cpu().numpy()
         assert np.all(mg >= 0)

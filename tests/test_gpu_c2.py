@@ -75,7 +75,7 @@ def test_A_and_labels_match_the_oracle_at_full_size(c2, ref):
         S = torch.empty((E, n), dtype=torch.uint8, device="cuda")
         ctx.fs_assign(out["A_hi"], out["A_lo"], n, E, gamma, S, None)
         S64, m64 = O.assign64(ref["A"], gamma)
-        assert_labels(S.cpu().numpy(), S64, m64, ref["A"], ref["slack"], what=f"C2 gamma={gamma}")
+        assert_labels(S.cpu().numpy(), S64, m64, ref["A"], A, what=f"C2 gamma={gamma}")
 
 
 def test_graph_batch_matches_the_oracle_at_full_size(c2, ref):
@@ -90,7 +90,7 @@ def test_graph_batch_matches_the_oracle_at_full_size(c2, ref):
     log(f"[c2] graph batch: pairs emitted {st2['pairs_emitted']} of {b.info()['pairs']} planned")
     assert abs(st2["blends"] - ref["blends"]) <= 1e-3 * ref["blends"]
     S64, m64 = O.assign64(ref["A"], 0.2)
-    assert_labels(b.S[0].cpu().numpy(), S64, m64, ref["A"], ref["slack"], what="C2 graph batch gamma=0.2")
+    assert_labels(b.S[0].cpu().numpy(), S64, m64, ref["A"], A, what="C2 graph batch gamma=0.2")
 
 
 def test_batched_equals_per_view(c2):

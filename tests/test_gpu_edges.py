@@ -71,7 +71,7 @@ def _solve_and_compare(ctx, sc, prm, what, reduction=L.FS_RED_AUTO, chunk=None):
         A += out["A_lo"].double().cpu().numpy()
     stats = assert_A(A, ref["A"], ref["slack"], what=what)
     S64, m64 = O.assign64(ref["A"], 0.0)
-    assert_labels(out["S"].cpu().numpy(), S64, m64, ref["A"], ref["slack"], what=what)
+    assert_labels(out["S"].cpu().numpy(), S64, m64, ref["A"], A, what=what)
     return stats, st, ref
 
 
@@ -235,13 +235,13 @@ def test_near_degenerate_splats_use_the_float64_conic(ctx):
     ref = O.solve64(sc, O.params())
     A = (out["A_hi"].double() + out["A_lo"].double()).cpu().numpy()
     deg = disks | needles
-    st_all, bad = compare_A(A, ref["A"], ref["slack"])
-    st_reg, bad_reg = compare_A(A[~deg], ref["A"][~deg], ref["slack"][~deg])
-    st_deg, _ = compare_A(A[deg], ref["A"][deg], ref["slack"][deg], rel=1e-2)
-    log(f"[degenerate] fp64 splats {st['fp64_splats']}; regular rows {st_reg}; degenerate rows {st_deg}")
-    # regular Gaussians keep the acceptance tolerance; the error of near-degenerate rows is reported
-    assert st_reg["rows_failing"] == 0 and st_reg["aggregate_rel"] <= 1e-4
-    assert st_deg["aggregate_rel"] <= 1e-2
+    st_reg, _ = compare_A(A[~deg], ref["A"][~deg], ref["slack"][~deg])
+    st_deg, _ = compare_A(A[deg], ref["A"][deg], ref["slack"][deg])
+    log(f"[degenerate] fp64 splats {st['fp64_splats']}; regular rows {st_reg}; needle and disk rows {st_deg}")
+    # every row, needles and disks included, meets the acceptance bound: the conic's LDL^T
+    # factors evaluate without cancellation
+    assert_A(A, ref["A"], ref["slack"], what="needles and disks")
+    assert st_deg["rows_failing"] == 0 and st_deg["aggregate_rel"] <= 1e-4
 
 
 def test_threshold_free_preset(ctx):

@@ -42,7 +42,8 @@ def test_sweep_equals_single_assignments_and_the_oracle(ctx, c1):
         ctx.fs_assign(out["A_hi"], out["A_lo"], n, E, g, one, None)
         assert np.array_equal(one.cpu().numpy(), Sg[k])  # same arithmetic as the single call
         _, m64 = O.assign64(ref["A"], g)
-        assert_labels(Sg[k], S64[k], m64, ref["A"], ref["slack"], what=f"sweep gamma={g}")
+        Ag = (out["A_hi"].double() + out["A_lo"].double()).cpu().numpy()
+        assert_labels(Sg[k], S64[k], m64, ref["A"], Ag, what=f"sweep gamma={g}")
     assert np.all(np.diff(counts, axis=0) <= 0)
     ctx.status()
 

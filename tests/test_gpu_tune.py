@@ -44,7 +44,8 @@ def test_tuner_picks_a_valid_setting_that_matches_the_oracle(tmp_path):
         A = A + b.A_lo[0].double()
     prm = pick["params"]
     ref = O.solve64(sc, O.params(tile_w=prm["tile_w"], tile_h=prm["tile_h"]))
-    assert_A(A.cpu().numpy(), ref["A"], ref["slack"], what="tuned settings")
+    A = A.cpu().numpy()
+    assert_A(A, ref["A"], ref["slack"], what="tuned settings")
     S64, m64 = O.assign64(ref["A"], 0.0)
-    assert_labels(b.S[0].cpu().numpy(), S64, m64, ref["A"], ref["slack"], what="tuned settings")
+    assert_labels(b.S[0].cpu().numpy(), S64, m64, ref["A"], A, what="tuned settings")
     b.close()
