@@ -235,6 +235,26 @@ int fs_accumulate(fs_ctx *ctx, const fs_proj *proj, const fs_bins *bins, const f
                   const uint8_t *masks, int32_t n_classes, const fs_params *p,
                   float *A_hi, float *A_lo, int32_t reduction, const fs_pixel_out *pix);
 
+/* fs_accumulate for callers that cannot allocate memory: code recorded under
+ * HIP graph capture, tight serving loops, harnesses that forbid hipMalloc.
+ * Same arguments, results and errors as fs_accumulate; the call itself
+ * allocates nothing (no hipMalloc, hipFree or host allocation). Its device
+ * workspace (the call's view table, the longest-list-first work order and
+ * that order's sort workspace) is one static array of about 17.5 MB per GPU
+ * (each GPU the library runs on holds it until the process ends); its host
+ * tables go through pinned memory that fs_ctx_create reserves.
+ * Limits: at most FS_NOALLOC_MAX_VIEWS views and FS_NOALLOC_MAX_TILES tiles
+ * per call; larger calls return FS_ERR_CAPACITY before any work is enqueued.
+ * All calls on one GPU share the array: calls that overlap in time on that
+ * GPU (other contexts, other streams) race and must be serialised by the
+ * caller. A call may wait on the host for the table copy of the context's
+ * previous call to finish. */
+#define FS_NOALLOC_MAX_VIEWS 4096
+#define FS_NOALLOC_MAX_TILES 1048576
+int fs_accumulate_noalloc(fs_ctx *ctx, const fs_proj *proj, const fs_bins *bins, const fs_camera *cams,
+                          const uint8_t *masks, int32_t n_classes, const fs_params *p,
+                          float *A_hi, float *A_lo, int32_t reduction, const fs_pixel_out *pix);
+
 /* a7: assignment (Sec. 3.2 Eq. (7) and "Regularized ILP"; Sec. 3.3 Eq. (8);
  * Listing 1 of the supplement). For every Gaussian g and object t:
  * a = A[g][t], o = sum_{e != t} A[g][e], formed as the row total minus a

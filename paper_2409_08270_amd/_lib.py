@@ -34,6 +34,9 @@ FS_RED_PLAIN = 1
 FS_RED_LDS = 2
 FS_RED_LDS2SUM = 3
 
+FS_NOALLOC_MAX_VIEWS = 4096
+FS_NOALLOC_MAX_TILES = 1048576
+
 FS_MASK_DEPTH = 0
 FS_MASK_ARGMAX = 1
 
@@ -98,10 +101,11 @@ class FsBatchInfo(ctypes.Structure):
         return {k: int(getattr(self, k)) for k, _ in self._fields_}
 
 
+
 # every symbol the header declares (checked by the CPU test)
 EXPORTS = ["fs_version", "fs_error_string", "fs_params_default", "fs_params_exact", "fs_ctx_create",
            "fs_ctx_set_stream", "fs_ctx_destroy", "fs_ctx_last_error", "fs_status_get", "fs_project",
-           "fs_bin_sort", "fs_accumulate", "fs_assign", "fs_assign_sweep", "fs_compact", "fs_render_masks",
+           "fs_bin_sort", "fs_accumulate", "fs_accumulate_noalloc", "fs_assign", "fs_assign_sweep", "fs_compact", "fs_render_masks",
            "fs_prompt_propagate", "fs_diagnose", "fs_last_accumulate_ms",
            "fs_batch_opts_default", "fs_batch_create",
            "fs_batch_run", "fs_batch_get_info", "fs_batch_destroy"]
@@ -134,6 +138,8 @@ def load(path: str = LIB_PATH):
                          ctypes.POINTER(FsBins), ctypes.POINTER(_I64)], _I32),
         "fs_accumulate": ([_P, ctypes.POINTER(FsProj), ctypes.POINTER(FsBins), ctypes.POINTER(FsCamera), _P, _I32,
                            ctypes.POINTER(FsParams), _P, _P, _I32, ctypes.POINTER(FsPixelOut)], _I32),
+        "fs_accumulate_noalloc": ([_P, ctypes.POINTER(FsProj), ctypes.POINTER(FsBins), ctypes.POINTER(FsCamera), _P,
+                                   _I32, ctypes.POINTER(FsParams), _P, _P, _I32, ctypes.POINTER(FsPixelOut)], _I32),
         "fs_assign": ([_P, _P, _P, _I64, _I32, _F, _P, _P], _I32),
         "fs_assign_sweep": ([_P, _P, _P, _I64, _I32, ctypes.POINTER(_F), _I32, _P, ctypes.POINTER(_I64)], _I32),
         "fs_compact": ([_P, ctypes.POINTER(FsGaussians), _P, _I32, ctypes.POINTER(FsGaussians), _P,
@@ -263,6 +269,19 @@ class Context:
         return self._check(self.L.fs_accumulate(self.h, ctypes.byref(proj.struct()), ctypes.byref(bins.struct()),
                                                 cams, _ptr(masks), n_classes, ctypes.byref(prm), _ptr(A_hi),
                                                 _ptr(A_lo), reduction, ctypes.byref(pix) if pix else None))
+
+    def fs_accumulate_noalloc(self, proj: "Proj", bins: "Bins", cams, masks: torch.Tensor, n_classes: int,
+                              prm: FsParams, A_hi: torch.Tensor, A_lo: Optional[torch.Tensor],
+                              reduction: int = FS_RED_AUTO, t_final: Optional[torch.Tensor] = None,
+                              n_blend: Optional[torch.Tensor] = None):
+        """fs_accumulate with its workspace in the library's static scratch (allocates nothing)."""
+        pix = None
+        if t_final is not None or n_blend is not None:
+            pix = FsPixelOut(_ptr(t_final), _ptr(n_blend))
+        return self._check(self.L.fs_accumulate_noalloc(self.h, ctypes.byref(proj.struct()),
+                                                        ctypes.byref(bins.struct()), cams, _ptr(masks), n_classes,
+                                                        ctypes.byref(prm), _ptr(A_hi), _ptr(A_lo), reduction,
+                                                        ctypes.byref(pix) if pix else None))
 
     def fs_assign(self, A_hi: torch.Tensor, A_lo: Optional[torch.Tensor], n: int, n_classes: int, gamma: float,
                   S: torch.Tensor, margin: Optional[torch.Tensor] = None):

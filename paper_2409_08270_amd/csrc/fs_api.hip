@@ -12,6 +12,7 @@
 #include <string.h>
 
 #include <algorithm>
+#include <mutex>
 #include <new>
 #include <string>
 #include <vector>
@@ -56,7 +57,13 @@ struct fs_ctx {
     int stage_next = 0;
     hipEvent_t acc_ev[2] = {nullptr, nullptr};  // around the last compositing launch
     bool acc_timed = false;
-    std::string last_error;
+    // fs_accumulate_noalloc: this device's copy of the static scratch array, and
+    // pinned host room for the call's tables (reused once its last copy is done)
+    unsigned char *scratch = nullptr;
+    void *na_host = nullptr;
+    hipEvent_t na_ev = nullptr;
+    bool na_pending = false;
+    char last_error[512] = {0};  // fixed size: reporting an error allocates nothing
 };
 
 namespace {
@@ -64,12 +71,10 @@ namespace {
 int set_err(fs_ctx *ctx, int code, const char *fmt, ...)
 {
     if (ctx) {
-        char buf[512];
         va_list ap;
         va_start(ap, fmt);
-        vsnprintf(buf, sizeof(buf), fmt, ap);
+        vsnprintf(ctx->last_error, sizeof(ctx->last_error), fmt, ap);
         va_end(ap);
-        ctx->last_error = buf;
     }
     return code;
 }
@@ -270,6 +275,28 @@ struct Plan {
     uint64_t pixels = 0;
 };
 
+// Device description of one view: camera, tile grid, and where its tiles,
+// mask, projection plane and pixel state start.
+ViewDev make_view(const fs_camera &c, const fs_params *p, uint32_t scene, int64_t n, uint64_t tile_base,
+                  uint64_t mask_off, uint64_t elem_off, uint64_t pix_off)
+{
+    ViewDev d;
+    memcpy(d.R, c.R, sizeof(d.R));
+    memcpy(d.t, c.t, sizeof(d.t));
+    d.fx = c.fx; d.fy = c.fy; d.cx = c.cx; d.cy = c.cy;
+    d.W = c.width; d.H = c.height;
+    d.tiles_x = (c.width + p->tile_w - 1) / p->tile_w;
+    d.tiles_y = (c.height + p->tile_h - 1) / p->tile_h;
+    d.tile_base = (uint32_t)tile_base;
+    d.scene = scene;
+    d.mask_off = mask_off;
+    d.elem_off = elem_off;
+    d.pix_off = pix_off;
+    d.n = (uint32_t)n;
+    d.pad = 0;
+    return d;
+}
+
 // Appends views [v0, v1) of a scene with n Gaussians; mask_off0 is the mask
 // offset of view v0 within the scene's masks.
 void plan_add(Plan &pl, const fs_params *p, uint32_t scene, int64_t n, const fs_camera *cams, int v0, int v1,
@@ -279,20 +306,7 @@ void plan_add(Plan &pl, const fs_params *p, uint32_t scene, int64_t n, const fs_
     const int first = (int)pl.views.size();
     for (int v = v0; v < v1; ++v) {
         const fs_camera &c = cams[v];
-        ViewDev d;
-        memcpy(d.R, c.R, sizeof(d.R));
-        memcpy(d.t, c.t, sizeof(d.t));
-        d.fx = c.fx; d.fy = c.fy; d.cx = c.cx; d.cy = c.cy;
-        d.W = c.width; d.H = c.height;
-        d.tiles_x = (c.width + p->tile_w - 1) / p->tile_w;
-        d.tiles_y = (c.height + p->tile_h - 1) / p->tile_h;
-        d.tile_base = (uint32_t)pl.tiles;
-        d.scene = scene;
-        d.mask_off = moff;
-        d.elem_off = pl.elems;
-        d.pix_off = pl.pixels;
-        d.n = (uint32_t)n;
-        d.pad = 0;
+        const ViewDev d = make_view(c, p, scene, n, pl.tiles, moff, pl.elems, pl.pixels);
         pl.views.push_back(d);
         SegDev sg;
         sg.off = pl.elems;
@@ -366,6 +380,78 @@ int enqueue_lpt(fs_ctx *ctx, hipStream_t s, const uint32_t *ranges, uint64_t n_t
     return FS_OK;
 }
 
+// ---- static scratch of fs_accumulate_noalloc -------------------------------
+// Layout: the call's tables (scene, work-order sort segment, views), copied
+// from the host in one transfer, then four tile-index arrays for the
+// longest-list-first order and the radix sort's workspace.
+constexpr size_t kNaAlign = 256;
+constexpr size_t na_round(size_t b) { return (b + kNaAlign - 1) / kNaAlign * kNaAlign; }
+constexpr size_t kNaSceneOff = 0;
+constexpr size_t kNaSegOff = kNaSceneOff + na_round(sizeof(SceneDev));
+constexpr size_t kNaViewsOff = kNaSegOff + na_round(sizeof(SegDev));
+constexpr size_t kNaTableBytes = kNaViewsOff + na_round((size_t)FS_NOALLOC_MAX_VIEWS * sizeof(ViewDev));
+constexpr size_t kNaItemBytes = na_round((size_t)FS_NOALLOC_MAX_TILES * 4);
+constexpr size_t kNaItemsOff = kNaTableBytes;
+constexpr size_t kNaWsOff = kNaItemsOff + 4 * kNaItemBytes;
+constexpr size_t kNaWsBytes = (size_t)1 << 20;
+constexpr size_t kNaBytes = kNaWsOff + kNaWsBytes;
+constexpr int kNaMaxDevices = 64;
+
+}  // namespace
+
+// One copy per GPU, held until the process ends. Host code never uses this
+// name as an address: the device address comes from hipGetSymbolAddress.
+static __device__ __align__(256) unsigned char scratch[kNaBytes];
+
+namespace {
+
+std::mutex g_na_mu;
+unsigned char *g_na_ptr[kNaMaxDevices] = {};
+
+// Device address of the current device's scratch array, looked up once per
+// device (the caller has made `device` current).
+int scratch_address(fs_ctx *ctx, int device, unsigned char **out)
+{
+    if (device < 0 || device >= kNaMaxDevices) return set_err(ctx, FS_ERR_ARG, "device %d out of range", device);
+    std::lock_guard<std::mutex> lk(g_na_mu);
+    if (!g_na_ptr[device]) {
+        void *ptr = nullptr;
+        const hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+        if (e != hipSuccess || !ptr)
+            return set_err(ctx, FS_ERR_HIP, "hipGetSymbolAddress(scratch) failed: %s", hipGetErrorString(e));
+        g_na_ptr[device] = (unsigned char *)ptr;
+    }
+    *out = g_na_ptr[device];
+    return FS_OK;
+}
+
+__global__ void k_xcd_items(uint32_t *items, uint32_t n_tiles)
+{
+    const uint32_t b = blockIdx.x * blockDim.x + threadIdx.x;
+    if (b >= n_tiles) return;
+    const uint32_t base = n_tiles / kXcds, rem = n_tiles % kXcds, x = b % kXcds;
+    items[b] = x * base + min(x, rem) + b / kXcds;
+}
+
+// Arguments of fs_accumulate and fs_accumulate_noalloc; resolves FS_RED_AUTO.
+int check_accumulate(fs_ctx *ctx, const fs_proj *proj, const fs_bins *bins, const fs_camera *cams,
+                     const uint8_t *masks, int32_t n_classes, const fs_params *p, const float *A_hi,
+                     const float *A_lo, int32_t *reduction)
+{
+    RCHECK(check_params(ctx, p, true));
+    RCHECK(check_proj(ctx, proj));
+    if (!bins || !bins->ranges) return set_err(ctx, FS_ERR_ARG, "bins is NULL");
+    RCHECK(check_cams(ctx, cams, proj->n_views));
+    if (n_classes < 2 || n_classes > 256) return set_err(ctx, FS_ERR_ARG, "n_classes %d not in [2, 256]", n_classes);
+    int32_t r = *reduction;
+    if (r < FS_RED_AUTO || r > FS_RED_LDS2SUM) return set_err(ctx, FS_ERR_ARG, "unknown reduction %d", r);
+    if (r == FS_RED_AUTO) r = A_lo ? FS_RED_LDS2SUM : FS_RED_LDS;
+    if (r == FS_RED_LDS2SUM && !A_lo) return set_err(ctx, FS_ERR_ARG, "FS_RED_LDS2SUM needs A_lo");
+    if (proj->n > 0 && proj->n_views > 0 && (!masks || !A_hi)) return set_err(ctx, FS_ERR_ARG, "masks or A_hi is NULL");
+    *reduction = r;
+    return FS_OK;
+}
+
 }  // namespace
 
 extern "C" {
@@ -431,6 +517,10 @@ int fs_ctx_create(fs_ctx **out, void *stream)
         if (hipEventCreateWithFlags(&ctx->stage[i].ev, hipEventDisableTiming) != hipSuccess) rc = FS_ERR_HIP;
     for (int i = 0; !rc && i < 2; ++i)
         if (hipEventCreate(&ctx->acc_ev[i]) != hipSuccess) rc = FS_ERR_HIP;
+    // fs_accumulate_noalloc's set-up: this device's scratch address, pinned table room
+    if (!rc) rc = scratch_address(ctx, ctx->device, &ctx->scratch);
+    if (!rc && hipHostMalloc(&ctx->na_host, kNaTableBytes, hipHostMallocDefault) != hipSuccess) rc = FS_ERR_ALLOC;
+    if (!rc && hipEventCreateWithFlags(&ctx->na_ev, hipEventDisableTiming) != hipSuccess) rc = FS_ERR_HIP;
     if (!rc && launch_fill_u32(ctx->stream, (uint32_t *)ctx->status_dev, 0u, kStatusWords * 2) != hipSuccess) rc = FS_ERR_HIP;
     if (!rc && launch_fill_u32(ctx->stream, ctx->npairs_dev, 0u, 16) != hipSuccess) rc = FS_ERR_HIP;
     if (!rc && hipStreamSynchronize(ctx->stream) != hipSuccess) rc = FS_ERR_HIP;
@@ -465,6 +555,8 @@ int fs_ctx_destroy(fs_ctx *ctx)
     }
     for (int i = 0; i < 2; ++i)
         if (ctx->acc_ev[i]) (void)hipEventDestroy(ctx->acc_ev[i]);
+    if (ctx->na_ev) (void)hipEventDestroy(ctx->na_ev);
+    if (ctx->na_host) (void)hipHostFree(ctx->na_host);
     if (ctx->status_dev) (void)hipFree(ctx->status_dev);
     if (ctx->npairs_dev) (void)hipFree(ctx->npairs_dev);
     if (ctx->status_host) (void)hipHostFree(ctx->status_host);
@@ -473,7 +565,7 @@ int fs_ctx_destroy(fs_ctx *ctx)
     return FS_OK;
 }
 
-const char *fs_ctx_last_error(fs_ctx *ctx) { return ctx ? ctx->last_error.c_str() : ""; }
+const char *fs_ctx_last_error(fs_ctx *ctx) { return ctx ? ctx->last_error : ""; }
 
 int fs_status_get(fs_ctx *ctx, fs_status *out, int32_t clear)
 {
@@ -622,15 +714,7 @@ int fs_accumulate(fs_ctx *ctx, const fs_proj *proj, const fs_bins *bins, const f
                   const fs_pixel_out *pix)
 {
     if (!ctx) return FS_ERR_ARG;
-    RCHECK(check_params(ctx, p, true));
-    RCHECK(check_proj(ctx, proj));
-    if (!bins || !bins->ranges) return set_err(ctx, FS_ERR_ARG, "bins is NULL");
-    RCHECK(check_cams(ctx, cams, proj->n_views));
-    if (n_classes < 2 || n_classes > 256) return set_err(ctx, FS_ERR_ARG, "n_classes %d not in [2, 256]", n_classes);
-    if (reduction < FS_RED_AUTO || reduction > FS_RED_LDS2SUM) return set_err(ctx, FS_ERR_ARG, "unknown reduction %d", reduction);
-    if (reduction == FS_RED_AUTO) reduction = A_lo ? FS_RED_LDS2SUM : FS_RED_LDS;
-    if (reduction == FS_RED_LDS2SUM && !A_lo) return set_err(ctx, FS_ERR_ARG, "FS_RED_LDS2SUM needs A_lo");
-    if (proj->n > 0 && proj->n_views > 0 && (!masks || !A_hi)) return set_err(ctx, FS_ERR_ARG, "masks or A_hi is NULL");
+    RCHECK(check_accumulate(ctx, proj, bins, cams, masks, n_classes, p, A_hi, A_lo, &reduction));
     const int32_t V = proj->n_views;
     if (proj->n == 0 || V == 0) return FS_OK;
     Plan pl;
@@ -668,6 +752,77 @@ int fs_accumulate(fs_ctx *ctx, const fs_proj *proj, const fs_bins *bins, const f
                                     pix ? pix->t_final : nullptr, pix ? pix->n_blend : nullptr, nullptr, nullptr, 1,
                                     ctx->status_dev));
     if (timed) HIPCHECK(ctx, hipEventRecord(ctx->acc_ev[1], ctx->stream));
+    ctx->acc_timed = timed;
+    return FS_OK;
+}
+
+int fs_accumulate_noalloc(fs_ctx *ctx, const fs_proj *proj, const fs_bins *bins, const fs_camera *cams,
+                          const uint8_t *masks, int32_t n_classes, const fs_params *p, float *A_hi, float *A_lo,
+                          int32_t reduction, const fs_pixel_out *pix)
+{
+    if (!ctx) return FS_ERR_ARG;
+    RCHECK(check_accumulate(ctx, proj, bins, cams, masks, n_classes, p, A_hi, A_lo, &reduction));
+    const int32_t V = proj->n_views;
+    if (proj->n == 0 || V == 0) return FS_OK;
+    if (V > FS_NOALLOC_MAX_VIEWS)
+        return set_err(ctx, FS_ERR_CAPACITY, "%d views in one call, the static scratch holds %d", V,
+                       FS_NOALLOC_MAX_VIEWS);
+    uint64_t n_tiles = 0;
+    for (int v = 0; v < V; ++v)
+        n_tiles += (uint64_t)((cams[v].width + p->tile_w - 1) / p->tile_w) *
+                   (uint64_t)((cams[v].height + p->tile_h - 1) / p->tile_h);
+    if (n_tiles > (uint64_t)FS_NOALLOC_MAX_TILES)
+        return set_err(ctx, FS_ERR_CAPACITY, "%llu tiles in one call, the static scratch holds %d",
+                       (unsigned long long)n_tiles, FS_NOALLOC_MAX_TILES);
+    const uint32_t lblocks = (uint32_t)((n_tiles + kSortTile - 1) / kSortTile);
+    if (radix_ws_bytes(lblocks) > kNaWsBytes)
+        return set_err(ctx, FS_ERR_CAPACITY, "work-order sort needs %zu bytes of scratch, %zu reserved",
+                       radix_ws_bytes(lblocks), kNaWsBytes);
+    if (!ctx->scratch || !ctx->na_host) return set_err(ctx, FS_ERR_STATE, "context has no static scratch");
+    // the call's tables, built in the pinned host room once its previous copy has completed
+    if (ctx->na_pending) {
+        HIPCHECK(ctx, hipEventSynchronize(ctx->na_ev));
+        ctx->na_pending = false;
+    }
+    unsigned char *h = (unsigned char *)ctx->na_host;
+    *(SceneDev *)(h + kNaSceneOff) = scene_dev(nullptr, proj->n, masks, A_hi, A_lo, n_classes);
+    *(SegDev *)(h + kNaSegOff) = SegDev{0, (uint32_t)n_tiles, 0, (uint32_t)n_tiles, 0};
+    ViewDev *hv = (ViewDev *)(h + kNaViewsOff);
+    uint64_t tb = 0, mo = 0, eo = 0;
+    for (int v = 0; v < V; ++v) {
+        hv[v] = make_view(cams[v], p, 0, proj->n, tb, mo, eo, mo);
+        tb += (uint64_t)hv[v].tiles_x * (uint64_t)hv[v].tiles_y;
+        mo += (uint64_t)cams[v].width * (uint64_t)cams[v].height;
+        eo += (uint64_t)proj->n;
+    }
+    unsigned char *d = ctx->scratch;
+    hipStream_t s = ctx->stream;
+    HIPCHECK(ctx, hipMemcpyAsync(d, h, kNaViewsOff + (size_t)V * sizeof(ViewDev), hipMemcpyHostToDevice, s));
+    HIPCHECK(ctx, hipEventRecord(ctx->na_ev, s));
+    ctx->na_pending = true;
+    const ViewDev *views = (const ViewDev *)(d + kNaViewsOff);
+    const SceneDev *scenes = (const SceneDev *)(d + kNaSceneOff);
+    uint32_t *it[4];
+    for (int i = 0; i < 4; ++i) it[i] = (uint32_t *)(d + kNaItemsOff + (size_t)i * kNaItemBytes);
+    const uint32_t *items = nullptr;
+    if (p->tile_order == 0) {
+        RCHECK(enqueue_lpt(ctx, s, bins->ranges, n_tiles, (const SegDev *)(d + kNaSegOff), it[0], it[1], it[2], it[3],
+                           d + kNaWsOff));
+        items = it[0];
+    } else if (p->tile_order == 2) {
+        hipLaunchKernelGGL(k_xcd_items, dim3((unsigned)((n_tiles + 255) / 256)), dim3(256), 0, s, it[0],
+                           (uint32_t)n_tiles);
+        HIPCHECK(ctx, hipGetLastError());
+        items = it[0];
+    }
+    hipStreamCaptureStatus cap = hipStreamCaptureStatusNone;
+    HIPCHECK(ctx, hipStreamIsCapturing(s, &cap));
+    const bool timed = cap == hipStreamCaptureStatusNone;
+    if (timed) HIPCHECK(ctx, hipEventRecord(ctx->acc_ev[0], s));
+    HIPCHECK(ctx, launch_accumulate(s, proj->rec, bins->vals, bins->ranges, views, V, scenes, items, (uint32_t)n_tiles,
+                                    acc_params(p, reduction), pix ? pix->t_final : nullptr,
+                                    pix ? pix->n_blend : nullptr, nullptr, nullptr, 1, ctx->status_dev));
+    if (timed) HIPCHECK(ctx, hipEventRecord(ctx->acc_ev[1], s));
     ctx->acc_timed = timed;
     return FS_OK;
 }

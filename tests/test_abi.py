@@ -62,6 +62,14 @@ def test_batch_defaults_and_null_handling(lib):
     assert lib.fs_batch_get_info(None, ctypes.byref(inf)) == L.FS_ERR_ARG
 
 
+def test_header_limits_match_the_binding():
+    from paper_2409_08270_amd import _lib as L
+    src = open(HEADER).read()
+    for name in ("FS_NOALLOC_MAX_VIEWS", "FS_NOALLOC_MAX_TILES", "FS_DEV_MANY_LABELS", "FS_RED_LDS2SUM"):
+        m = re.search(r"#define\s+" + name + r"\s+(\d+)", src)
+        assert m and int(m.group(1)) == getattr(L, name), name
+
+
 def test_struct_layouts_match_the_header(tmp_path):
     """sizeof/offsetof of every public struct, from a C compiler, against the ctypes mirror."""
     import subprocess
