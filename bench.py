@@ -1,14 +1,20 @@
 #!/usr/bin/env python3
 """Throughput of the splat-and-accumulate path on one MI355X.
 
-Workload: the 200k-Gaussian plain configuration (4 clustered objects plus a
-background shell, 50 orbit views at 640x480, binary masks with boundary
-erosion, background bias 0), synthetic and seeded. One step = one full solve:
-project, bin/sort, composite + accumulate over all 50 views, then assign.
+Default workload: the multi-scene batch, the largest configuration that fits
+one GPU: 32 synthetic scenes of uneven size (50k-800k Gaussians, 20-120
+views each, 320x240 to 1008x756, 2-32 classes, ray-cast label masks with 3%
+relabels, background bias 0), seeded. One step = the whole solve of all 32
+scenes as one hipGraph launch: project, bin/sort, composite + accumulate over
+every view, then every scene's assignment. `--config C2|C3|C4` runs one of
+the single-scene workloads instead.
 
 Prints one JSON line: views/s of the batched path (value), blends/s, the
-plain per-view path for comparison, the roofline of the compositing kernel,
-and the CPU oracle timed on a bounded sample of views.
+plain per-view path (per view: project, bin with a host count, composite with
+one global atomic per weight) and the per-view path with the LDS reduction for
+comparison, the roofline of the compositing kernel (launches timed with HIP
+events on the streams they run on), per-variant error against the float64
+oracle, and the CPU oracle timed on a bounded sample of views.
 """
 from __future__ import annotations
 
@@ -21,8 +27,14 @@ import time
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
-PEAK_ALU_OPS = 256 * 64 * 2.4e9   # fp32 lane-ops/s: 256 CUs x 64 lanes/clk x 2.4 GHz (no packed, no FMA credit)
+# MI355X published peaks: fp32 vector 157.3 TFLOP/s (256 CUs x 128 lanes x 2 (FMA) x 2.4 GHz, packed
+# fp32 counted); HBM3E 8 TB/s
+PEAK_FP32 = 157.3e12
 PEAK_HBM = 8.0e12
+# issue rate of one (non-packed) VALU lane operation per lane and clock: 256 CUs x 64 lanes x 2.4 GHz
+PEAK_LANE_OPS = 256 * 64 * 2.4e9
+
+TRAFFIC_RECORD = os.path.join(ROOT, "profiles", "k_accum_c5_traffic.json")
 
 
 def parse():
@@ -30,32 +42,40 @@ def parse():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=2)
-    ap.add_argument("--config", default="C2")
-    ap.add_argument("--cpu-views", type=int, default=24, help="views of the CPU oracle sample (0: skip)")
-    ap.add_argument("--no-plain", action="store_true")
+    ap.add_argument("--config", default="C5", help="C5 (multi-scene batch, default) or C1-C4")
+    ap.add_argument("--scenes", type=int, default=32, help="scenes of the C5 batch")
+    ap.add_argument("--cpu-views", type=int, default=16, help="views of the CPU oracle sample (0: skip)")
+    ap.add_argument("--no-plain", action="store_true", help="skip the per-view comparators")
+    ap.add_argument("--no-precision", action="store_true", help="skip the per-variant error report")
     ap.add_argument("--lanes", type=int, default=0, help="batch lanes (0: the tuned or the library's default)")
     ap.add_argument("--tuned", default=None, help="tuning table (default: the package's tuned.json)")
     ap.add_argument("--no-tuned", action="store_true", help="run the library's default settings")
-    ap.add_argument("--no-strategies", action="store_true",
-                    help="skip the per-strategy compositing comparison (keeps one launch shape per kernel)")
     ap.add_argument("--copy-probe", type=int, default=0, metavar="MIB",
                     help="only run a device-to-device copy of this many MiB (HBM counter calibration)")
     return ap.parse_args()
 
 
-def recorded_traffic():
-    """HBM bytes per compositing launch from the committed rocprofv3 FETCH_SIZE / WRITE_SIZE
-    summary (scaled by the copy-probe calibration), or None when the kernel source has changed
-    since the counters were taken."""
+def log(msg):
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+
+def kernel_source_hash():
     import hashlib
-    path = os.path.join(ROOT, "profiles", "k_accum_c2_traffic.json")
-    try:
-        rec = json.load(open(path))
-    except (OSError, ValueError):
-        return None
     csrc = os.path.join(ROOT, "paper_2409_08270_amd", "csrc")
     src = open(os.path.join(csrc, "fs_accum.hip"), "rb").read() + open(os.path.join(csrc, "fs_internal.h"), "rb").read()
-    if hashlib.sha256(src).hexdigest() != rec.get("kernel_source_sha256"):
+    return hashlib.sha256(src).hexdigest()
+
+
+def recorded_traffic(workload: str, settings: dict):
+    """HBM bytes per compositing launch from the committed rocprofv3 FETCH_SIZE / WRITE_SIZE
+    record (scaled by the copy-probe calibration), or None when the kernel source, the workload or
+    the launch settings differ from those the counters were taken on."""
+    try:
+        rec = json.load(open(TRAFFIC_RECORD))
+    except (OSError, ValueError):
+        return None
+    if rec.get("kernel_source_sha256") != kernel_source_hash() or rec.get("workload") != workload \
+            or rec.get("settings") != settings:
         return None
     return float(rec["hbm_bytes_per_launch"])
 
@@ -75,6 +95,23 @@ def copy_probe(mib: int):
     print(json.dumps({"copy_probe_bytes_each_way": n * 4, "launches": 3}))
 
 
+def row_errors(parts):
+    """Per-row L1 relative error against the float64 oracle over (A, A64, slack) parts
+    (one per scene; seen rows only)."""
+    import numpy as np
+    d = np.concatenate([np.abs(A - A64).sum(1) for A, A64, _ in parts])
+    s = np.concatenate([np.abs(A64).sum(1) for _, A64, _ in parts])
+    slack = np.concatenate([sl for _, _, sl in parts])
+    seen = s > 0
+    r = d[seen] / s[seen]
+    if r.size == 0:
+        return {"rows": 0}
+    return {"rows": int(seen.sum()), "max": float(r.max()), "p99": float(np.percentile(r, 99)),
+            "median": float(np.median(r)),
+            "rows_over_1e-4_with_slack": int((d > 1e-4 * s + slack + 1e-9).sum()),
+            "rows_over_1e-4_without_slack": int((d > 1e-4 * s + 1e-9).sum())}
+
+
 def main():
     args = parse()
     if args.copy_probe:
@@ -89,48 +126,63 @@ def main():
 
     import scenegen as sg
     from paper_2409_08270_amd import _lib as L
+    from paper_2409_08270_amd import tune as T
     from paper_2409_08270_amd.solve import Solver
 
     torch.cuda.set_device(0)
     t0 = time.time()
-    sc = sg.make_config(args.config)
-    print(f"[bench] scene {args.config}: N={sc.n} views={sc.n_views} {int(sc.W[0])}x{int(sc.H[0])} E={sc.E} "
-          f"(generated in {time.time() - t0:.1f}s)", file=sys.stderr, flush=True)
-    ds = L.DeviceScene(sc)
+    if args.config == "C5":
+        scenes = sg.make_batch(args.scenes)
+    else:
+        scenes = [sg.make_config(args.config)]
+    n_sc = len(scenes)
+    V = sum(s.n_views for s in scenes)
+    N = sum(s.n for s in scenes)
+    px_total = sum(s.pixels() for s in scenes)
+    if args.config == "C5":
+        res = sorted({f"{int(s.W[0])}x{int(s.H[0])}" for s in scenes}, key=lambda r: int(r.split("x")[0]))
+        workload = (f"C5: {n_sc} scenes of uneven size ({min(s.n for s in scenes)}-{max(s.n for s in scenes)} "
+                    f"Gaussians, {min(s.n_views for s in scenes)}-{max(s.n_views for s in scenes)} views each, "
+                    f"{V} views in total, {' '.join(res)}, {min(s.E for s in scenes)}-{max(s.E for s in scenes)} "
+                    f"classes), gamma=0")
+    else:
+        s = scenes[0]
+        workload = f"{args.config}: {s.n} Gaussians, {s.n_views} views {int(s.W[0])}x{int(s.H[0])}, E={s.E}, gamma=0"
+    log(f"workload {workload}; {N} Gaussians, {px_total} pixels (generated in {time.time() - t0:.1f}s)")
+    dss = [L.DeviceScene(s) for s in scenes]
     ctx = L.Context()
-    V = sc.n_views
+    gam = [0.0] * n_sc
 
-    # settings of the batched solve: the tuner's entry for this workload shape, if any
-    from paper_2409_08270_amd import tune as T
-    tuned = None if args.no_tuned else T.lookup(T.load(args.tuned or T.TABLE_PATH), T.scene_key(sc))
+    # settings of the batched solve: the tuner's entry for this workload, if any
+    key = T.batch_key(scenes)
+    tuned = None if args.no_tuned else T.lookup(T.load(args.tuned or T.TABLE_PATH), key)
     prm_kw = dict(tuned["params"]) if tuned else {}
     opt_kw = dict(tuned["opts"]) if tuned else {}
     if args.lanes:
         opt_kw["lanes"] = args.lanes
-    print(f"[bench] settings: {'tuned ' + str(tuned) if tuned else 'library defaults'}; overrides {opt_kw}",
-          file=sys.stderr, flush=True)
+    log(f"settings for {key}: {'tuned ' + str(tuned) if tuned else 'library defaults'}; overrides {opt_kw}")
 
-    # ---- batched: the whole solve (all views, assignment included) as one graph launch ----
-    # The timed graph runs without the per-step evaluation/blend counters (count_ops = 0:
-    # same A and S, two fewer instructions per pixel step); the work it does is counted by
-    # one replay of an instrumented graph of the same workload.
+    # ---- counted replay: the work the solve does (blends, in-support evaluations, staged entries)
     prm = L.params(count_ops=0, **prm_kw)
     prm_count = L.params(count_ops=1, **prm_kw)
-    counted = L.Batch(ctx, [ds], prm_count, gammas=[0.0], **opt_kw)
+    counted = L.Batch(ctx, dss, prm_count, gammas=gam, **opt_kw)
     ctx.status()
     counted.run()
     torch.cuda.synchronize()
     st = ctx.status()
-    S_counted = counted.S[0].cpu().numpy()
+    S_counted = [x.cpu().numpy() for x in counted.S]
     counted.close()
     del counted
     blends = float(st["blends"])
     evals = float(st["evaluated"])
     staged = float(st["entries_staged"])
     wsteps, wsteps_max = float(st["wave_steps"]), float(st["wave_steps_max"])
-    batch = L.Batch(ctx, [ds], prm, gammas=[0.0], **opt_kw)
+
+    # ---- batched: the whole solve as one graph launch, timed -------------------------------------
+    # The timed graph runs without the evaluation/blend counters (count_ops = 0: same A and S).
+    batch = L.Batch(ctx, dss, prm, gammas=gam, **opt_kw)
     binfo = batch.info()
-    print(f"[bench] batch planned: {binfo}", file=sys.stderr, flush=True)
+    log(f"batch planned: {binfo}")
     for _ in range(args.warmup):
         batch.run()
     torch.cuda.synchronize()
@@ -143,67 +195,51 @@ def main():
     dt_b = (time.perf_counter() - t) / args.steps
     st_t = ctx.status()
     assert st_t["blends"] == 0 and st_t["evaluated"] == 0, "the timed graph was not the uncounted one"
-    labels_differ = int((batch.S[0].cpu().numpy() != S_counted).sum())
+    labels_differ = int(sum((b.cpu().numpy() != a).sum() for a, b in zip(S_counted, batch.S)))
     pairs_emitted = st_t["pairs_emitted"] / args.steps
     pairs = binfo["pairs"]
+    log(f"batched graph: {dt_b * 1e3:.2f} ms/step, {V / dt_b:.0f} views/s, pairs planned {pairs} sorted "
+        f"{pairs_emitted:.0f}, blends {blends:.3e}, evaluated {evals:.3e}")
 
-    # ---- the compositing kernel alone, same launch as inside the graph, timed with HIP events
-    # recorded on the stream it runs on
-    solver = Solver(ctx, ds, prm)
-    solver.solve(chunk=V, want_margin=False)
-    cams, nv = ds.cams()
-    n, E = sc.n, sc.E
-    A_hi = torch.zeros((n, E), dtype=torch.float32, device="cuda")
-    A_lo = torch.zeros((n, E), dtype=torch.float32, device="cuda")
-    ctx.status()
-    ctx.fs_accumulate(solver.proj, solver.bins, cams, ds.masks, E, prm_count, A_hi, A_lo, L.FS_RED_LDS2SUM)
-    st_acc = ctx.status()
-    assert abs(st_acc["blends"] - blends) <= 1e-6 * blends, "standalone compositing saw different work than the graph"
-    acc_ms = []
+    # ---- the compositing launches of the same solve, each timed with HIP events recorded on the
+    # stream it runs on (the same plan and launches, enqueued without the graph)
+    nog = L.Batch(ctx, dss, prm, gammas=gam, use_graph=0, **opt_kw)
+    nog.run()
+    torch.cuda.synchronize()
+    acc_tot, acc_n = [], 0
     for _ in range(args.steps):
-        # HIP events that the library records on its stream right around the compositing launch
-        ctx.fs_accumulate(solver.proj, solver.bins, cams, ds.masks, E, prm, A_hi, A_lo, L.FS_RED_LDS2SUM)
-        acc_ms.append(ctx.fs_last_accumulate_ms())
-    print(f"[bench] batched graph: {dt_b * 1e3:.2f} ms/step, pairs planned {pairs} sorted {pairs_emitted:.0f}, "
-          f"blends {blends:.3e}, "
-          f"evaluated {evals:.3e}, accumulate kernel {np.mean(acc_ms):.3f} ms; wave steps {wsteps:.3e}, "
-          f"4 x per-tile max {4 * wsteps_max:.3e}", file=sys.stderr, flush=True)
-
-    # ---- compositing kernel alone, per reduction strategy (same bins) --------
-    strat = {}
-    prm_img = L.params(tile_order=1, count_ops=0)
-    prm_xcd = L.params(tile_order=2, count_ops=0)
-    for name, red, comp, prm_s in (() if args.no_strategies else (("plain_atomics", L.FS_RED_PLAIN, False, prm),
-                                 ("lds", L.FS_RED_LDS, False, prm),
-                                 ("lds_two_sum", L.FS_RED_LDS2SUM, True, prm),
-                                 ("lds_two_sum_image_order", L.FS_RED_LDS2SUM, True, prm_img),
-                                 ("lds_two_sum_xcd_runs", L.FS_RED_LDS2SUM, True, prm_xcd))):
-        n, E = sc.n, sc.E
-        A_hi = torch.zeros((n, E), dtype=torch.float32, device="cuda")
-        A_lo = torch.zeros((n, E), dtype=torch.float32, device="cuda") if comp else None
-        ts = []
-        for _ in range(3):
-            ctx.fs_accumulate(solver.proj, solver.bins, cams, ds.masks, E, prm_s, A_hi, A_lo, red)
-            ts.append(ctx.fs_last_accumulate_ms())
-        strat[name] = float(np.median(ts))
+        nog.run()
+        ms, acc_n = nog.accumulate_ms()
+        acc_tot.append(ms)
+    torch.cuda.synchronize()
     ctx.status()
-    print(f"[bench] compositing kernel per strategy (ms): {strat}", file=sys.stderr, flush=True)
+    nog.close()
+    del nog
+    acc_ms_step = float(np.median(acc_tot))
+    launch_ms = acc_ms_step / max(1, acc_n)
+    log(f"compositing: {acc_n} launches per step, {acc_ms_step:.3f} ms per step, {launch_ms:.3f} ms per launch")
 
-    # ---- plain (per view) ---------------------------------------------------
-    dt_p = None
+    # ---- per-view comparators: the paper's scheme (per view: project, bin with a host count,
+    # composite with one global float32 atomic per weight) and the same calls with the LDS reduction
+    dt_p = dt_pl = None
     if not args.no_plain:
-        for _ in range(max(1, args.warmup // 2)):
-            solver.solve(chunk=1, want_margin=False)
-        torch.cuda.synchronize()
-        t = time.perf_counter()
-        for _ in range(args.steps):
-            solver.solve(chunk=1, want_margin=False)
-        torch.cuda.synchronize()
-        dt_p = (time.perf_counter() - t) / args.steps
-        ctx.status()
-        print(f"[bench] plain: {dt_p * 1e3:.2f} ms/step", file=sys.stderr, flush=True)
+        def per_view(reduction, compensated):
+            solvers = [Solver(ctx, ds, prm) for ds in dss]
+            solvers[0].solve(chunk=1, reduction=reduction, compensated=compensated, want_margin=False,
+                             views=[0, 1])  # warm-up
+            torch.cuda.synchronize()
+            t = time.perf_counter()
+            for sv in solvers:
+                sv.solve(chunk=1, reduction=reduction, compensated=compensated, want_margin=False)
+            torch.cuda.synchronize()
+            ctx.status()
+            return time.perf_counter() - t
+        dt_p = per_view(L.FS_RED_PLAIN, False)
+        log(f"plain per view (global atomics, float32): {dt_p * 1e3:.1f} ms per pass, {V / dt_p:.0f} views/s")
+        dt_pl = per_view(L.FS_RED_AUTO, True)
+        log(f"per view with the LDS reduction + two-sum: {dt_pl * 1e3:.1f} ms per pass, {V / dt_pl:.0f} views/s")
 
-    # ---- follow-ups once A is known: bias sweep, object removal ----------------
+    # ---- follow-ups once A is known, on the largest scene ----------------------------------------
     def timed(fn, reps=5):
         ts = []
         for _ in range(reps):
@@ -215,98 +251,134 @@ def main():
             ts.append(e0.elapsed_time(e1))
         return float(np.median(ts))
 
-    S_one = torch.empty((sc.E, sc.n), dtype=torch.uint8, device="cuda")
-    m_one = torch.empty((sc.E, sc.n), dtype=torch.float32, device="cuda")
-    assign_ms = timed(lambda: ctx.fs_assign(batch.A_hi[0], batch.A_lo[0], sc.n, sc.E, 0.0, S_one, m_one))
-    gam = [float(x) for x in np.linspace(-0.5, 0.5, 64)]
-    S_sw = torch.empty((64, sc.E, sc.n), dtype=torch.uint8, device="cuda")
-    sweep_ms = timed(lambda: ctx.fs_assign_sweep(batch.A_hi[0], batch.A_lo[0], sc.n, sc.E, gam, S_sw,
+    big = int(np.argmax([s.n for s in scenes]))
+    sb, db = scenes[big], dss[big]
+    S_one = torch.empty((sb.E, sb.n), dtype=torch.uint8, device="cuda")
+    m_one = torch.empty((sb.E, sb.n), dtype=torch.float32, device="cuda")
+    assign_ms = timed(lambda: ctx.fs_assign(batch.A_hi[big], batch.A_lo[big], sb.n, sb.E, 0.0, S_one, m_one))
+    ng = max(1, min(64, 4096 // sb.E))
+    gams = [float(x) for x in np.linspace(-0.5, 0.5, ng)]
+    S_sw = torch.empty((ng, sb.E, sb.n), dtype=torch.uint8, device="cuda")
+    sweep_ms = timed(lambda: ctx.fs_assign_sweep(batch.A_hi[big], batch.A_lo[big], sb.n, sb.E, gams, S_sw,
                                                  want_counts=False))
-    sel = batch.S[0][1].contiguous()
-    compact_ms = timed(lambda: ctx.fs_compact(ds, sel, False))
-    labels = torch.empty(sc.pixels(), dtype=torch.uint8, device="cuda")
-    render_ms = timed(lambda: ctx.fs_render_masks(solver.proj, solver.bins, cams, batch.S[0], sc.E, prm, 0.1,
-                                                  L.FS_MASK_DEPTH, labels))
-    agree = float((labels.cpu().numpy() == ds.masks.cpu().numpy()).mean())
-    # point-prompt propagation (synchronous call: wall clock, host copies included)
-    rng = np.random.default_rng(11)
-    prompts = np.stack([rng.uniform(0, sc.W[0], 16), rng.uniform(0, sc.H[0], 16),
-                        rng.uniform(2.0, 5.0, 16)], 1).astype(np.float32)
-    ctx.fs_prompt_propagate(ds, 0, prompts, k=10)
-    pts = []
-    for _ in range(5):
-        t = time.perf_counter()
-        ctx.fs_prompt_propagate(ds, 0, prompts, k=10)
-        pts.append((time.perf_counter() - t) * 1e3)
-    followups = {"assign_ms": assign_ms, "prompt_propagation_16_prompts_ms": float(np.median(pts)), "bias_sweep_64_gammas_ms": sweep_ms, "object_removal_compaction_ms": compact_ms,
-                 "mask_render_all_views_ms": render_ms, "mask_render_views_per_sec": V / (render_ms * 1e-3),
-                 "rendered_masks_agree_with_inputs": agree, "gaussians": sc.n}
-    print(f"[bench] follow-ups: {followups}", file=sys.stderr, flush=True)
+    sel = batch.S[big][1].contiguous()
+    compact_ms = timed(lambda: ctx.fs_compact(db, sel, False))
+    followups = {"scene": big, "gaussians": sb.n, "classes": sb.E, "assign_ms": assign_ms,
+                 f"bias_sweep_{ng}_gammas_ms": sweep_ms, "object_removal_compaction_ms": compact_ms,
+                 "assign_all_scenes_in_graph": True}
+    log(f"follow-ups: {followups}")
 
-    # ---- roofline of the compositing kernel (one launch over all views) -----
-    # algorithmic fp32 ops: 15 per (pixel, Gaussian) pair inside the support (offset, quadratic form,
-    # support test, exp, opacity, clamp, alpha test) + 5 per blend (1-alpha, T update, stop test, w, add)
-    ops = 15.0 * evals + 5.0 * blends
-    acc_s = float(np.mean(acc_ms)) * 1e-3
-    achieved = ops / acc_s
-    roof = {"bound": "alu", "achieved": achieved / 1e12, "peak": PEAK_ALU_OPS / 1e12, "unit": "TFLOP/s",
-            "frac": achieved / PEAK_ALU_OPS,
-            # the counters were taken on 16x16 tiles in the longest-first order
-            "traffic": recorded_traffic() if (prm.tile_w, prm.tile_h, prm.tile_order) == (16, 16, 0) else None,
-            "traffic_unit": "bytes per launch (HBM)",
-            "kernel": "k_accum",
-            "ops_per_launch": ops, "launch_ms": acc_s * 1e3,
+    # ---- roofline of the compositing kernel --------------------------------------------------------
+    # algorithmic fp32 flops: 15 per blend (offset, quadratic form, opacity, clamp, alpha test, weight,
+    # transmittance update, stop test, accumulate) + 1 exp per in-support evaluation
+    flops = 15.0 * blends + 1.0 * evals
+    acc_s = acc_ms_step * 1e-3
+    achieved = flops / acc_s
+    settings = {"tile": f"{prm.tile_w}x{prm.tile_h}", "tile_order": int(prm.tile_order), **opt_kw}
+    roof = {"bound": "alu", "achieved": achieved / 1e12, "peak": PEAK_FP32 / 1e12, "unit": "TFLOP/s",
+            "frac": achieved / PEAK_FP32,
+            "traffic": recorded_traffic(workload, settings),
+            "traffic_unit": "HBM bytes per launch (rocprofv3 FETCH_SIZE + WRITE_SIZE, copy-calibrated)",
+            "kernel": "k_accum", "launches_per_step": acc_n, "launch_ms": launch_ms,
+            "flops_per_launch": flops / max(1, acc_n),
+            "flop_count": "15 per blend + 1 exp per in-support evaluation",
+            "lane_ops": {"per_step": 15.0 * evals + 5.0 * blends,
+                         "rate": (15.0 * evals + 5.0 * blends) / acc_s / 1e12, "unit": "T lane-ops/s",
+                         "peak": PEAK_LANE_OPS / 1e12,
+                         "frac": (15.0 * evals + 5.0 * blends) / acc_s / PEAK_LANE_OPS},
             "wave_steps": wsteps, "wave_balance": wsteps / max(1.0, 4 * wsteps_max)}
 
-    # ---- the whole path against the HBM roof --------------------------------
-    # algorithmic bytes of one step (what the method must move, from counted quantities):
-    # Gaussians read once per chunk, 44 B per (Gaussian, view) for the projected record and its
-    # count, 36 B per pair (emit + one sort read and write), 8 B per tile range, 28 B per staged
-    # list entry (id + gathered record), the masks, and A written, read and S written once
+    # ---- the whole path against the HBM roof --------------------------------------------------------
+    # algorithmic bytes of one step (what the method must move, from counted quantities): Gaussians
+    # read once, 44 B per (Gaussian, view) for the projected record and its count, 36 B per
+    # pair (emit + one sort read and write), 8 B per tile range, 28 B per staged list entry (id +
+    # gathered record), the masks, and A written, read and S written once
     n_chunks = binfo["n_chunks"]
-    terms = {"gaussians": 44.0 * sc.n * n_chunks, "projected": 44.0 * sc.n * V, "pairs": 36.0 * pairs,
-             "ranges": 8.0 * binfo["tiles"], "staged": 28.0 * staged, "masks": float(sc.pixels()),
-             "assign": 17.0 * sc.n * sc.E}
+    NE = sum(s.n * s.E for s in scenes)
+    terms = {"gaussians": 44.0 * N,
+             "projected": 44.0 * binfo["elements"], "pairs": 36.0 * pairs, "ranges": 8.0 * binfo["tiles"],
+             "staged": 28.0 * staged, "masks": float(px_total), "assign": 17.0 * NE}
     path_bytes = sum(terms.values())
     hbm_frac = path_bytes / dt_b / PEAK_HBM
     path = {"hbm": {"algorithmic_bytes_per_step": path_bytes, "achieved": path_bytes / dt_b / 1e9,
                     "peak": PEAK_HBM / 1e9, "unit": "GB/s", "frac": hbm_frac, "terms": terms,
                     "entries_staged": staged},
-            "alu_compositing_frac": roof["frac"],
-            "binding": "alu (compositing)" if roof["frac"] >= hbm_frac else "hbm"}
+            "compositing_share_of_step": acc_ms_step / (dt_b * 1e3),
+            "binding": "alu (compositing)" if acc_ms_step / (dt_b * 1e3) >= 0.5 else "hbm (binning)"}
 
-    # ---- CPU oracle on a bounded sample of views -----------------------------
-    cpu = None
-    parity = None
+    # ---- CPU oracle on a bounded sample of views; parity and precision of the GPU on the same views
+    cpu = parity = precision = None
     if args.cpu_views > 0:
         import oracle as O
-        sample = [int(round(i * V / args.cpu_views)) for i in range(args.cpu_views)]
+        from concurrent.futures import ThreadPoolExecutor
+        k = min(args.cpu_views, V)
+        if n_sc > 1:
+            # the middle view of k scenes spread over the batch
+            picks = sorted(set(int(x) for x in np.linspace(0, n_sc - 1, min(k, n_sc)).round()))
+            sample = [(si, scenes[si].n_views // 2) for si in picks]
+        else:
+            sample = [(0, int(round(i * V / k))) for i in range(k)]
         cores = len(os.sched_getaffinity(0))
-        os.environ.setdefault("OMP_NUM_THREADS", str(cores))
+        threads = max(1, min(16, cores, len(sample)))
+        by_scene = {}
+        for si, v in sample:
+            by_scene.setdefault(si, []).append(v)
         t = time.perf_counter()
-        ref = O.solve64(sc, O.params(), views=sample)
+        with ThreadPoolExecutor(threads) as ex:
+            refs = dict(zip(by_scene, ex.map(lambda it: O.solve64(scenes[it[0]], O.params(), views=it[1]),
+                                             by_scene.items())))
         dt_c = time.perf_counter() - t
-        cpu = {"value": len(sample) / dt_c, "unit": "views/s", "cores": int(os.environ.get("OMP_NUM_THREADS", cores)),
-               "kind": "oracle", "sample": f"views {sample} of {args.config} (binning in binary32 + compositing "
-                                           f"and accumulation in binary64), {dt_c:.1f}s",
-               "blends_per_sec": ref["blends"] / dt_c}
-        # parity of the GPU path on the same views
-        n, E = sc.n, sc.E
-        A_hi = torch.zeros((n, E), dtype=torch.float32, device="cuda")
-        A_lo = torch.zeros((n, E), dtype=torch.float32, device="cuda")
-        s2 = Solver(ctx, ds)
-        for v in sample:
-            s2.accumulate_views([v], A_hi, A_lo)
-        A = (A_hi.double() + A_lo.double()).cpu().numpy()
-        d = np.abs(A - ref["A"]).sum(1)
-        s = np.abs(ref["A"]).sum(1)
-        bad = d > 1e-4 * s + ref["slack"] + 1e-9
-        S64, m64 = O.assign64(ref["A"], 0.0)
-        S_g = torch.empty((E, n), dtype=torch.uint8, device="cuda")
-        ctx.fs_assign(A_hi, A_lo, n, E, 0.0, S_g, None)
-        mism = int(((S_g.cpu().numpy() != S64) & (m64 >= 1e-4)).sum())
-        parity = {"views": sample, "rows_off_tolerance": int(bad.sum()), "aggregate_rel": float(d.sum() / s.sum()),
-                  "label_mismatches_margin_ge_1e-4": mism, "low_margin_entries": int((m64 < 1e-4).sum())}
+        oblends = sum(r["blends"] for r in refs.values())
+        cpu = {"value": len(sample) / dt_c, "unit": "views/s", "cores": threads, "kind": "oracle",
+               "sample": f"{len(sample)} (scene, view) pairs of {args.config} {sample}: binning in binary32, "
+                         f"compositing and accumulation in binary64, {threads} host threads (one scene each), "
+                         f"{dt_c:.1f}s; whole workload extrapolated: {V * dt_c / len(sample):.0f}s",
+               "blends_per_sec": oblends / dt_c,
+               "extrapolated_seconds_per_step": V * dt_c / len(sample)}
+        log(f"cpu oracle: {cpu}")
+        # the GPU on the same views, per reduction variant
+        variants = {"fp32_global_atomics": (L.FS_RED_PLAIN, False), "fp32_lds": (L.FS_RED_LDS, False),
+                    "lds_two_sum": (L.FS_RED_LDS2SUM, True)}
+        if args.no_precision:
+            variants = {"lds_two_sum": variants["lds_two_sum"]}
+        precision = {k_: {"rows": 0} for k_ in variants}
+        acc_rows = {k_: [] for k_ in variants}
+        fp64_rows = []
+        mism = low = 0
+        bad_rows = 0
+        for si, views in by_scene.items():
+            sc_, ref = scenes[si], refs[si]
+            for name, (red, comp) in variants.items():
+                A_hi = torch.zeros((sc_.n, sc_.E), dtype=torch.float32, device="cuda")
+                A_lo = torch.zeros_like(A_hi) if comp else None
+                sv = Solver(ctx, dss[si], L.params())
+                for v in views:
+                    sv.accumulate_views([v], A_hi, A_lo, red)
+                A = A_hi.double().cpu().numpy()
+                if A_lo is not None:
+                    A += A_lo.double().cpu().numpy()
+                acc_rows[name].append((A, ref["A"], ref["slack"]))
+                if name == "lds_two_sum":
+                    d = np.abs(A - ref["A"]).sum(1)
+                    s_ = np.abs(ref["A"]).sum(1)
+                    bad_rows += int((d > 1e-4 * s_ + ref["slack"] + 1e-9).sum())
+                    S64, m64 = O.assign64(ref["A"], 0.0)
+                    S_g = torch.empty((sc_.E, sc_.n), dtype=torch.uint8, device="cuda")
+                    ctx.fs_assign(A_hi, A_lo, sc_.n, sc_.E, 0.0, S_g, None)
+                    mism += int(((S_g.cpu().numpy() != S64) & (m64 >= 1e-4)).sum())
+                    low += int((m64 < 1e-4).sum())
+                    deg = np.zeros(sc_.n, bool)
+                    for v in views:
+                        deg |= (O.project32(sc_, v, O.params())["flags"] & 2) != 0
+                    fp64_rows.append((A[deg], ref["A"][deg], ref["slack"][deg]))
+            ctx.status()
+        for name in variants:
+            precision[name] = row_errors(acc_rows[name])
+        if fp64_rows:
+            precision["lds_two_sum_fp64_conic_rows"] = row_errors(fp64_rows)
+        parity = {"views": sample, "rows_off_tolerance": bad_rows,
+                  "label_mismatches_margin_ge_1e-4": mism, "low_margin_entries": low}
+        log(f"parity on the sample: {parity}; precision: {precision}")
 
     res = {
         "metric": "views/sec + Gaussian-pixel blends/sec; batched vs plain, labels matching oracle",
@@ -321,28 +393,29 @@ def main():
         "vs_baseline": None,
         "dtype": "f32",
         "data": "synthetic",
-        "config": {"workload": f"{args.config}: {sc.n} Gaussians (4 clusters + shell), {V} views "
-                               f"{int(sc.W[0])}x{int(sc.H[0])}, E={sc.E}, gamma=0", "mode": "batched, one hipGraph",
+        "config": {"workload": workload, "mode": "batched, one hipGraph per step",
                    "reduction": {L.FS_RED_LDS: "lds", L.FS_RED_LDS2SUM: "lds+two-sum"}.get(
                        opt_kw.get("reduction", L.FS_RED_LDS2SUM), "lds+two-sum"),
-                   "chunks": binfo["n_chunks"], "lanes": opt_kw.get("lanes", 2),
+                   "chunks": n_chunks, "lanes": opt_kw.get("lanes", 2),
                    "tile": f"{prm.tile_w}x{prm.tile_h}", "tile_order": int(prm.tile_order),
-                   "settings": "tuned" if tuned else "library defaults"},
+                   "settings": ("tuned " + key) if tuned else "library defaults"},
         "blends_per_sec": blends / dt_b,
-        "op_counts": "timed graph and compositing launches run with count_ops=0; evaluations and blends "
-                     "come from one instrumented replay of the same workload",
+        "views_per_step": V,
+        "op_counts": "timed graph runs with count_ops=0; evaluations and blends come from one instrumented "
+                     "replay of the same workload",
         "labels_differ_instrumented_vs_timed": labels_differ,
         "pairs_planned_per_step": pairs,
         "pairs_sorted_per_step": pairs_emitted,
-        "depth_slabs": 1,
         "plain_views_per_sec": (V / dt_p) if dt_p else None,
         "batched_over_plain": (dt_p / dt_b) if dt_p else None,
-        "accumulate_ms_by_strategy": strat,
+        "per_view_lds_views_per_sec": (V / dt_pl) if dt_pl else None,
+        "batched_over_per_view_lds": (dt_pl / dt_b) if dt_pl else None,
         "followups": followups,
         "roofline": roof,
         "path_roofline": path,
         "cpu_baseline": cpu,
         "parity_sample": parity,
+        "precision_vs_fp64_oracle": precision,
     }
     print(json.dumps(res))
 

@@ -57,8 +57,8 @@ extern "C" {
 #define FS_DEV_PAIR_OVERFLOW 2u  /* more tile pairs than the bins capacity (excess dropped) */
 #define FS_DEV_INVALID_GAUSS 4u  /* a Gaussian had non-finite values, a zero quaternion or a
                                     non-positive scale (culled) */
-#define FS_DEV_MANY_LABELS 8u    /* a tile held more distinct labels than the pre-reduction
-                                    slots; that tile used per-pixel atomics (informational) */
+#define FS_DEV_MANY_LABELS 8u    /* a tile held more than 64 distinct labels (the pre-reduction
+                                    slots); that tile used per-pixel atomics (informational) */
 
 /* reduction strategies of fs_accumulate */
 #define FS_RED_AUTO 0   /* library choice (currently FS_RED_LDS2SUM when A_lo != NULL, else FS_RED_LDS) */
@@ -109,6 +109,12 @@ typedef struct {
                                 blends into the status (fs_status_get); 0 leaves those two
                                 counters alone and saves two instructions per pixel step
                                 (A, S and every other output are the same either way) */
+    int32_t persistent;      /* compositing launch: 0 (default) one workgroup per tile; 1 as many
+                                workgroups as the chip holds at once, each taking the next tile of
+                                the work order from a device counter until none is left */
+    int32_t lds_batch;       /* most tile-list entries staged in LDS per compositing batch:
+                                32, 64, 128 or 256 (0 = default 256); tiles with more than 8
+                                labels stage fewer (128, 64, 32 for 16, 32, 64 labels) */
 } fs_params;
 
 /* Projected Gaussians, caller-owned device buffers, one plane per view:
@@ -427,6 +433,34 @@ int fs_batch_create(fs_ctx *ctx, const fs_scene *scenes, int32_t n_scenes, const
 int fs_batch_run(fs_batch *b);
 int fs_batch_get_info(fs_batch *b, fs_batch_info *out);
 int fs_batch_destroy(fs_batch *b);
+
+/* Measurement: total duration in ms of the compositing launches (Eq. (1),
+ * Eq. (7)-(8)) of the last fs_batch_run of a batch created with
+ * use_graph = 0, from HIP events recorded on each lane's stream right before
+ * and after every launch; *n_launches receives their number. Waits for the
+ * run to finish. FS_ERR_STATE for a graph batch or before a run. */
+int fs_batch_accumulate_ms(fs_batch *b, float *total_ms, int32_t *n_launches);
+
+/* Inspection of the tile lists (Sec. 3.1) that the batched solve builds for
+ * chunk `chunk` (0 <= chunk < n_chunks; batches with depth_slabs = 1): the
+ * chunk's projection, depth sort, pair emission, pair sort and ranges are
+ * re-run on the context's stream with the kernels and workspace of
+ * fs_batch_run, without compositing, and copied out. vals: device uint32
+ * [vals_cap], the Gaussian ids (within their scene) of every tile list, lists
+ * in tile order; ranges: device uint32 [ranges_cap][2], every tile's
+ * [start, end) into vals ([0, 0) when empty), tiles numbered view by view in
+ * chunk order, row-major within a view; view_refs: host int32
+ * [refs_cap][2], (scene, view) of the chunk's views in order. With vals,
+ * ranges or view_refs NULL only *info is filled. Synchronises the stream;
+ * FS_ERR_CAPACITY if an output is too small. */
+typedef struct {
+    int32_t n_views;
+    int32_t packed;            /* 1: the chunk sorts packed (tile, Gaussian) words per view */
+    int64_t n_tiles;
+    int64_t n_pairs;
+} fs_chunk_info;
+int fs_batch_chunk_lists(fs_batch *b, int32_t chunk, uint32_t *vals, int64_t vals_cap, uint32_t *ranges,
+                         int64_t ranges_cap, int32_t *view_refs, int32_t refs_cap, fs_chunk_info *info);
 
 #ifdef __cplusplus
 }

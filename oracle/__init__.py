@@ -203,23 +203,46 @@ def composite64(scene, v: int, prm: np.ndarray, bins: dict, A: np.ndarray, slack
 
 
 def solve64(scene, prm: Optional[np.ndarray] = None, views: Optional[Sequence[int]] = None,
-            want_pixels: bool = False, E: Optional[int] = None):
-    """A64 and slack over the given views (default: all), plus per-view details."""
+            want_pixels: bool = False, E: Optional[int] = None, threads: int = 1):
+    """A64 and slack over the given views (default: all), plus per-view details.
+
+    A is a sum over views (Eq. (7)): with threads > 1 the views are split
+    round-robin over that many host threads (the C routines run without the
+    interpreter lock), each adding into its own A and slack, and the partial
+    sums are added in thread order."""
     prm = params() if prm is None else prm
     E = scene.E if E is None else E
-    views = range(scene.n_views) if views is None else views
-    A = np.zeros((scene.n, E), np.float64)
-    slack = np.zeros(scene.n, np.float64)
-    per_view = {}
-    tot = dict(blends=0, flagged=0, bad_labels=0, evaluated=0)
+    views = list(range(scene.n_views) if views is None else views)
     g = _gauss(scene)
-    for v in views:
-        b = bin_view(scene, v, prm, project32(scene, v, prm, g))
-        p64 = project64(scene, v, prm, g)
-        r = composite64(scene, v, prm, b, A, slack, p64=p64, want_pixels=want_pixels)
-        for k in tot:
-            tot[k] += r[k]
-        per_view[v] = dict(bins=b, p64=p64, **r)
+
+    def run(group):
+        A = np.zeros((scene.n, E), np.float64)
+        slack = np.zeros(scene.n, np.float64)
+        per_view = {}
+        tot = dict(blends=0, flagged=0, bad_labels=0, evaluated=0)
+        for v in group:
+            b = bin_view(scene, v, prm, project32(scene, v, prm, g))
+            p64 = project64(scene, v, prm, g)
+            r = composite64(scene, v, prm, b, A, slack, p64=p64, want_pixels=want_pixels)
+            for k in tot:
+                tot[k] += r[k]
+            per_view[v] = dict(bins=b, p64=p64, **r)
+        return A, slack, per_view, tot
+
+    threads = max(1, min(int(threads), len(views)))
+    if threads == 1:
+        A, slack, per_view, tot = run(views)
+    else:
+        from concurrent.futures import ThreadPoolExecutor
+        with ThreadPoolExecutor(threads) as ex:
+            parts = list(ex.map(run, [views[i::threads] for i in range(threads)]))
+        A, slack, per_view, tot = parts[0]
+        for Ai, si, pv, ti in parts[1:]:
+            A += Ai
+            slack += si
+            per_view.update(pv)
+            for k in tot:
+                tot[k] += ti[k]
     return dict(A=A, slack=slack, views=per_view, **tot)
 
 

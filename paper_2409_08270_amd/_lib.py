@@ -58,7 +58,8 @@ class FsCamera(ctypes.Structure):
 class FsParams(ctypes.Structure):
     _fields_ = [("tile_w", _I32), ("tile_h", _I32), ("sigma_k", _F), ("lowpass", _F), ("znear", _F),
                 ("guard", _F), ("alpha_min", _F), ("alpha_max", _F), ("t_min", _F), ("fp64_cond", _F),
-                ("fp64_conic", _I32), ("tile_order", _I32), ("count_ops", _I32)]
+                ("fp64_conic", _I32), ("tile_order", _I32), ("count_ops", _I32), ("persistent", _I32),
+                ("lds_batch", _I32)]
 
 
 class FsProj(ctypes.Structure):
@@ -101,6 +102,12 @@ class FsBatchInfo(ctypes.Structure):
         return {k: int(getattr(self, k)) for k, _ in self._fields_}
 
 
+class FsChunkInfo(ctypes.Structure):
+    _fields_ = [("n_views", _I32), ("packed", _I32), ("n_tiles", _I64), ("n_pairs", _I64)]
+
+    def as_dict(self):
+        return {k: int(getattr(self, k)) for k, _ in self._fields_}
+
 
 # every symbol the header declares (checked by the CPU test)
 EXPORTS = ["fs_version", "fs_error_string", "fs_params_default", "fs_params_exact", "fs_ctx_create",
@@ -108,7 +115,8 @@ EXPORTS = ["fs_version", "fs_error_string", "fs_params_default", "fs_params_exac
            "fs_bin_sort", "fs_accumulate", "fs_accumulate_noalloc", "fs_assign", "fs_assign_sweep", "fs_compact", "fs_render_masks",
            "fs_prompt_propagate", "fs_diagnose", "fs_last_accumulate_ms",
            "fs_batch_opts_default", "fs_batch_create",
-           "fs_batch_run", "fs_batch_get_info", "fs_batch_destroy"]
+           "fs_batch_run", "fs_batch_get_info", "fs_batch_destroy", "fs_batch_accumulate_ms",
+           "fs_batch_chunk_lists"]
 
 _lib = None
 
@@ -156,6 +164,9 @@ def load(path: str = LIB_PATH):
         "fs_batch_run": ([_P], _I32),
         "fs_batch_get_info": ([_P, ctypes.POINTER(FsBatchInfo)], _I32),
         "fs_batch_destroy": ([_P], _I32),
+        "fs_batch_accumulate_ms": ([_P, ctypes.POINTER(_F), ctypes.POINTER(_I32)], _I32),
+        "fs_batch_chunk_lists": ([_P, _I32, _P, _I64, _P, _I64, ctypes.POINTER(_I32), _I32,
+                                  ctypes.POINTER(FsChunkInfo)], _I32),
     }
     for name, (args, res) in sig.items():
         f = getattr(L, name)
@@ -465,6 +476,28 @@ class Batch:
         inf = FsBatchInfo()
         self.ctx._check(self.L.fs_batch_get_info(self.h, ctypes.byref(inf)))
         return inf.as_dict()
+
+    def accumulate_ms(self):
+        """(total ms, launches) of the compositing launches of the last run (batches without a graph)."""
+        ms, cnt = _F(0.0), _I32(0)
+        self.ctx._check(self.L.fs_batch_accumulate_ms(self.h, ctypes.byref(ms), ctypes.byref(cnt)))
+        return float(ms.value), int(cnt.value)
+
+    def chunk_lists(self, chunk: int):
+        """The tile lists the solve builds for one chunk: (info, vals [n_pairs] u32 numpy,
+        ranges [n_tiles, 2] u32 numpy, view refs [(scene, view)])."""
+        inf = FsChunkInfo()
+        self.ctx._check(self.L.fs_batch_chunk_lists(self.h, chunk, None, 0, None, 0, None, 0, ctypes.byref(inf)))
+        dev = self.ctx.stream.device
+        vals = torch.empty(max(1, inf.n_pairs), dtype=torch.int32, device=dev)
+        ranges = torch.empty((max(1, inf.n_tiles), 2), dtype=torch.int32, device=dev)
+        refs = (_I32 * (2 * max(1, inf.n_views)))()
+        self.ctx._check(self.L.fs_batch_chunk_lists(self.h, chunk, _ptr(vals), vals.numel(), _ptr(ranges),
+                                                    ranges.shape[0], refs, inf.n_views, ctypes.byref(inf)))
+        v = vals[:inf.n_pairs].cpu().numpy().view(np.uint32)
+        r = ranges[:inf.n_tiles].cpu().numpy().view(np.uint32)
+        rr = [(refs[2 * j], refs[2 * j + 1]) for j in range(inf.n_views)]
+        return inf.as_dict(), v, r, rr
 
     def close(self):
         if getattr(self, "h", None) is not None:

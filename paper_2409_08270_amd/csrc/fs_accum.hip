@@ -8,19 +8,27 @@
 // and every thread walks the batch for its pixel.
 //
 // Scatter-add. The paper adds alpha*T with one atomic per (pixel, Gaussian).
-// Here the distinct labels of the tile are compacted into a few slots; each
-// wave sums its lanes' weights of 8 Gaussians at once per slot with a
-// cross-lane reduce-scatter, the four waves combine in an LDS partial, and
-// one global atomic per (tile, Gaussian, label) remains. With A_lo, the exact
-// rounding error of that atomic (two-sum on the returned old value) goes to
-// A_lo, so that A_hi + A_lo carries the sum to about one rounding.
+// Here the distinct labels of the tile are compacted into slots (up to 64);
+// a label that many lanes of a wave share is summed over the wave for 8
+// Gaussians at once with a cross-lane reduce-scatter, the few lanes whose
+// label is rare in their wave add their weights to LDS directly, the four
+// waves combine in an LDS partial per (Gaussian, slot), and one global atomic
+// per (tile, Gaussian, label) remains. The partials hold 2048 floats: a tile
+// with up to 8 labels stages 256 Gaussians per batch, with 16, 32 or 64
+// labels 128, 64 or 32. With A_lo, the exact rounding error of the global
+// atomic (two-sum on the returned old value) goes to A_lo, so that
+// A_hi + A_lo carries the sum to about one rounding.
+#include <algorithm>
+
 #include "fs_internal.h"
 
 namespace fs {
 namespace {
 
-constexpr int kSlots = 8;     // distinct labels per tile handled by pre-reduction
-constexpr int kBatch = 256;   // Gaussians staged per batch
+constexpr int kPart = 2048;   // LDS partial sums: staged Gaussians x label slots
+constexpr int kMaxSlots = 64; // distinct labels per tile handled by pre-reduction
+constexpr int kBatch = 256;   // most Gaussians staged per batch
+constexpr int kMajor = 4;     // a label held by this many lanes of a wave is summed across the wave
 constexpr float kLoFloor = -200.0f;  // floor of log2(opacity): 2^-200 is zero in float32
 
 template <int CTRL>
@@ -118,14 +126,15 @@ __device__ __forceinline__ bool block_hit(float u, float v, float p, float r, fl
     return qmin <= lim;
 }
 
+// Composites one tile (the whole workgroup); every thread calls it with the same tile.
 template <bool PIX, bool COUNT>
-__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(7, 7))) void k_accum(const float4 *__restrict__ rec, const uint32_t *__restrict__ vals,
-                                               const uint2 *__restrict__ ranges, const ViewDev *__restrict__ views,
-                                               int32_t n_views, const SceneDev *__restrict__ scenes,
-                                               const uint32_t *__restrict__ items, AccParams P,
-                                               float *__restrict__ t_final, int32_t *__restrict__ n_blend,
-                                               float *__restrict__ tstate, uint8_t *__restrict__ tile_done,
-                                               int32_t first, unsigned long long *__restrict__ status)
+__device__ __forceinline__ void accum_tile(const uint32_t tile, const float4 *__restrict__ rec,
+                                           const uint32_t *__restrict__ vals, const uint2 *__restrict__ ranges,
+                                           const ViewDev *__restrict__ views, int32_t n_views,
+                                           const SceneDev *__restrict__ scenes, const AccParams &P,
+                                           float *__restrict__ t_final, int32_t *__restrict__ n_blend,
+                                           float *__restrict__ tstate, uint8_t *__restrict__ tile_done,
+                                           int32_t first, unsigned long long *__restrict__ status)
 {
     // staged entry e: s_rec[e] = (u, v, p', r), (s', lo, thr, sup), with the LDL^T factors
     // p, s scaled to log2 units, lo = log2(opacity), sup = cut2 + lo (the support bound on the power) and
@@ -133,17 +142,16 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(7, 7))) voi
     // is the support test and the alpha_min test in one comparison; entry kBatch is a null record
     __shared__ float4 s_rec[2 * (kBatch + 1)];
     __shared__ uint32_t s_g[kBatch];
-    __shared__ float s_part[kBatch][kSlots];
+    __shared__ float s_part[kPart];        // [entry][stride]: partial sums per staged entry and slot
     __shared__ uint8_t s_wmask[kBatch];    // bit w: wave w's 8x8 block can be reached
     __shared__ __align__(16) uint32_t s_list[4][kBatch + 16];  // per-wave compacted entries (byte offsets
                                                                // into s_rec), padded with the null record
     __shared__ uint32_t s_bits[8];
-    __shared__ int32_t s_slot_label[kSlots];
-    __shared__ uint32_t s_wslots[4];
+    __shared__ int32_t s_slot_label[kMaxSlots];
+    __shared__ unsigned long long s_wslots[4];
     __shared__ uint32_t s_misc[5];      // bad labels, longest wave walk, blends, evaluations, walked entries
     __shared__ int4 s_wbox[4];          // per wave: columns x0..x1, rows y0..y1 of its live pixels
 
-    const uint32_t tile = items ? items[blockIdx.x] : blockIdx.x;
     if (tile_done && tile_done[tile]) return;  // every pixel of this tile has finished (whole block)
     const int view = find_view_of_tile(views, n_views, tile);
     const ViewDev &C = views[view];
@@ -187,21 +195,37 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(7, 7))) voi
         }
         slot += __popc(s_bits[word] & ((1u << (lab & 31)) - 1u));
     }
-    const bool plain = (P.reduction == FS_RED_PLAIN) || nslot > kSlots;
+    const bool plain = (P.reduction == FS_RED_PLAIN) || nslot > kMaxSlots;
+    // partial layout: `stride` slots per staged entry, `bsz` entries per batch
+    const int sh = nslot <= 8 ? 3 : (nslot <= 16 ? 4 : (nslot <= 32 ? 5 : 6));
+    const int stride = 1 << sh;
+    const uint32_t bsz = min(plain ? (uint32_t)kBatch : (uint32_t)(kPart >> sh), (uint32_t)P.batch);
     if (active && !plain) {
         s_slot_label[slot] = lab;
-        atomicOr(&s_wslots[w], 1u << slot);
+        atomicOr(&s_wslots[w], 1ull << slot);
     }
     __syncthreads();
-    const uint32_t wslots = s_wslots[w];
+    // labels held by at least kMajor lanes of this wave are summed across the
+    // wave; the other lanes (minor) add their weights to LDS themselves
+    unsigned long long wmajor = 0;
+    {
+        unsigned long long sl = s_wslots[w];
+        while (sl) {
+            const int sidx = __ffsll((long long)sl) - 1;
+            sl &= sl - 1ull;
+            if (__popcll(__ballot(active && slot == sidx)) >= kMajor) wmajor |= 1ull << sidx;
+        }
+    }
+    const bool minor = active && !plain && !((wmajor >> slot) & 1ull);
+    const bool wminor = __ballot(minor) != 0ull;
     if (tid == 0) {
         if (s_misc[0]) {
             status_add(status, ST_BAD_LABELS, (unsigned long long)s_misc[0]);
             status_flag(status, (unsigned long long)FS_DEV_BAD_LABEL);
         }
-        if (nslot > kSlots && P.reduction != FS_RED_PLAIN) status_flag(status, (unsigned long long)FS_DEV_MANY_LABELS);
+        if (nslot > kMaxSlots && P.reduction != FS_RED_PLAIN) status_flag(status, (unsigned long long)FS_DEV_MANY_LABELS);
     }
-    for (int i = tid; i < kBatch * kSlots; i += 256) (&s_part[0][0])[i] = 0.0f;
+    for (int i = tid; i < kPart; i += 256) s_part[i] = 0.0f;
     if (tid == 0) {  // null record: far away, never inside its support, zero opacity
         s_rec[2 * kBatch] = make_float4(-1.0e6f, -1.0e6f, 0.0f, 0.0f);
         s_rec[2 * kBatch + 1] = make_float4(0.0f, kLoFloor, 3.0e38f, 3.0e38f);
@@ -226,8 +250,8 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(7, 7))) voi
     const bool any_live = __syncthreads_or(live) != 0;
     const int64_t rec_base = (int64_t)C.elem_off;
 
-    for (uint32_t base = any_live ? rg.x : rg.y; base < rg.y; base += kBatch) {
-        const uint32_t cnt = min((uint32_t)kBatch, rg.y - base);
+    for (uint32_t base = any_live ? rg.x : rg.y; base < rg.y; base += bsz) {
+        const uint32_t cnt = min(bsz, rg.y - base);
         staged += cnt;
         // the box of this wave's live pixels (lane = 8 * row + column): pixels only
         // ever finish, so entries that cannot reach the box cannot add a weight
@@ -318,9 +342,9 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(7, 7))) voi
 
         if (__ballot(live) != 0ull) {
             if (!plain) {
-                // the weights of 8 entries are summed at once, per label of the wave
-                const bool one = __popc(wslots) == 1;
-                const int slot0 = __ffs(wslots) - 1;
+                // the weights of 8 entries are summed at once, per major label of the wave
+                const bool one = __popcll(wmajor) == 1 && !wminor;
+                const int slot0 = __ffsll((long long)wmajor) - 1;
                 for (int g0 = 0; g0 < nlist; g0 += 8) {
                     steps_w += 8;
                     float wr[8];
@@ -346,18 +370,24 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(7, 7))) voi
                     const bool head = (lane & 7) == 0 && g0 + e < nlist;
                     if (one) {
                         const float tot = reduce_scatter8(wr);
-                        if (head && tot != 0.0f) atomicAdd(&s_part[s_list[w][g0 + e] >> 5][slot0], tot);
+                        if (head && tot != 0.0f) atomicAdd(&s_part[((s_list[w][g0 + e] >> 5) << sh) + slot0], tot);
                     } else {
-                        // several labels in this wave's block: one reduce-scatter per label
-                        uint32_t sl = wslots;
+                        // several labels in this wave's block: one reduce-scatter per major label
+                        unsigned long long sl = wmajor;
                         while (sl) {
-                            const int sidx = __ffs(sl) - 1;
-                            sl &= sl - 1u;
+                            const int sidx = __ffsll((long long)sl) - 1;
+                            sl &= sl - 1ull;
                             float v[8];
 #pragma unroll
                             for (int k = 0; k < 8; ++k) v[k] = slot == sidx ? wr[k] : 0.0f;
                             const float tot = reduce_scatter8(v);
-                            if (head && tot != 0.0f) atomicAdd(&s_part[s_list[w][g0 + e] >> 5][sidx], tot);
+                            if (head && tot != 0.0f) atomicAdd(&s_part[((s_list[w][g0 + e] >> 5) << sh) + sidx], tot);
+                        }
+                        // lanes with a rare label add their own nonzero weights
+                        if (wminor && minor) {
+#pragma unroll
+                            for (int k = 0; k < 8; ++k)
+                                if (wr[k] != 0.0f) atomicAdd(&s_part[((jj[k] >> 5) << sh) + slot], wr[k]);
                         }
                     }
                     if (__ballot(live) == 0ull) break;
@@ -375,13 +405,27 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(7, 7))) voi
             }
         }
         __syncthreads();
-        if (!plain && (uint32_t)tid < cnt) {
-            const uint32_t g = s_g[tid];
-            for (int sidx = 0; sidx < nslot; ++sidx) {
-                const float vpart = s_part[tid][sidx];
-                if (vpart != 0.0f) {
-                    add_global(A_hi, A_lo, (int64_t)g * E + s_slot_label[sidx], vpart);
-                    s_part[tid][sidx] = 0.0f;
+        if (!plain) {
+            if (sh == 3) {
+                if ((uint32_t)tid < cnt) {
+                    const uint32_t g = s_g[tid];
+                    for (int sidx = 0; sidx < nslot; ++sidx) {
+                        const float vpart = s_part[(tid << 3) + sidx];
+                        if (vpart != 0.0f) {
+                            add_global(A_hi, A_lo, (int64_t)g * E + s_slot_label[sidx], vpart);
+                            s_part[(tid << 3) + sidx] = 0.0f;
+                        }
+                    }
+                }
+            } else {
+                // many labels, fewer entries: the block's threads share the (entry, slot) cells
+                for (uint32_t i = (uint32_t)tid; i < (cnt << sh); i += 256u) {
+                    const int sidx = (int)(i & (uint32_t)(stride - 1));
+                    const float vpart = s_part[i];
+                    if (sidx < nslot && vpart != 0.0f) {
+                        add_global(A_hi, A_lo, (int64_t)s_g[i >> sh] * E + s_slot_label[sidx], vpart);
+                        s_part[i] = 0.0f;
+                    }
                 }
             }
         }
@@ -420,21 +464,92 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(7, 7))) voi
     }
 }
 
+// One workgroup per work item (tile), or (PERSIST) resident workgroups that
+// take the next item from the device counter `queue` until none is left.
+template <bool PIX, bool COUNT, bool PERSIST>
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(7, 7))) void k_accum(
+    const float4 *__restrict__ rec, const uint32_t *__restrict__ vals, const uint2 *__restrict__ ranges,
+    const ViewDev *__restrict__ views, int32_t n_views, const SceneDev *__restrict__ scenes,
+    const uint32_t *__restrict__ items, uint32_t n_items, AccParams P, float *__restrict__ t_final,
+    int32_t *__restrict__ n_blend, float *__restrict__ tstate, uint8_t *__restrict__ tile_done, int32_t first,
+    unsigned long long *__restrict__ status, uint32_t *__restrict__ queue)
+{
+    if (!PERSIST) {
+        accum_tile<PIX, COUNT>(items ? items[blockIdx.x] : blockIdx.x, rec, vals, ranges, views, n_views, scenes, P,
+                               t_final, n_blend, tstate, tile_done, first, status);
+        return;
+    }
+    __shared__ uint32_t s_next;
+    // Control flow here is kept wave-uniform (scalar branches only): a lane-divergent
+    // branch around the fetch (thread 0 alone) let the compiler route that lane and the
+    // block's other lanes around the loop by different paths, so that the others passed
+    // the barriers again, re-read the old item and never saw a new one.
+    const bool wave0 = __builtin_amdgcn_readfirstlane(threadIdx.x) == 0;
+    for (;;) {
+        // the previous tile's last LDS reads are behind the accum_tile's final barrier
+        // or behind the two barriers here
+        if (wave0) {
+            // every lane of wave 0 takes part (lane 0 adds 1, the others 0); lane 0's
+            // returned value is the counter before its own increment: this block's item
+            const uint32_t old = atomicAdd(queue, (threadIdx.x & 63u) == 0u ? 1u : 0u);
+            s_next = __builtin_amdgcn_readfirstlane(old);
+        }
+        __syncthreads();
+        const uint32_t it = __builtin_amdgcn_readfirstlane(s_next);
+        __syncthreads();
+        if (it >= n_items) break;
+        accum_tile<PIX, COUNT>(items ? items[it] : it, rec, vals, ranges, views, n_views, scenes, P, t_final,
+                               n_blend, tstate, tile_done, first, status);
+    }
+}
+
+// resident workgroups of a compositing kernel on this device (cached per kernel)
+template <class K>
+uint32_t resident_blocks(K kern)
+{
+    static int cached = 0;
+    if (cached == 0) {
+        int per_cu = 0, cus = 0, dev = 0;
+        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kern, 256, 0) != hipSuccess || per_cu < 1) per_cu = 1;
+        if (hipGetDevice(&dev) != hipSuccess ||
+            hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || cus < 1)
+            cus = 256;
+        cached = per_cu * cus;
+    }
+    return (uint32_t)cached;
+}
+
 }  // namespace
 
 hipError_t launch_accumulate(hipStream_t s, const float *rec, const uint32_t *vals, const uint32_t *ranges,
                              const ViewDev *views, int32_t n_views, const SceneDev *scenes, const uint32_t *items,
                              uint32_t n_items, const AccParams &p, float *t_final, int32_t *n_blend,
-                             float *tstate, uint8_t *tile_done, int32_t first, unsigned long long *status)
+                             float *tstate, uint8_t *tile_done, int32_t first, unsigned long long *status,
+                             uint32_t *queue)
 {
     if (n_items == 0) return hipSuccess;
     const bool pix = t_final || n_blend;
     const bool count = p.count || n_blend;  // per-pixel blend counts need the counters
-    auto kern = pix ? (count ? k_accum<true, true> : k_accum<true, false>)
-                    : (count ? k_accum<false, true> : k_accum<false, false>);
-    hipLaunchKernelGGL(kern, dim3(n_items), dim3(256), 0, s, reinterpret_cast<const float4 *>(rec), vals,
-                       reinterpret_cast<const uint2 *>(ranges), views, n_views, scenes, items, p, t_final, n_blend,
-                       tstate, tile_done, first, status);
+    const float4 *r4 = reinterpret_cast<const float4 *>(rec);
+    const uint2 *rg = reinterpret_cast<const uint2 *>(ranges);
+    if (p.persistent) {
+        if (!queue) return hipErrorInvalidValue;
+        auto kern = pix ? (count ? k_accum<true, true, true> : k_accum<true, false, true>)
+                        : (count ? k_accum<false, true, true> : k_accum<false, false, true>);
+        const uint32_t grid = std::min(n_items, pix ? (count ? resident_blocks(k_accum<true, true, true>)
+                                                             : resident_blocks(k_accum<true, false, true>))
+                                                    : (count ? resident_blocks(k_accum<false, true, true>)
+                                                             : resident_blocks(k_accum<false, false, true>)));
+        hipError_t e = launch_fill_u32(s, queue, 0u, 1);
+        if (e != hipSuccess) return e;
+        hipLaunchKernelGGL(kern, dim3(grid), dim3(256), 0, s, r4, vals, rg, views, n_views, scenes, items, n_items,
+                           p, t_final, n_blend, tstate, tile_done, first, status, queue);
+        return hipGetLastError();
+    }
+    auto kern = pix ? (count ? k_accum<true, true, false> : k_accum<true, false, false>)
+                    : (count ? k_accum<false, true, false> : k_accum<false, false, false>);
+    hipLaunchKernelGGL(kern, dim3(n_items), dim3(256), 0, s, r4, vals, rg, views, n_views, scenes, items, n_items, p,
+                       t_final, n_blend, tstate, tile_done, first, status, queue);
     return hipGetLastError();
 }
 

@@ -36,6 +36,7 @@ struct Staging {
 };
 
 constexpr int kStaging = 8;
+constexpr int kQueueWord = 8;  // word of the context's npairs_dev block used as the persistent launch's counter
 
 }  // namespace
 
@@ -176,6 +177,9 @@ int check_params(fs_ctx *ctx, const fs_params *p, bool for_accum)
     if (!finite_f(p->fp64_cond) || p->fp64_cond < 1.f) return set_err(ctx, FS_ERR_ARG, "fp64_cond must be >= 1");
     if (p->tile_order < 0 || p->tile_order > 2) return set_err(ctx, FS_ERR_ARG, "tile_order must be 0, 1 or 2");
     if (p->count_ops != 0 && p->count_ops != 1) return set_err(ctx, FS_ERR_ARG, "count_ops must be 0 or 1");
+    if (p->persistent != 0 && p->persistent != 1) return set_err(ctx, FS_ERR_ARG, "persistent must be 0 or 1");
+    if (!(p->lds_batch == 0 || p->lds_batch == 32 || p->lds_batch == 64 || p->lds_batch == 128 || p->lds_batch == 256))
+        return set_err(ctx, FS_ERR_ARG, "lds_batch must be 0, 32, 64, 128 or 256");
     return FS_OK;
 }
 
@@ -252,6 +256,8 @@ AccParams acc_params(const fs_params *p, int32_t reduction)
     ap.tile_h = p->tile_h;
     ap.reduction = reduction;
     ap.count = p->count_ops ? 1 : 0;
+    ap.batch = p->lds_batch ? p->lds_batch : 256;
+    ap.persistent = p->persistent;
     return ap;
 }
 
@@ -382,12 +388,15 @@ int enqueue_lpt(fs_ctx *ctx, hipStream_t s, const uint32_t *ranges, uint64_t n_t
 
 // ---- static scratch of fs_accumulate_noalloc -------------------------------
 // Layout: the call's tables (scene, work-order sort segment, views), copied
-// from the host in one transfer, then four tile-index arrays for the
-// longest-list-first order and the radix sort's workspace.
+// from the host in one transfer (the persistent launch's work counter sits
+// in the segment's block; the launch clears it after that copy), then four
+// tile-index arrays for the longest-list-first order and the radix sort's
+// workspace.
 constexpr size_t kNaAlign = 256;
 constexpr size_t na_round(size_t b) { return (b + kNaAlign - 1) / kNaAlign * kNaAlign; }
 constexpr size_t kNaSceneOff = 0;
 constexpr size_t kNaSegOff = kNaSceneOff + na_round(sizeof(SceneDev));
+constexpr size_t kNaQueueOff = kNaSegOff + kNaAlign / 2;  // the persistent launch's work counter (device-written)
 constexpr size_t kNaViewsOff = kNaSegOff + na_round(sizeof(SegDev));
 constexpr size_t kNaTableBytes = kNaViewsOff + na_round((size_t)FS_NOALLOC_MAX_VIEWS * sizeof(ViewDev));
 constexpr size_t kNaItemBytes = na_round((size_t)FS_NOALLOC_MAX_TILES * 4);
@@ -488,6 +497,8 @@ void fs_params_default(fs_params *p)
     p->fp64_conic = 1;
     p->tile_order = 0;
     p->count_ops = 1;
+    p->persistent = 0;
+    p->lds_batch = 0;
 }
 
 void fs_params_exact(fs_params *p)
@@ -750,7 +761,7 @@ int fs_accumulate(fs_ctx *ctx, const fs_proj *proj, const fs_bins *bins, const f
     HIPCHECK(ctx, launch_accumulate(ctx->stream, proj->rec, bins->vals, bins->ranges, (const ViewDev *)ctx->views.p, V,
                                     (const SceneDev *)ctx->scenes.p, items, (uint32_t)pl.tiles, acc_params(p, reduction),
                                     pix ? pix->t_final : nullptr, pix ? pix->n_blend : nullptr, nullptr, nullptr, 1,
-                                    ctx->status_dev));
+                                    ctx->status_dev, ctx->npairs_dev + kQueueWord));
     if (timed) HIPCHECK(ctx, hipEventRecord(ctx->acc_ev[1], ctx->stream));
     ctx->acc_timed = timed;
     return FS_OK;
@@ -821,7 +832,8 @@ int fs_accumulate_noalloc(fs_ctx *ctx, const fs_proj *proj, const fs_bins *bins,
     if (timed) HIPCHECK(ctx, hipEventRecord(ctx->acc_ev[0], s));
     HIPCHECK(ctx, launch_accumulate(s, proj->rec, bins->vals, bins->ranges, views, V, scenes, items, (uint32_t)n_tiles,
                                     acc_params(p, reduction), pix ? pix->t_final : nullptr,
-                                    pix ? pix->n_blend : nullptr, nullptr, nullptr, 1, ctx->status_dev));
+                                    pix ? pix->n_blend : nullptr, nullptr, nullptr, 1, ctx->status_dev,
+                                    (uint32_t *)(d + kNaQueueOff)));
     if (timed) HIPCHECK(ctx, hipEventRecord(ctx->acc_ev[1], s));
     ctx->acc_timed = timed;
     return FS_OK;
@@ -1068,7 +1080,7 @@ struct Chunk {
 struct Work {
     DevBuf rec, rect, ntiles, flags, codes, dkeys, dvals, dkeys2, dvals2, counts, offsets;
     DevBuf ptiles, pvals, pk_alt, pv_alt, ranges, items, items_k, items_k2, items_v2;
-    DevBuf sort_ws, scan_ws, tscan_ws, view_offs, tstate, tile_done;
+    DevBuf sort_ws, scan_ws, tscan_ws, view_offs, tstate, tile_done, queue;
     hipStream_t stream = nullptr;  // default priority, created with the batch (lanes > 1)
     hipEvent_t done = nullptr;
 };
@@ -1089,6 +1101,9 @@ struct fs_batch {
     uint32_t max_dblocks = 0, max_pblocks = 0, max_lblocks = 0;
     hipGraph_t graph = nullptr;
     hipGraphExec_t exec = nullptr;
+    // without a graph: events right around every compositing launch, [chunk][slab][2]
+    std::vector<hipEvent_t> acc_ev;
+    bool acc_recorded = false;
     int64_t ws_bytes = 0;
     int64_t total_pairs = 0, total_elems = 0, total_tiles = 0;
 };
@@ -1102,7 +1117,7 @@ std::vector<DevBuf *> batch_bufs(fs_batch *b)
         for (DevBuf *d : {&w.rec, &w.rect, &w.ntiles, &w.flags, &w.codes, &w.dkeys, &w.dvals, &w.dkeys2, &w.dvals2,
                           &w.counts, &w.offsets, &w.ptiles, &w.pvals, &w.pk_alt, &w.pv_alt, &w.ranges, &w.items, &w.items_k,
                           &w.items_k2, &w.items_v2, &w.sort_ws, &w.scan_ws, &w.tscan_ws, &w.view_offs, &w.tstate,
-                          &w.tile_done})
+                          &w.tile_done, &w.queue})
             v.push_back(d);
     for (Chunk &c : b->chunks) {
         v.push_back(&c.views);
@@ -1167,7 +1182,7 @@ int enqueue_full_count(fs_batch *b, Work &w, Chunk &c, uint32_t *np, hipStream_t
 // resuming every pixel's transmittance from the previous slab. Tiles whose
 // pixels have all finished are marked by the compositing and get no pairs in
 // later slabs, so the long tails of dense tiles are never sorted.
-int enqueue_slabs(fs_batch *b, Work &w, Chunk &c, int chunk_idx, hipStream_t s)
+int enqueue_slabs(fs_batch *b, Work &w, Chunk &c, int chunk_idx, hipStream_t s, bool composite = true)
 {
     fs_ctx *ctx = b->ctx;
     const Plan &pl = c.plan;
@@ -1226,6 +1241,7 @@ int enqueue_slabs(fs_batch *b, Work &w, Chunk &c, int chunk_idx, hipStream_t s)
         }
         HIPCHECK(ctx, scan_exclusive(s, tcount, tstart, (int64_t)pl.tiles, nullptr, w.tscan_ws.p));
         HIPCHECK(ctx, launch_count_ranges(s, tcount, tstart, (int64_t)pl.tiles, (uint32_t *)w.ranges.p));
+        if (!composite) continue;
         const uint32_t *items = nullptr;
         if (b->p.tile_order == 0) {
             RCHECK(enqueue_lpt(ctx, s, (const uint32_t *)w.ranges.p, pl.tiles, (const SegDev *)c.lsegs.p,
@@ -1233,11 +1249,14 @@ int enqueue_slabs(fs_batch *b, Work &w, Chunk &c, int chunk_idx, hipStream_t s)
                                (uint32_t *)w.items_v2.p, w.sort_ws.p));
             items = (const uint32_t *)w.items.p;
         }
+        hipEvent_t *ev = b->acc_ev.empty() ? nullptr : &b->acc_ev[2 * ((size_t)chunk_idx * S + k)];
+        if (ev) HIPCHECK(ctx, hipEventRecord(ev[0], s));
         HIPCHECK(ctx, launch_accumulate(s, (const float *)w.rec.p, pv, (const uint32_t *)w.ranges.p,
                                         (const ViewDev *)c.views.p, V, (const SceneDev *)b->scenes_d.p, items,
                                         (uint32_t)pl.tiles, acc_params(&b->p, b->o.reduction), nullptr, nullptr,
                                         tstate, done, k == 0 ? 1 : 0,
-                                        ctx->status_dev));
+                                        ctx->status_dev, (uint32_t *)w.queue.p));
+        if (ev) HIPCHECK(ctx, hipEventRecord(ev[1], s));
     }
     return FS_OK;
 }
@@ -1534,6 +1553,7 @@ int batch_build(fs_batch *b, const fs_scene *scenes, int32_t n_scenes)
         RCHECK(batch_alloc(b, w.items_v2, T4));
         RCHECK(batch_alloc(b, w.tscan_ws, scan_ws_bytes((int64_t)std::max<uint64_t>(b->max_tiles, 1))));
         RCHECK(batch_alloc(b, w.sort_ws, radix_ws_bytes(sb)));
+        RCHECK(batch_alloc(b, w.queue, 256));
         if (S > 1) {
             RCHECK(batch_alloc(b, w.tstate, (size_t)std::max<uint64_t>(b->max_pixels, 1) * 4));
             RCHECK(batch_alloc(b, w.tile_done, ((size_t)b->max_tiles + 3) / 4 * 4 + 4));
@@ -1545,6 +1565,10 @@ int batch_build(fs_batch *b, const fs_scene *scenes, int32_t n_scenes)
             HIPCHECK(ctx, hipStreamCreateWithFlags(&w.stream, hipStreamNonBlocking));
             HIPCHECK(ctx, hipEventCreateWithFlags(&w.done, hipEventDisableTiming));
         }
+    }
+    if (!b->o.use_graph) {
+        b->acc_ev.assign(2 * b->chunks.size() * (size_t)S, nullptr);
+        for (hipEvent_t &e : b->acc_ev) HIPCHECK(ctx, hipEventCreate(&e));
     }
     HIPCHECK(ctx, hipStreamSynchronize(ctx->stream));
 
@@ -1650,7 +1674,71 @@ int fs_batch_run(fs_batch *b)
         HIPCHECK(ctx, hipGraphLaunch(b->exec, ctx->stream));
         return FS_OK;
     }
-    return enqueue_run(b, ctx->stream);
+    b->acc_recorded = false;
+    RCHECK(enqueue_run(b, ctx->stream));
+    b->acc_recorded = !b->acc_ev.empty();
+    return FS_OK;
+}
+
+int fs_batch_accumulate_ms(fs_batch *b, float *total_ms, int32_t *n_launches)
+{
+    if (!b || !total_ms || !n_launches) return FS_ERR_ARG;
+    fs_ctx *ctx = b->ctx;
+    if (!b->acc_recorded) return set_err(ctx, FS_ERR_STATE, "no fs_batch_run without a graph has been timed");
+    double sum = 0.0;
+    int32_t cnt = 0;
+    for (size_t i = 0; i < b->chunks.size(); ++i) {
+        const Chunk &c = b->chunks[i];
+        if (c.plan.elems == 0 || c.pair_cap == 0 || c.plan.tiles == 0) continue;  // nothing was launched
+        for (int k = 0; k < b->n_slabs; ++k) {
+            hipEvent_t e0 = b->acc_ev[2 * (i * (size_t)b->n_slabs + k)], e1 = b->acc_ev[2 * (i * (size_t)b->n_slabs + k) + 1];
+            HIPCHECK(ctx, hipEventSynchronize(e1));
+            float ms = 0.0f;
+            HIPCHECK(ctx, hipEventElapsedTime(&ms, e0, e1));
+            sum += ms;
+            ++cnt;
+        }
+    }
+    *total_ms = (float)sum;
+    *n_launches = cnt;
+    return FS_OK;
+}
+
+int fs_batch_chunk_lists(fs_batch *b, int32_t chunk, uint32_t *vals, int64_t vals_cap, uint32_t *ranges,
+                         int64_t ranges_cap, int32_t *view_refs, int32_t refs_cap, fs_chunk_info *info)
+{
+    if (!b || !info) return FS_ERR_ARG;
+    fs_ctx *ctx = b->ctx;
+    if (chunk < 0 || chunk >= (int32_t)b->chunks.size())
+        return set_err(ctx, FS_ERR_ARG, "chunk %d of %zu", chunk, b->chunks.size());
+    if (b->n_slabs != 1) return set_err(ctx, FS_ERR_STATE, "tile lists are per depth slab when depth_slabs > 1");
+    Chunk &c = b->chunks[chunk];
+    info->n_views = (int32_t)c.refs.size();
+    info->n_tiles = (int64_t)c.plan.tiles;
+    info->n_pairs = (int64_t)c.pairs;
+    info->packed = c.packed ? 1 : 0;
+    if (!vals || !ranges || !view_refs) return FS_OK;  // sizes only
+    if (vals_cap < (int64_t)c.pairs || ranges_cap < (int64_t)c.plan.tiles || refs_cap < (int32_t)c.refs.size())
+        return set_err(ctx, FS_ERR_CAPACITY, "chunk %d needs %llu ids, %llu ranges, %zu view refs", chunk,
+                       (unsigned long long)c.pairs, (unsigned long long)c.plan.tiles, c.refs.size());
+    for (size_t j = 0; j < c.refs.size(); ++j) {
+        view_refs[2 * j] = (int32_t)c.refs[j].scene;
+        view_refs[2 * j + 1] = c.refs[j].v;
+    }
+    // the chunk's binning on lane 0's workspace, as the solve runs it, without the compositing
+    HIPCHECK(ctx, hipStreamSynchronize(ctx->stream));
+    for (Work &w : b->work)
+        if (w.stream) HIPCHECK(ctx, hipStreamSynchronize(w.stream));
+    Work &w = b->work[0];
+    hipStream_t s = ctx->stream;
+    RCHECK(enqueue_front(b, w, c, s));
+    RCHECK(enqueue_slabs(b, w, c, chunk, s, false));
+    if (c.pairs > 0)
+        HIPCHECK(ctx, hipMemcpyAsync(vals, w.pvals.p, (size_t)c.pairs * 4, hipMemcpyDeviceToDevice, s));
+    if (c.plan.tiles > 0)
+        HIPCHECK(ctx, hipMemcpyAsync(ranges, w.ranges.p, (size_t)c.plan.tiles * 8, hipMemcpyDeviceToDevice, s));
+    HIPCHECK(ctx, hipStreamSynchronize(s));
+    return FS_OK;
 }
 
 int fs_batch_get_info(fs_batch *b, fs_batch_info *out)
@@ -1682,6 +1770,8 @@ int fs_batch_destroy(fs_batch *b)
         if (w.done) (void)hipEventDestroy(w.done);
     }
     if (b->fork) (void)hipEventDestroy(b->fork);
+    for (hipEvent_t e : b->acc_ev)
+        if (e) (void)hipEventDestroy(e);
     for (DevBuf *d : batch_bufs(b)) free_buf(*d);
     delete b;
     return FS_OK;

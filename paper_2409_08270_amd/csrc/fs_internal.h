@@ -226,6 +226,8 @@ struct AccParams {
     int32_t tile_w, tile_h;
     int32_t reduction;
     int32_t count;    // 1: count in-support evaluations and blends
+    int32_t batch;    // most list entries staged per batch (32..256)
+    int32_t persistent;  // 1: resident workgroups pull tiles from a device counter
 };
 
 // Resumable compositing (depth slabs): with `tstate` set, each pixel's
@@ -233,10 +235,13 @@ struct AccParams {
 // `first`, which starts from T = 1) and written back at the end, -1 marking a
 // pixel whose compositing has ended; with `tile_done` set, tiles already marked
 // are skipped and tiles left without a live pixel are marked.
+// With p.persistent, `queue` (one u32 of device memory, cleared here by a fill
+// kernel before the launch) hands out the items.
 hipError_t launch_accumulate(hipStream_t s, const float *rec, const uint32_t *vals, const uint32_t *ranges,
                              const ViewDev *views, int32_t n_views, const SceneDev *scenes, const uint32_t *items,
                              uint32_t n_items, const AccParams &p, float *t_final, int32_t *n_blend,
-                             float *tstate, uint8_t *tile_done, int32_t first, unsigned long long *status);
+                             float *tstate, uint8_t *tile_done, int32_t first, unsigned long long *status,
+                             uint32_t *queue);
 
 hipError_t launch_assign(hipStream_t s, const float *A_hi, const float *A_lo, int64_t n, int32_t E, float gamma,
                          uint8_t *S, float *margin, unsigned long long *status);

@@ -1,21 +1,28 @@
-"""Tuner for the batched solve (fs_batch): picks, per workload shape, the tile
-shape, compositing reduction, tile work order and number of lanes that give
-the shortest graph replay, among settings whose result agrees with the
-library's defaults. The defaults are kept unless a setting is at least
-`min_gain` faster, so that timing noise does not decide. By default only the
-compensated reduction (LDS pre-reduction + two-sum into A_lo) is a candidate;
-`compensated=False` also tries the plain LDS pre-reduction.
+"""Tuner for the batched solve (fs_batch): picks, per workload, the tile
+shape, compositing work order, compositing launch (one workgroup per tile or
+resident workgroups pulling tiles from a counter), LDS batch depth, reduction
+strategy and number of lanes that give the shortest graph replay, among
+settings whose result agrees with the library's defaults. The defaults are
+kept unless a setting is at least `min_gain` faster, so that timing noise does
+not decide. By default only the compensated reduction (LDS pre-reduction +
+two-sum into A_lo) is a candidate; `compensated=False` also tries the LDS
+pre-reduction without A_lo.
 
-The support of a splat is an ellipse, so A does not depend on the tile shape
-or on the order of the work beyond floating-point summation order (Eq. (7)
-sums the same weights); a candidate is kept only if its A agrees with the
-reference run's within `rel` (aggregate L1) and its labels are identical
-wherever the reference's margin is at least `margin`.
+The support of a splat is an ellipse, so A does not depend on the tile shape,
+the work order, the launch shape or the batch depth beyond floating-point
+summation order (Eq. (7) sums the same weights); a candidate is kept only if
+its A agrees with the reference run's within `rel` (aggregate L1) and its
+labels are identical wherever the reference's margin is at least `margin`.
+
+Search: `search="staged"` (default) tunes one setting at a time in the order
+of KNOBS, starting from the defaults and keeping the best value of each
+before moving to the next; `search="all"` times every combination.
 
 The table is JSON: {"version": 1, "entries": {key: {"params": {...},
 "opts": {...}, "ms": t, "reference_ms": t0, "candidates": [...]}}}, keyed by
-`workload_key` (classes, image size, Gaussian-count bucket, views).
-Timing runs on the GPU; the key, the candidate list and the table I/O are
+`batch_key` (one scene: classes, image size, Gaussian-count bucket, views;
+several: scene count, Gaussian and pixel buckets, views, classes).
+Timing runs on the GPU; the keys, the candidate lists and the table I/O are
 plain Python.
 """
 import itertools
@@ -43,50 +50,84 @@ def scene_key(scene) -> str:
     return workload_key(scene.n, int(scene.W[0]), int(scene.H[0]), scene.E, scene.n_views)
 
 
-def candidates(width: int, height: int, compensated: bool = True) -> List[dict]:
-    """Settings to try: 256-pixel tile shapes, reductions, work orders and lanes."""
+def batch_key(scenes) -> str:
+    """Table key of a batch: one scene's key, or for several scenes their count, total
+    Gaussians and pixels (rounded up to powers of two), total views and largest class count."""
+    scenes = list(scenes)
+    if len(scenes) == 1:
+        return scene_key(scenes[0])
+    n = sum(int(s.n) for s in scenes)
+    px = sum(int(s.pixels()) for s in scenes)
+    return (f"B{len(scenes)}-N{_bucket(n)}-P{_bucket(px)}-V{sum(int(s.n_views) for s in scenes)}"
+            f"-E{max(int(s.E) for s in scenes)}")
+
+
+# tunable settings in search order: (table section, name, values); "tile" sets tile_w x tile_h
+KNOBS = [("opts", "lanes", [1, 2, 3, 4]),
+         ("params", "tile", [(16, 16), (32, 8), (8, 32)]),
+         ("params", "tile_order", [0, 1]),
+         ("params", "persistent", [0, 1]),
+         ("params", "lds_batch", [256, 128, 64]),
+         ("opts", "reduction", None)]  # None: the reductions allowed by `compensated`
+
+
+def _reductions(compensated: bool):
     from . import _lib as L
-    shapes = [(16, 16), (32, 8), (8, 32)]
-    reds = [L.FS_RED_LDS2SUM] if compensated else [L.FS_RED_LDS2SUM, L.FS_RED_LDS]
-    orders = [0, 1]  # longest list first, image order (the batch takes these two)
-    lanes = [1, 2, 3, 4]
-    out = []
-    for (tw, th), red, order, ln in itertools.product(shapes, reds, orders, lanes):
-        out.append({"params": {"tile_w": tw, "tile_h": th, "tile_order": order},
-                    "opts": {"reduction": red, "lanes": ln}})
-    return out
+    return [L.FS_RED_LDS2SUM] if compensated else [L.FS_RED_LDS2SUM, L.FS_RED_LDS]
 
 
 def reference() -> dict:
-    """The library's defaults (16x16 tiles, LDS + two-sum, longest list first, 2 lanes)."""
+    """The library's defaults (16x16 tiles, longest list first, one workgroup per tile,
+    256-entry LDS batches, LDS + two-sum, 2 lanes)."""
     from . import _lib as L
-    return {"params": {"tile_w": 16, "tile_h": 16, "tile_order": 0}, "opts": {"reduction": L.FS_RED_LDS2SUM,
-                                                                                  "lanes": 2}}
+    return {"params": {"tile_w": 16, "tile_h": 16, "tile_order": 0, "persistent": 0, "lds_batch": 256},
+            "opts": {"reduction": L.FS_RED_LDS2SUM, "lanes": 2}}
+
+
+def _with(c: dict, sec: str, name: str, value) -> dict:
+    out = {"params": dict(c["params"]), "opts": dict(c["opts"])}
+    if name == "tile":
+        out["params"]["tile_w"], out["params"]["tile_h"] = value
+    else:
+        out[sec][name] = value
+    return out
+
+
+def candidates(width: int = 0, height: int = 0, compensated: bool = True) -> List[dict]:
+    """Every combination of the tunable settings (256-pixel tiles)."""
+    ref = reference()
+    lists = [(sec, name, vals if vals is not None else _reductions(compensated)) for sec, name, vals in KNOBS]
+    out = []
+    for combo in itertools.product(*[v for _, _, v in lists]):
+        c = ref
+        for (sec, name, _), val in zip(lists, combo):
+            c = _with(c, sec, name, val)
+        out.append(c)
+    return out
 
 
 def _same(a: dict, b: dict) -> bool:
     return a["params"] == b["params"] and a["opts"] == b["opts"]
 
 
-def tune(scene, cands: Optional[Sequence[dict]] = None, steps: int = 4, warmup: int = 1, rel: float = 2e-5,
-         margin: float = 1e-4, min_gain: float = 0.01, compensated: bool = True, log=None) -> dict:
-    """Times every candidate on `scene` (a scenegen Scene) and returns the table entry."""
+def tune(scenes, cands: Optional[Sequence[dict]] = None, steps: int = 4, warmup: int = 1, rel: float = 2e-5,
+         margin: float = 1e-4, min_gain: float = 0.01, compensated: bool = True, search: str = "staged",
+         log=None) -> dict:
+    """Times settings on `scenes` (one scenegen Scene or a list, solved as one batch) and
+    returns the table entry. With `cands` given, exactly those are timed (the first
+    is the reference); otherwise `search` decides."""
     import numpy as np
     import torch
     from . import _lib as L
 
+    scenes = list(scenes) if isinstance(scenes, (list, tuple)) else [scenes]
     ctx = L.Context()
-    ds = L.DeviceScene(scene)
-    ref = reference()
-    cands = list(cands) if cands is not None else candidates(int(scene.W[0]), int(scene.H[0]), compensated)
-    if not any(_same(c, ref) for c in cands):
-        cands.insert(0, ref)
-    else:
-        cands.sort(key=lambda c: 0 if _same(c, ref) else 1)
+    dss = [L.DeviceScene(s) for s in scenes]
+    gam = [0.0] * len(scenes)
 
     def run(c, want_margin):
         prm = L.params(count_ops=0, **c["params"])
-        b = L.Batch(ctx, [ds], prm, gammas=[0.0], want_margin=want_margin, **c["opts"])
+        b = L.Batch(ctx, dss, prm, gammas=gam, want_margin=want_margin, **c["opts"])
         for _ in range(warmup):
             b.run()
         torch.cuda.synchronize()
@@ -97,37 +138,67 @@ def tune(scene, cands: Optional[Sequence[dict]] = None, steps: int = 4, warmup: 
                 b.run()
             torch.cuda.synchronize()
             best = min(best, (time.perf_counter() - t) / steps)
-        A = b.A_hi[0].double()
-        if b.A_lo[0] is not None:
-            A = A + b.A_lo[0].double()
-        res = {"A": A.cpu().numpy(), "S": b.S[0].cpu().numpy(),
-               "margin": b.margin[0].cpu().numpy() if want_margin else None, "ms": best * 1e3}
+        A, S, M = [], [], []
+        for i in range(len(scenes)):
+            a = b.A_hi[i].double()
+            if b.A_lo[i] is not None:
+                a = a + b.A_lo[i].double()
+            A.append(a.cpu().numpy())
+            S.append(b.S[i].cpu().numpy())
+            M.append(b.margin[i].cpu().numpy() if want_margin else None)
         b.close()
-        return res
+        ctx.status()
+        return {"A": A, "S": S, "margin": M, "ms": best * 1e3}
 
-    base = run(cands[0], True)
-    s_ref = np.abs(base["A"]).sum()
-    low = base["margin"] < margin
+    base = None
     rows = []
-    for i, c in enumerate(cands):
+
+    def measure(c):
+        nonlocal base
+        for r in rows:
+            if _same(r, c):
+                return r
         try:
-            r = base if i == 0 else run(c, False)
+            r = run(c, base is None)
         except L.FlashSplatError as err:  # a setting the library rejects for this workload
-            rows.append({**c, "ms": None, "a_rel": None, "label_flips": None, "valid": False, "error": str(err)})
+            row = {**c, "ms": None, "a_rel": None, "label_flips": None, "valid": False, "error": str(err)}
+            rows.append(row)
             if log:
                 log(f"[tune] {c['params']} {c['opts']}: rejected by the library ({err})")
-            continue
-        d = float(np.abs(r["A"] - base["A"]).sum() / max(s_ref, 1e-300))
-        flips = int(((r["S"] != base["S"]) & ~low).sum())
+            return row
+        if base is None:
+            base = r
+        s_ref = sum(np.abs(a).sum() for a in base["A"])
+        d = float(sum(np.abs(a - a0).sum() for a, a0 in zip(r["A"], base["A"])) / max(s_ref, 1e-300))
+        flips = int(sum(((x != x0) & ~(m0 < margin)).sum() for x, x0, m0 in zip(r["S"], base["S"], base["margin"])))
         ok = d <= rel and flips == 0
-        rows.append({**c, "ms": r["ms"], "a_rel": d, "label_flips": flips, "valid": ok})
+        row = {**c, "ms": r["ms"], "a_rel": d, "label_flips": flips, "valid": ok}
+        rows.append(row)
         if log:
             log(f"[tune] {c['params']} {c['opts']}: {r['ms']:.3f} ms, A rel {d:.2e}, flips {flips}"
                 f"{'' if ok else ' (rejected)'}")
-    valid = [r for r in rows if r["valid"]]
-    best = min(valid, key=lambda r: r["ms"])
+        return row
+
+    if cands is not None:
+        for c in list(cands):
+            measure(c)
+        best = min((r for r in rows if r["valid"]), key=lambda r: r["ms"])
+    else:
+        best = measure(reference())
+        if search == "all":
+            for c in candidates(compensated=compensated):
+                measure(c)
+            best = min((r for r in rows if r["valid"]), key=lambda r: r["ms"])
+        else:
+            cur = reference()
+            for sec, name, vals in KNOBS:
+                for v in (vals if vals is not None else _reductions(compensated)):
+                    r = measure(_with(cur, sec, name, v))
+                    if r["valid"] and r["ms"] < best["ms"] * (1.0 - min_gain):
+                        best = r
+                cur = {"params": dict(best["params"]), "opts": dict(best["opts"])}
     if best["ms"] > rows[0]["ms"] * (1.0 - min_gain):
-        best = rows[0]  # not clearly faster than the defaults
+        best = rows[0]  # not clearly faster than the reference
     ctx.close()
     return {"params": best["params"], "opts": best["opts"], "ms": best["ms"], "reference_ms": rows[0]["ms"],
             "candidates": rows}
@@ -161,22 +232,25 @@ def main(argv: Optional[Iterable[str]] = None) -> int:
     import argparse
     import sys
     ap = argparse.ArgumentParser(description="tune the batched solve for synthetic workloads")
-    ap.add_argument("--config", action="append", default=None, help="scenegen config (repeatable; default C2)")
+    ap.add_argument("--config", action="append", default=None,
+                    help="scenegen config, C1-C4 or C5 (the 32-scene batch); repeatable; default C2")
     ap.add_argument("--out", default=TABLE_PATH, help="table to update")
     ap.add_argument("--steps", type=int, default=4)
+    ap.add_argument("--search", default="staged", choices=["staged", "all"])
     ap.add_argument("--uncompensated", action="store_true", help="also try the reduction without two-sum")
     args = ap.parse_args(list(argv) if argv is not None else None)
     import scenegen as sg
     table = load(args.out) if os.path.exists(args.out) else {"version": 1, "entries": {}}
     for name in args.config or ["C2"]:
-        sc = sg.make_config(name)
-        key = scene_key(sc)
-        e = tune(sc, steps=args.steps, compensated=not args.uncompensated,
+        scenes = sg.make_batch(32) if name == "C5" else [sg.make_config(name)]
+        key = batch_key(scenes)
+        e = tune(scenes, steps=args.steps, compensated=not args.uncompensated, search=args.search,
                  log=lambda m: print(m, file=sys.stderr, flush=True))
+        e["workload"] = name
         table["entries"][key] = e
+        save(table, args.out)
         print(f"[tune] {name} -> {key}: {e['params']} {e['opts']} {e['ms']:.3f} ms "
               f"(defaults {e['reference_ms']:.3f} ms)", flush=True)
-    save(table, args.out)
     return 0
 
 

@@ -75,7 +75,10 @@ def compare_labels(S_gpu, S64, margin64, A64=None, A_gpu=None):
         reld = np.where(s > 0, d / np.maximum(s, 1e-300), 0.0)
         by_row = ~low & (margin64 < 4.0 * reld[None, :])
     mism = S_gpu != S64
-    st = dict(entries=int(S64.size), excluded_low_margin=int(low.sum()),
+    seen = (np.abs(A64).sum(axis=1) > 0)[None, :] if A64 is not None else np.ones_like(low)
+    st = dict(entries=int(S64.size), entries_of_seen_rows=int((seen & np.ones_like(low)).sum()),
+              excluded_low_margin_seen_rows=int((low & seen).sum()),
+              excluded_low_margin=int(low.sum()),
               mismatches_low_margin=int((mism & low).sum()),
               excused_by_row_difference=int((mism & by_row).sum()),
               mismatches=int((mism & ~low & ~by_row).sum()))

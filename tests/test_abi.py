@@ -60,6 +60,10 @@ def test_batch_defaults_and_null_handling(lib):
     assert lib.fs_batch_destroy(None) == L.FS_ERR_ARG
     inf = L.FsBatchInfo()
     assert lib.fs_batch_get_info(None, ctypes.byref(inf)) == L.FS_ERR_ARG
+    ms, cnt = ctypes.c_float(), ctypes.c_int32()
+    assert lib.fs_batch_accumulate_ms(None, ctypes.byref(ms), ctypes.byref(cnt)) == L.FS_ERR_ARG
+    ci = L.FsChunkInfo()
+    assert lib.fs_batch_chunk_lists(None, 0, None, 0, None, 0, None, 0, ctypes.byref(ci)) == L.FS_ERR_ARG
 
 
 def test_header_limits_match_the_binding():
@@ -76,7 +80,8 @@ def test_struct_layouts_match_the_header(tmp_path):
     from paper_2409_08270_amd import _lib as L
     structs = {"fs_gaussians": L.FsGaussians, "fs_camera": L.FsCamera, "fs_params": L.FsParams,
                "fs_proj": L.FsProj, "fs_bins": L.FsBins, "fs_pixel_out": L.FsPixelOut, "fs_status": L.FsStatus,
-               "fs_scene": L.FsScene, "fs_batch_opts": L.FsBatchOpts, "fs_batch_info": L.FsBatchInfo}
+               "fs_scene": L.FsScene, "fs_batch_opts": L.FsBatchOpts, "fs_batch_info": L.FsBatchInfo,
+               "fs_chunk_info": L.FsChunkInfo}
     lines = ['#include <stdio.h>', '#include <stddef.h>', f'#include "{HEADER}"', "int main(void) {"]
     for cname, cls in structs.items():
         lines.append(f'printf("{cname} %zu\\n", sizeof({cname}));')

@@ -284,3 +284,47 @@ def test_lanes_give_the_one_lane_result(ctx, use_graph):
         b.close()
     with pytest.raises(RuntimeError):
         L.Batch(ctx, dss, L.params(), lanes=5)
+
+
+@pytest.mark.parametrize("persistent,lds_batch,lanes", [(1, 0, 2), (1, 64, 1), (0, 32, 2), (0, 128, 3)])
+def test_launch_shapes_match_the_oracle(ctx, persistent, lds_batch, lanes):
+    # the persistent compositing launch (resident workgroups pulling tiles from a
+    # device counter) and smaller LDS batches give the oracle's A and labels,
+    # in the graph and replayed
+    scenes = _uneven_scenes()
+    dss = [L.DeviceScene(s) for s in scenes]
+    prm = L.params(persistent=persistent, lds_batch=lds_batch)
+    b = L.Batch(ctx, dss, prm, gammas=[0.0, 0.3, -0.2], lanes=lanes)
+    for _ in range(2):
+        b.run()
+    torch.cuda.synchronize()
+    st = ctx.status()
+    assert st["flags"] == 0
+    for i, sc in enumerate(scenes):
+        ref = O.solve64(sc, O.params())
+        what = f"persistent={persistent} lds_batch={lds_batch} scene {i}"
+        assert_A(_A(b, i), ref["A"], ref["slack"], what=what)
+        S64, m64 = O.assign64(ref["A"], [0.0, 0.3, -0.2][i])
+        assert_labels(b.S[i].cpu().numpy(), S64, m64, ref["A"], _A(b, i), what=what)
+    b.close()
+
+
+def test_compositing_launches_are_timed_without_a_graph(ctx):
+    scenes = _uneven_scenes()
+    dss = [L.DeviceScene(s) for s in scenes]
+    g = L.Batch(ctx, dss, L.params(), lanes=2)
+    g.run()
+    with pytest.raises(RuntimeError):
+        g.accumulate_ms()                  # a graph batch records no per-launch events
+    b = L.Batch(ctx, dss, L.params(), lanes=2, use_graph=0)
+    with pytest.raises(RuntimeError):
+        b.accumulate_ms()                  # nothing run yet
+    b.run()
+    ms, n = b.accumulate_ms()
+    assert n == b.info()["n_chunks"] and 0.0 < ms < 1000.0
+    torch.cuda.synchronize()
+    ctx.status()
+    for i in range(len(scenes)):
+        assert np.allclose(_A(b, i), _A(g, i), rtol=1e-6, atol=1e-9)
+    b.close()
+    g.close()

@@ -10,6 +10,7 @@ import oracle as O
 import scenegen as sg
 from paper_2409_08270_amd import _lib as L
 from paper_2409_08270_amd.solve import Solver, tiles_of
+from tests._lists import check_chunk_lists
 from tests._parity import assert_A, assert_labels, log
 
 pytestmark = [pytest.mark.gpu, pytest.mark.slow]
@@ -38,7 +39,20 @@ def ref(c2):
     return O.solve64(sc, O.params())
 
 
-def test_batched_bins_are_bit_exact_on_sampled_views(c2):
+def test_graph_batch_lists_are_bit_exact_on_sampled_views(c2):
+    # the tile lists the timed batched solve itself builds (packed per-view pair
+    # sort, span codes, per-tile counts and ranges), chunk by chunk, on two lanes
+    sc, ds, ctx, solver, out, st = c2
+    b = L.Batch(ctx, [ds], solver.prm, gammas=[0.0], lanes=2)
+    info = b.info()
+    n, chunks, packed = check_chunk_lists(b, [sc], [(0, v) for v in SAMPLE], solver.prm, "C2 batch")
+    log(f"[c2] batch lists: {n} entries compared bit for bit over views {SAMPLE}; {chunks} chunks, "
+        f"{packed} packed")
+    assert info["n_chunks"] >= 2 and packed >= 1
+    b.close()
+
+
+def test_call_bins_are_bit_exact_on_sampled_views(c2):
     sc, ds, ctx, solver, out, st = c2
     bins = solver.bins
     prm = solver.prm

@@ -205,13 +205,30 @@ def test_maximum_class_count(ctx):
     _solve_and_compare(ctx, sc, L.params(), "E=256")
 
 
-def test_many_labels_per_tile_fall_back_to_pixel_atomics(ctx):
-    sc = sg.make_config("C1", n=1500, views=2, res=64)
-    rng = np.random.default_rng(5)
-    sc.masks = [rng.integers(0, 40, size=(64, 64)).astype(np.uint8) for _ in range(2)]
-    sc.E = 40
-    stats, st, _ = _solve_and_compare(ctx, sc, L.params(), "40 labels per tile")
-    assert st["flags"] & L.FS_DEV_MANY_LABELS
+@pytest.mark.parametrize("E,noise", [(12, 1.0), (40, 1.0), (64, 0.05), (100, 1.0)])
+def test_many_labels_per_tile(ctx, E, noise):
+    """Tiles holding many distinct labels: up to 64 are pre-reduced in LDS
+    (fewer Gaussians staged per batch, rare labels of a wave added lane by
+    lane), more than 64 fall back to per-pixel atomics and raise the
+    informational flag. Masks: a few large regions with a fraction `noise` of
+    the pixels relabelled uniformly over the E labels (1.0: every pixel)."""
+    res = 64
+    sc = sg.make_config("C1", n=1500, views=2, res=res)
+    rng = np.random.default_rng(5 + E)
+    yy, xx = np.mgrid[0:res, 0:res]
+    masks = []
+    for _ in range(sc.n_views):
+        m = ((xx // 24) + 3 * (yy // 24)) % E
+        flip = rng.random((res, res)) < noise
+        m[flip] = rng.integers(0, E, size=int(flip.sum()))
+        masks.append(m.astype(np.uint8))
+    sc.masks = masks
+    sc.E = E
+    stats, st, _ = _solve_and_compare(ctx, sc, L.params(), f"{E} labels, noise {noise}")
+    if E > 64:
+        assert st["flags"] & L.FS_DEV_MANY_LABELS
+    else:
+        assert not st["flags"] & L.FS_DEV_MANY_LABELS
 
 
 def test_near_degenerate_splats_use_the_float64_conic(ctx):

@@ -1,17 +1,18 @@
-"""GPU parity at the sizes of the multi-class, large-scene and multi-scene
-workloads, in the batched launch configuration (one graph per solve, chunked
-by the planner):
+"""GPU parity at the full sizes of the multi-class, large-scene and
+multi-scene workloads, in the batched launch configuration (one graph per
+solve, chunked by the planner):
 
 - multi-class: 1M Gaussians (16 objects + shell), 200 views 1008x756, E = 17;
-- large: 3M Gaussians (30% near-degenerate), 1297x840, E = 64, on 12 of its
-  300 views (the oracle needs about half a minute per view at this density);
-- multi-scene: the first 8 of the 32 uneven scenes (50k-800k Gaussians,
-  20-120 views, 320x240 to 1008x756, 2-32 classes).
+- large: 3M Gaussians (30% near-degenerate), all 300 views 1297x840, E = 64;
+- multi-scene: all 32 uneven scenes (50k-800k Gaussians, 20-120 views,
+  320x240 to 1008x756, 2-32 classes) in one batch.
 
 The oracle composites whole views, so A is compared on sampled views (the GPU
 solves the same view subset); the full-size solves are checked through
 properties that hold at any size: view additivity of A, blend counts, and
-that the batch of many scenes equals each scene solved alone."""
+that the batch of many scenes equals each scene solved alone. The tile lists
+that the full-size batches build are compared bit for bit with the oracle's
+binning on sampled views."""
 import numpy as np
 import pytest
 import torch
@@ -19,6 +20,7 @@ import torch
 import oracle as O
 import scenegen as sg
 from paper_2409_08270_amd import _lib as L
+from tests._lists import check_chunk_lists
 from tests._parity import assert_A, assert_labels, compare_A, log
 
 pytestmark = [pytest.mark.gpu, pytest.mark.slow]
@@ -43,11 +45,11 @@ def _solve(ctx, scenes, **kw):
     return b, ctx.status()
 
 
-def _check_sample(ctx, sc, views, what, report_degenerate=False):
+def _check_sample(ctx, sc, views, what, report_degenerate=False, threads=4):
     sub = sc.subset_views(views)
     b, st = _solve(ctx, [sub])
     log(f"[{what}] oracle on views {views}")
-    ref = O.solve64(sub, O.params())
+    ref = O.solve64(sub, O.params(), threads=threads)
     A = _A(b)
     if report_degenerate:
         # rows of splats whose conic takes the float64 path in a sampled view, reported apart
@@ -88,30 +90,54 @@ def test_multi_class_scene(ctx):
     _check_sample(ctx, sc, [0, 150], "C3 sampled views")
     info = _check_additivity(ctx, sc, "C3 all views")
     assert info["n_chunks"] > 1  # the planner split the solve to fit its pair budget
+    b = L.Batch(ctx, [L.DeviceScene(sc)], L.params(), gammas=[0.0])
+    n, chunks, packed = check_chunk_lists(b, [sc], [(0, 0), (0, 150)], L.params(), "C3 batch")
+    log(f"[C3] batch lists: {n} entries compared bit for bit on views 0 and 150, {chunks} chunks, {packed} packed")
+    b.close()
 
 
-def test_large_scene_with_degenerate_splats(ctx):
-    log("[C4] generating 3M Gaussians, 12 views 1297x840")
-    sc = sg.make_config("C4", views=12)
-    _check_sample(ctx, sc, [5], "C4 sampled view", report_degenerate=True)
-    _check_additivity(ctx, sc, "C4 12 views")
-    st = ctx.status()
+def test_large_scene_all_views_with_degenerate_splats(ctx):
+    log("[C4] generating 3M Gaussians, 300 views 1297x840")
+    sc = sg.make_config("C4")
+    assert sc.n_views == 300
+    sample = [0, 99, 199, 299]
+    _check_sample(ctx, sc, sample, "C4 sampled views", report_degenerate=True)
+    info = _check_additivity(ctx, sc, "C4 all 300 views")
+    assert info["n_views"] == 300 and info["n_chunks"] > 1
     b, st = _solve(ctx, [sc.subset_views([0, 1])])
     assert st["fp64_splats"] > 0
+    b.close()
+    # the full solve's own lists: 3M Gaussians need 22 id bits, so these chunks
+    # sort (tile, depth) keys over the whole chunk rather than packed words
+    b = L.Batch(ctx, [L.DeviceScene(sc)], L.params(), gammas=[0.0])
+    n, chunks, packed = check_chunk_lists(b, [sc], [(0, 150), (0, 299)], L.params(), "C4 batch")
+    log(f"[C4] batch lists: {n} entries compared bit for bit on views 150 and 299, {chunks} chunks, {packed} packed")
+    assert packed == 0
+    b.close()
 
 
-def test_multi_scene_batch(ctx):
-    log("[C5] generating 8 uneven scenes")
-    scenes = sg.make_batch(8)
+def test_multi_scene_batch_all_32_scenes(ctx):
+    log("[C5] generating 32 uneven scenes")
+    scenes = sg.make_batch(32)
+    assert len(scenes) == 32
     both, st = _solve(ctx, scenes)
-    log(f"[C5] batch of 8 scenes: {both.info()}")
-    for i in (0, 3, 7):
+    info = both.info()
+    log(f"[C5] batch of 32 scenes: {info}")
+    assert info["n_views"] == sum(s.n_views for s in scenes)
+    for i in (0, 9, 18, 31):
         alone, _ = _solve(ctx, [scenes[i]])
         a, c = _A(both, i), _A(alone)
         d = np.abs(a - c).sum(1)
         assert np.all(d <= 1e-5 * np.abs(c).sum(1) + 1e-9), f"scene {i}"
-        assert np.array_equal(both.S[i].cpu().numpy(), alone.S[0].cpu().numpy()) or \
-            (both.S[i].cpu().numpy() != alone.S[0].cpu().numpy()).sum() <= 2
-    for i in (1, 6):
+        diff = int((both.S[i].cpu().numpy() != alone.S[0].cpu().numpy()).sum())
+        log(f"[C5] scene {i}: batch vs alone, max row difference {float((d / np.maximum(np.abs(c).sum(1), 1e-300)).max()):.2e}, "
+            f"labels differing {diff}")
+        assert diff <= 2
+        alone.close()
+    for i in (1, 6, 13, 27):
         sc = scenes[i]
-        _check_sample(ctx, sc, [0, sc.n_views - 1], f"C5 scene {i} sampled views")
+        _check_sample(ctx, sc, [0, sc.n_views - 1], f"C5 scene {i} (N={sc.n}, E={sc.E}) sampled views")
+    want = [(2, 0), (17, scenes[17].n_views // 2), (30, scenes[30].n_views - 1)]
+    n, chunks, packed = check_chunk_lists(both, scenes, want, L.params(), "C5 batch")
+    log(f"[C5] batch lists: {n} entries compared bit for bit on {want}, {chunks} chunks, {packed} packed")
+    both.close()

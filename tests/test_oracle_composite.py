@@ -215,3 +215,16 @@ def test_slack_bounds_every_threshold_flip_within_the_band(cfg):
     assert slack.sum() <= 2.0 * total.sum(), (slack.sum(), total.sum())
     loose = slack > 4.0 * total + 1e-12 * s
     assert loose.sum() <= 0.03 * has.sum(), (int(loose.sum()), int(has.sum()))
+
+
+def test_threaded_solve_equals_the_sequential_sum_over_views():
+    # A is a sum over views (Eq. (7)): splitting the views over host threads, each
+    # with its own partial A, changes only the order of the float64 additions
+    sc = sg.make_config("C1", n=800, views=5, res=64)
+    a = O.solve64(sc, O.params())
+    b = O.solve64(sc, O.params(), threads=3)
+    assert a["blends"] == b["blends"] and a["evaluated"] == b["evaluated"]
+    s = np.abs(a["A"]).sum()
+    assert np.abs(a["A"] - b["A"]).sum() <= 1e-13 * s
+    assert np.allclose(a["slack"], b["slack"], rtol=1e-12, atol=1e-18)
+    assert sorted(b["views"]) == list(range(5))

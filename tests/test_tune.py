@@ -21,12 +21,25 @@ def test_candidates_cover_the_tunable_settings_and_include_the_defaults():
                                                                                           L.FS_RED_LDS2SUM}
     assert {c["opts"]["lanes"] for c in cs} == {1, 2, 3, 4}
     assert {c["params"]["tile_order"] for c in cs} == {0, 1}
-    assert any(T._same(c, T.reference()) for c in cs)
+    assert {c["params"]["persistent"] for c in cs} == {0, 1}
+    assert {c["params"]["lds_batch"] for c in cs} == {64, 128, 256}
+    assert len(cs) == 3 * 2 * 4 * 2 * 3
+    assert sum(T._same(c, T.reference()) for c in cs) == 1
     # the reference is what the library's defaults are
     p = L.params()
-    assert T.reference()["params"] == {"tile_w": p.tile_w, "tile_h": p.tile_h, "tile_order": p.tile_order}
+    assert T.reference()["params"] == {"tile_w": p.tile_w, "tile_h": p.tile_h, "tile_order": p.tile_order,
+                                       "persistent": p.persistent, "lds_batch": p.lds_batch or 256}
     o = L.batch_opts()
     assert o.lanes == 0 and o.reduction == L.FS_RED_AUTO  # 0: two lanes; auto: LDS + two-sum with A_lo
+
+
+def test_batch_key_names_single_scenes_like_scene_key():
+    import scenegen as sg
+    sc = sg.make_config("C1", n=300, views=2, res=32)
+    assert T.batch_key([sc]) == T.scene_key(sc)
+    sc2 = sg.make_config("C1", seed=3, n=500, views=3, res=48)
+    k = T.batch_key([sc, sc2])
+    assert k == f"B2-N1024-P{T._bucket(2 * 32 * 32 + 3 * 48 * 48)}-V5-E2"
 
 
 def test_table_round_trip(tmp_path):
@@ -48,7 +61,7 @@ def test_table_round_trip(tmp_path):
 def test_committed_table_is_well_formed():
     t = T.load()
     for key, e in t["entries"].items():
-        assert key.startswith("E") and "-N" in key
+        assert key[0] in "EB" and "-N" in key
         assert e["params"]["tile_w"] * e["params"]["tile_h"] == 256
         assert e["opts"]["reduction"] in (L.FS_RED_LDS, L.FS_RED_LDS2SUM)
         assert 1 <= e["opts"]["lanes"] <= 4

@@ -43,9 +43,9 @@ def _composite(ctx, fn, ds, cams, proj, bins, prm):
     return A, tf.cpu().numpy(), nb.cpu().numpy(), st
 
 
-def _check_one(ctx, sc, tile_order, what):
+def _check_one(ctx, sc, tile_order, what, persistent=0):
     ds = L.DeviceScene(sc)
-    prm = L.params(tile_order=tile_order)
+    prm = L.params(tile_order=tile_order, persistent=persistent)
     cams, nv, proj, bins = _lists(ctx, ds, prm)
     log(f"[no-alloc] {what}: {sc.n} Gaussians, {nv} views, tile_order {tile_order}, {bins.capacity} pairs")
     A0, tf0, nb0, st0 = _composite(ctx, ctx.fs_accumulate, ds, cams, proj, bins, prm)
@@ -78,6 +78,9 @@ def test_noalloc_matches_fs_accumulate_on_two_calls_in_a_row():
     for order in (1, 2):
         _check_one(ctx, small, order, f"smaller call, tile_order {order}")
         _check_one(ctx, big, order, f"larger call, tile_order {order}")
+    # the persistent launch, whose work counter also lives in the scratch array
+    _check_one(ctx, big, 0, "larger call, persistent", persistent=1)
+    _check_one(ctx, small, 0, "smaller call, persistent", persistent=1)
     ctx.close()
 
 
