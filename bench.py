@@ -44,6 +44,8 @@ def parse():
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--config", default="C5", help="C5 (multi-scene batch, default) or C1-C4")
     ap.add_argument("--scenes", type=int, default=32, help="scenes of the C5 batch")
+    ap.add_argument("--scene-cache", default=None, metavar="DIR",
+                    help="read the C5 scenes from DIR (written there on the first run)")
     ap.add_argument("--cpu-views", type=int, default=16, help="views of the CPU oracle sample (0: skip)")
     ap.add_argument("--no-plain", action="store_true", help="skip the per-view comparators")
     ap.add_argument("--no-precision", action="store_true", help="skip the per-variant error report")
@@ -132,7 +134,7 @@ def main():
     torch.cuda.set_device(0)
     t0 = time.time()
     if args.config == "C5":
-        scenes = sg.make_batch(args.scenes)
+        scenes = sg.make_batch_cached(args.scenes, args.scene_cache)
     else:
         scenes = [sg.make_config(args.config)]
     n_sc = len(scenes)
@@ -344,7 +346,7 @@ def main():
         precision = {k_: {"rows": 0} for k_ in variants}
         acc_rows = {k_: [] for k_ in variants}
         fp64_rows = []
-        mism = low = 0
+        mism = low = low_seen = excused = 0
         bad_rows = 0
         for si, views in by_scene.items():
             sc_, ref = scenes[si], refs[si]
@@ -365,8 +367,16 @@ def main():
                     S64, m64 = O.assign64(ref["A"], 0.0)
                     S_g = torch.empty((sc_.E, sc_.n), dtype=torch.uint8, device="cuda")
                     ctx.fs_assign(A_hi, A_lo, sc_.n, sc_.E, 0.0, S_g, None)
-                    mism += int(((S_g.cpu().numpy() != S64) & (m64 >= 1e-4)).sum())
-                    low += int((m64 < 1e-4).sum())
+                    # as the tests: excluded where the margin is < 1e-4, excused (counted apart)
+                    # where the row's own A difference can move the margin past zero
+                    wrong = S_g.cpu().numpy() != S64
+                    lo_m = m64 < 1e-4
+                    reld = np.where(s_ > 0, d / np.maximum(s_, 1e-300), 0.0)
+                    by_row = ~lo_m & (m64 < 4.0 * reld[None, :])
+                    mism += int((wrong & ~lo_m & ~by_row).sum())
+                    excused += int((wrong & by_row).sum())
+                    low += int(lo_m.sum())
+                    low_seen += int((lo_m & (s_ > 0)[None, :]).sum())
                     deg = np.zeros(sc_.n, bool)
                     for v in views:
                         deg |= (O.project32(sc_, v, O.params())["flags"] & 2) != 0
@@ -377,7 +387,8 @@ def main():
         if fp64_rows:
             precision["lds_two_sum_fp64_conic_rows"] = row_errors(fp64_rows)
         parity = {"views": sample, "rows_off_tolerance": bad_rows,
-                  "label_mismatches_margin_ge_1e-4": mism, "low_margin_entries": low}
+                  "label_mismatches": mism, "label_mismatches_excused_by_row_difference": excused,
+                  "low_margin_entries": low, "low_margin_entries_of_seen_rows": low_seen}
         log(f"parity on the sample: {parity}; precision: {precision}")
 
     res = {

@@ -234,8 +234,11 @@ int fs_bin_sort(fs_ctx *ctx, const fs_proj *proj, const fs_camera *cams, const f
  * A[g][label(pixel)] += alpha*T and T *= 1 - alpha.
  * masks: device uint8, views concatenated, each [H][W]. A_hi: device float32
  * [n][n_classes], ADDED INTO (the caller zeroes it once; views may be
- * processed over any number of calls). A_lo: same shape, receives the exact
- * rounding error of the additions into A_hi (FS_RED_LDS2SUM) or NULL.
+ * processed over any number of calls). A_lo: same shape, or NULL; with
+ * FS_RED_LDS2SUM it receives the exact rounding error of every addition into
+ * A_hi, and the partial sums of labels that no 8x8 pixel block of a tile holds
+ * in 4 or more pixels (stray, noise-like labels), which are small; the
+ * accumulated result is A_hi + A_lo.
  * n_classes in [2, 256]. pix: optional per-pixel outputs, or NULL. */
 int fs_accumulate(fs_ctx *ctx, const fs_proj *proj, const fs_bins *bins, const fs_camera *cams,
                   const uint8_t *masks, int32_t n_classes, const fs_params *p,

@@ -17,7 +17,9 @@
 // with up to 8 labels stages 256 Gaussians per batch, with 16, 32 or 64
 // labels 128, 64 or 32. With A_lo, the exact rounding error of the global
 // atomic (two-sum on the returned old value) goes to A_lo, so that
-// A_hi + A_lo carries the sum to about one rounding.
+// A_hi + A_lo carries the sum to about one rounding; the partials of labels
+// that only appear as stray pixels in a tile (relabel noise) are small and go
+// to A_lo directly, without waiting for a returned value.
 #include <algorithm>
 
 #include "fs_internal.h"
@@ -29,6 +31,7 @@ constexpr int kPart = 2048;   // LDS partial sums: staged Gaussians x label slot
 constexpr int kMaxSlots = 64; // distinct labels per tile handled by pre-reduction
 constexpr int kBatch = 256;   // most Gaussians staged per batch
 constexpr int kMajor = 4;     // a label held by this many lanes of a wave is summed across the wave
+constexpr int kMinorStage = 4;  // minor lanes per wave whose weights go through the LDS staging area
 constexpr float kLoFloor = -200.0f;  // floor of log2(opacity): 2^-200 is zero in float32
 
 template <int CTRL>
@@ -149,8 +152,10 @@ __device__ __forceinline__ void accum_tile(const uint32_t tile, const float4 *__
     __shared__ uint32_t s_bits[8];
     __shared__ int32_t s_slot_label[kMaxSlots];
     __shared__ unsigned long long s_wslots[4];
+    __shared__ unsigned long long s_tmajor;  // slots that are major in at least one wave of the tile
     __shared__ uint32_t s_misc[5];      // bad labels, longest wave walk, blends, evaluations, walked entries
     __shared__ int4 s_wbox[4];          // per wave: columns x0..x1, rows y0..y1 of its live pixels
+    __shared__ __align__(16) float s_mstage[4][kMinorStage][8];  // per wave: 8 weights of each minor lane
 
     if (tile_done && tile_done[tile]) return;  // every pixel of this tile has finished (whole block)
     const int view = find_view_of_tile(views, n_views, tile);
@@ -179,6 +184,7 @@ __device__ __forceinline__ void accum_tile(const uint32_t tile, const float4 *__
     }
     if (tid < 8) s_bits[tid] = 0;
     if (tid < 4) s_wslots[tid] = 0;
+    if (tid == 0) s_tmajor = 0;
     if (tid < 5) s_misc[tid] = 0;
     __syncthreads();
     if (inside && !active && (first || tstate == nullptr)) atomicAdd(&s_misc[0], 1u);  // counted once per solve
@@ -216,8 +222,31 @@ __device__ __forceinline__ void accum_tile(const uint32_t tile, const float4 *__
             if (__popcll(__ballot(active && slot == sidx)) >= kMajor) wmajor |= 1ull << sidx;
         }
     }
+    if (lane == 0 && wmajor) atomicOr(&s_tmajor, wmajor);
     const bool minor = active && !plain && !((wmajor >> slot) & 1ull);
-    const bool wminor = __ballot(minor) != 0ull;
+    const unsigned long long mmask = __ballot(minor);
+    const bool wminor = mmask != 0ull;
+    // Minor weights of a group of 8 entries: with at most kMinorStage minor lanes,
+    // each writes its 8 weights to the wave's staging area and the 8 * (minor lanes)
+    // lanes of the wave ("carriers": lane = 8 * minor rank + entry) each add one of
+    // them to LDS, so one atomic instruction covers them all; with more minor
+    // lanes, each adds its own nonzero weights.
+    const int n_minor = __popcll(mmask);
+    const bool mstage = n_minor <= kMinorStage;
+    const int mrank = __popcll(mmask & ((1ull << lane) - 1ull));
+    int carrier_slot = 0;
+    const bool carrier = mstage && (lane >> 3) < n_minor;
+    {
+        // lane of the (lane >> 3)-th minor lane, then its slot
+        unsigned long long mm = mmask;
+        int src = 0;
+        for (int m = 0; m < kMinorStage && mm; ++m) {
+            const int l = __ffsll((long long)mm) - 1;
+            mm &= mm - 1ull;
+            if ((lane >> 3) == m) src = l;
+        }
+        carrier_slot = __shfl(slot, src);
+    }
     if (tid == 0) {
         if (s_misc[0]) {
             status_add(status, ST_BAD_LABELS, (unsigned long long)s_misc[0]);
@@ -372,7 +401,31 @@ __device__ __forceinline__ void accum_tile(const uint32_t tile, const float4 *__
                         const float tot = reduce_scatter8(wr);
                         if (head && tot != 0.0f) atomicAdd(&s_part[((s_list[w][g0 + e] >> 5) << sh) + slot0], tot);
                     } else {
-                        // several labels in this wave's block: one reduce-scatter per major label
+                        if (wminor) {
+                            if (mstage) {
+                                // minor lanes stage their weights; carrier lane 8 m + k adds
+                                // minor lane m's weight of entry k (padding entries weigh 0)
+                                if (minor) {
+                                    float4 *dst = reinterpret_cast<float4 *>(&s_mstage[w][mrank][0]);
+                                    dst[0] = make_float4(wr[0], wr[1], wr[2], wr[3]);
+                                    dst[1] = make_float4(wr[4], wr[5], wr[6], wr[7]);
+                                }
+                                __builtin_amdgcn_wave_barrier();
+                                if (carrier) {
+                                    const float val = s_mstage[w][lane >> 3][lane & 7];
+                                    if (val != 0.0f)
+                                        atomicAdd(&s_part[((s_list[w][g0 + (lane & 7)] >> 5) << sh) + carrier_slot], val);
+                                }
+                                __builtin_amdgcn_wave_barrier();
+                            } else if (minor) {
+                                // many rare labels: each lane adds its own nonzero weights
+#pragma unroll
+                                for (int k = 0; k < 8; ++k)
+                                    if (wr[k] != 0.0f) atomicAdd(&s_part[((jj[k] >> 5) << sh) + slot], wr[k]);
+                            }
+                        }
+                        // one reduce-scatter per major label of the wave (minor lanes never
+                        // hold a major slot, so the selection leaves them out)
                         unsigned long long sl = wmajor;
                         while (sl) {
                             const int sidx = __ffsll((long long)sl) - 1;
@@ -382,12 +435,6 @@ __device__ __forceinline__ void accum_tile(const uint32_t tile, const float4 *__
                             for (int k = 0; k < 8; ++k) v[k] = slot == sidx ? wr[k] : 0.0f;
                             const float tot = reduce_scatter8(v);
                             if (head && tot != 0.0f) atomicAdd(&s_part[((s_list[w][g0 + e] >> 5) << sh) + sidx], tot);
-                        }
-                        // lanes with a rare label add their own nonzero weights
-                        if (wminor && minor) {
-#pragma unroll
-                            for (int k = 0; k < 8; ++k)
-                                if (wr[k] != 0.0f) atomicAdd(&s_part[((jj[k] >> 5) << sh) + slot], wr[k]);
                         }
                     }
                     if (__ballot(live) == 0ull) break;
@@ -406,13 +453,21 @@ __device__ __forceinline__ void accum_tile(const uint32_t tile, const float4 *__
         }
         __syncthreads();
         if (!plain) {
+            // Partials of a slot that no wave holds in kMajor pixels (relabel noise) are
+            // small; with A_lo they go there with a plain atomic (no returned value to
+            // wait for), as A_lo only carries small values. The others take the two-sum.
+            const unsigned long long tmajor = s_tmajor;
+            auto flush = [&](int64_t idx, int sidx, float vpart) {
+                if (A_lo != nullptr && !((tmajor >> sidx) & 1ull)) unsafeAtomicAdd(A_lo + idx, vpart);
+                else add_global(A_hi, A_lo, idx, vpart);
+            };
             if (sh == 3) {
                 if ((uint32_t)tid < cnt) {
                     const uint32_t g = s_g[tid];
                     for (int sidx = 0; sidx < nslot; ++sidx) {
                         const float vpart = s_part[(tid << 3) + sidx];
                         if (vpart != 0.0f) {
-                            add_global(A_hi, A_lo, (int64_t)g * E + s_slot_label[sidx], vpart);
+                            flush((int64_t)g * E + s_slot_label[sidx], sidx, vpart);
                             s_part[(tid << 3) + sidx] = 0.0f;
                         }
                     }
@@ -423,7 +478,7 @@ __device__ __forceinline__ void accum_tile(const uint32_t tile, const float4 *__
                     const int sidx = (int)(i & (uint32_t)(stride - 1));
                     const float vpart = s_part[i];
                     if (sidx < nslot && vpart != 0.0f) {
-                        add_global(A_hi, A_lo, (int64_t)s_g[i >> sh] * E + s_slot_label[sidx], vpart);
+                        flush((int64_t)s_g[i >> sh] * E + s_slot_label[sidx], sidx, vpart);
                         s_part[i] = 0.0f;
                     }
                 }

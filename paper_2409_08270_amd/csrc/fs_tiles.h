@@ -34,7 +34,18 @@
 // rows of the chord of the Lo ellipse (widened the same way) can pass, and
 // each of those centres is decided by the definition's own test. So the
 // listed set is the definition's exactly; the approximations only choose
-// which centres to test. The count (fs_project) and the emission
+// which centres to test.
+//
+// Most walks are skipped. The inner ellipse q <= Li = L (1 - rq), shrunk by
+// the same margins, holds only centres whose binary32 q is surely <= L; on
+// the band row nearest the ellipse's left-most point its chord gives a column
+// that surely holds a passing centre. The first passing column lies between
+// the candidate bound and that column, so when both fall in one tile the
+// row's first listed tile is known without a test (likewise on the right).
+// When those rows hold none, the band row nearest the centre (the widest
+// chord) is tried. A walk remains only where a tile boundary falls between
+// the two, or where the band holds no surely passing centre (the very top
+// and bottom of the ellipse). The count (fs_project) and the emission
 // (fs_bin_sort) call the same code on the same record, so they agree. Small
 // splats hand their spans from the count to the emission as a span code.
 //
@@ -70,6 +81,7 @@ __host__ __device__ __forceinline__ float approx_rcp(float x)
 struct Span32 {
     float u, v, p, r, s, lim;  // the definition's inputs
     float lo, A, B, C, dt, iC, xe, ye, yx, mx, my;  // candidate bounds (approximate, widened)
+    float li;  // inner level L (1 - rq): centres with exact q <= li pass in binary32
     bool full, ok;
 };
 
@@ -112,7 +124,7 @@ __host__ __device__ __forceinline__ Span32 make_span32(float u, float v, float p
     sp.u = u; sp.v = v; sp.p = p; sp.r = r; sp.s = s; sp.lim = lim;
     sp.full = full;
     sp.ok = false;
-    sp.lo = sp.A = sp.B = sp.C = sp.dt = sp.iC = sp.xe = sp.ye = sp.yx = sp.mx = sp.my = 0.0f;
+    sp.lo = sp.A = sp.B = sp.C = sp.dt = sp.iC = sp.xe = sp.ye = sp.yx = sp.mx = sp.my = sp.li = 0.0f;
     if (full) return sp;
     sp.A = p;
     sp.B = p * r;
@@ -124,6 +136,7 @@ __host__ __device__ __forceinline__ Span32 make_span32(float u, float v, float p
     const float rq = 0x1p-8f + 0x1p-17f * kap;              // bound on the relative rounding of q, widened
     const float rc = approx_sqrt(0x1p-15f * (kap + 2.0f));  // relative error of the chord and edge half-widths
     sp.lo = lim * (1.0f + rq);
+    sp.li = lim * (1.0f - rq);
     sp.iC = approx_rcp(sp.C);
     const float iD = approx_rcp(sp.dt);
     sp.xe = approx_sqrt((sp.lo * sp.C) * iD);
@@ -175,6 +188,22 @@ __host__ __device__ __forceinline__ bool column_hit(const Span32 &sp, int k, int
     return false;
 }
 
+// Columns [ka, kb] of pixel row j whose centres lie inside the inner ellipse
+// q <= li, shrunk by the edge margin: each of them passes the definition's
+// test in binary32. False if the shrunk chord holds no column centre.
+__host__ __device__ __forceinline__ bool sure_columns(const Span32 &sp, int j, int &ka, int &kb)
+{
+    const float y = ((float)j + 0.5f) - sp.v;
+    const float h = approx_sqrt(fmaxf((sp.li - (sp.s * y) * y) * approx_rcp(sp.p), 0.0f));
+    const float xc = sp.u - (sp.r * y);
+    const float lo = ((xc - h) - 0.5f) + sp.mx;
+    const float hi = ((xc + h) - 0.5f) - sp.mx;
+    if (!(lo <= hi) || !(lo > -1.0e9f) || !(hi < 1.0e9f)) return false;
+    ka = (int)ceilf(lo);
+    kb = (int)floorf(hi);
+    return ka <= kb;
+}
+
 // n / t for n >= 0: a shift when the tile size t is a power of two (t is the
 // same for every lane, so the choice costs one uniform branch)
 __host__ __device__ __forceinline__ int tile_of(int n, int t)
@@ -210,6 +239,37 @@ __host__ __device__ __forceinline__ bool row_span(const Span32 &sp, int ty, int 
         // centre columns k with k + 0.5 - u in [xmin - mx, xmax + mx]
         cl = clamp_index(floorf(((sp.u + xmin) - 0.5f) - sp.mx), k0, k1 + 1);
         cr = clamp_index(ceilf(((sp.u + xmax) - 0.5f) + sp.mx), k0 - 1, k1);
+    }
+    if (sp.ok && cl <= cr) {
+        // a surely passing column near each end, on the band row nearest the
+        // ellipse's left-most (right-most) point
+        int la, lb, ra, rb, sl = 0, sr = -1;
+        const int jl = clamp_index(floorf(sp.v + sp.yx), j0, j1);
+        const int jr = clamp_index(floorf(sp.v - sp.yx), j0, j1);
+        if (sure_columns(sp, jl, la, lb) && sure_columns(sp, jr, ra, rb) && max(la, k0) <= min(lb, k1) &&
+            max(ra, k0) <= min(rb, k1)) {
+            sl = max(la, k0);
+            sr = min(rb, k1);
+        } else {
+            // the band row nearest the ellipse's centre, where its chord is widest
+            const int jc = clamp_index(floorf(sp.v), j0, j1);
+            if (sure_columns(sp, jc, la, lb)) {
+                sl = max(la, k0);
+                sr = min(lb, k1);
+            }
+        }
+        if (sl <= sr) {
+            // first passing column in [cl, sl], last in [sr, cr]
+            int kl = cl;
+            if (tile_of(cl, tw) != tile_of(sl, tw))
+                while (kl < sl && !column_hit(sp, kl, j0, j1)) ++kl;
+            int kr = cr;
+            if (tile_of(cr, tw) != tile_of(sr, tw))
+                while (kr > sr && !column_hit(sp, kr, j0, j1)) --kr;
+            l = tile_of(kl, tw);
+            r = tile_of(kr, tw);
+            return true;
+        }
     }
     int kl = cl;
     while (kl <= cr && !column_hit(sp, kl, j0, j1)) ++kl;

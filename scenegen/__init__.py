@@ -503,6 +503,56 @@ def make_batch(n_scenes=32, first=0):
     return [_c5_scene(s) for s in range(first, first + n_scenes)]
 
 
+_ARRAYS = ("mx", "my", "mz", "qw", "qx", "qy", "qz", "sx", "sy", "sz", "op", "R", "t", "fx", "fy", "cx", "cy",
+           "W", "H", "gt")
+
+
+def save_scenes(path: str, scenes) -> None:
+    """Writes scenes to one uncompressed .npz (no pickled objects): every array,
+    the masks of each scene concatenated, and the scalar fields."""
+    out = {"n_scenes": np.array(len(scenes))}
+    for i, sc in enumerate(scenes):
+        for f in _ARRAYS:
+            out[f"{i}.{f}"] = getattr(sc, f)
+        out[f"{i}.masks"] = np.concatenate([m.reshape(-1) for m in sc.masks]) if sc.masks else np.zeros(0, np.uint8)
+        out[f"{i}.meta"] = np.array([sc.seed, sc.E], np.int64)
+        out[f"{i}.gamma"] = np.array(sc.gamma, np.float64)
+        out[f"{i}.name"] = np.frombuffer(sc.name.encode(), np.uint8)
+    tmp = path + ".tmp.npz"
+    np.savez(tmp, **out)
+    os.replace(tmp, path)
+
+
+def load_scenes(path: str):
+    """Scenes written by save_scenes."""
+    z = np.load(path, allow_pickle=False)
+    scenes = []
+    for i in range(int(z["n_scenes"])):
+        kw = {f: z[f"{i}.{f}"] for f in _ARRAYS}
+        flat = z[f"{i}.masks"]
+        masks, off = [], 0
+        for w, h in zip(kw["W"], kw["H"]):
+            masks.append(flat[off:off + int(w) * int(h)].reshape(int(h), int(w)))
+            off += int(w) * int(h)
+        seed, E = (int(x) for x in z[f"{i}.meta"])
+        scenes.append(Scene(name=bytes(z[f"{i}.name"]).decode(), seed=seed, masks=masks, E=E,
+                            gamma=float(z[f"{i}.gamma"]), **kw))
+    return scenes
+
+
+def make_batch_cached(n_scenes: int = 32, cache_dir: Optional[str] = None):
+    """make_batch(n_scenes), read from (or written to) cache_dir when it is given."""
+    if not cache_dir:
+        return make_batch(n_scenes)
+    path = os.path.join(cache_dir, f"c5_{n_scenes}.npz")
+    if os.path.exists(path):
+        return load_scenes(path)
+    scenes = make_batch(n_scenes)
+    os.makedirs(cache_dir, exist_ok=True)
+    save_scenes(path, scenes)
+    return scenes
+
+
 def make_tiny(seed, n=10, views=3, res=32, E=2, spread=0.25, masks="random"):
     """Tiny, heavily overlapping scenes for exhaustive checks (N <= 12)."""
     rng = np.random.Generator(np.random.PCG64(seed))
