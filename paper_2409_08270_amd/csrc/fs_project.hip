@@ -14,8 +14,32 @@ namespace {
 
 __device__ __forceinline__ bool finite32(float x) { return __builtin_isfinite(x); }
 
+// Inclusive sum over the 256 threads of the block (all threads call it).
+__device__ __forceinline__ uint32_t block_incl_sum(uint32_t x, uint32_t *s_wsum)
+{
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+#pragma unroll
+    for (int off = 1; off < 64; off <<= 1) {
+        const uint32_t y = __shfl_up(x, off);
+        if (lane >= off) x += y;
+    }
+    if (lane == 63) s_wsum[w] = x;
+    __syncthreads();
+    for (int k = 0; k < w; ++k) x += s_wsum[k];
+    __syncthreads();
+    return x;
+}
+
 // Block b belongs to the task whose [blk0, next blk0) holds b; the task's
 // Gaussians are loaded once and projected into its (up to kProjViews) views.
+//
+// Listed tiles. The tile rows of a splat's rectangle are listed one by one
+// (row_span), and splats differ widely in their number of rows, so each thread
+// listing its own splat's rows would leave the wave waiting for its largest
+// splat. Instead the block lists the rows of all its 256 splats together:
+// every thread takes rows in turn from the block's concatenated row list (a
+// binary search in the block's row offsets finds the splat), and the counts
+// and span-code bytes are gathered per splat in LDS.
 __global__ __launch_bounds__(256) void k_project(const ProjTask *__restrict__ tasks, int32_t n_tasks,
                                                  const SceneDev *__restrict__ scenes, const ViewDev *__restrict__ views,
                                                  ProjParams P, float4 *__restrict__ rec, short4 *__restrict__ rect,
@@ -72,6 +96,14 @@ __global__ __launch_bounds__(256) void k_project(const ProjTask *__restrict__ ta
             for (int j = 0; j < 3; ++j) L[i * 3 + j] = q[i * 3 + j] * s[j];
     }
 
+    __shared__ Span32 s_span[256];
+    __shared__ int4 s_rect[256];        // x0, y0, x1, small (span code kept)
+    __shared__ uint32_t s_off[257];     // first row of each splat in the block's row list
+    __shared__ uint32_t s_cnt[256];     // listed tiles per splat
+    __shared__ __align__(16) uint8_t s_code[256][16];
+    __shared__ uint32_t s_wsum[4];
+    const int tid = threadIdx.x;
+
     int n_invalid = 0, n_fp64 = 0;
     for (int v = v0; v < v1; ++v) {
         const ViewDev &C = views[v];
@@ -79,6 +111,9 @@ __global__ __launch_bounds__(256) void k_project(const ProjTask *__restrict__ ta
         const int64_t idx = (int64_t)C.elem_off + g;
         uint8_t f = 0;
         int nt = 0;
+        uint32_t rows = 0;                 // tile rows of this splat to list
+        Span32 sp_mine = make_span32(0.f, 0.f, 1.f, 0.f, 1.f, true, 1.0f);
+        int4 rect_mine = make_int4(0, 0, -1, 0);
         SpanCode code = no_code();
         short4 rc = make_short4(0, 0, 0, 0);
         float4 r0 = make_float4(0.f, 0.f, 0.f, 0.f), r1 = make_float4(0.f, 0.f, 0.f, 0.f);
@@ -161,20 +196,50 @@ __global__ __launch_bounds__(256) void k_project(const ProjTask *__restrict__ ta
                         int x0 = tile_of(kmin, P.tile_w), y0 = tile_of(jmin, P.tile_h);
                         int x1 = tile_of(kmax, P.tile_w), y1 = tile_of(jmax, P.tile_h);
                         rc = make_short4((short)x0, (short)y0, (short)x1, (short)y1);
-                        // tiles of the rectangle that the support reaches, row by row
-                        const Span32 sp = make_span32(u, vv, cp, cr, cs, deg, support_limit(P.sigma_k));
+                        // tiles of the rectangle that the support reaches: listed below, row by row
+                        sp_mine = make_span32(u, vv, cp, cr, cs, deg, support_limit(P.sigma_k));
                         const bool small = y1 - y0 < kSpanCodeRows && x1 - x0 < 16;
-                        for (int ty = y0; ty <= y1; ++ty) {
-                            int l, r;
-                            if (row_span(sp, ty, x0, x1, P.tile_w, P.tile_h, C.W, C.H, l, r)) {
-                                nt += r - l + 1;
-                                if (small) code_set(code, ty - y0, l, r, x0);
-                            }
-                        }
+                        rect_mine = make_int4(x0, y0, x1, small ? 1 : 0);
+                        rows = (uint32_t)(y1 - y0 + 1);
                     }
                 }
             }
         }
+        // the block's splats list their tile rows together
+        s_span[tid] = sp_mine;
+        s_rect[tid] = rect_mine;
+        s_cnt[tid] = 0;
+        *reinterpret_cast<uint4 *>(&s_code[tid][0]) = make_uint4(~0u, ~0u, ~0u, ~0u);
+        const uint32_t incl = block_incl_sum(rows, s_wsum);  // ends with a barrier
+        s_off[tid + 1] = incl;
+        if (tid == 0) s_off[0] = 0;
+        __syncthreads();
+        const uint32_t n_rows = s_off[256];
+        for (uint32_t i = (uint32_t)tid; i < n_rows; i += 256u) {
+            // the splat e with s_off[e] <= i < s_off[e + 1]
+            int lo_e = 0, hi_e = 255;
+            while (lo_e < hi_e) {
+                const int mid = (lo_e + hi_e + 1) >> 1;
+                if (s_off[mid] <= i) lo_e = mid; else hi_e = mid - 1;
+            }
+            const int e = lo_e;
+            const int4 re = s_rect[e];
+            const int row = (int)(i - s_off[e]);
+            int l, r;
+            if (row_span(s_span[e], re.y + row, re.x, re.z, P.tile_w, P.tile_h, C.W, C.H, l, r)) {
+                atomicAdd(&s_cnt[e], (uint32_t)(r - l + 1));
+                if (re.w) s_code[e][row] = (uint8_t)((uint32_t)(l - re.x) | ((uint32_t)(r - l) << 4));
+            }
+        }
+        __syncthreads();
+        if (rows > 0) {
+            nt = (int)s_cnt[tid];
+            if (rect_mine.w) {
+                const uint4 cw = *reinterpret_cast<const uint4 *>(&s_code[tid][0]);
+                code = SpanCode{(uint64_t)cw.x | ((uint64_t)cw.y << 32), (uint64_t)cw.z | ((uint64_t)cw.w << 32)};
+            }
+        }
+        __syncthreads();  // the next view reuses the block's LDS
         if (live) {
             rec[idx * 2 + 0] = r0;
             rec[idx * 2 + 1] = r1;
