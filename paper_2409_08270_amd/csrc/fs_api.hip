@@ -1224,7 +1224,7 @@ int enqueue_slabs(fs_batch *b, Work &w, Chunk &c, int chunk_idx, hipStream_t s, 
             HIPCHECK(ctx, launch_emit(s, dk, dv, (const uint32_t *)w.offsets.p, (const uint32_t *)w.counts.p,
                                       (const float *)w.rec.p, (const int16_t *)w.rect.p, fl,
                                       (const ViewDev *)c.views.p, V, total, c.pair_cap, b->p.tile_w, b->p.tile_h,
-                                      b->p.sigma_k, nullptr, pt, nullptr, ctx->status_dev, c.gbits,
+                                      b->p.sigma_k, k > 0 ? done : nullptr, pt, nullptr, ctx->status_dev, c.gbits,
                                       (const uint64_t *)w.codes.p));
             HIPCHECK(ctx, launch_pair_segs(s, (const uint32_t *)w.offsets.p, (const ViewDev *)c.views.p, V, total, np,
                                            c.pair_cap, (SegDev *)c.psegs.p, ctx->status_dev));
@@ -1506,7 +1506,9 @@ int batch_build(fs_batch *b, const fs_scene *scenes, int32_t n_scenes)
             }
             c.gbits = bits_for(max_n);
             c.tbits = bits_for(max_tv);
-            c.packed = S == 1 && c.tbits <= 16 && c.gbits + c.tbits <= 32 && c.vpairs.size() == c.plan.views.size();
+            // (with depth slabs every slab's pairs of a view are at most the view's planned
+            // pairs, so the per-view capacities below hold for every slab)
+            c.packed = c.tbits <= 16 && c.gbits + c.tbits <= 32 && c.vpairs.size() == c.plan.views.size();
             if (c.packed) {
                 // per-view capacities (planned count plus slack) and blocks
                 uint64_t sum = 0;

@@ -82,6 +82,7 @@ struct Span32 {
     float u, v, p, r, s, lim;  // the definition's inputs
     float lo, A, B, C, dt, iC, xe, ye, yx, mx, my;  // candidate bounds (approximate, widened)
     float li;  // inner level L (1 - rq): centres with exact q <= li pass in binary32
+    float ip;  // approximate 1 / p
     bool full, ok;
 };
 
@@ -124,7 +125,7 @@ __host__ __device__ __forceinline__ Span32 make_span32(float u, float v, float p
     sp.u = u; sp.v = v; sp.p = p; sp.r = r; sp.s = s; sp.lim = lim;
     sp.full = full;
     sp.ok = false;
-    sp.lo = sp.A = sp.B = sp.C = sp.dt = sp.iC = sp.xe = sp.ye = sp.yx = sp.mx = sp.my = sp.li = 0.0f;
+    sp.lo = sp.A = sp.B = sp.C = sp.dt = sp.iC = sp.xe = sp.ye = sp.yx = sp.mx = sp.my = sp.li = sp.ip = 0.0f;
     if (full) return sp;
     sp.A = p;
     sp.B = p * r;
@@ -138,6 +139,7 @@ __host__ __device__ __forceinline__ Span32 make_span32(float u, float v, float p
     sp.lo = lim * (1.0f + rq);
     sp.li = lim * (1.0f - rq);
     sp.iC = approx_rcp(sp.C);
+    sp.ip = approx_rcp(p);
     const float iD = approx_rcp(sp.dt);
     sp.xe = approx_sqrt((sp.lo * sp.C) * iD);
     sp.ye = approx_sqrt((sp.lo * p) * iD);
@@ -152,7 +154,7 @@ __host__ __device__ __forceinline__ Span32 make_span32(float u, float v, float p
 // x of the widened ellipse's boundary at offset y: left (sgn = -1) or right (+1)
 __host__ __device__ __forceinline__ float edge_x(const Span32 &sp, float y, float sgn)
 {
-    const float h = approx_sqrt(fmaxf((sp.lo - (sp.s * y) * y) * approx_rcp(sp.p), 0.0f));
+    const float h = approx_sqrt(fmaxf((sp.lo - (sp.s * y) * y) * sp.ip, 0.0f));
     return -(sp.r * y) + sgn * h;
 }
 
@@ -194,7 +196,7 @@ __host__ __device__ __forceinline__ bool column_hit(const Span32 &sp, int k, int
 __host__ __device__ __forceinline__ bool sure_columns(const Span32 &sp, int j, int &ka, int &kb)
 {
     const float y = ((float)j + 0.5f) - sp.v;
-    const float h = approx_sqrt(fmaxf((sp.li - (sp.s * y) * y) * approx_rcp(sp.p), 0.0f));
+    const float h = approx_sqrt(fmaxf((sp.li - (sp.s * y) * y) * sp.ip, 0.0f));
     const float xc = sp.u - (sp.r * y);
     const float lo = ((xc - h) - 0.5f) + sp.mx;
     const float hi = ((xc + h) - 0.5f) - sp.mx;

@@ -1,7 +1,8 @@
 """Tuner for the batched solve (fs_batch): picks, per workload, the tile
 shape, compositing work order, compositing launch (one workgroup per tile or
-resident workgroups pulling tiles from a counter), LDS batch depth, reduction
-strategy and number of lanes that give the shortest graph replay, among
+resident workgroups pulling tiles from a counter), LDS batch depth, depth
+slabs, reduction strategy and number of lanes that give the shortest graph
+replay, among
 settings whose result agrees with the library's defaults. The defaults are
 kept unless a setting is at least `min_gain` faster, so that timing noise does
 not decide. By default only the compensated reduction (LDS pre-reduction +
@@ -68,6 +69,7 @@ KNOBS = [("opts", "lanes", [1, 2, 3, 4]),
          ("params", "tile_order", [0, 1]),
          ("params", "persistent", [0, 1]),
          ("params", "lds_batch", [256, 128, 64]),
+         ("opts", "depth_slabs", [1, 2, 3]),
          ("opts", "reduction", None)]  # None: the reductions allowed by `compensated`
 
 
@@ -78,10 +80,10 @@ def _reductions(compensated: bool):
 
 def reference() -> dict:
     """The library's defaults (16x16 tiles, longest list first, one workgroup per tile,
-    256-entry LDS batches, LDS + two-sum, 2 lanes)."""
+    256-entry LDS batches, one depth slab, LDS + two-sum, 2 lanes)."""
     from . import _lib as L
     return {"params": {"tile_w": 16, "tile_h": 16, "tile_order": 0, "persistent": 0, "lds_batch": 256},
-            "opts": {"reduction": L.FS_RED_LDS2SUM, "lanes": 2}}
+            "opts": {"reduction": L.FS_RED_LDS2SUM, "lanes": 2, "depth_slabs": 1}}
 
 
 def _with(c: dict, sec: str, name: str, value) -> dict:

@@ -221,13 +221,40 @@ def test_uncounted_batch_gives_the_same_result(ctx):
         L.Batch(ctx, dss, L.params(count_ops=2))
 
 
+def test_depth_slabs_on_the_global_key_sort(ctx):
+    """Depth slabs where the pairs cannot be packed into one word (3M Gaussians need
+    22 id bits, 1297x840 views 13 tile bits): the (tile, depth) key sort with tiles
+    that finished skipped in later slabs gives the single-pass result."""
+    sc = sg.make_config("C4", views=2)
+    ds = L.DeviceScene(sc)
+    out = {}
+    for S in (1, 2):
+        b = L.Batch(ctx, [ds], L.params(), gammas=[0.0], depth_slabs=S)
+        ctx.status()
+        b.run()
+        torch.cuda.synchronize()
+        st = ctx.status()
+        out[S] = (_A(b, 0), b.S[0].cpu().numpy(), st)
+        if S == 1:
+            inf, _, _, _ = b.chunk_lists(0)
+            assert inf["packed"] == 0
+        b.close()
+    (a1, s1, st1), (a2, s2, st2) = out[1], out[2]
+    log(f"[slabs, global keys] pairs emitted {st2['pairs_emitted']} of {st1['pairs_emitted']}")
+    assert st2["pairs_emitted"] < st1["pairs_emitted"]
+    assert abs(st2["blends"] - st1["blends"]) <= 1e-4 * st1["blends"]
+    d = np.abs(a1 - a2).sum(1)
+    assert np.all(d <= 1e-5 * np.abs(a1).sum(1) + 1e-9)
+    assert (s1 != s2).sum() <= 2
+
+
 @pytest.mark.parametrize("slabs", [1, 2])
 def test_grown_inputs_overflow_is_latched(ctx, slabs):
     # The plan (pair capacities, per-view sort segments) is exact for the inputs
     # at creation. Scaling the Gaussians up afterwards makes every view need more
     # pairs: the excess must be dropped and latched, never written out of bounds,
-    # and restoring the inputs restores the result. One slab takes the packed
-    # per-view pair sort, two slabs the global (tile, id) sort.
+    # and restoring the inputs restores the result (one slab and two slabs, both
+    # on the packed per-view pair sort).
     sc = sg.make_config("C1", n=5000, views=3, res=96)
     ds = L.DeviceScene(sc)
     b = L.Batch(ctx, [ds], L.params(), depth_slabs=slabs)

@@ -23,7 +23,8 @@ def test_candidates_cover_the_tunable_settings_and_include_the_defaults():
     assert {c["params"]["tile_order"] for c in cs} == {0, 1}
     assert {c["params"]["persistent"] for c in cs} == {0, 1}
     assert {c["params"]["lds_batch"] for c in cs} == {64, 128, 256}
-    assert len(cs) == 3 * 2 * 4 * 2 * 3
+    assert {c["opts"]["depth_slabs"] for c in cs} == {1, 2, 3}
+    assert len(cs) == 3 * 2 * 4 * 2 * 3 * 3
     assert sum(T._same(c, T.reference()) for c in cs) == 1
     # the reference is what the library's defaults are
     p = L.params()
@@ -31,6 +32,7 @@ def test_candidates_cover_the_tunable_settings_and_include_the_defaults():
                                        "persistent": p.persistent, "lds_batch": p.lds_batch or 256}
     o = L.batch_opts()
     assert o.lanes == 0 and o.reduction == L.FS_RED_AUTO  # 0: two lanes; auto: LDS + two-sum with A_lo
+    assert o.depth_slabs == 0  # 0: one slab
 
 
 def test_batch_key_names_single_scenes_like_scene_key():
