@@ -451,13 +451,36 @@ __global__ void k_slab_counts(const uint32_t *__restrict__ skeys, const uint32_t
     counts[i] = c;
 }
 
-// Emission of the (tile, Gaussian) pairs. Block b handles the depth-sorted
-// items [256 b, 256 b + 256), whose outputs form one contiguous range. Each
-// thread enumerates its Gaussian's tiles (the row_span rule, as in the count)
-// into an LDS window of kEmitWin pairs, and the block writes the window out
-// with consecutive threads on consecutive addresses.
-constexpr int kEmitWin = 2048;
+// Inclusive sum of x over the block's threads; *total receives the block sum.
+__device__ __forceinline__ uint32_t block_scan_incl(uint32_t x, uint32_t *s_wsum, uint32_t *total)
+{
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+#pragma unroll
+    for (int off = 1; off < 64; off <<= 1) {
+        const uint32_t y = __shfl_up(x, off);
+        if (lane >= off) x += y;
+    }
+    if (lane == 63) s_wsum[w] = x;
+    __syncthreads();
+    uint32_t t = 0;
+    for (int k = 0; k < kWaves; ++k) {
+        if (k < w) x += s_wsum[k];
+        t += s_wsum[k];
+    }
+    *total = t;
+    __syncthreads();
+    return x;
+}
 
+// Emission of the (tile, Gaussian) pairs. Block b handles the depth-sorted
+// elements [256 b, 256 b + 256), whose outputs form one contiguous range from
+// offsets[256 b]. Splats differ widely in their number of tile rows and of
+// tiles, so the block lists the rows of its elements together: a block prefix
+// sum of the row counts concatenates them, and in rounds of 256 rows every
+// thread takes one row (a binary search in LDS finds its element), takes the
+// row's span (span code or the row_span rule, as in the count, without the
+// tiles already finished), and a block prefix sum of the rows' pair counts
+// gives each row its place in the output, where the thread writes its pairs.
 __global__ __launch_bounds__(kThreads) void k_emit(const uint32_t *__restrict__ skeys, const uint32_t *__restrict__ svals,
                                                    const uint32_t *__restrict__ offsets, const uint32_t *__restrict__ counts,
                                                    const float4 *__restrict__ rec, const short4 *__restrict__ rect,
@@ -468,95 +491,109 @@ __global__ __launch_bounds__(kThreads) void k_emit(const uint32_t *__restrict__ 
                                                    uint32_t *__restrict__ vals_out, unsigned long long *__restrict__ status,
                                                    int32_t gbits, const ulonglong2 *__restrict__ codes)
 {
-    __shared__ uint32_t s_t[kEmitWin];
-    __shared__ uint32_t s_g[kEmitWin];
-    __shared__ uint32_t s_lo, s_hi;
+    __shared__ Span32 s_span[kThreads];
+    __shared__ ulonglong2 s_code[kThreads];
+    __shared__ short4 s_rc[kThreads];
+    __shared__ uint4 s_vw[kThreads];        // tile base, tiles per row, width, height of the element's view
+    __shared__ uint32_t s_g[kThreads];
+    __shared__ uint32_t s_roff[kThreads + 1];
+    __shared__ uint32_t s_wsum[kWaves];
+    __shared__ uint32_t s_lo;
+    const int tid = threadIdx.x;
     const int64_t b0 = (int64_t)blockIdx.x * kThreads;
-    const int64_t last = min(total, b0 + kThreads) - 1;
-    const int64_t i = b0 + threadIdx.x;
+    const int64_t i = b0 + tid;
     const bool live = i < total && skeys[i] != 0xFFFFFFFFu;
-    const uint32_t off = i < total ? offsets[i] : 0u;
     const uint32_t cnt = live ? counts[i] : 0u;
-    if (threadIdx.x == 0) s_lo = offsets[b0];
-    if (i == last) s_hi = off + cnt;
-    __syncthreads();
-    const uint32_t lo = s_lo, hi = s_hi;
+    if (tid == 0) s_lo = offsets[b0];
 
-    uint32_t g = 0, tbase = 0, tiles_x = 0;
-    short4 rc = make_short4(0, 0, -1, -1);
-    Span32 sp = make_span32(0.f, 0.f, 1.f, 0.f, 1.f, true, 1.0f);
-    SpanCode code = no_code();
-    int W = 0, H = 0;
+    uint32_t rows = 0;
     if (cnt > 0) {
         const int vw = find_view_of_elem(views, n_views, i);
-        g = svals[i];
+        const uint32_t g = svals[i];
         const ViewDev &C = views[vw];
         const int64_t idx = (int64_t)C.elem_off + g;
-        rc = rect[idx];
-        code = load_code(codes, idx);
+        const short4 rc = rect[idx];
+        const SpanCode code = load_code(codes, idx);
+        Span32 sp = make_span32(0.f, 0.f, 1.f, 0.f, 1.f, true, 1.0f);
         if (!has_code(code)) {
             const float4 r0 = rec[2 * idx];
             const float4 r1 = rec[2 * idx + 1];
             // rec's mark: non-zero for splats that list their whole rectangle
             sp = make_span32(r0.x, r0.y, r0.z, r0.w, r1.x, r1.w != 0.0f, support_limit(sigma_k));
         }
-        tbase = C.tile_base;
-        tiles_x = (uint32_t)C.tiles_x;
-        W = C.W;
-        H = C.H;
+        s_span[tid] = sp;
+        s_code[tid] = make_ulonglong2(code.lo, code.hi);
+        s_rc[tid] = rc;
+        s_vw[tid] = make_uint4(C.tile_base, (uint32_t)C.tiles_x, (uint32_t)C.W, (uint32_t)C.H);
+        s_g[tid] = g;
+        rows = (uint32_t)(rc.w - rc.y + 1);
     }
-    uint32_t dropped = 0;
-    for (uint32_t w0 = lo; w0 < hi; w0 += kEmitWin) {
-        const uint32_t wend = min(hi, w0 + (uint32_t)kEmitWin);
-        if (cnt > 0 && off < wend && off + cnt > w0) {
-            uint32_t p = off;
-            for (int ty = rc.y; ty <= rc.w && p < wend; ++ty) {
-                int l, r;
-                const bool any = has_code(code) ? code_span(code, ty - rc.y, rc.x, l, r)
-                                                : row_span(sp, ty, rc.x, rc.z, tw, th, W, H, l, r);
-                if (!any) continue;
-                const uint32_t rowbase = tbase + (uint32_t)ty * tiles_x;
-                const uint32_t outbase = gbits ? rowbase - tbase : rowbase;  // packed: the view's local tile
-                if (done == nullptr) {
-                    const uint32_t n_row = (uint32_t)(r - l + 1);
-                    if (p + n_row > w0) {
-                        const uint32_t a = p < w0 ? w0 - p : 0u;
-                        const uint32_t b = min(n_row, wend - p);
-                        for (uint32_t e = a; e < b; ++e) {
-                            s_t[p + e - w0] = outbase + (uint32_t)l + e;
-                            s_g[p + e - w0] = g;
-                        }
-                    }
-                    p += n_row;
-                } else {
-                    for (int t = l; t <= r && p < wend; ++t) {
-                        if (done[rowbase + (uint32_t)t]) continue;
-                        if (p >= w0) {
-                            s_t[p - w0] = outbase + (uint32_t)t;
-                            s_g[p - w0] = g;
-                        }
-                        ++p;
-                    }
-                }
+    uint32_t n_rows = 0;
+    const uint32_t incl = block_scan_incl(rows, s_wsum, &n_rows);
+    s_roff[tid + 1] = incl;
+    if (tid == 0) s_roff[0] = 0;
+    __syncthreads();
+    const uint32_t lo = s_lo;
+
+    uint32_t dropped = 0, carry = 0;
+    for (uint32_t c0 = 0; c0 < n_rows; c0 += kThreads) {
+        const uint32_t item = c0 + (uint32_t)tid;
+        int e = 0, l = 0, r = -1;
+        uint32_t n = 0;
+        if (item < n_rows) {
+            // the element e with s_roff[e] <= item < s_roff[e + 1]
+            int a = 0, b = kThreads - 1;
+            while (a < b) {
+                const int mid = (a + b + 1) >> 1;
+                if (s_roff[mid] <= item) a = mid; else b = mid - 1;
             }
-        }
-        __syncthreads();
-        for (uint32_t q = threadIdx.x; q < wend - w0; q += kThreads) {
-            const uint32_t p = w0 + q;
-            if (p < capacity) {
-                if (gbits) {
-                    tiles_out[p] = (s_t[q] << gbits) | s_g[q];
+            e = a;
+            const short4 rc = s_rc[e];
+            const int row = (int)(item - s_roff[e]);
+            const ulonglong2 cw = s_code[e];
+            const SpanCode code{cw.x, cw.y};
+            const uint4 vw = s_vw[e];
+            const bool any = has_code(code) ? code_span(code, row, rc.x, l, r)
+                                            : row_span(s_span[e], rc.y + row, rc.x, rc.z, tw, th, (int)vw.z, (int)vw.w, l, r);
+            if (any) {
+                if (done == nullptr) {
+                    n = (uint32_t)(r - l + 1);
                 } else {
-                    tiles_out[p] = s_t[q];
-                    vals_out[p] = s_g[q];
+                    const uint8_t *d = done + vw.x + (uint32_t)(rc.y + row) * vw.y;
+                    for (int t = l; t <= r; ++t) n += d[t] ? 0u : 1u;
                 }
             } else {
-                dropped++;
+                r = l - 1;
             }
         }
-        __syncthreads();
+        uint32_t round_total = 0;
+        const uint32_t ex = block_scan_incl(n, s_wsum, &round_total) - n;
+        if (n > 0) {
+            const short4 rc = s_rc[e];
+            const uint4 vw = s_vw[e];
+            const uint32_t g = s_g[e];
+            const uint32_t ty = (uint32_t)(rc.y + (int)(item - s_roff[e]));
+            const uint32_t rowbase = vw.x + ty * vw.y;
+            const uint32_t outbase = gbits ? rowbase - vw.x : rowbase;  // packed: the view's local tile
+            uint32_t p = lo + carry + ex;
+            for (int t = l; t <= r; ++t) {
+                if (done != nullptr && done[rowbase + (uint32_t)t]) continue;
+                if (p < capacity) {
+                    if (gbits) {
+                        tiles_out[p] = ((outbase + (uint32_t)t) << gbits) | g;
+                    } else {
+                        tiles_out[p] = outbase + (uint32_t)t;
+                        vals_out[p] = g;
+                    }
+                } else {
+                    dropped++;
+                }
+                ++p;
+            }
+        }
+        carry += round_total;
     }
-    if (threadIdx.x == 0 && hi > lo) status_add(status, ST_PAIRS, (unsigned long long)(hi - lo));
+    if (tid == 0 && carry > 0) status_add(status, ST_PAIRS, (unsigned long long)carry);
     if (__ballot(dropped != 0) && dropped) {
         status_add(status, ST_DROPPED, (unsigned long long)dropped);
         status_flag(status, (unsigned long long)FS_DEV_PAIR_OVERFLOW);
