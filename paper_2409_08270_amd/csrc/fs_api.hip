@@ -300,6 +300,12 @@ ViewDev make_view(const fs_camera &c, const fs_params *p, uint32_t scene, int64_
     d.pix_off = pix_off;
     d.n = (uint32_t)n;
     d.pad = 0;
+    {
+        // binary32, in the projection's operation order (the same value for every element)
+#pragma clang fp contract(off)
+        d.limx = p->guard * ((0.5f * (float)c.width) / c.fx);
+        d.limy = p->guard * ((0.5f * (float)c.height) / c.fy);
+    }
     return d;
 }
 

@@ -33,6 +33,7 @@ struct ViewDev {
     uint64_t pix_off;     // first pixel of this view in the call's per-pixel state buffer
     uint32_t n;           // Gaussians in the scene (= plane length)
     uint32_t pad;
+    float limx, limy;     // guard-band limits of x/z, y/z: guard * ((0.5 W) / fx), likewise for y
 };
 
 struct SceneDev {

@@ -132,10 +132,8 @@ __global__ __launch_bounds__(256) void k_project(const ProjTask *__restrict__ ta
 #pragma unroll
                     for (int j = 0; j < 3; ++j)
                         Vm[i * 3 + j] = (R[i * 3 + 0] * L[0 * 3 + j] + R[i * 3 + 1] * L[1 * 3 + j]) + R[i * 3 + 2] * L[2 * 3 + j];
-                const float Wf = (float)C.W, Hf = (float)C.H;
                 float xr = px / pz, yr = py / pz;
-                float limx = P.guard * ((0.5f * Wf) / C.fx);
-                float limy = P.guard * ((0.5f * Hf) / C.fy);
+                const float limx = C.limx, limy = C.limy;  // guard * ((0.5 W) / fx), per view
                 float txc = fminf(fmaxf(xr, -limx), limx);
                 float tyc = fminf(fmaxf(yr, -limy), limy);
                 float j00 = C.fx / pz, j02 = -((C.fx * txc) / pz);
