@@ -49,6 +49,7 @@ def parse():
     ap.add_argument("--cpu-views", type=int, default=16, help="views of the CPU oracle sample (0: skip)")
     ap.add_argument("--no-plain", action="store_true", help="skip the per-view comparators")
     ap.add_argument("--no-precision", action="store_true", help="skip the per-variant error report")
+    ap.add_argument("--no-det", action="store_true", help="skip timing the bit-reproducible reduction")
     ap.add_argument("--lanes", type=int, default=0, help="batch lanes (0: the tuned or the library's default)")
     ap.add_argument("--tuned", default=None, help="tuning table (default: the package's tuned.json)")
     ap.add_argument("--no-tuned", action="store_true", help="run the library's default settings")
@@ -270,6 +271,27 @@ def main():
                  "assign_all_scenes_in_graph": True}
     log(f"follow-ups: {followups}")
 
+    # ---- the same batch with the bit-reproducible reduction (fixed-point sums), for its cost
+    det = None
+    if not args.no_det:
+        batch_S = [x.cpu().numpy() for x in batch.S]
+        batch.close()
+        opt_det = dict(opt_kw, reduction=L.FS_RED_DET)
+        bd = L.Batch(ctx, dss, prm, gammas=gam, **opt_det)
+        bd.run()
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        for _ in range(args.steps):
+            bd.run()
+        torch.cuda.synchronize()
+        dt_d = (time.perf_counter() - t) / args.steps
+        ctx.status()
+        det = {"views_per_sec": V / dt_d, "ms_per_step": dt_d * 1e3, "settings": opt_det,
+               "labels_differ_from_timed": int(sum((b.cpu().numpy() != a).sum() for a, b in zip(batch_S, bd.S)))}
+        bd.close()
+        del bd
+        log(f"bit-reproducible reduction: {det}")
+
     # ---- roofline of the compositing kernel --------------------------------------------------------
     # algorithmic fp32 flops: 15 per blend (offset, quadratic form, opacity, clamp, alpha test, weight,
     # transmittance update, stop test, accumulate) + 1 exp per in-support evaluation
@@ -340,7 +362,7 @@ def main():
         log(f"cpu oracle: {cpu}")
         # the GPU on the same views, per reduction variant
         variants = {"fp32_global_atomics": (L.FS_RED_PLAIN, False), "fp32_lds": (L.FS_RED_LDS, False),
-                    "lds_two_sum": (L.FS_RED_LDS2SUM, True)}
+                    "lds_two_sum": (L.FS_RED_LDS2SUM, True), "fixed_point_det": (L.FS_RED_DET, True)}
         if args.no_precision:
             variants = {"lds_two_sum": variants["lds_two_sum"]}
         precision = {k_: {"rows": 0} for k_ in variants}
@@ -405,7 +427,7 @@ def main():
         "dtype": "f32",
         "data": "synthetic",
         "config": {"workload": workload, "mode": "batched, one hipGraph per step",
-                   "reduction": {L.FS_RED_LDS: "lds", L.FS_RED_LDS2SUM: "lds+two-sum"}.get(
+                   "reduction": {L.FS_RED_LDS: "lds", L.FS_RED_LDS2SUM: "lds+two-sum", L.FS_RED_DET: "det"}.get(
                        opt_kw.get("reduction", L.FS_RED_LDS2SUM), "lds+two-sum"),
                    "chunks": n_chunks, "lanes": opt_kw.get("lanes", 2),
                    "tile": f"{prm.tile_w}x{prm.tile_h}", "tile_order": int(prm.tile_order),
@@ -422,6 +444,7 @@ def main():
         "per_view_lds_views_per_sec": (V / dt_pl) if dt_pl else None,
         "batched_over_per_view_lds": (dt_pl / dt_b) if dt_pl else None,
         "followups": followups,
+        "bit_reproducible_reduction": det,
         "roofline": roof,
         "path_roofline": path,
         "cpu_baseline": cpu,

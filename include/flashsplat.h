@@ -65,6 +65,9 @@ extern "C" {
 #define FS_RED_PLAIN 1  /* one global atomic per contributing (pixel, Gaussian) */
 #define FS_RED_LDS 2    /* per-tile pre-reduction over the tile's pixels, one atomic per (tile, Gaussian, label) */
 #define FS_RED_LDS2SUM 3 /* as FS_RED_LDS, plus the rounding error of each atomic (exact two-sum) into A_lo */
+#define FS_RED_DET 4     /* bit-reproducible: as FS_RED_LDS, with every label summed across the wave and each
+                            partial rounded to a 64-bit fixed-point integer (units of 2^-34) and added exactly;
+                            the call's totals then go into A_hi (and A_lo) once per entry */
 
 typedef struct fs_ctx fs_ctx;
 
@@ -239,6 +242,14 @@ int fs_bin_sort(fs_ctx *ctx, const fs_proj *proj, const fs_camera *cams, const f
  * A_hi, and the partial sums of labels that no 8x8 pixel block of a tile holds
  * in 4 or more pixels (stray, noise-like labels), which are small; the
  * accumulated result is A_hi + A_lo.
+ * FS_RED_DET: the call's weights are summed exactly as 64-bit fixed-point
+ * integers in units of 2^-34 (each wave's float sum per (Gaussian, label) is
+ * rounded once to that grid, about 3e-11), in a context workspace of
+ * n * n_classes * 8 bytes; the totals are then added into A_hi (with A_lo:
+ * by an exact two-sum, the error into A_lo) once per entry. A_hi and A_lo
+ * come out bit-identical on every run and for every tile_order and
+ * persistent setting. Such a call covers at most 2^29 pixels in total
+ * (FS_ERR_ARG beyond).
  * n_classes in [2, 256]. pix: optional per-pixel outputs, or NULL. */
 int fs_accumulate(fs_ctx *ctx, const fs_proj *proj, const fs_bins *bins, const fs_camera *cams,
                   const uint8_t *masks, int32_t n_classes, const fs_params *p,
@@ -254,6 +265,7 @@ int fs_accumulate(fs_ctx *ctx, const fs_proj *proj, const fs_bins *bins, const f
  * tables go through pinned memory that fs_ctx_create reserves.
  * Limits: at most FS_NOALLOC_MAX_VIEWS views and FS_NOALLOC_MAX_TILES tiles
  * per call; larger calls return FS_ERR_CAPACITY before any work is enqueued.
+ * FS_RED_DET, whose workspace grows with n, returns FS_ERR_ARG here.
  * All calls on one GPU share the array: calls that overlap in time on that
  * GPU (other contexts, other streams) race and must be serialised by the
  * caller. A call may wait on the host for the table copy of the context's
@@ -409,7 +421,11 @@ typedef struct {
     int64_t elem_budget;       /* max (Gaussian, view) elements per chunk (0: 2^26) */
     int32_t zero_accumulators; /* 1: each run starts from A = 0 (default 1) */
     int32_t use_graph;         /* 1 (default): capture into a hipGraph; 0: enqueue the kernels per run */
-    int32_t reduction;         /* FS_RED_* for the compositing (default FS_RED_AUTO) */
+    int32_t reduction;         /* FS_RED_* for the compositing (default FS_RED_AUTO); FS_RED_DET keeps
+                                  n * n_classes 64-bit totals per scene in the batch workspace, adds
+                                  them into A after every view of the run (the same bits for any
+                                  lanes, chunking, depth_slabs or tile_order) and takes at most 2^29
+                                  pixels per scene */
     int32_t depth_slabs;       /* 1..4: the Gaussians of each view are binned and composited in this
                                   many depth slabs, front to back, and tiles whose pixels have all
                                   finished get no pairs from later slabs; 0 (default): 1, one pass

@@ -33,6 +33,7 @@ FS_RED_AUTO = 0
 FS_RED_PLAIN = 1
 FS_RED_LDS = 2
 FS_RED_LDS2SUM = 3
+FS_RED_DET = 4
 
 FS_NOALLOC_MAX_VIEWS = 4096
 FS_NOALLOC_MAX_TILES = 1048576

@@ -20,6 +20,14 @@
 // A_hi + A_lo carries the sum to about one rounding; the partials of labels
 // that only appear as stray pixels in a tile (relabel noise) are small and go
 // to A_lo directly, without waiting for a returned value.
+//
+// Bit-reproducible sums (FS_RED_DET). Atomic float additions round in whatever
+// order they arrive. In this mode every label of a wave is summed by the
+// reduce-scatter (a fixed butterfly, so the same bits on every run), each such
+// sum is rounded once to a 64-bit fixed-point integer, and from there on all
+// additions (the tile's LDS partials, the global totals) are integer additions,
+// which are exact and so independent of their order. The call's totals are
+// then added into A_hi (and A_lo) once per entry.
 #include <algorithm>
 
 #include "fs_internal.h"
@@ -85,6 +93,13 @@ __device__ __forceinline__ float reduce_scatter8(const float (&x)[8])
     return t;
 }
 
+// x in units of 2^-kFixShift, rounded to nearest (|x| < 2^29)
+__device__ __forceinline__ unsigned long long to_fix(float x)
+{
+    return (unsigned long long)(long long)__builtin_rintf(x * 0x1p34f);
+}
+static_assert(kFixShift == 34, "to_fix scales by 2^34");
+
 __device__ __forceinline__ void add_global(float *hi, float *lo, int64_t idx, float x)
 {
     if (lo == nullptr) {
@@ -130,7 +145,7 @@ __device__ __forceinline__ bool block_hit(float u, float v, float p, float r, fl
 }
 
 // Composites one tile (the whole workgroup); every thread calls it with the same tile.
-template <bool PIX, bool COUNT>
+template <bool PIX, bool COUNT, bool DET>
 __device__ __forceinline__ void accum_tile(const uint32_t tile, const float4 *__restrict__ rec,
                                            const uint32_t *__restrict__ vals, const uint2 *__restrict__ ranges,
                                            const ViewDev *__restrict__ views, int32_t n_views,
@@ -145,7 +160,9 @@ __device__ __forceinline__ void accum_tile(const uint32_t tile, const float4 *__
     // is the support test and the alpha_min test in one comparison; entry kBatch is a null record
     __shared__ float4 s_rec[2 * (kBatch + 1)];
     __shared__ uint32_t s_g[kBatch];
-    __shared__ float s_part[kPart];        // [entry][stride]: partial sums per staged entry and slot
+    __shared__ __align__(8) float s_part[kPart];  // [entry][stride]: partial sums per staged entry and slot
+    // FS_RED_DET: the same memory as [entry][stride] 64-bit fixed-point partials
+    unsigned long long *const s_part64 = reinterpret_cast<unsigned long long *>(s_part);
     __shared__ uint8_t s_wmask[kBatch];    // bit w: wave w's 8x8 block can be reached
     __shared__ __align__(16) uint32_t s_list[4][kBatch + 16];  // per-wave compacted entries (byte offsets
                                                                // into s_rec), padded with the null record
@@ -164,6 +181,8 @@ __device__ __forceinline__ void accum_tile(const uint32_t tile, const float4 *__
     const uint8_t *__restrict__ masks = SC.masks;
     float *__restrict__ A_hi = SC.A_hi;
     float *__restrict__ A_lo = P.reduction == FS_RED_LDS2SUM ? SC.A_lo : nullptr;
+    constexpr bool det = DET;  // P.reduction == FS_RED_DET
+    unsigned long long *__restrict__ A_fix = SC.A_fix;
     const int E = SC.E;
     const uint32_t local = tile - C.tile_base;
     const int tx = (int)(local % (uint32_t)C.tiles_x), ty = (int)(local / (uint32_t)C.tiles_x);
@@ -205,7 +224,8 @@ __device__ __forceinline__ void accum_tile(const uint32_t tile, const float4 *__
     // partial layout: `stride` slots per staged entry, `bsz` entries per batch
     const int sh = nslot <= 8 ? 3 : (nslot <= 16 ? 4 : (nslot <= 32 ? 5 : 6));
     const int stride = 1 << sh;
-    const uint32_t bsz = min(plain ? (uint32_t)kBatch : (uint32_t)(kPart >> sh), (uint32_t)P.batch);
+    // (fixed-point partials take two words: half as many entries)
+    const uint32_t bsz = min(plain ? (uint32_t)kBatch : (uint32_t)(kPart >> (det ? sh + 1 : sh)), (uint32_t)P.batch);
     if (active && !plain) {
         s_slot_label[slot] = lab;
         atomicOr(&s_wslots[w], 1ull << slot);
@@ -219,7 +239,7 @@ __device__ __forceinline__ void accum_tile(const uint32_t tile, const float4 *__
         while (sl) {
             const int sidx = __ffsll((long long)sl) - 1;
             sl &= sl - 1ull;
-            if (__popcll(__ballot(active && slot == sidx)) >= kMajor) wmajor |= 1ull << sidx;
+            if (__popcll(__ballot(active && slot == sidx)) >= (det ? 1 : kMajor)) wmajor |= 1ull << sidx;
         }
     }
     if (lane == 0 && wmajor) atomicOr(&s_tmajor, wmajor);
@@ -368,6 +388,11 @@ __device__ __forceinline__ void accum_tile(const uint32_t tile, const float4 *__
         auto rec_at = [&](uint32_t off) -> const float4 * {
             return reinterpret_cast<const float4 *>(reinterpret_cast<const char *>(s_rec) + off);
         };
+        // a wave's sum for (staged entry, slot) cell into the tile's partials
+        auto part_add = [&](uint32_t cell, float tot) {
+            if (det) atomicAdd(&s_part64[cell], to_fix(tot));
+            else atomicAdd(&s_part[cell], tot);
+        };
 
         if (__ballot(live) != 0ull) {
             if (!plain) {
@@ -399,7 +424,7 @@ __device__ __forceinline__ void accum_tile(const uint32_t tile, const float4 *__
                     const bool head = (lane & 7) == 0 && g0 + e < nlist;
                     if (one) {
                         const float tot = reduce_scatter8(wr);
-                        if (head && tot != 0.0f) atomicAdd(&s_part[((s_list[w][g0 + e] >> 5) << sh) + slot0], tot);
+                        if (head && tot != 0.0f) part_add(((s_list[w][g0 + e] >> 5) << sh) + slot0, tot);
                     } else {
                         if (wminor) {
                             if (mstage) {
@@ -434,7 +459,7 @@ __device__ __forceinline__ void accum_tile(const uint32_t tile, const float4 *__
 #pragma unroll
                             for (int k = 0; k < 8; ++k) v[k] = slot == sidx ? wr[k] : 0.0f;
                             const float tot = reduce_scatter8(v);
-                            if (head && tot != 0.0f) atomicAdd(&s_part[((s_list[w][g0 + e] >> 5) << sh) + sidx], tot);
+                            if (head && tot != 0.0f) part_add(((s_list[w][g0 + e] >> 5) << sh) + sidx, tot);
                         }
                     }
                     if (__ballot(live) == 0ull) break;
@@ -446,7 +471,10 @@ __device__ __forceinline__ void accum_tile(const uint32_t tile, const float4 *__
                     const uint32_t off = s_list[w][it];
                     const uint32_t j = off >> 5;
                     const float wgt = step(rec_at(off)[0], rec_at(off)[1]);
-                    if (wgt != 0.0f) add_global(A_hi, A_lo, (int64_t)s_g[j] * E + lab, wgt);
+                    if (wgt != 0.0f) {
+                        if (det) atomicAdd(A_fix + (int64_t)s_g[j] * E + lab, to_fix(wgt));
+                        else add_global(A_hi, A_lo, (int64_t)s_g[j] * E + lab, wgt);
+                    }
                     if ((it & 15) == 15 && __ballot(live) == 0ull) break;
                 }
             }
@@ -461,7 +489,17 @@ __device__ __forceinline__ void accum_tile(const uint32_t tile, const float4 *__
                 if (A_lo != nullptr && !((tmajor >> sidx) & 1ull)) unsafeAtomicAdd(A_lo + idx, vpart);
                 else add_global(A_hi, A_lo, idx, vpart);
             };
-            if (sh == 3) {
+            if (det) {
+                // fixed-point cells: exact integer additions into the call's totals
+                for (uint32_t i = (uint32_t)tid; i < (cnt << sh); i += 256u) {
+                    const int sidx = (int)(i & (uint32_t)(stride - 1));
+                    const unsigned long long vpart = s_part64[i];
+                    if (sidx < nslot && vpart != 0ull) {
+                        atomicAdd(A_fix + (int64_t)s_g[i >> sh] * E + s_slot_label[sidx], vpart);
+                        s_part64[i] = 0ull;
+                    }
+                }
+            } else if (sh == 3) {
                 if ((uint32_t)tid < cnt) {
                     const uint32_t g = s_g[tid];
                     for (int sidx = 0; sidx < nslot; ++sidx) {
@@ -521,7 +559,7 @@ __device__ __forceinline__ void accum_tile(const uint32_t tile, const float4 *__
 
 // One workgroup per work item (tile), or (PERSIST) resident workgroups that
 // take the next item from the device counter `queue` until none is left.
-template <bool PIX, bool COUNT, bool PERSIST>
+template <bool PIX, bool COUNT, bool PERSIST, bool DET>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(7, 7))) void k_accum(
     const float4 *__restrict__ rec, const uint32_t *__restrict__ vals, const uint2 *__restrict__ ranges,
     const ViewDev *__restrict__ views, int32_t n_views, const SceneDev *__restrict__ scenes,
@@ -530,7 +568,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(7, 7))) voi
     unsigned long long *__restrict__ status, uint32_t *__restrict__ queue)
 {
     if (!PERSIST) {
-        accum_tile<PIX, COUNT>(items ? items[blockIdx.x] : blockIdx.x, rec, vals, ranges, views, n_views, scenes, P,
+        accum_tile<PIX, COUNT, DET>(items ? items[blockIdx.x] : blockIdx.x, rec, vals, ranges, views, n_views, scenes, P,
                                t_final, n_blend, tstate, tile_done, first, status);
         return;
     }
@@ -553,10 +591,36 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(7, 7))) voi
         const uint32_t it = __builtin_amdgcn_readfirstlane(s_next);
         __syncthreads();
         if (it >= n_items) break;
-        accum_tile<PIX, COUNT>(items ? items[it] : it, rec, vals, ranges, views, n_views, scenes, P, t_final,
+        accum_tile<PIX, COUNT, DET>(items ? items[it] : it, rec, vals, ranges, views, n_views, scenes, P, t_final,
                                n_blend, tstate, tile_done, first, status);
     }
 }
+
+// FS_RED_DET: the call's fixed-point totals into A_hi (+ A_lo), one thread per entry
+__global__ __launch_bounds__(256) void k_fix_finish(const unsigned long long *__restrict__ fix, float *__restrict__ A_hi,
+                                                    float *__restrict__ A_lo, int64_t count)
+{
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= count) return;
+    const long long q = (long long)fix[i];
+    if (q == 0) return;
+    const double v = (double)q * 0x1p-34;
+    if (A_lo == nullptr) {
+        A_hi[i] = (float)((double)A_hi[i] + v);
+        return;
+    }
+    // v = vh + vl to about 2^-48 relative; A_hi + vh by an exact two-sum, the
+    // error and vl into A_lo
+    const float vh = (float)v;
+    const float vl = (float)(v - (double)vh);
+    const float a = A_hi[i];
+    const float sum = a + vh;
+    const float bp = sum - a;
+    const float err = (a - (sum - bp)) + (vh - bp);
+    A_hi[i] = sum;
+    A_lo[i] = A_lo[i] + (err + vl);
+}
+static_assert(kFixShift == 34, "k_fix_finish scales by 2^-34");
 
 // resident workgroups of a compositing kernel on this device (cached per kernel)
 template <class K>
@@ -574,7 +638,38 @@ uint32_t resident_blocks(K kern)
     return (uint32_t)cached;
 }
 
+// one compositing launch: a grid of one workgroup per item, or (p.persistent)
+// the resident workgroups pulling items from `queue`
+template <bool PIX, bool COUNT, bool DET>
+hipError_t launch_k(hipStream_t s, const AccParams &p, uint32_t *queue, uint32_t n_items, const float *rec,
+                    const uint32_t *vals, const uint32_t *ranges, const ViewDev *views, int32_t n_views,
+                    const SceneDev *scenes, const uint32_t *items, float *t_final, int32_t *n_blend, float *tstate,
+                    uint8_t *tile_done, int32_t first, unsigned long long *status)
+{
+    const float4 *r4 = reinterpret_cast<const float4 *>(rec);
+    const uint2 *rg = reinterpret_cast<const uint2 *>(ranges);
+    if (p.persistent) {
+        if (!queue) return hipErrorInvalidValue;
+        const uint32_t grid = std::min(n_items, resident_blocks(k_accum<PIX, COUNT, true, DET>));
+        hipError_t e = launch_fill_u32(s, queue, 0u, 1);
+        if (e != hipSuccess) return e;
+        hipLaunchKernelGGL((k_accum<PIX, COUNT, true, DET>), dim3(grid), dim3(256), 0, s, r4, vals, rg, views, n_views,
+                           scenes, items, n_items, p, t_final, n_blend, tstate, tile_done, first, status, queue);
+        return hipGetLastError();
+    }
+    hipLaunchKernelGGL((k_accum<PIX, COUNT, false, DET>), dim3(n_items), dim3(256), 0, s, r4, vals, rg, views, n_views,
+                       scenes, items, n_items, p, t_final, n_blend, tstate, tile_done, first, status, queue);
+    return hipGetLastError();
+}
+
 }  // namespace
+
+hipError_t launch_fix_finish(hipStream_t s, const unsigned long long *fix, float *A_hi, float *A_lo, int64_t count)
+{
+    if (count <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_fix_finish, dim3((unsigned)((count + 255) / 256)), dim3(256), 0, s, fix, A_hi, A_lo, count);
+    return hipGetLastError();
+}
 
 hipError_t launch_accumulate(hipStream_t s, const float *rec, const uint32_t *vals, const uint32_t *ranges,
                              const ViewDev *views, int32_t n_views, const SceneDev *scenes, const uint32_t *items,
@@ -585,27 +680,28 @@ hipError_t launch_accumulate(hipStream_t s, const float *rec, const uint32_t *va
     if (n_items == 0) return hipSuccess;
     const bool pix = t_final || n_blend;
     const bool count = p.count || n_blend;  // per-pixel blend counts need the counters
-    const float4 *r4 = reinterpret_cast<const float4 *>(rec);
-    const uint2 *rg = reinterpret_cast<const uint2 *>(ranges);
-    if (p.persistent) {
-        if (!queue) return hipErrorInvalidValue;
-        auto kern = pix ? (count ? k_accum<true, true, true> : k_accum<true, false, true>)
-                        : (count ? k_accum<false, true, true> : k_accum<false, false, true>);
-        const uint32_t grid = std::min(n_items, pix ? (count ? resident_blocks(k_accum<true, true, true>)
-                                                             : resident_blocks(k_accum<true, false, true>))
-                                                    : (count ? resident_blocks(k_accum<false, true, true>)
-                                                             : resident_blocks(k_accum<false, false, true>)));
-        hipError_t e = launch_fill_u32(s, queue, 0u, 1);
-        if (e != hipSuccess) return e;
-        hipLaunchKernelGGL(kern, dim3(grid), dim3(256), 0, s, r4, vals, rg, views, n_views, scenes, items, n_items,
-                           p, t_final, n_blend, tstate, tile_done, first, status, queue);
-        return hipGetLastError();
-    }
-    auto kern = pix ? (count ? k_accum<true, true, false> : k_accum<true, false, false>)
-                    : (count ? k_accum<false, true, false> : k_accum<false, false, false>);
-    hipLaunchKernelGGL(kern, dim3(n_items), dim3(256), 0, s, r4, vals, rg, views, n_views, scenes, items, n_items, p,
-                       t_final, n_blend, tstate, tile_done, first, status, queue);
-    return hipGetLastError();
+    if (p.reduction == FS_RED_DET)
+        return pix ? (count ? launch_k<true, true, true>(s, p, queue, n_items, rec, vals, ranges, views, n_views,
+                                                         scenes, items, t_final, n_blend, tstate, tile_done, first,
+                                                         status)
+                            : launch_k<true, false, true>(s, p, queue, n_items, rec, vals, ranges, views, n_views,
+                                                          scenes, items, t_final, n_blend, tstate, tile_done, first,
+                                                          status))
+                   : (count ? launch_k<false, true, true>(s, p, queue, n_items, rec, vals, ranges, views, n_views,
+                                                          scenes, items, t_final, n_blend, tstate, tile_done, first,
+                                                          status)
+                            : launch_k<false, false, true>(s, p, queue, n_items, rec, vals, ranges, views, n_views,
+                                                           scenes, items, t_final, n_blend, tstate, tile_done, first,
+                                                           status));
+    return pix ? (count ? launch_k<true, true, false>(s, p, queue, n_items, rec, vals, ranges, views, n_views, scenes,
+                                                      items, t_final, n_blend, tstate, tile_done, first, status)
+                        : launch_k<true, false, false>(s, p, queue, n_items, rec, vals, ranges, views, n_views, scenes,
+                                                       items, t_final, n_blend, tstate, tile_done, first, status))
+               : (count ? launch_k<false, true, false>(s, p, queue, n_items, rec, vals, ranges, views, n_views, scenes,
+                                                       items, t_final, n_blend, tstate, tile_done, first, status)
+                        : launch_k<false, false, false>(s, p, queue, n_items, rec, vals, ranges, views, n_views,
+                                                        scenes, items, t_final, n_blend, tstate, tile_done, first,
+                                                        status));
 }
 
 }  // namespace fs

@@ -53,6 +53,7 @@ struct fs_ctx {
     DevBuf dkeys, dvals, dkeys2, dvals2, counts, offsets;
     DevBuf pk_alt, pv_alt, sort_ws, scan_ws;
     DevBuf items, items_k, items_k2, items_v2, items_ws;
+    DevBuf fix;                // FS_RED_DET: the call's fixed-point totals
     uint64_t items_tiles = 0;  // tile count the XCD-run table in `items` was built for
     Staging stage[kStaging];
     int stage_next = 0;
@@ -352,6 +353,7 @@ SceneDev scene_dev(const fs_gaussians *g, int64_t n, const uint8_t *masks, float
     s.masks = masks;
     s.A_hi = A_hi;
     s.A_lo = A_lo;
+    s.A_fix = nullptr;
     s.n = (uint32_t)n;
     s.E = E;
     return s;
@@ -448,6 +450,9 @@ __global__ void k_xcd_items(uint32_t *items, uint32_t n_tiles)
     items[b] = x * base + min(x, rem) + b / kXcds;
 }
 
+// FS_RED_DET: pixels per call (per scene in a batch); see to_fix's range
+constexpr uint64_t kFixMaxPixels = (uint64_t)1 << 29;
+
 // Arguments of fs_accumulate and fs_accumulate_noalloc; resolves FS_RED_AUTO.
 int check_accumulate(fs_ctx *ctx, const fs_proj *proj, const fs_bins *bins, const fs_camera *cams,
                      const uint8_t *masks, int32_t n_classes, const fs_params *p, const float *A_hi,
@@ -459,10 +464,18 @@ int check_accumulate(fs_ctx *ctx, const fs_proj *proj, const fs_bins *bins, cons
     RCHECK(check_cams(ctx, cams, proj->n_views));
     if (n_classes < 2 || n_classes > 256) return set_err(ctx, FS_ERR_ARG, "n_classes %d not in [2, 256]", n_classes);
     int32_t r = *reduction;
-    if (r < FS_RED_AUTO || r > FS_RED_LDS2SUM) return set_err(ctx, FS_ERR_ARG, "unknown reduction %d", r);
+    if (r < FS_RED_AUTO || r > FS_RED_DET) return set_err(ctx, FS_ERR_ARG, "unknown reduction %d", r);
     if (r == FS_RED_AUTO) r = A_lo ? FS_RED_LDS2SUM : FS_RED_LDS;
     if (r == FS_RED_LDS2SUM && !A_lo) return set_err(ctx, FS_ERR_ARG, "FS_RED_LDS2SUM needs A_lo");
     if (proj->n > 0 && proj->n_views > 0 && (!masks || !A_hi)) return set_err(ctx, FS_ERR_ARG, "masks or A_hi is NULL");
+    if (r == FS_RED_DET) {
+        // every pixel adds at most 1 in total, so the fixed-point totals stay below 2^29 * 2^34
+        uint64_t px = 0;
+        for (int v = 0; v < proj->n_views; ++v) px += (uint64_t)cams[v].width * (uint64_t)cams[v].height;
+        if (px > kFixMaxPixels)
+            return set_err(ctx, FS_ERR_ARG, "FS_RED_DET: %llu pixels in one call, at most %llu",
+                           (unsigned long long)px, (unsigned long long)kFixMaxPixels);
+    }
     *reduction = r;
     return FS_OK;
 }
@@ -564,7 +577,7 @@ int fs_ctx_destroy(fs_ctx *ctx)
     DevBuf *bufs[] = {&ctx->views, &ctx->scenes, &ctx->tasks, &ctx->dsegs, &ctx->psegs, &ctx->lsegs,
                       &ctx->dkeys, &ctx->dvals, &ctx->dkeys2, &ctx->dvals2, &ctx->counts, &ctx->offsets,
                       &ctx->pk_alt, &ctx->pv_alt, &ctx->sort_ws, &ctx->scan_ws, &ctx->items, &ctx->items_k,
-                      &ctx->items_k2, &ctx->items_v2, &ctx->items_ws};
+                      &ctx->items_k2, &ctx->items_v2, &ctx->items_ws, &ctx->fix};
     for (DevBuf *b : bufs) free_buf(*b);
     for (int i = 0; i < kStaging; ++i) {
         if (ctx->stage[i].host) (void)hipHostFree(ctx->stage[i].host);
@@ -737,6 +750,12 @@ int fs_accumulate(fs_ctx *ctx, const fs_proj *proj, const fs_bins *bins, const f
     Plan pl;
     plan_add(pl, p, 0, proj->n, cams, 0, V, 0);
     std::vector<SceneDev> sc{scene_dev(nullptr, proj->n, masks, A_hi, A_lo, n_classes)};
+    const int64_t n_fix = proj->n * (int64_t)n_classes;
+    if (reduction == FS_RED_DET) {
+        RCHECK(ensure(ctx, ctx->fix, (size_t)n_fix * 8));
+        HIPCHECK(ctx, launch_fill_u32(ctx->stream, (uint32_t *)ctx->fix.p, 0u, 2 * n_fix));
+        sc[0].A_fix = (unsigned long long *)ctx->fix.p;
+    }
     RCHECK(upload_vec(ctx, ctx->views, pl.views));
     RCHECK(upload_vec(ctx, ctx->scenes, sc));
     const uint32_t *items = nullptr;
@@ -770,6 +789,8 @@ int fs_accumulate(fs_ctx *ctx, const fs_proj *proj, const fs_bins *bins, const f
                                     ctx->status_dev, ctx->npairs_dev + kQueueWord));
     if (timed) HIPCHECK(ctx, hipEventRecord(ctx->acc_ev[1], ctx->stream));
     ctx->acc_timed = timed;
+    if (reduction == FS_RED_DET)
+        HIPCHECK(ctx, launch_fix_finish(ctx->stream, (const unsigned long long *)ctx->fix.p, A_hi, A_lo, n_fix));
     return FS_OK;
 }
 
@@ -779,6 +800,8 @@ int fs_accumulate_noalloc(fs_ctx *ctx, const fs_proj *proj, const fs_bins *bins,
 {
     if (!ctx) return FS_ERR_ARG;
     RCHECK(check_accumulate(ctx, proj, bins, cams, masks, n_classes, p, A_hi, A_lo, &reduction));
+    if (reduction == FS_RED_DET)
+        return set_err(ctx, FS_ERR_ARG, "FS_RED_DET needs an n x n_classes workspace; use fs_accumulate");
     const int32_t V = proj->n_views;
     if (proj->n == 0 || V == 0) return FS_OK;
     if (V > FS_NOALLOC_MAX_VIEWS)
@@ -1051,6 +1074,7 @@ struct SceneIn {
     const uint8_t *masks;
     int32_t E;
     float *A_hi, *A_lo;
+    unsigned long long *fix = nullptr;  // FS_RED_DET: this scene's fixed-point totals
     uint8_t *S;
     float *margin;
     float gamma;
@@ -1098,6 +1122,8 @@ struct fs_batch {
     std::vector<SceneIn> scenes;
     std::vector<Chunk> chunks;
     DevBuf scenes_d;
+    DevBuf fix;              // FS_RED_DET: every scene's fixed-point totals
+    int64_t fix_words = 0;
     std::vector<Work> work;  // one per lane
     hipEvent_t fork = nullptr;
     DevBuf npairs;
@@ -1118,7 +1144,7 @@ namespace {
 
 std::vector<DevBuf *> batch_bufs(fs_batch *b)
 {
-    std::vector<DevBuf *> v = {&b->scenes_d, &b->npairs};
+    std::vector<DevBuf *> v = {&b->scenes_d, &b->npairs, &b->fix};
     for (Work &w : b->work)
         for (DevBuf *d : {&w.rec, &w.rect, &w.ntiles, &w.flags, &w.codes, &w.dkeys, &w.dvals, &w.dkeys2, &w.dvals2,
                           &w.counts, &w.offsets, &w.ptiles, &w.pvals, &w.pk_alt, &w.pv_alt, &w.ranges, &w.items, &w.items_k,
@@ -1278,6 +1304,8 @@ int enqueue_run(fs_batch *b, hipStream_t s)
             if (sc.A_lo) HIPCHECK(ctx, launch_fill_u32(s, (uint32_t *)sc.A_lo, 0u, cnt));
         }
     }
+    if (b->o.reduction == FS_RED_DET && b->fix_words > 0)
+        HIPCHECK(ctx, launch_fill_u32(s, (uint32_t *)b->fix.p, 0u, 2 * b->fix_words));
     const size_t L = b->work.size();
     if (L > 1) {
         // fork: every lane starts after the zeroing; chunk i runs on lane i % L
@@ -1297,6 +1325,9 @@ int enqueue_run(fs_batch *b, hipStream_t s)
             HIPCHECK(ctx, hipStreamWaitEvent(s, w.done, 0));
         }
     }
+    if (b->o.reduction == FS_RED_DET)
+        for (const SceneIn &sc : b->scenes)
+            HIPCHECK(ctx, launch_fix_finish(s, sc.fix, sc.A_hi, sc.A_lo, (int64_t)sc.g.n * sc.E));
     for (const SceneIn &sc : b->scenes)
         if (sc.S)
             HIPCHECK(ctx, launch_assign(s, sc.A_hi, sc.A_lo, sc.g.n, sc.E, sc.gamma, sc.S, sc.margin, ctx->status_dev));
@@ -1337,6 +1368,18 @@ int batch_build(fs_batch *b, const fs_scene *scenes, int32_t n_scenes)
         s.gamma = in.gamma;
         b->scenes.push_back(s);
         sd.push_back(scene_dev(&in.gauss, in.gauss.n, in.masks, in.A_hi, in.A_lo, in.n_classes));
+    }
+    if (b->o.reduction == FS_RED_DET) {
+        int64_t words = 0;
+        for (const SceneIn &s : b->scenes) words += (int64_t)s.g.n * s.E;
+        RCHECK(batch_alloc(b, b->fix, (size_t)words * 8));
+        b->fix_words = words;
+        int64_t off = 0;
+        for (size_t i = 0; i < b->scenes.size(); ++i) {
+            b->scenes[i].fix = (unsigned long long *)b->fix.p + off;
+            sd[i].A_fix = b->scenes[i].fix;
+            off += (int64_t)b->scenes[i].g.n * b->scenes[i].E;
+        }
     }
     RCHECK(batch_alloc(b, b->scenes_d, sd.size() * sizeof(SceneDev)));
     RCHECK(upload_vec(ctx, b->scenes_d, sd));
@@ -1636,7 +1679,7 @@ int fs_batch_create(fs_ctx *ctx, const fs_scene *scenes, int32_t n_scenes, const
     fs_batch_opts o;
     fs_batch_opts_default(&o);
     if (opts) o = *opts;
-    if (o.reduction < FS_RED_AUTO || o.reduction > FS_RED_LDS2SUM) return set_err(ctx, FS_ERR_ARG, "unknown reduction");
+    if (o.reduction < FS_RED_AUTO || o.reduction > FS_RED_DET) return set_err(ctx, FS_ERR_ARG, "unknown reduction");
     if (o.depth_slabs < 0 || o.depth_slabs > 4) return set_err(ctx, FS_ERR_ARG, "depth_slabs must be in [0, 4]");
     if (o.lanes < 0 || o.lanes > 4) return set_err(ctx, FS_ERR_ARG, "lanes must be in [0, 4]");
     bool all_lo = true;
@@ -1649,6 +1692,13 @@ int fs_batch_create(fs_ctx *ctx, const fs_scene *scenes, int32_t n_scenes, const
             return set_err(ctx, FS_ERR_ARG, "scene %d: A_hi or masks is NULL", i);
         if (s.S && (!finite_f(s.gamma) || s.gamma < -1.f || s.gamma > 1.f))
             return set_err(ctx, FS_ERR_ARG, "scene %d: gamma must be finite in [-1, 1]", i);
+        if (o.reduction == FS_RED_DET) {
+            uint64_t px = 0;
+            for (int v = 0; v < s.n_views; ++v) px += (uint64_t)s.cams[v].width * (uint64_t)s.cams[v].height;
+            if (px > kFixMaxPixels)
+                return set_err(ctx, FS_ERR_ARG, "scene %d: FS_RED_DET takes at most %llu pixels per scene", i,
+                               (unsigned long long)kFixMaxPixels);
+        }
         all_lo = all_lo && s.A_lo != nullptr;
     }
     if (o.reduction == FS_RED_AUTO) o.reduction = all_lo ? FS_RED_LDS2SUM : FS_RED_LDS;

@@ -41,9 +41,15 @@ struct SceneDev {
     const uint8_t *masks;
     float *A_hi;
     float *A_lo;          // NULL: no compensation
+    unsigned long long *A_fix;  // FS_RED_DET: the call's fixed-point sums [n][E] (else NULL)
     uint32_t n;
     int32_t E;
 };
+
+// FS_RED_DET: a partial x is added as the integer round(x * 2^kFixShift) (two's
+// complement in 64 bits); integer addition is exact, so the totals do not
+// depend on the order of the additions
+constexpr int kFixShift = 34;
 
 // projection work: blocks [blk0, blk0 + ceil(n/256)) project the Gaussians of
 // `scene` into views [v0, v0 + nv) (all of that scene)
@@ -243,6 +249,10 @@ hipError_t launch_accumulate(hipStream_t s, const float *rec, const uint32_t *va
                              uint32_t n_items, const AccParams &p, float *t_final, int32_t *n_blend,
                              float *tstate, uint8_t *tile_done, int32_t first, unsigned long long *status,
                              uint32_t *queue);
+
+// FS_RED_DET: adds the fixed-point totals fix[i] (i < count) into A_hi (and A_lo),
+// once per entry, in a fixed order of operations
+hipError_t launch_fix_finish(hipStream_t s, const unsigned long long *fix, float *A_hi, float *A_lo, int64_t count);
 
 hipError_t launch_assign(hipStream_t s, const float *A_hi, const float *A_lo, int64_t n, int32_t E, float gamma,
                          uint8_t *S, float *margin, unsigned long long *status);

@@ -5,9 +5,9 @@ slabs, reduction strategy and number of lanes that give the shortest graph
 replay, among
 settings whose result agrees with the library's defaults. The defaults are
 kept unless a setting is at least `min_gain` faster, so that timing noise does
-not decide. By default only the compensated reduction (LDS pre-reduction +
-two-sum into A_lo) is a candidate; `compensated=False` also tries the LDS
-pre-reduction without A_lo.
+not decide. By default the compensated reductions (LDS pre-reduction +
+two-sum into A_lo, and the bit-reproducible fixed-point sums) are candidates;
+`compensated=False` also tries the LDS pre-reduction without A_lo.
 
 The support of a splat is an ellipse, so A does not depend on the tile shape,
 the work order, the launch shape or the batch depth beyond floating-point
@@ -75,7 +75,8 @@ KNOBS = [("opts", "lanes", [1, 2, 3, 4]),
 
 def _reductions(compensated: bool):
     from . import _lib as L
-    return [L.FS_RED_LDS2SUM] if compensated else [L.FS_RED_LDS2SUM, L.FS_RED_LDS]
+    # FS_RED_DET (fixed-point sums, bit-reproducible) keeps A_lo compensated too
+    return [L.FS_RED_LDS2SUM, L.FS_RED_DET] if compensated else [L.FS_RED_LDS2SUM, L.FS_RED_LDS, L.FS_RED_DET]
 
 
 def reference() -> dict:

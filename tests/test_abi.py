@@ -69,7 +69,8 @@ def test_batch_defaults_and_null_handling(lib):
 def test_header_limits_match_the_binding():
     from paper_2409_08270_amd import _lib as L
     src = open(HEADER).read()
-    for name in ("FS_NOALLOC_MAX_VIEWS", "FS_NOALLOC_MAX_TILES", "FS_DEV_MANY_LABELS", "FS_RED_LDS2SUM"):
+    for name in ("FS_NOALLOC_MAX_VIEWS", "FS_NOALLOC_MAX_TILES", "FS_DEV_MANY_LABELS", "FS_RED_PLAIN", "FS_RED_LDS",
+                 "FS_RED_LDS2SUM", "FS_RED_DET"):
         m = re.search(r"#define\s+" + name + r"\s+(\d+)", src)
         assert m and int(m.group(1)) == getattr(L, name), name
 

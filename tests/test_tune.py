@@ -16,15 +16,15 @@ def test_candidates_cover_the_tunable_settings_and_include_the_defaults():
     shapes = {(c["params"]["tile_w"], c["params"]["tile_h"]) for c in cs}
     assert shapes == {(16, 16), (32, 8), (8, 32)}
     assert all(c["params"]["tile_w"] * c["params"]["tile_h"] == 256 for c in cs)
-    assert {c["opts"]["reduction"] for c in cs} == {L.FS_RED_LDS2SUM}
-    assert {c["opts"]["reduction"] for c in T.candidates(640, 480, compensated=False)} == {L.FS_RED_LDS,
-                                                                                          L.FS_RED_LDS2SUM}
+    assert {c["opts"]["reduction"] for c in cs} == {L.FS_RED_LDS2SUM, L.FS_RED_DET}
+    assert {c["opts"]["reduction"] for c in T.candidates(640, 480, compensated=False)} == {
+        L.FS_RED_LDS, L.FS_RED_LDS2SUM, L.FS_RED_DET}
     assert {c["opts"]["lanes"] for c in cs} == {1, 2, 3, 4}
     assert {c["params"]["tile_order"] for c in cs} == {0, 1}
     assert {c["params"]["persistent"] for c in cs} == {0, 1}
     assert {c["params"]["lds_batch"] for c in cs} == {64, 128, 256}
     assert {c["opts"]["depth_slabs"] for c in cs} == {1, 2, 3}
-    assert len(cs) == 3 * 2 * 4 * 2 * 3 * 3
+    assert len(cs) == 3 * 2 * 4 * 2 * 3 * 3 * 2
     assert sum(T._same(c, T.reference()) for c in cs) == 1
     # the reference is what the library's defaults are
     p = L.params()
