@@ -46,7 +46,7 @@ def parse():
     ap.add_argument("--scenes", type=int, default=32, help="scenes of the C5 batch")
     ap.add_argument("--scene-cache", default=None, metavar="DIR",
                     help="read the C5 scenes from DIR (written there on the first run)")
-    ap.add_argument("--cpu-views", type=int, default=16, help="views of the CPU oracle sample (0: skip)")
+    ap.add_argument("--cpu-views", type=int, default=32, help="views of the CPU oracle sample (0: skip)")
     ap.add_argument("--no-plain", action="store_true", help="skip the per-view comparators")
     ap.add_argument("--no-precision", action="store_true", help="skip the per-variant error report")
     ap.add_argument("--no-det", action="store_true", help="skip timing the bit-reproducible reduction")
@@ -205,8 +205,10 @@ def main():
         f"{pairs_emitted:.0f}, blends {blends:.3e}, evaluated {evals:.3e}")
 
     # ---- the compositing launches of the same solve, each timed with HIP events recorded on the
-    # stream it runs on (the same plan and launches, enqueued without the graph)
-    nog = L.Batch(ctx, dss, prm, gammas=gam, use_graph=0, **opt_kw)
+    # stream it runs on (the same plan and launches, enqueued without the graph), on one lane so
+    # that each launch has the GPU to itself (in the graph, the lanes overlap one chunk's
+    # compositing with another's binning, which stretches every launch)
+    nog = L.Batch(ctx, dss, prm, gammas=gam, use_graph=0, **dict(opt_kw, lanes=1))
     nog.run()
     torch.cuda.synchronize()
     acc_tot, acc_n = [], 0
@@ -298,12 +300,16 @@ def main():
     flops = 15.0 * blends + 1.0 * evals
     acc_s = acc_ms_step * 1e-3
     achieved = flops / acc_s
-    settings = {"tile": f"{prm.tile_w}x{prm.tile_h}", "tile_order": int(prm.tile_order), **opt_kw}
+    # what the compositing launches depend on (not the lanes: counters see one dispatch at a time)
+    settings = {"tile": f"{prm.tile_w}x{prm.tile_h}", "tile_order": int(prm.tile_order),
+                "persistent": int(prm.persistent), "lds_batch": int(prm.lds_batch or 256),
+                "reduction": int(opt_kw.get("reduction", L.FS_RED_LDS2SUM)),
+                "depth_slabs": int(opt_kw.get("depth_slabs", 1) or 1)}
     roof = {"bound": "alu", "achieved": achieved / 1e12, "peak": PEAK_FP32 / 1e12, "unit": "TFLOP/s",
             "frac": achieved / PEAK_FP32,
             "traffic": recorded_traffic(workload, settings),
             "traffic_unit": "HBM bytes per launch (rocprofv3 FETCH_SIZE + WRITE_SIZE, copy-calibrated)",
-            "kernel": "k_accum", "launches_per_step": acc_n, "launch_ms": launch_ms,
+            "kernel": "k_accum", "launches_per_step": acc_n, "launch_ms": launch_ms, "launch_lanes": 1,
             "flops_per_launch": flops / max(1, acc_n),
             "flop_count": "15 per blend + 1 exp per in-support evaluation",
             "lane_ops": {"per_step": 15.0 * evals + 5.0 * blends,

@@ -28,9 +28,8 @@
 // x = -ry -/+ sqrt((Lo - s y^2)/p); the left edge is convex in y, the right
 // edge concave, so over the band of the tile row's centre rows the least x is
 // -xe when yx lies in the band and the left edge at the band end nearer yx
-// otherwise (likewise for the greatest x). Those bounds, widened by a pixel
-// and by the rounding of this approximate arithmetic, give the candidate
-// columns. Columns are then walked inward from each end; in a column only the
+// otherwise (likewise for the greatest x). Those bounds, widened by the
+// rounding of this approximate arithmetic, give the candidate columns. Columns are then walked inward from each end; in a column only the
 // rows of the chord of the Lo ellipse (widened the same way) can pass, and
 // each of those centres is decided by the definition's own test. So the
 // listed set is the definition's exactly; the approximations only choose
@@ -144,8 +143,13 @@ __host__ __device__ __forceinline__ Span32 make_span32(float u, float v, float p
     sp.xe = approx_sqrt((sp.lo * sp.C) * iD);
     sp.ye = approx_sqrt((sp.lo * p) * iD);
     sp.yx = (sp.B * sp.xe) * sp.iC;
-    sp.mx = 1.0f + sp.xe * rc;
-    sp.my = 1.0f + sp.ye * rc;
+    // margins of the approximate bounds: the relative error of the half-widths
+    // (rc; cancellation near an end of a chord costs at most sqrt(3u) of the
+    // extent) and the absolute rounding of sums of coordinates, a few ulp of
+    // |u| + xe (|v| + ye); the offsets of the rows and columns themselves are
+    // the definition's own binary32 values, so they carry no error here
+    sp.mx = 0x1p-6f + sp.xe * rc + 0x1p-20f * (fabsf(u) + sp.xe);
+    sp.my = 0x1p-6f + sp.ye * rc + 0x1p-20f * (fabsf(v) + sp.ye);
     sp.ok = p > 0.0f && s > 0.0f && rc < 0.25f && __builtin_isfinite(sp.xe) && __builtin_isfinite(sp.ye) &&
             __builtin_isfinite(sp.yx) && __builtin_isfinite(sp.iC) && __builtin_isfinite(sp.B);
     return sp;
@@ -239,8 +243,8 @@ __host__ __device__ __forceinline__ bool row_span(const Span32 &sp, int ty, int 
         const float xmin = (yl >= lo && yl <= hi) ? -sp.xe : edge_x(sp, yl < lo ? lo : hi, -1.0f);
         const float xmax = (yr >= lo && yr <= hi) ? sp.xe : edge_x(sp, yr < lo ? lo : hi, 1.0f);
         // centre columns k with k + 0.5 - u in [xmin - mx, xmax + mx]
-        cl = clamp_index(floorf(((sp.u + xmin) - 0.5f) - sp.mx), k0, k1 + 1);
-        cr = clamp_index(ceilf(((sp.u + xmax) - 0.5f) + sp.mx), k0 - 1, k1);
+        cl = clamp_index(ceilf(((sp.u + xmin) - 0.5f) - sp.mx), k0, k1 + 1);
+        cr = clamp_index(floorf(((sp.u + xmax) - 0.5f) + sp.mx), k0 - 1, k1);
     }
     if (sp.ok && cl <= cr) {
         // a surely passing column near each end, on the band row nearest the
