@@ -164,10 +164,10 @@ __device__ __forceinline__ void accum_tile(const uint32_t tile, const float4 *__
     // FS_RED_DET: the same memory as [entry][stride] 64-bit fixed-point partials
     unsigned long long *const s_part64 = reinterpret_cast<unsigned long long *>(s_part);
     __shared__ uint8_t s_wmask[kBatch];    // bit w: wave w's 8x8 block can be reached
-    __shared__ __align__(16) uint32_t s_list[4][kBatch + 16];  // per-wave compacted entries (byte offsets
+    __shared__ __align__(16) uint32_t s_list[4][kBatch + 8];  // per-wave compacted entries (byte offsets
                                                                // into s_rec), padded with the null record
     __shared__ uint32_t s_bits[8];
-    __shared__ int32_t s_slot_label[kMaxSlots];
+    __shared__ uint8_t s_slot_label[kMaxSlots];  // labels are < n_classes <= 256
     __shared__ unsigned long long s_wslots[4];
     __shared__ unsigned long long s_tmajor;  // slots that are major in at least one wave of the tile
     __shared__ uint32_t s_misc[5];      // bad labels, longest wave walk, blends, evaluations, walked entries
@@ -227,7 +227,7 @@ __device__ __forceinline__ void accum_tile(const uint32_t tile, const float4 *__
     // (fixed-point partials take two words: half as many entries)
     const uint32_t bsz = min(plain ? (uint32_t)kBatch : (uint32_t)(kPart >> (det ? sh + 1 : sh)), (uint32_t)P.batch);
     if (active && !plain) {
-        s_slot_label[slot] = lab;
+        s_slot_label[slot] = (uint8_t)lab;
         atomicOr(&s_wslots[w], 1ull << slot);
     }
     __syncthreads();
@@ -352,7 +352,7 @@ __device__ __forceinline__ void accum_tile(const uint32_t tile, const float4 *__
             if (hit) s_list[w][nlist + __popcll(bm & ((1ull << lane) - 1ull))] = (uint32_t)e * 32u;
             nlist += __popcll(bm);
         }
-        if (lane < 16) s_list[w][nlist + lane] = (uint32_t)kBatch * 32u;  // pad the last group with the null record
+        if (lane < 8) s_list[w][nlist + lane] = (uint32_t)kBatch * 32u;  // pad the last group with the null record
         __builtin_amdgcn_wave_barrier();
 
         // one front-to-back step of this lane's pixel over a staged entry: power in
