@@ -1434,7 +1434,7 @@ int batch_build(fs_batch *b, const fs_scene *scenes, int32_t n_scenes)
         RCHECK(batch_alloc(b, w.rect, E4 * 2));
         RCHECK(batch_alloc(b, w.ntiles, E4));
         RCHECK(batch_alloc(b, w.flags, E4 / 4 + 256));
-        RCHECK(batch_alloc(b, w.codes, E4 * 4));
+        RCHECK(batch_alloc(b, w.codes, E4 * 8));  // 32-byte emission records
         RCHECK(batch_alloc(b, w.dkeys, E4));
         RCHECK(batch_alloc(b, w.dvals, E4));
         RCHECK(batch_alloc(b, w.dkeys2, E4));

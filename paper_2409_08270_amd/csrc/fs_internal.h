@@ -122,7 +122,8 @@ hipError_t launch_fill_u32(hipStream_t s, uint32_t *p, uint32_t v, int64_t count
 // a1: projection of every task; optionally also writes the depth-sort keys
 // (float bits of depth for elements that emit pairs, 0xFFFFFFFF otherwise) and
 // values (Gaussian id within its scene) of every element, and (if `codes` is
-// not NULL) every element's 16-byte span code (fs_tiles.h), two u64 per element.
+// not NULL) every element's 32-byte emission record (span code and tile
+// rectangle, fs_tiles.h), four u64 per element.
 hipError_t launch_project(hipStream_t s, const ProjTask *tasks, int32_t n_tasks, uint32_t n_blocks,
                           const SceneDev *scenes, const ViewDev *views, const ProjParams &p, float *rec,
                           int16_t *rect, int32_t *ntiles, uint8_t *flags, uint32_t *dkeys, uint32_t *dvals,
@@ -196,8 +197,9 @@ hipError_t launch_slab_counts(hipStream_t s, const uint32_t *sorted_keys, const 
 // (tiles marked in `done`, if not NULL, are skipped, as in launch_slab_counts;
 // `flags` may be NULL as there). With gbits > 0 each pair is one packed item
 // (tile index within its view << gbits) | Gaussian id in tiles_out, and
-// vals_out is not used. `codes` (may be NULL) are the projection's span
-// codes; elements with one skip the row_span recomputation.
+// vals_out is not used. `codes` (may be NULL) are the projection's emission
+// records (span code and rectangle); elements with a code skip the row_span
+// recomputation, and the rectangle is read from the record, not from `rect`.
 hipError_t launch_emit(hipStream_t s, const uint32_t *sorted_keys, const uint32_t *sorted_vals,
                        const uint32_t *offsets, const uint32_t *counts, const float *rec, const int16_t *rect,
                        const uint8_t *flags, const ViewDev *views, int32_t n_views, int64_t total,

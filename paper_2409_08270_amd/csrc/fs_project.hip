@@ -244,7 +244,7 @@ __global__ __launch_bounds__(256) void k_project(const ProjTask *__restrict__ ta
             rect[idx] = rc;
             ntiles[idx] = nt;
             flags[idx] = f;
-            if (codes) codes[idx] = make_ulonglong2(code.lo, code.hi);
+            if (codes) store_emit_record(codes, idx, code, rc);
             if (dkeys) {
                 // depth-sort key: positive float bits order like the depths; the
                 // sentinel puts elements without pairs last

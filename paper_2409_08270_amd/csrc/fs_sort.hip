@@ -429,8 +429,9 @@ __global__ void k_slab_counts(const uint32_t *__restrict__ skeys, const uint32_t
             if (done == nullptr) {
                 c = (uint32_t)ntiles[idx];
             } else {
-                const short4 rc = rect[idx];
-                const SpanCode code = load_code(codes, idx);
+                short4 rc;
+                SpanCode code;
+                load_emit_record(codes, rect, idx, code, rc);
                 Span32 sp = make_span32(0.f, 0.f, 1.f, 0.f, 1.f, true, 1.0f);
                 if (!has_code(code)) {
                     const float4 r0 = rec[2 * idx];
@@ -512,8 +513,9 @@ __global__ __launch_bounds__(kThreads) void k_emit(const uint32_t *__restrict__ 
         const uint32_t g = svals[i];
         const ViewDev &C = views[vw];
         const int64_t idx = (int64_t)C.elem_off + g;
-        const short4 rc = rect[idx];
-        const SpanCode code = load_code(codes, idx);
+        short4 rc;
+        SpanCode code;
+        load_emit_record(codes, rect, idx, code, rc);
         Span32 sp = make_span32(0.f, 0.f, 1.f, 0.f, 1.f, true, 1.0f);
         if (!has_code(code)) {
             const float4 r0 = rec[2 * idx];

@@ -321,11 +321,41 @@ __device__ __forceinline__ bool code_span(const SpanCode &c, int row, int x0, in
     return true;
 }
 
-__device__ __forceinline__ SpanCode load_code(const ulonglong2 *codes, int64_t idx)
+// The batch keeps, per element, a 32-byte emission record: the span code and
+// the tile rectangle (x0, y0, x1, y1 as 16-bit fields), so that the emission's
+// gather of an element touches one 32-byte block instead of two arrays.
+__device__ __forceinline__ unsigned long long pack_rect(short4 rc)
 {
-    if (codes == nullptr) return no_code();
-    const ulonglong2 q = codes[idx];
-    return SpanCode{q.x, q.y};
+    return (unsigned long long)(uint16_t)rc.x | ((unsigned long long)(uint16_t)rc.y << 16) |
+           ((unsigned long long)(uint16_t)rc.z << 32) | ((unsigned long long)(uint16_t)rc.w << 48);
+}
+
+__device__ __forceinline__ short4 unpack_rect(unsigned long long v)
+{
+    return make_short4((short)(uint16_t)(v & 0xFFFFull), (short)(uint16_t)((v >> 16) & 0xFFFFull),
+                       (short)(uint16_t)((v >> 32) & 0xFFFFull), (short)(uint16_t)(v >> 48));
+}
+
+__device__ __forceinline__ void store_emit_record(ulonglong2 *recs, int64_t idx, const SpanCode &c, short4 rc)
+{
+    recs[2 * idx] = make_ulonglong2(c.lo, c.hi);
+    recs[2 * idx + 1] = make_ulonglong2(pack_rect(rc), 0ull);
+}
+
+// span code and rectangle of element idx: from the emission records when there
+// are any (`recs`), else no code and the rectangle array
+__device__ __forceinline__ void load_emit_record(const ulonglong2 *recs, const short4 *rect, int64_t idx,
+                                                 SpanCode &code, short4 &rc)
+{
+    if (recs == nullptr) {
+        code = no_code();
+        rc = rect[idx];
+        return;
+    }
+    const ulonglong2 a = recs[2 * idx];
+    const ulonglong2 b = recs[2 * idx + 1];
+    code = SpanCode{a.x, a.y};
+    rc = unpack_rect(b.x);
 }
 
 }  // namespace fs
