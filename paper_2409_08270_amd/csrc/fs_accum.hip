@@ -48,6 +48,15 @@ __device__ __forceinline__ float dpp_mov(float x)
     return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(x), CTRL, 0xF, 0xF, false));
 }
 
+// a 64-bit value that is the same in every lane, kept in scalar registers, so
+// that loops over its bits are scalar loops
+__device__ __forceinline__ unsigned long long uniform64(unsigned long long x)
+{
+    const uint32_t lo = __builtin_amdgcn_readfirstlane((uint32_t)x);
+    const uint32_t hi = __builtin_amdgcn_readfirstlane((uint32_t)(x >> 32));
+    return ((unsigned long long)hi << 32) | lo;
+}
+
 // value of lane (lane ^ 8), within each 16-lane row (row rotate by 8)
 __device__ __forceinline__ float dpp_xor8(float x) { return dpp_mov<0x128>(x); }
 
@@ -235,12 +244,13 @@ __device__ __forceinline__ void accum_tile(const uint32_t tile, const float4 *__
     // wave; the other lanes (minor) add their weights to LDS themselves
     unsigned long long wmajor = 0;
     {
-        unsigned long long sl = s_wslots[w];
+        unsigned long long sl = uniform64(s_wslots[w]);
         while (sl) {
             const int sidx = __ffsll((long long)sl) - 1;
             sl &= sl - 1ull;
             if (__popcll(__ballot(active && slot == sidx)) >= (det ? 1 : kMajor)) wmajor |= 1ull << sidx;
         }
+        wmajor = uniform64(wmajor);
     }
     if (lane == 0 && wmajor) atomicOr(&s_tmajor, wmajor);
     const bool minor = active && !plain && !((wmajor >> slot) & 1ull);
