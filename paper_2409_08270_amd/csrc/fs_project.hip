@@ -14,6 +14,11 @@ namespace {
 
 __device__ __forceinline__ bool finite32(float x) { return __builtin_isfinite(x); }
 
+// rows of a block's list whose splat is looked up in a table rather than by a
+// binary search in the row offsets (a multiple of 256, so the choice is the
+// same for every lane of a wave)
+constexpr uint32_t kRowMap = 2048;
+
 // Inclusive sum over the 256 threads of the block (all threads call it).
 __device__ __forceinline__ uint32_t block_incl_sum(uint32_t x, uint32_t *s_wsum)
 {
@@ -102,6 +107,7 @@ __global__ __launch_bounds__(256) void k_project(const ProjTask *__restrict__ ta
     __shared__ uint32_t s_cnt[256];     // listed tiles per splat
     __shared__ __align__(16) uint8_t s_code[256][16];
     __shared__ uint32_t s_wsum[4];
+    __shared__ uint8_t s_rowsplat[kRowMap];  // the splat of each of the block's first kRowMap rows
     const int tid = threadIdx.x;
 
     int n_invalid = 0, n_fp64 = 0;
@@ -211,16 +217,23 @@ __global__ __launch_bounds__(256) void k_project(const ProjTask *__restrict__ ta
         const uint32_t incl = block_incl_sum(rows, s_wsum);  // ends with a barrier
         s_off[tid + 1] = incl;
         if (tid == 0) s_off[0] = 0;
+        for (uint32_t r = incl - rows; r < min(incl, kRowMap); ++r) s_rowsplat[r] = (uint8_t)tid;
         __syncthreads();
         const uint32_t n_rows = s_off[256];
         for (uint32_t i = (uint32_t)tid; i < n_rows; i += 256u) {
-            // the splat e with s_off[e] <= i < s_off[e + 1]
-            int lo_e = 0, hi_e = 255;
-            while (lo_e < hi_e) {
-                const int mid = (lo_e + hi_e + 1) >> 1;
-                if (s_off[mid] <= i) lo_e = mid; else hi_e = mid - 1;
+            // the splat e with s_off[e] <= i < s_off[e + 1]: from the map, or by a
+            // binary search past its end (i < kRowMap is the same for the whole wave)
+            int e;
+            if (i < kRowMap) {
+                e = s_rowsplat[i];
+            } else {
+                int lo_e = 0, hi_e = 255;
+                while (lo_e < hi_e) {
+                    const int mid = (lo_e + hi_e + 1) >> 1;
+                    if (s_off[mid] <= i) lo_e = mid; else hi_e = mid - 1;
+                }
+                e = lo_e;
             }
-            const int e = lo_e;
             const int4 re = s_rect[e];
             const int row = (int)(i - s_off[e]);
             int l, r;

@@ -17,6 +17,9 @@ namespace fs {
 namespace {
 
 constexpr int kThreads = 256;
+// rows of an emission block whose element is looked up in a table rather than
+// by a binary search in the row offsets (a multiple of 256: one choice per wave)
+constexpr uint32_t kRowMap = 2048;
 constexpr int kItems = 16;
 constexpr int kTile = kThreads * kItems;  // 4096 items per block tile
 constexpr int kWaves = kThreads / 64;
@@ -500,6 +503,7 @@ __global__ __launch_bounds__(kThreads) void k_emit(const uint32_t *__restrict__ 
     __shared__ uint32_t s_roff[kThreads + 1];
     __shared__ uint32_t s_wsum[kWaves];
     __shared__ uint32_t s_lo;
+    __shared__ uint8_t s_rowelem[kRowMap];  // the element of each of the block's first kRowMap rows
     const int tid = threadIdx.x;
     const int64_t b0 = (int64_t)blockIdx.x * kThreads;
     const int64_t i = b0 + tid;
@@ -534,6 +538,7 @@ __global__ __launch_bounds__(kThreads) void k_emit(const uint32_t *__restrict__ 
     const uint32_t incl = block_scan_incl(rows, s_wsum, &n_rows);
     s_roff[tid + 1] = incl;
     if (tid == 0) s_roff[0] = 0;
+    for (uint32_t r = incl - rows; r < min(incl, kRowMap); ++r) s_rowelem[r] = (uint8_t)tid;
     __syncthreads();
     const uint32_t lo = s_lo;
 
@@ -543,13 +548,18 @@ __global__ __launch_bounds__(kThreads) void k_emit(const uint32_t *__restrict__ 
         int e = 0, l = 0, r = -1;
         uint32_t n = 0;
         if (item < n_rows) {
-            // the element e with s_roff[e] <= item < s_roff[e + 1]
-            int a = 0, b = kThreads - 1;
-            while (a < b) {
-                const int mid = (a + b + 1) >> 1;
-                if (s_roff[mid] <= item) a = mid; else b = mid - 1;
+            // the element e with s_roff[e] <= item < s_roff[e + 1]: from the map,
+            // or by a binary search past its end (the same choice for the whole wave)
+            if (item < kRowMap) {
+                e = s_rowelem[item];
+            } else {
+                int a = 0, b = kThreads - 1;
+                while (a < b) {
+                    const int mid = (a + b + 1) >> 1;
+                    if (s_roff[mid] <= item) a = mid; else b = mid - 1;
+                }
+                e = a;
             }
-            e = a;
             const short4 rc = s_rc[e];
             const int row = (int)(item - s_roff[e]);
             const ulonglong2 cw = s_code[e];
