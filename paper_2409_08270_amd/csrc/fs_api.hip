@@ -241,6 +241,7 @@ ProjParams proj_params(const fs_params *p)
     q.guard = p->guard;
     q.fp64_cond = p->fp64_cond;
     q.fp64_conic = p->fp64_conic;
+    q.cshift = 0;
     return q;
 }
 
@@ -1098,6 +1099,7 @@ struct Chunk {
     // one sort segment per view; used when both fit in 32 bits (single pass)
     bool packed = false;
     int32_t gbits = 0, tbits = 0;
+    int32_t cshift = 0;  // depth-sort values: Gaussian id | listed-tile count << cshift (0: id only)
     uint32_t lblocks = 0;
     int passes = 0;
     DevBuf views, tasks, dsegs, psegs, lsegs;
@@ -1183,8 +1185,10 @@ int enqueue_front(fs_batch *b, Work &w, Chunk &c, hipStream_t s)
     const Plan &pl = c.plan;
     if (pl.elems == 0) return FS_OK;
     uint32_t *dk = (uint32_t *)w.dkeys.p, *dv = (uint32_t *)w.dvals.p;
+    ProjParams pp = proj_params(&b->p);
+    pp.cshift = c.cshift;
     HIPCHECK(ctx, launch_project(s, (const ProjTask *)c.tasks.p, (int32_t)pl.tasks.size(), pl.proj_blocks,
-                                 (const SceneDev *)b->scenes_d.p, (const ViewDev *)c.views.p, proj_params(&b->p),
+                                 (const SceneDev *)b->scenes_d.p, (const ViewDev *)c.views.p, pp,
                                  (float *)w.rec.p, (int16_t *)w.rect.p, (int32_t *)w.ntiles.p, (uint8_t *)w.flags.p,
                                  dk, dv, (uint64_t *)w.codes.p, ctx->status_dev));
     HIPCHECK(ctx, radix_sort(s, dk, dv, (uint32_t *)w.dkeys2.p, (uint32_t *)w.dvals2.p, (const SegDev *)c.dsegs.p,
@@ -1204,7 +1208,7 @@ int enqueue_full_count(fs_batch *b, Work &w, Chunk &c, uint32_t *np, hipStream_t
     }
     HIPCHECK(ctx, launch_gather_counts(s, (const uint32_t *)w.dkeys.p, (const uint32_t *)w.dvals.p,
                                        (const int32_t *)w.ntiles.p, (const ViewDev *)c.views.p,
-                                       (int32_t)pl.views.size(), total, (uint32_t *)w.counts.p));
+                                       (int32_t)pl.views.size(), total, (uint32_t *)w.counts.p, c.cshift));
     HIPCHECK(ctx, scan_exclusive(s, (const uint32_t *)w.counts.p, (uint32_t *)w.offsets.p, total, np, w.scan_ws.p));
     return FS_OK;
 }
@@ -1242,7 +1246,7 @@ int enqueue_slabs(fs_batch *b, Work &w, Chunk &c, int chunk_idx, hipStream_t s, 
                                          (const int32_t *)w.ntiles.p,
                                          (const ViewDev *)c.views.p, V, total, sl, k > 0 ? done : nullptr,
                                          b->p.tile_w, b->p.tile_h, b->p.sigma_k, (const uint64_t *)w.codes.p,
-                                         (uint32_t *)w.counts.p));
+                                         (uint32_t *)w.counts.p, c.cshift));
         HIPCHECK(ctx, scan_exclusive(s, (const uint32_t *)w.counts.p, (uint32_t *)w.offsets.p, total, np,
                                      w.scan_ws.p));
         const uint8_t *fl = b->p.fp64_conic ? nullptr : (const uint8_t *)w.flags.p;
@@ -1257,7 +1261,7 @@ int enqueue_slabs(fs_batch *b, Work &w, Chunk &c, int chunk_idx, hipStream_t s, 
                                       (const float *)w.rec.p, (const int16_t *)w.rect.p, fl,
                                       (const ViewDev *)c.views.p, V, total, c.pair_cap, b->p.tile_w, b->p.tile_h,
                                       b->p.sigma_k, k > 0 ? done : nullptr, pt, nullptr, ctx->status_dev, c.gbits,
-                                      (const uint64_t *)w.codes.p));
+                                      (const uint64_t *)w.codes.p, c.cshift));
             HIPCHECK(ctx, launch_pair_segs(s, (const uint32_t *)w.offsets.p, (const ViewDev *)c.views.p, V, total, np,
                                            c.pair_cap, (SegDev *)c.psegs.p, ctx->status_dev));
             HIPCHECK(ctx, radix_sort_packed(s, pt, pta, pv, (const SegDev *)c.psegs.p, V, c.pblocks, c.gbits, c.tbits,
@@ -1267,7 +1271,7 @@ int enqueue_slabs(fs_batch *b, Work &w, Chunk &c, int chunk_idx, hipStream_t s, 
                                       (const float *)w.rec.p, (const int16_t *)w.rect.p, fl,
                                       (const ViewDev *)c.views.p, V, total, c.pair_cap, b->p.tile_w, b->p.tile_h,
                                       b->p.sigma_k, k > 0 ? done : nullptr, k0, v0, ctx->status_dev, 0,
-                                      (const uint64_t *)w.codes.p));
+                                      (const uint64_t *)w.codes.p, c.cshift));
             HIPCHECK(ctx, radix_sort(s, k0, v0, k1, v1, (const SegDev *)c.psegs.p, 1, c.pblocks, c.passes * 8,
                                      w.sort_ws.p, np, c.ptpb, tcount, false));
         }
@@ -1555,6 +1559,7 @@ int batch_build(fs_batch *b, const fs_scene *scenes, int32_t n_scenes)
             }
             c.gbits = bits_for(max_n);
             c.tbits = bits_for(max_tv);
+            c.cshift = c.gbits <= 24 ? c.gbits : 0;  // at least 8 bits for the carried count
             // (with depth slabs every slab's pairs of a view are at most the view's planned
             // pairs, so the per-view capacities below hold for every slab)
             c.packed = c.tbits <= 16 && c.gbits + c.tbits <= 32 && c.vpairs.size() == c.plan.views.size();

@@ -76,7 +76,24 @@ struct ProjParams {
     int32_t tile_w, tile_h;
     float sigma_k, lowpass, znear, guard, fp64_cond;
     int32_t fp64_conic;
+    int32_t cshift;  // > 0: depth-sort values carry the listed-tile count (see packed_val)
 };
+
+// Depth-sort values. With cshift = 0 a value is the Gaussian id g. With
+// cshift > 0 (ids below 2^cshift) it also carries the element's listed-tile
+// count above the id, saturated at kCountSat(cshift), so that the count is
+// read in sorted order with the value rather than gathered per element.
+__host__ __device__ __forceinline__ uint32_t count_sat(int32_t cshift) { return 0xFFFFFFFFu >> cshift; }
+__host__ __device__ __forceinline__ uint32_t packed_val(uint32_t g, uint32_t nt, int32_t cshift)
+{
+    if (cshift == 0) return g;
+    const uint32_t c = nt < count_sat(cshift) ? nt : count_sat(cshift);
+    return g | (c << cshift);
+}
+__host__ __device__ __forceinline__ uint32_t val_id(uint32_t v, int32_t cshift)
+{
+    return cshift == 0 ? v : (v & ((1u << cshift) - 1u));
+}
 
 // Device status block (ctx-owned): 64-bit counters, each striped over
 // kStatusLanes words (indexed by the updating block) so that many blocks
@@ -169,10 +186,11 @@ hipError_t launch_pair_segs(hipStream_t s, const uint32_t *offsets, const ViewDe
 size_t scan_ws_bytes(int64_t n);
 hipError_t scan_exclusive(hipStream_t s, const uint32_t *in, uint32_t *out, int64_t n, uint32_t *total_out, void *ws);
 
-// counts[i] = ntiles of depth-sorted element i (0 if its key is the sentinel)
+// counts[i] = ntiles of depth-sorted element i (0 if its key is the sentinel);
+// cshift: how the values are packed (ProjParams)
 hipError_t launch_gather_counts(hipStream_t s, const uint32_t *sorted_keys, const uint32_t *sorted_vals,
                                 const int32_t *ntiles, const ViewDev *views, int32_t n_views, int64_t total,
-                                uint32_t *counts);
+                                uint32_t *counts, int32_t cshift = 0);
 
 // Depth slab [lo, hi) of a view holding n Gaussians, as fractions num/1024 of its
 // depth-sorted elements: ranks [(n*num_lo) >> 10, (n*num_hi) >> 10).
@@ -189,7 +207,7 @@ hipError_t launch_slab_counts(hipStream_t s, const uint32_t *sorted_keys, const 
                               const float *rec, const int16_t *rect, const uint8_t *flags, const int32_t *ntiles,
                               const ViewDev *views, int32_t n_views, int64_t total, Slab slab, const uint8_t *done,
                               int32_t tile_w, int32_t tile_h, float sigma_k, const uint64_t *codes,
-                              uint32_t *counts);
+                              uint32_t *counts, int32_t cshift = 0);
 
 // emits, for every depth-sorted element, one (tile, id) pair per listed tile
 // (the row_span rule) at offsets[i]; pairs at or beyond `capacity` are
@@ -205,7 +223,7 @@ hipError_t launch_emit(hipStream_t s, const uint32_t *sorted_keys, const uint32_
                        const uint8_t *flags, const ViewDev *views, int32_t n_views, int64_t total,
                        uint32_t capacity, int32_t tile_w, int32_t tile_h, float sigma_k, const uint8_t *done,
                        uint32_t *tiles_out, uint32_t *vals_out, unsigned long long *status, int32_t gbits = 0,
-                       const uint64_t *codes = nullptr);
+                       const uint64_t *codes = nullptr, int32_t cshift = 0);
 
 // ranges[t] = [starts[t], starts[t] + counts[t]), or [0, 0) if counts[t] == 0
 hipError_t launch_count_ranges(hipStream_t s, const uint32_t *counts, const uint32_t *starts, int64_t n_tiles,

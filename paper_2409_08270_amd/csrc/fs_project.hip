@@ -262,7 +262,7 @@ __global__ __launch_bounds__(256) void k_project(const ProjTask *__restrict__ ta
                 // depth-sort key: positive float bits order like the depths; the
                 // sentinel puts elements without pairs last
                 dkeys[idx] = ((f & 1u) && nt > 0) ? __float_as_uint(r1.z) : 0xFFFFFFFFu;
-                dvals[idx] = (uint32_t)g;
+                dvals[idx] = packed_val((uint32_t)g, (uint32_t)nt, P.cshift);
             }
         }
     }

@@ -393,7 +393,7 @@ __global__ void k_depth_keys(const float4 *__restrict__ rec, const int32_t *__re
 
 __global__ void k_gather_counts(const uint32_t *__restrict__ skeys, const uint32_t *__restrict__ svals,
                                 const int32_t *__restrict__ ntiles, const ViewDev *__restrict__ views,
-                                int32_t n_views, int64_t total, uint32_t *__restrict__ counts)
+                                int32_t n_views, int64_t total, uint32_t *__restrict__ counts, int32_t cshift)
 {
     int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= total) return;
@@ -401,8 +401,13 @@ __global__ void k_gather_counts(const uint32_t *__restrict__ skeys, const uint32
         counts[i] = 0u;
         return;
     }
+    const uint32_t vv = svals[i];
+    if (cshift != 0 && (vv >> cshift) < count_sat(cshift)) {
+        counts[i] = vv >> cshift;  // the count travels with the value
+        return;
+    }
     const int v = find_view_of_elem(views, n_views, i);
-    counts[i] = (uint32_t)ntiles[(int64_t)views[v].elem_off + svals[i]];
+    counts[i] = (uint32_t)ntiles[(int64_t)views[v].elem_off + val_id(vv, cshift)];
 }
 
 // Depth-slab pair counts. An element outside the slab counts 0; inside, its
@@ -419,35 +424,42 @@ __global__ void k_slab_counts(const uint32_t *__restrict__ skeys, const uint32_t
                               const uint8_t *__restrict__ flags, const int32_t *__restrict__ ntiles,
                               const ViewDev *__restrict__ views, int32_t n_views, int64_t total, Slab sl,
                               const uint8_t *__restrict__ done, int32_t tw, int32_t th, float sigma_k,
-                              const ulonglong2 *__restrict__ codes, uint32_t *__restrict__ counts)
+                              const ulonglong2 *__restrict__ codes, uint32_t *__restrict__ counts, int32_t cshift)
 {
     int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= total) return;
     uint32_t c = 0;
     if (skeys[i] != 0xFFFFFFFFu) {
-        const int v = find_view_of_elem(views, n_views, i);
-        const ViewDev &C = views[v];
-        if (in_slab(C, i, sl)) {
-            const int64_t idx = (int64_t)C.elem_off + svals[i];
-            if (done == nullptr) {
-                c = (uint32_t)ntiles[idx];
-            } else {
-                short4 rc;
-                SpanCode code;
-                load_emit_record(codes, rect, idx, code, rc);
-                Span32 sp = make_span32(0.f, 0.f, 1.f, 0.f, 1.f, true, 1.0f);
-                if (!has_code(code)) {
-                    const float4 r0 = rec[2 * idx];
-                    const float4 r1 = rec[2 * idx + 1];
-                    sp = make_span32(r0.x, r0.y, r0.z, r0.w, r1.x, r1.w != 0.0f, support_limit(sigma_k));
-                }
-                for (int ty = rc.y; ty <= rc.w; ++ty) {
-                    int l, r;
-                    const bool any = has_code(code) ? code_span(code, ty - rc.y, rc.x, l, r)
-                                                    : row_span(sp, ty, rc.x, rc.z, tw, th, C.W, C.H, l, r);
-                    if (!any) continue;
-                    const uint8_t *d = done + C.tile_base + (uint32_t)ty * (uint32_t)C.tiles_x;
-                    for (int t = l; t <= r; ++t) c += d[t] ? 0u : 1u;
+        const uint32_t vv = svals[i];
+        // the count travels with the value unless it saturated
+        const bool carried = cshift != 0 && (vv >> cshift) < count_sat(cshift);
+        if (done == nullptr && carried && sl.num_lo == 0 && sl.num_hi >= 1024) {
+            c = vv >> cshift;  // one slab holds every element: no view lookup
+        } else {
+            const int v = find_view_of_elem(views, n_views, i);
+            const ViewDev &C = views[v];
+            if (in_slab(C, i, sl)) {
+                const int64_t idx = (int64_t)C.elem_off + val_id(vv, cshift);
+                if (done == nullptr) {
+                    c = carried ? (vv >> cshift) : (uint32_t)ntiles[idx];
+                } else {
+                    short4 rc;
+                    SpanCode code;
+                    load_emit_record(codes, rect, idx, code, rc);
+                    Span32 sp = make_span32(0.f, 0.f, 1.f, 0.f, 1.f, true, 1.0f);
+                    if (!has_code(code)) {
+                        const float4 r0 = rec[2 * idx];
+                        const float4 r1 = rec[2 * idx + 1];
+                        sp = make_span32(r0.x, r0.y, r0.z, r0.w, r1.x, r1.w != 0.0f, support_limit(sigma_k));
+                    }
+                    for (int ty = rc.y; ty <= rc.w; ++ty) {
+                        int l, r;
+                        const bool any = has_code(code) ? code_span(code, ty - rc.y, rc.x, l, r)
+                                                        : row_span(sp, ty, rc.x, rc.z, tw, th, C.W, C.H, l, r);
+                        if (!any) continue;
+                        const uint8_t *d = done + C.tile_base + (uint32_t)ty * (uint32_t)C.tiles_x;
+                        for (int t = l; t <= r; ++t) c += d[t] ? 0u : 1u;
+                    }
                 }
             }
         }
@@ -493,7 +505,7 @@ __global__ __launch_bounds__(kThreads) void k_emit(const uint32_t *__restrict__ 
                                                    float sigma_k, const uint8_t *__restrict__ done,
                                                    uint32_t *__restrict__ tiles_out,
                                                    uint32_t *__restrict__ vals_out, unsigned long long *__restrict__ status,
-                                                   int32_t gbits, const ulonglong2 *__restrict__ codes)
+                                                   int32_t gbits, const ulonglong2 *__restrict__ codes, int32_t cshift)
 {
     __shared__ Span32 s_span[kThreads];
     __shared__ ulonglong2 s_code[kThreads];
@@ -514,7 +526,7 @@ __global__ __launch_bounds__(kThreads) void k_emit(const uint32_t *__restrict__ 
     uint32_t rows = 0;
     if (cnt > 0) {
         const int vw = find_view_of_elem(views, n_views, i);
-        const uint32_t g = svals[i];
+        const uint32_t g = val_id(svals[i], cshift);
         const ViewDev &C = views[vw];
         const int64_t idx = (int64_t)C.elem_off + g;
         short4 rc;
@@ -847,11 +859,11 @@ hipError_t launch_depth_keys(hipStream_t s, const float *rec, const int32_t *nti
 
 hipError_t launch_gather_counts(hipStream_t s, const uint32_t *sorted_keys, const uint32_t *sorted_vals,
                                 const int32_t *ntiles, const ViewDev *views, int32_t n_views, int64_t total,
-                                uint32_t *counts)
+                                uint32_t *counts, int32_t cshift)
 {
     if (total == 0) return hipSuccess;
     hipLaunchKernelGGL(k_gather_counts, dim3(grid_for(total, 256)), dim3(256), 0, s, sorted_keys, sorted_vals,
-                       ntiles, views, n_views, total, counts);
+                       ntiles, views, n_views, total, counts, cshift);
     return hipGetLastError();
 }
 
@@ -860,13 +872,14 @@ hipError_t launch_emit(hipStream_t s, const uint32_t *sorted_keys, const uint32_
                        const uint8_t *flags, const ViewDev *views, int32_t n_views, int64_t total,
                        uint32_t capacity, int32_t tile_w, int32_t tile_h, float sigma_k, const uint8_t *done,
                        uint32_t *tiles_out,
-                       uint32_t *vals_out, unsigned long long *status, int32_t gbits, const uint64_t *codes)
+                       uint32_t *vals_out, unsigned long long *status, int32_t gbits, const uint64_t *codes,
+                       int32_t cshift)
 {
     if (total == 0) return hipSuccess;
     hipLaunchKernelGGL(k_emit, dim3(grid_for(total, kThreads)), dim3(kThreads), 0, s, sorted_keys, sorted_vals, offsets,
                        counts, reinterpret_cast<const float4 *>(rec), reinterpret_cast<const short4 *>(rect), flags,
                        views, n_views, total, capacity, tile_w, tile_h, sigma_k, done, tiles_out, vals_out, status,
-                       gbits, reinterpret_cast<const ulonglong2 *>(codes));
+                       gbits, reinterpret_cast<const ulonglong2 *>(codes), cshift);
     return hipGetLastError();
 }
 
@@ -893,13 +906,13 @@ hipError_t launch_slab_counts(hipStream_t s, const uint32_t *sorted_keys, const 
                               const float *rec, const int16_t *rect, const uint8_t *flags, const int32_t *ntiles,
                               const ViewDev *views, int32_t n_views, int64_t total, Slab slab, const uint8_t *done,
                               int32_t tile_w, int32_t tile_h, float sigma_k, const uint64_t *codes,
-                              uint32_t *counts)
+                              uint32_t *counts, int32_t cshift)
 {
     if (total == 0) return hipSuccess;
     hipLaunchKernelGGL(k_slab_counts, dim3(grid_for(total, 256)), dim3(256), 0, s, sorted_keys, sorted_vals,
                        reinterpret_cast<const float4 *>(rec), reinterpret_cast<const short4 *>(rect), flags, ntiles,
                        views, n_views, total, slab, done, tile_w, tile_h, sigma_k,
-                       reinterpret_cast<const ulonglong2 *>(codes), counts);
+                       reinterpret_cast<const ulonglong2 *>(codes), counts, cshift);
     return hipGetLastError();
 }
 
