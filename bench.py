@@ -349,19 +349,26 @@ def main():
         else:
             sample = [(0, int(round(i * V / k))) for i in range(k)]
         cores = len(os.sched_getaffinity(0))
-        threads = max(1, min(16, cores, len(sample)))
         by_scene = {}
         for si, v in sample:
             by_scene.setdefault(si, []).append(v)
+        # one host thread per scene of the sample; a single scene splits its views over the threads
+        threads = max(1, min(16, cores, len(sample)))
+        per_scene = 1 if len(by_scene) > 1 else threads
         t = time.perf_counter()
-        with ThreadPoolExecutor(threads) as ex:
-            refs = dict(zip(by_scene, ex.map(lambda it: O.solve64(scenes[it[0]], O.params(), views=it[1]),
+        with ThreadPoolExecutor(max(1, min(threads, len(by_scene)))) as ex:
+            refs = dict(zip(by_scene, ex.map(lambda it: O.solve64(scenes[it[0]], O.params(), views=it[1],
+                                                                  threads=per_scene),
                                              by_scene.items())))
         dt_c = time.perf_counter() - t
         oblends = sum(r["blends"] for r in refs.values())
-        cpu = {"value": len(sample) / dt_c, "unit": "views/s", "cores": threads, "kind": "oracle",
+        omp = int(os.environ.get("OMP_NUM_THREADS", "0") or 0) or cores  # the oracle's binning loops use OpenMP
+        used = max(threads, min(omp, cores))
+        cpu = {"value": len(sample) / dt_c, "unit": "views/s", "cores": used, "kind": "oracle",
                "sample": f"{len(sample)} (scene, view) pairs of {args.config} {sample}: binning in binary32, "
-                         f"compositing and accumulation in binary64, {threads} host threads (one scene each), "
+                         f"compositing and accumulation in binary64 on {threads} host threads "
+                         f"({'one scene each' if per_scene == 1 else 'views split over them'}), the binning's "
+                         f"OpenMP loops on {min(omp, cores)}, "
                          f"{dt_c:.1f}s; whole workload extrapolated: {V * dt_c / len(sample):.0f}s",
                "blends_per_sec": oblends / dt_c,
                "extrapolated_seconds_per_step": V * dt_c / len(sample)}
