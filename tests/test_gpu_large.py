@@ -113,6 +113,14 @@ def test_large_scene_all_views_with_degenerate_splats(ctx):
     n, chunks, packed = check_chunk_lists(b, [sc], [(0, 150), (0, 299)], L.params(), "C4 batch")
     log(f"[C4] batch lists: {n} entries compared bit for bit on views 150 and 299, {chunks} chunks, {packed} packed")
     assert packed == 0
+    # the depth sort's values carry each element's tile count in the bits above the
+    # Gaussian id, saturating at 2^(32 - id bits) - 1; on these views many elements list
+    # more tiles than that, so the lists above also cover the gather for saturated counts
+    id_bits = max(1, int(np.ceil(np.log2(sc.n))))
+    sat = (1 << (32 - id_bits)) - 1
+    n_sat = sum(int((O.project32(sc, v, O.params())["ntiles"] >= sat).sum()) for v in (150, 299))
+    log(f"[C4] elements whose tile count reaches {sat} on views 150 and 299: {n_sat}")
+    assert n_sat > 0
     b.close()
 
 
