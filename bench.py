@@ -268,8 +268,30 @@ def main():
                                                  want_counts=False))
     sel = batch.S[big][1].contiguous()
     compact_ms = timed(lambda: ctx.fs_compact(db, sel, False))
+    # depth-guided masks (Sec. 3.4) of every view of the largest scene from its labels: projection,
+    # binning and rendering, per view
+    from paper_2409_08270_amd.solve import tiles_of
+    cams_b, nv_b = db.cams()
+    proj_b = L.Proj(sb.n, nv_b)
+    tt_b = sum(tiles_of(int(sb.W[v]), int(sb.H[v]), prm) for v in range(nv_b))
+    ctx.fs_project(db, cams_b, nv_b, prm, proj_b)
+    bins_b = L.Bins(1, tt_b)
+    need = ctx.fs_bin_sort(proj_b, cams_b, prm, bins_b, sync_count=True)
+    if need < 0:
+        bins_b = L.Bins(-need, tt_b)
+    lab_b = torch.empty(int(sb.pixels()), dtype=torch.uint8, device="cuda")
+    S_big = batch.S[big].contiguous()
+
+    def render_all():
+        ctx.fs_project(db, cams_b, nv_b, prm, proj_b)
+        ctx.fs_bin_sort(proj_b, cams_b, prm, bins_b)
+        ctx.fs_render_masks(proj_b, bins_b, cams_b, S_big, sb.E, prm, 0.1, L.FS_MASK_DEPTH, lab_b)
+    render_ms = timed(render_all, reps=3)
+    del proj_b, bins_b, lab_b
     followups = {"scene": big, "gaussians": sb.n, "classes": sb.E, "assign_ms": assign_ms,
                  f"bias_sweep_{ng}_gammas_ms": sweep_ms, "object_removal_compaction_ms": compact_ms,
+                 "novel_view_masks": {"views": nv_b, "ms": render_ms, "views_per_sec": nv_b / (render_ms * 1e-3),
+                                      "includes": "projection, binning and depth-guided mask rendering"},
                  "assign_all_scenes_in_graph": True}
     log(f"follow-ups: {followups}")
 

@@ -9,15 +9,22 @@
 //   depth-guided: the object with rho_e > tau of least D_e (0 if none), or
 //   argmax:       argmax over all objects (background included) of rho_e.
 //
-// One workgroup renders one tile (one pixel per thread). For each object the
-// tile's depth-ordered list is staged through LDS in batches; the members of
-// the object are compacted with wave ballots and every thread walks them.
+// One workgroup renders one tile (one pixel per thread). The objects are
+// taken kObj at a time: one walk over the tile's depth-ordered list serves all
+// of them, since a Gaussian's alpha at a pixel does not depend on the object.
+// The list is staged through LDS in batches with each entry's membership bits
+// for those objects; entries that belong to none of them are compacted away
+// with wave ballots, and every thread walks the rest, updating the
+// transmittance, alpha mask and depth sum of each object the entry belongs to
+// (a uniform loop over the entry's bits). Each object's arithmetic is the same
+// sequence of operations as compositing it alone.
 #include "fs_internal.h"
 
 namespace fs {
 namespace {
 
 constexpr int kRBatch = 256;
+constexpr int kObj = 8;  // objects composited in one walk of a tile's list
 
 __global__ __launch_bounds__(256) void k_render(const float4 *__restrict__ rec, const uint32_t *__restrict__ vals,
                                                 const uint2 *__restrict__ ranges, const ViewDev *__restrict__ views,
@@ -28,6 +35,7 @@ __global__ __launch_bounds__(256) void k_render(const float4 *__restrict__ rec, 
 {
     __shared__ float4 s_q[kRBatch];   // u, v, p', r (LDL^T factors, p in log2 units)
     __shared__ float4 s_q2[kRBatch];  // c', lo, thr, z
+    __shared__ uint8_t s_member[kRBatch];  // bit k: the entry belongs to object e0 + k
     __shared__ uint16_t s_list[kRBatch];
     __shared__ uint32_t s_wcnt[4];
 
@@ -48,27 +56,36 @@ __global__ __launch_bounds__(256) void k_render(const float4 *__restrict__ rec, 
 
     int best = 0;
     float best_d = 3.0e38f, best_rho = -1.0f;
-    for (int e = (mode == 1 ? 0 : 1); e < E; ++e) {
-        const uint8_t *__restrict__ member = S + (int64_t)e * n;
-        float T = 1.0f, rho = 0.0f, dz = 0.0f;
-        bool live = inside;
+    for (int e0 = (mode == 1 ? 0 : 1); e0 < E; e0 += kObj) {
+        const int ne = min(kObj, E - e0);
+        float T[kObj], rho[kObj], dz[kObj];
+#pragma unroll
+        for (int k = 0; k < kObj; ++k) {
+            T[k] = 1.0f;
+            rho[k] = 0.0f;
+            dz[k] = 0.0f;
+        }
+        // bit k: this pixel still composites object e0 + k
+        uint32_t live = inside ? ((1u << ne) - 1u) : 0u;
         for (uint32_t base = rg.x; base < rg.y; base += kRBatch) {
             const uint32_t cnt = min((uint32_t)kRBatch, rg.y - base);
             __syncthreads();  // previous batch consumed
-            bool mine = false;
+            uint32_t mbits = 0;
             if ((uint32_t)tid < cnt) {
                 const uint32_t g = vals[base + tid];
-                mine = member[g] != 0;
-                if (mine) {
+                for (int k = 0; k < ne; ++k) mbits |= (S[(int64_t)(e0 + k) * n + g] != 0 ? 1u : 0u) << k;
+                if (mbits) {
                     const float4 r0 = rec[(rec_base + g) * 2];
                     const float4 r1 = rec[(rec_base + g) * 2 + 1];
                     const float lo = fmaxf(__builtin_amdgcn_logf(r1.y), -200.0f);
                     s_q[tid] = make_float4(r0.x, r0.y, -0.5f * LOG2E * r0.z, r0.w);
                     s_q2[tid] = make_float4(-0.5f * LOG2E * r1.x, lo, P.cut2 + lo, r1.z);
+                    s_member[tid] = (uint8_t)mbits;
                 }
             }
-            // members of the batch in list order: per-wave ballots, then wave offsets
-            const unsigned long long bm = __ballot(mine);
+            // entries of the batch that belong to any of the objects, in list order:
+            // per-wave ballots, then wave offsets
+            const unsigned long long bm = __ballot(mbits != 0u);
             if (lane == 0) s_wcnt[w] = (uint32_t)__popcll(bm);
             __syncthreads();
             uint32_t before = 0, total = 0;
@@ -77,11 +94,13 @@ __global__ __launch_bounds__(256) void k_render(const float4 *__restrict__ rec, 
                 if (i < w) before += c;
                 total += c;
             }
-            if (mine) s_list[before + (uint32_t)__popcll(bm & ((1ull << lane) - 1ull))] = (uint16_t)tid;
+            if (mbits) s_list[before + (uint32_t)__popcll(bm & ((1ull << lane) - 1ull))] = (uint16_t)tid;
             __syncthreads();
             if (live) {
-                for (uint32_t k = 0; k < total; ++k) {
-                    const uint32_t j = s_list[k];
+                for (uint32_t i = 0; i < total; ++i) {
+                    const uint32_t j = s_list[i];
+                    const uint32_t mem = s_member[j] & live;
+                    if (mem == 0u) continue;
                     const float4 q = s_q[j];
                     const float4 q2 = s_q2[j];
                     const float dx = pxc - q.x, dy = pyc - q.y;
@@ -90,33 +109,45 @@ __global__ __launch_bounds__(256) void k_render(const float4 *__restrict__ rec, 
                     if (pw < q2.z) continue;
                     const float alpha = fminf(P.alpha_max, __builtin_amdgcn_exp2f(pw));
                     if (alpha < P.alpha_min) continue;
-                    const float Tn = fmaf(-T, alpha, T);
-                    if (Tn < P.t_min) {
-                        live = false;
-                        break;
+                    // each object the entry belongs to, as if composited alone
+#pragma unroll
+                    for (int k = 0; k < kObj; ++k) {
+                        if ((mem >> k) & 1u) {
+                            const float Tn = fmaf(-T[k], alpha, T[k]);
+                            if (Tn < P.t_min) {
+                                live &= ~(1u << k);
+                            } else {
+                                const float wv = alpha * T[k];
+                                rho[k] += wv;
+                                dz[k] = fmaf(wv, q2.w, dz[k]);
+                                T[k] = Tn;
+                            }
+                        }
                     }
-                    const float wv = alpha * T;
-                    rho += wv;
-                    dz = fmaf(wv, q2.w, dz);
-                    T = Tn;
+                    if (live == 0u) break;
                 }
             }
-            if (__syncthreads_or(live) == 0) break;
+            if (__syncthreads_or(live != 0u) == 0) break;
         }
-        const float d = rho > 0.0f ? dz / rho : 3.0e38f;
-        if (inside) {
-            const int64_t o = (int64_t)e * n_pixels + pix;
-            if (rho_out) rho_out[o] = rho;
-            if (depth_out) depth_out[o] = d;
-        }
-        if (mode == 1) {
-            if (rho > best_rho) {
-                best_rho = rho;
-                best = e;
+#pragma unroll
+        for (int k = 0; k < kObj; ++k) {
+            if (k >= ne) break;
+            const int eo = e0 + k;
+            const float d = rho[k] > 0.0f ? dz[k] / rho[k] : 3.0e38f;
+            if (inside) {
+                const int64_t o = (int64_t)eo * n_pixels + pix;
+                if (rho_out) rho_out[o] = rho[k];
+                if (depth_out) depth_out[o] = d;
             }
-        } else if (rho > tau && d < best_d) {
-            best_d = d;
-            best = e;
+            if (mode == 1) {
+                if (rho[k] > best_rho) {
+                    best_rho = rho[k];
+                    best = eo;
+                }
+            } else if (rho[k] > tau && d < best_d) {
+                best_d = d;
+                best = eo;
+            }
         }
     }
     if (inside) labels[pix] = (uint8_t)best;

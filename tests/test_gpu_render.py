@@ -61,7 +61,10 @@ def _compare(sc, S_host, E, mode, got, tau=0.1, what=""):
         r_g = rho_g[:, sl].reshape(E, H, W)
         e0 = 0 if mode == 1 else 1
         d = np.abs(r_g[e0:] - rho[e0:])
-        assert np.quantile(d, 0.999) <= 1e-4 and d.max() <= 0.05, (what, v, float(d.max()))
+        # a threshold decision (support at k = 3, alpha_min) taken differently in float32 and
+        # float64 moves rho by about one boundary alpha, at most o * exp(-9/2) ~ 0.011; the
+        # bound allows two such decisions in one pixel
+        assert np.quantile(d, 0.999) <= 1e-4 and d.max() <= 0.025, (what, v, float(d.max()))
         dmax = max(dmax, float(d.max()))
         n_over += int((d > 1e-4).sum())
         # labels: identical except where the oracle's own decision is within a band of its threshold
