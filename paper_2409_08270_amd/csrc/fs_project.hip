@@ -45,7 +45,7 @@ __device__ __forceinline__ uint32_t block_incl_sum(uint32_t x, uint32_t *s_wsum)
 // every thread takes rows in turn from the block's concatenated row list (a
 // binary search in the block's row offsets finds the splat), and the counts
 // and span-code bytes are gathered per splat in LDS.
-__global__ __launch_bounds__(256) void k_project(const ProjTask *__restrict__ tasks, int32_t n_tasks,
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(5, 5))) void k_project(const ProjTask *__restrict__ tasks, int32_t n_tasks,
                                                  const SceneDev *__restrict__ scenes, const ViewDev *__restrict__ views,
                                                  ProjParams P, float4 *__restrict__ rec, short4 *__restrict__ rect,
                                                  int32_t *__restrict__ ntiles, uint8_t *__restrict__ flags,

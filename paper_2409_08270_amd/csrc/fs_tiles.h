@@ -79,7 +79,7 @@ __host__ __device__ __forceinline__ float approx_rcp(float x)
 
 struct Span32 {
     float u, v, p, r, s, lim;  // the definition's inputs
-    float lo, A, B, C, dt, iC, xe, ye, yx, mx, my;  // candidate bounds (approximate, widened)
+    float lo, B, C, dt, iC, xe, ye, yx, mx, my;  // candidate bounds (approximate, widened; A = p)
     float li;  // inner level L (1 - rq): centres with exact q <= li pass in binary32
     float ip;  // approximate 1 / p
     bool full, ok;
@@ -124,9 +124,8 @@ __host__ __device__ __forceinline__ Span32 make_span32(float u, float v, float p
     sp.u = u; sp.v = v; sp.p = p; sp.r = r; sp.s = s; sp.lim = lim;
     sp.full = full;
     sp.ok = false;
-    sp.lo = sp.A = sp.B = sp.C = sp.dt = sp.iC = sp.xe = sp.ye = sp.yx = sp.mx = sp.my = sp.li = sp.ip = 0.0f;
+    sp.lo = sp.B = sp.C = sp.dt = sp.iC = sp.xe = sp.ye = sp.yx = sp.mx = sp.my = sp.li = sp.ip = 0.0f;
     if (full) return sp;
-    sp.A = p;
     sp.B = p * r;
     sp.C = s + sp.B * r;
     sp.dt = p * s;
