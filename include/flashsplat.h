@@ -331,7 +331,9 @@ int fs_compact(fs_ctx *ctx, const fs_gaussians *in, const uint8_t *select, int32
  * output. labels: device uint8, the views' pixels concatenated [H][W] each.
  * rho, depth: device float32 [n_classes][pixels of all views], or NULL
  * (entries for objects that are not rendered are left untouched; depth is
- * 3e38 where rho_e = 0). tau: finite. */
+ * 3e38 where rho_e = 0). tau: finite. The context keeps n bytes of
+ * workspace per 8 rendered objects (each Gaussian's membership bits, built
+ * from S at the start of the call). */
 #define FS_MASK_DEPTH 0
 #define FS_MASK_ARGMAX 1
 int fs_render_masks(fs_ctx *ctx, const fs_proj *proj, const fs_bins *bins, const fs_camera *cams,

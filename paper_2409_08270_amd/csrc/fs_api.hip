@@ -54,6 +54,7 @@ struct fs_ctx {
     DevBuf pk_alt, pv_alt, sort_ws, scan_ws;
     DevBuf items, items_k, items_k2, items_v2, items_ws;
     DevBuf fix;                // FS_RED_DET: the call's fixed-point totals
+    DevBuf memb;               // fs_render_masks: object membership bytes
     uint64_t items_tiles = 0;  // tile count the XCD-run table in `items` was built for
     Staging stage[kStaging];
     int stage_next = 0;
@@ -578,7 +579,7 @@ int fs_ctx_destroy(fs_ctx *ctx)
     DevBuf *bufs[] = {&ctx->views, &ctx->scenes, &ctx->tasks, &ctx->dsegs, &ctx->psegs, &ctx->lsegs,
                       &ctx->dkeys, &ctx->dvals, &ctx->dkeys2, &ctx->dvals2, &ctx->counts, &ctx->offsets,
                       &ctx->pk_alt, &ctx->pv_alt, &ctx->sort_ws, &ctx->scan_ws, &ctx->items, &ctx->items_k,
-                      &ctx->items_k2, &ctx->items_v2, &ctx->items_ws, &ctx->fix};
+                      &ctx->items_k2, &ctx->items_v2, &ctx->items_ws, &ctx->fix, &ctx->memb};
     for (DevBuf *b : bufs) free_buf(*b);
     for (int i = 0; i < kStaging; ++i) {
         if (ctx->stage[i].host) (void)hipHostFree(ctx->stage[i].host);
@@ -908,9 +909,10 @@ int fs_render_masks(fs_ctx *ctx, const fs_proj *proj, const fs_bins *bins, const
     Plan pl;
     plan_add(pl, p, 0, proj->n, cams, 0, V, 0);
     RCHECK(upload_vec(ctx, ctx->views, pl.views));
+    RCHECK(ensure(ctx, ctx->memb, (size_t)render_member_bytes(proj->n, n_classes, mode)));
     HIPCHECK(ctx, launch_render(ctx->stream, proj->rec, bins->vals, bins->ranges, (const ViewDev *)ctx->views.p, V,
                                 (uint32_t)pl.tiles, S, proj->n, n_classes, acc_params(p, FS_RED_LDS), tau, mode, labels,
-                                rho, depth, (int64_t)pl.pixels));
+                                rho, depth, (int64_t)pl.pixels, (uint8_t *)ctx->memb.p));
     return FS_OK;
 }
 

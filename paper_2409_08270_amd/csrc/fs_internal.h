@@ -277,11 +277,14 @@ hipError_t launch_fix_finish(hipStream_t s, const unsigned long long *fix, float
 hipError_t launch_assign(hipStream_t s, const float *A_hi, const float *A_lo, int64_t n, int32_t E, float gamma,
                          uint8_t *S, float *margin, unsigned long long *status);
 
-// novel-view masks (fs_render.hip)
+// novel-view masks (fs_render.hip); memb is workspace of
+// render_member_bytes(n, E, mode) bytes (one byte per group of objects and
+// Gaussian, rebuilt from S by the launch)
 hipError_t launch_render(hipStream_t s, const float *rec, const uint32_t *vals, const uint32_t *ranges,
                          const ViewDev *views, int32_t n_views, uint32_t n_tiles, const uint8_t *S, int64_t n,
                          int32_t E, const AccParams &p, float tau, int32_t mode, uint8_t *labels, float *rho,
-                         float *depth, int64_t n_pixels);
+                         float *depth, int64_t n_pixels, uint8_t *memb);
+int64_t render_member_bytes(int64_t n, int32_t E, int32_t mode);
 
 // per-Gaussian diagnostics (fs_diag.hip): histograms [E+1] and overlap [E][3],
 // zeroed by the caller

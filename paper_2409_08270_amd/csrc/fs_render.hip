@@ -18,6 +18,11 @@
 // transmittance, alpha mask and depth sum of each object the entry belongs to
 // (a uniform loop over the entry's bits). Each object's arithmetic is the same
 // sequence of operations as compositing it alone.
+//
+// The membership bits come from one byte per (group of kObj objects,
+// Gaussian), built from S beforehand with reads that are contiguous along the
+// Gaussians, so that staging an entry gathers one byte per group instead of
+// one row of S per object.
 #include "fs_internal.h"
 
 namespace fs {
@@ -26,9 +31,22 @@ namespace {
 constexpr int kRBatch = 256;
 constexpr int kObj = 8;  // objects composited in one walk of a tile's list
 
+// memb[q][g], bit k: Gaussian g belongs to object e_first + kObj q + k
+__global__ void k_member_bytes(const uint8_t *__restrict__ S, int64_t n, int32_t e_first, int32_t E,
+                               uint8_t *__restrict__ memb)
+{
+    const int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (g >= n) return;
+    for (int q = 0, e0 = e_first; e0 < E; ++q, e0 += kObj) {
+        uint32_t bits = 0;
+        for (int k = 0; k < kObj && e0 + k < E; ++k) bits |= (S[(int64_t)(e0 + k) * n + g] != 0 ? 1u : 0u) << k;
+        memb[(int64_t)q * n + g] = (uint8_t)bits;
+    }
+}
+
 __global__ __launch_bounds__(256) void k_render(const float4 *__restrict__ rec, const uint32_t *__restrict__ vals,
                                                 const uint2 *__restrict__ ranges, const ViewDev *__restrict__ views,
-                                                int32_t n_views, const uint8_t *__restrict__ S, int64_t n, int32_t E,
+                                                int32_t n_views, const uint8_t *__restrict__ memb, int64_t n, int32_t E,
                                                 AccParams P, float tau, int32_t mode, uint8_t *__restrict__ labels,
                                                 float *__restrict__ rho_out, float *__restrict__ depth_out,
                                                 int64_t n_pixels)
@@ -56,7 +74,9 @@ __global__ __launch_bounds__(256) void k_render(const float4 *__restrict__ rec, 
 
     int best = 0;
     float best_d = 3.0e38f, best_rho = -1.0f;
-    for (int e0 = (mode == 1 ? 0 : 1); e0 < E; e0 += kObj) {
+    const int e_first = mode == 1 ? 0 : 1;
+    for (int e0 = e_first; e0 < E; e0 += kObj) {
+        const uint8_t *__restrict__ mq = memb + (int64_t)((e0 - e_first) / kObj) * n;
         const int ne = min(kObj, E - e0);
         float T[kObj], rho[kObj], dz[kObj];
 #pragma unroll
@@ -73,7 +93,7 @@ __global__ __launch_bounds__(256) void k_render(const float4 *__restrict__ rec, 
             uint32_t mbits = 0;
             if ((uint32_t)tid < cnt) {
                 const uint32_t g = vals[base + tid];
-                for (int k = 0; k < ne; ++k) mbits |= (S[(int64_t)(e0 + k) * n + g] != 0 ? 1u : 0u) << k;
+                mbits = mq[g];
                 if (mbits) {
                     const float4 r0 = rec[(rec_base + g) * 2];
                     const float4 r1 = rec[(rec_base + g) * 2 + 1];
@@ -158,13 +178,25 @@ __global__ __launch_bounds__(256) void k_render(const float4 *__restrict__ rec, 
 hipError_t launch_render(hipStream_t s, const float *rec, const uint32_t *vals, const uint32_t *ranges,
                          const ViewDev *views, int32_t n_views, uint32_t n_tiles, const uint8_t *S, int64_t n,
                          int32_t E, const AccParams &p, float tau, int32_t mode, uint8_t *labels, float *rho,
-                         float *depth, int64_t n_pixels)
+                         float *depth, int64_t n_pixels, uint8_t *memb)
 {
     if (n_tiles == 0) return hipSuccess;
+    if (n > 0) {
+        hipLaunchKernelGGL(k_member_bytes, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, S, n,
+                           mode == 1 ? 0 : 1, E, memb);
+        const hipError_t e = hipGetLastError();
+        if (e != hipSuccess) return e;
+    }
     hipLaunchKernelGGL(k_render, dim3(n_tiles), dim3(256), 0, s, reinterpret_cast<const float4 *>(rec), vals,
-                       reinterpret_cast<const uint2 *>(ranges), views, n_views, S, n, E, p, tau, mode, labels, rho,
+                       reinterpret_cast<const uint2 *>(ranges), views, n_views, memb, n, E, p, tau, mode, labels, rho,
                        depth, n_pixels);
     return hipGetLastError();
+}
+
+int64_t render_member_bytes(int64_t n, int32_t E, int32_t mode)
+{
+    const int e_first = mode == 1 ? 0 : 1;
+    return n * (int64_t)((E - e_first + kObj - 1) / kObj);
 }
 
 }  // namespace fs
