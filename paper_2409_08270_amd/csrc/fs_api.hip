@@ -1014,10 +1014,12 @@ int fs_assign_sweep(fs_ctx *ctx, const float *A_hi, const float *A_lo, int64_t n
     if (!S && !counts) return set_err(ctx, FS_ERR_ARG, "nothing to compute: S and counts are NULL");
     const size_t ncnt = (size_t)n_gamma * n_classes;
     RCHECK(upload(ctx, ctx->items_ws, gammas, sizeof(float) * n_gamma));
-    RCHECK(ensure(ctx, ctx->items_k, ncnt * 8));
-    HIPCHECK(ctx, launch_fill_u32(ctx->stream, (uint32_t *)ctx->items_k.p, 0u, (int64_t)ncnt * 2));
+    if (counts) {
+        RCHECK(ensure(ctx, ctx->items_k, ncnt * 8));
+        HIPCHECK(ctx, launch_fill_u32(ctx->stream, (uint32_t *)ctx->items_k.p, 0u, (int64_t)ncnt * 2));
+    }
     HIPCHECK(ctx, launch_assign_sweep(ctx->stream, A_hi, A_lo, n, n_classes, (const float *)ctx->items_ws.p, n_gamma,
-                                      S, (unsigned long long *)ctx->items_k.p));
+                                      S, counts ? (unsigned long long *)ctx->items_k.p : nullptr));
     if (counts) {
         HIPCHECK(ctx, hipMemcpyAsync(counts, ctx->items_k.p, ncnt * 8, hipMemcpyDeviceToHost, ctx->stream));
         HIPCHECK(ctx, hipStreamSynchronize(ctx->stream));

@@ -11,13 +11,16 @@
 //
 // Memory: A is row-major [n][E] (one row per Gaussian) and S is [E][n]. A
 // block stages a tile of rows in LDS with coalesced loads and writes S and
-// the margins column-tile by column-tile, so both sides stay coalesced.
+// the margins column-tile by column-tile, so both sides stay coalesced. The
+// staged rows are E | 1 doubles apart: consecutive lanes read one column of
+// consecutive rows, and an even stride (E = 64: 512 bytes) would send them
+// all to the same LDS banks.
 #include "fs_internal.h"
 
 namespace fs {
 namespace {
 
-constexpr int kLdsDoubles = 4096;  // 32 KiB of staged rows
+constexpr int kLdsDoubles = 4160;  // staged rows: 64 rows of 65 doubles at E = 64
 
 __global__ __launch_bounds__(256) void k_assign(const float *__restrict__ A_hi, const float *__restrict__ A_lo,
                                                 int64_t n, int32_t E, int32_t rows_per_block, float gamma,
@@ -32,17 +35,28 @@ __global__ __launch_bounds__(256) void k_assign(const float *__restrict__ A_hi, 
     const int R = (int)min((int64_t)rows_per_block, n - r0);
     const int tid = threadIdx.x;
     if (tid < 3) s_cnt[tid] = 0;
-    // coalesced load of R rows x E columns
+    const int stride = E | 1;
+    // coalesced load of R rows x E columns; (r, e) of element i advance with i
     const int64_t base = r0 * E;
-    for (int i = tid; i < R * E; i += 256) {
-        double v = (double)A_hi[base + i];
-        if (A_lo) v += (double)A_lo[base + i];
-        s_a[i] = v;
+    {
+        int r = tid / E, e = tid - (tid / E) * E;
+        const int qd = 256 / E, qm = 256 - qd * E;
+        for (int i = tid; i < R * E; i += 256) {
+            double v = (double)A_hi[base + i];
+            if (A_lo) v += (double)A_lo[base + i];
+            s_a[r * stride + e] = v;
+            r += qd;
+            e += qm;
+            if (e >= E) {
+                e -= E;
+                ++r;
+            }
+        }
     }
     __syncthreads();
     if (tid < R) {
         double tot = 0.0;
-        for (int e = 0; e < E; ++e) tot += s_a[tid * E + e];
+        for (int e = 0; e < E; ++e) tot += s_a[tid * stride + e];
         s_tot[tid] = tot;
         s_members[tid] = 0;
         if (tot == 0.0) atomicAdd(&s_cnt[0], 1u);
@@ -50,9 +64,11 @@ __global__ __launch_bounds__(256) void k_assign(const float *__restrict__ A_hi, 
     __syncthreads();
     const double gd = (double)gamma;
     uint32_t low = 0;
+    // element i = t * R + r (object t, row r); (t, r) advance with i
+    int t = tid / R, r = tid - (tid / R) * R;
+    const int qd = 256 / R, qm = 256 - qd * R;
     for (int i = tid; i < R * E; i += 256) {
-        const int t = i / R, r = i % R;
-        const double a = s_a[r * E + t];
+        const double a = s_a[r * stride + t];
         double o = s_tot[r] - a;
         if (o < 0.0) o = 0.0;
         const double s = fmax(a + o, 1e-12);
@@ -63,6 +79,12 @@ __global__ __launch_bounds__(256) void k_assign(const float *__restrict__ A_hi, 
         if (margin) margin[(int64_t)t * n + r0 + r] = (float)m;
         if (in) atomicAdd(&s_members[r], 1u);
         if (m < 1e-4) low++;
+        t += qd;
+        r += qm;
+        if (r >= R) {
+            r -= R;
+            ++t;
+        }
     }
     if (low) atomicAdd(&s_cnt[2], low);
     __syncthreads();
@@ -81,7 +103,7 @@ hipError_t launch_assign(hipStream_t s, const float *A_hi, const float *A_lo, in
                          uint8_t *S, float *margin, unsigned long long *status)
 {
     if (n == 0) return hipSuccess;
-    int rows = kLdsDoubles / E;
+    int rows = kLdsDoubles / (E | 1);
     if (rows > 256) rows = 256;
     if (rows < 1) rows = 1;
     const int64_t blocks = (n + rows - 1) / rows;

@@ -7,11 +7,17 @@
 namespace fs {
 namespace {
 
-constexpr int kSweepLds = 4096;     // doubles of staged rows
+constexpr int kSweepLds = 4160;     // doubles of staged rows (64 rows of 65)
 constexpr int kSweepCounters = 4096;  // n_gamma * E counters per block
 
 // S[k][t][g] = a_n > o_n + gamma_k for every gamma of the sweep, from one read
-// of A (same arithmetic as the single assignment); counts[k][t] += members.
+// of A (same arithmetic as the single assignment); counts[k][t] += members
+// (counts may be NULL). A block stages `rows_per_block` rows; thread i takes
+// object t = i / R and row i % R, so with R a multiple of 64 every wave holds
+// one object and counts its members with one ballot per gamma (waves that
+// straddle two objects fall back to one LDS atomic per member). Staged rows
+// are E | 1 doubles apart, so that a wave reading one column of consecutive
+// rows spreads over the LDS banks.
 __global__ __launch_bounds__(256) void k_assign_sweep(const float *__restrict__ A_hi, const float *__restrict__ A_lo,
                                                       int64_t n, int32_t E, int32_t rows_per_block,
                                                       const float *__restrict__ gammas, int32_t n_gamma,
@@ -27,32 +33,71 @@ __global__ __launch_bounds__(256) void k_assign_sweep(const float *__restrict__ 
     const int tid = threadIdx.x;
     for (int i = tid; i < n_gamma * E; i += 256) s_cnt[i] = 0;
     if (tid < n_gamma) s_g[tid] = gammas[tid];
+    const int stride = E | 1;
     const int64_t base = r0 * E;
-    for (int i = tid; i < R * E; i += 256) {
-        double v = (double)A_hi[base + i];
-        if (A_lo) v += (double)A_lo[base + i];
-        s_a[i] = v;
+    {
+        // (r, e) of element i advance with i
+        int r = tid / E, e = tid - (tid / E) * E;
+        const int qd = 256 / E, qm = 256 - qd * E;
+        for (int i = tid; i < R * E; i += 256) {
+            double v = (double)A_hi[base + i];
+            if (A_lo) v += (double)A_lo[base + i];
+            s_a[r * stride + e] = v;
+            r += qd;
+            e += qm;
+            if (e >= E) {
+                e -= E;
+                ++r;
+            }
+        }
     }
     __syncthreads();
     if (tid < R) {
         double tot = 0.0;
-        for (int e = 0; e < E; ++e) tot += s_a[tid * E + e];
+        for (int e = 0; e < E; ++e) tot += s_a[tid * stride + e];
         s_tot[tid] = tot;
     }
     __syncthreads();
-    for (int i = tid; i < R * E; i += 256) {
-        const int t = i / R, r = i % R;
-        const double a = s_a[r * E + t];
-        double o = s_tot[r] - a;
-        if (o < 0.0) o = 0.0;
-        const double s = fmax(a + o, 1e-12);
-        const double an = a / s, on = o / s;
+    const int lane = tid & 63;
+    // element i = t * R + r (object t, row r); (t, r) advance with i
+    int ti = tid / R, ri = tid - (tid / R) * R;
+    const int qd = 256 / R, qm = 256 - qd * R;
+    for (int i0 = tid - lane; i0 < R * E; i0 += 256) {
+        const int i = i0 + lane;
+        const bool ok = i < R * E;
+        const int t = ok ? ti : 0, r = ok ? ri : 0;
+        ti += qd;
+        ri += qm;
+        if (ri >= R) {
+            ri -= R;
+            ++ti;
+        }
+        double an = 0.0, on = 1.0;
+        if (ok) {
+            const double a = s_a[r * stride + t];
+            double o = s_tot[r] - a;
+            if (o < 0.0) o = 0.0;
+            const double s = fmax(a + o, 1e-12);
+            an = a / s;
+            on = o / s;
+        }
+        // the wave's lanes in range all hold object t0
+        const int t0 = __builtin_amdgcn_readfirstlane(t);
+        const bool one_obj = __ballot(ok && t != t0) == 0ull;
         for (int k = 0; k < n_gamma; ++k) {
-            const bool in = an > on + (double)s_g[k];
-            if (S) S[((int64_t)k * E + t) * n + r0 + r] = in ? 1 : 0;
-            if (in) atomicAdd(&s_cnt[k * E + t], 1u);
+            const bool in = ok && an > on + (double)s_g[k];
+            if (S && ok) S[((int64_t)k * E + t) * n + r0 + r] = in ? 1 : 0;
+            if (counts) {
+                if (one_obj) {
+                    const unsigned long long b = __ballot(in);
+                    if (lane == 0 && b) atomicAdd(&s_cnt[k * E + t0], (uint32_t)__popcll(b));
+                } else if (in) {
+                    atomicAdd(&s_cnt[k * E + t], 1u);
+                }
+            }
         }
     }
+    if (!counts) return;
     __syncthreads();
     for (int i = tid; i < n_gamma * E; i += 256)
         if (s_cnt[i]) atomicAdd(&counts[i], (unsigned long long)s_cnt[i]);
@@ -92,8 +137,9 @@ hipError_t launch_assign_sweep(hipStream_t s, const float *A_hi, const float *A_
                                const float *gammas_dev, int32_t n_gamma, uint8_t *S, unsigned long long *counts)
 {
     if (n == 0 || n_gamma == 0) return hipSuccess;
-    int rows = kSweepLds / E;
+    int rows = kSweepLds / (E | 1);
     if (rows > 256) rows = 256;
+    if (rows >= 64) rows &= ~63;  // whole waves per object (E <= 63)
     if (rows < 1) rows = 1;
     const int64_t blocks = (n + rows - 1) / rows;
     hipLaunchKernelGGL(k_assign_sweep, dim3((unsigned)blocks), dim3(256), 0, s, A_hi, A_lo, n, E, rows, gammas_dev,

@@ -68,6 +68,31 @@ def test_sweep_many_classes_and_limits(ctx):
         ctx.fs_assign_sweep(A_hi, None, n, E, [1.5], None)
 
 
+@pytest.mark.parametrize("E", [17, 100])
+def test_sweep_counts_when_waves_straddle_objects(ctx, E):
+    """Row blocks that are not whole waves per object (E = 100: 40 rows, every
+    wave holds two objects) and a partial last block: the counts equal the
+    labels' sums, the labels equal single assignments, with or without counts."""
+    rng = np.random.default_rng(E)
+    n = 3001
+    A = rng.gamma(0.3, 1.0, size=(n, E)).astype(np.float32)
+    A[rng.random((n, E)) < 0.6] = 0
+    A_hi = torch.from_numpy(A).cuda()
+    gammas = [-0.4, -0.1, 0.0, 0.1, 0.3]
+    S = torch.empty((len(gammas), E, n), dtype=torch.uint8, device="cuda")
+    counts = ctx.fs_assign_sweep(A_hi, None, n, E, gammas, S)
+    Sg = S.cpu().numpy()
+    assert np.array_equal(counts, Sg.sum(axis=2))
+    S2 = torch.full((len(gammas), E, n), 7, dtype=torch.uint8, device="cuda")
+    assert ctx.fs_assign_sweep(A_hi, None, n, E, gammas, S2, want_counts=False) is None
+    assert np.array_equal(S2.cpu().numpy(), Sg)
+    for k, g in enumerate(gammas):
+        one = torch.empty((E, n), dtype=torch.uint8, device="cuda")
+        ctx.fs_assign(A_hi, None, n, E, g, one, None)
+        assert np.array_equal(one.cpu().numpy(), Sg[k])
+    ctx.status()
+
+
 def test_extraction_and_removal(ctx, c1):
     sc, ds, out, ref = c1
     S = out["S"]
