@@ -56,6 +56,8 @@ __global__ __launch_bounds__(256) void k_assign(const float *__restrict__ A_hi, 
     __syncthreads();
     if (tid < R) {
         double tot = 0.0;
+        // in order e = 0, 1, ...; unrolled so that several LDS reads are in flight
+#pragma unroll 8
         for (int e = 0; e < E; ++e) tot += s_a[tid * stride + e];
         s_tot[tid] = tot;
         s_members[tid] = 0;

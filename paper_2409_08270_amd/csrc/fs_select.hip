@@ -54,6 +54,8 @@ __global__ __launch_bounds__(256) void k_assign_sweep(const float *__restrict__ 
     __syncthreads();
     if (tid < R) {
         double tot = 0.0;
+        // in order e = 0, 1, ...; unrolled so that several LDS reads are in flight
+#pragma unroll 8
         for (int e = 0; e < E; ++e) tot += s_a[tid * stride + e];
         s_tot[tid] = tot;
     }
@@ -84,15 +86,24 @@ __global__ __launch_bounds__(256) void k_assign_sweep(const float *__restrict__ 
         // the wave's lanes in range all hold object t0
         const int t0 = __builtin_amdgcn_readfirstlane(t);
         const bool one_obj = __ballot(ok && t != t0) == 0ull;
-        for (int k = 0; k < n_gamma; ++k) {
-            const bool in = ok && an > on + (double)s_g[k];
-            if (S && ok) S[((int64_t)k * E + t) * n + r0 + r] = in ? 1 : 0;
-            if (counts) {
-                if (one_obj) {
-                    const unsigned long long b = __ballot(in);
-                    if (lane == 0 && b) atomicAdd(&s_cnt[k * E + t0], (uint32_t)__popcll(b));
-                } else if (in) {
-                    atomicAdd(&s_cnt[k * E + t], 1u);
+        // biases 8 at a time, their LDS reads issued together
+        for (int k0 = 0; k0 < n_gamma; k0 += 8) {
+            double gk[8];
+#pragma unroll
+            for (int j = 0; j < 8; ++j) gk[j] = k0 + j < n_gamma ? (double)s_g[k0 + j] : 0.0;
+#pragma unroll
+            for (int j = 0; j < 8; ++j) {
+                const int k = k0 + j;
+                if (k >= n_gamma) break;
+                const bool in = ok && an > on + gk[j];
+                if (S && ok) S[((int64_t)k * E + t) * n + r0 + r] = in ? 1 : 0;
+                if (counts) {
+                    if (one_obj) {
+                        const unsigned long long b = __ballot(in);
+                        if (lane == 0 && b) atomicAdd(&s_cnt[k * E + t0], (uint32_t)__popcll(b));
+                    } else if (in) {
+                        atomicAdd(&s_cnt[k * E + t], 1u);
+                    }
                 }
             }
         }
