@@ -20,7 +20,7 @@
 namespace fs {
 namespace {
 
-constexpr int kLdsDoubles = 4160;  // staged rows: 64 rows of 65 doubles at E = 64
+constexpr int kLdsDoubles = 2080;  // staged rows, 16.25 KiB (eight blocks per CU): 32 rows of 65 doubles at E = 64
 
 __global__ __launch_bounds__(256) void k_assign(const float *__restrict__ A_hi, const float *__restrict__ A_lo,
                                                 int64_t n, int32_t E, int32_t rows_per_block, float gamma,
